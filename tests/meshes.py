@@ -1,0 +1,34 @@
+"""Tiny hand-built meshes shared by the CPU and GPU tests (inputs only)."""
+import numpy as np
+
+from paper_2203_02054_amd import meshgen as mg
+
+
+def voxel_box(nx, ny, nz, h=1.0, mode=mg.BODY, chamber=-1):
+    solid = np.ones((nx, ny, nz), bool)
+    xyz, tets, _, _ = mg.kuhn_tets(solid, h)
+    T = tets.shape[1]
+    return dict(rest_xyz=xyz, tets=tets, tet_mode=np.full(T, mode, np.uint8),
+                tet_chamber=np.full(T, chamber, np.int16),
+                fixed=np.zeros(xyz.shape[1], np.uint8))
+
+
+def slit_pair(h=1.0, gap=1, depth=2):
+    """Two voxel blocks facing each other across an empty slab (a slit)."""
+    nx = 2 * depth + gap
+    solid = np.ones((nx, 2, 2), bool)
+    solid[depth:depth + gap] = False
+    xyz, tets, vijk, _ = mg.kuhn_tets(solid, h)
+    T = tets.shape[1]
+    return dict(rest_xyz=xyz, tets=tets, tet_mode=np.zeros(T, np.uint8),
+                tet_chamber=np.full(T, -1, np.int16),
+                fixed=np.zeros(xyz.shape[1], np.uint8)), vijk
+
+
+def random_rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
