@@ -1,0 +1,250 @@
+/*
+ * geosim.h - C ABI of the MI355X (gfx950) library for collision-aware,
+ * geometry-based soft-robot simulation on tetrahedral meshes.
+ *
+ * The method (Fang, Tian, Weightman, Wang, "Collision-Aware Fast Simulation
+ * for Soft Robots by Optimization-Based Geometric Computing") finds the
+ * deformed shape of an actuated soft robot by minimising the augmented
+ * geometric objective of Eq. (9) with a local/global iteration
+ * (Section III-B, inner loop of Algorithm 1):
+ *
+ *   local step   every tet is projected onto its target shape: chamber
+ *                elements onto their volume-scaled rest shape (Section
+ *                III-A.1, Eq. 2), body elements onto the Mooney-Rivlin blend
+ *                of Eq. (6) rescaled to the rest volume by Eq. (7); the
+ *                rotation is the SVD (Kabsch) fit below Eq. (1);
+ *   collision    surface vertices inside other tets (Eq. 3) or inside
+ *                obstacles (Eq. 4) get virtual springs (Eq. 5) towards
+ *                targets on the offset boundary (Section II-C), kept or
+ *                released by Eq. (8);
+ *   global step  with targets fixed, Eq. (9) is a linear least-squares
+ *                problem in the vertex positions, solved here by a
+ *                Jacobi-preconditioned conjugate gradient on a CSR matrix.
+ *
+ * Conventions
+ * -----------
+ * - All arrays are structure-of-arrays: positions [3][n] (x row, y row,
+ *   z row), tets [4][T].  Indices are int32, zero-based.
+ * - "dev_" pointers are device (HIP) memory owned by the caller; all other
+ *   pointers are host memory.  The library never allocates or frees device
+ *   memory: the caller provides one workspace (gs_workspace_size bytes) at
+ *   gs_bind, plus the in/out buffers of each call.
+ * - Every device call is enqueued on the stream given to gs_bind (a
+ *   hipStream_t passed as void*).  Calls that return host data (statistics,
+ *   contacts, candidate lists) synchronise that stream.
+ * - Status codes: 0 ok, > 0 warning, < 0 error.  A negative code leaves the
+ *   handle usable except after GS_EHIP.  gs_last_error() gives a message for
+ *   the last failing call on the calling thread.  No C++ exception crosses
+ *   this interface.
+ * - Floating-point width of the solve is chosen per problem
+ *   (gs_mesh_desc.precision = 4 or 8): dev_x, dev_alpha and the debug
+ *   outputs use that width; geometric predicates are always evaluated in
+ *   double precision.
+ */
+#ifndef GEOSIM_H
+#define GEOSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GEOSIM_VERSION 100
+
+typedef int32_t gs_status;
+
+enum {
+  GS_OK = 0,
+  GS_NOT_CONVERGED = 1, /* max_iter reached; the last iterate is written      */
+  GS_EINVAL = -1,       /* bad size, index, null pointer or non-finite input  */
+  GS_EDEGENERATE = -2,  /* rest tet with |Vol| <= 1e-12 h_ref^3               */
+  GS_EBREAKDOWN = -3,   /* NaN/Inf in the iteration or CG curvature p'Ap <= 0 */
+  GS_ECAPACITY = -4,    /* caller buffer too small; the needed count is given */
+  GS_ESTATE = -5,       /* call out of order (e.g. solve before bind)         */
+  GS_EHIP = -6          /* HIP runtime error; see gs_last_error()             */
+};
+
+/* Element classes (Section II-A): body elements (M_b) and chamber elements
+ * (M_c).  A chamber element of class GS_CH_ISO targets alpha^(1/3) times its
+ * rest shape (Section III-A.1); GS_CH_AX_{X,Y,Z} stretch the rest shape by
+ * alpha along one rest-frame axis (length actuation, footnote of Section
+ * II-A).  Both reach volume ratio alpha (Eq. 2). */
+enum { GS_BODY = 0, GS_CH_ISO = 1, GS_CH_AX_X = 2, GS_CH_AX_Y = 3, GS_CH_AX_Z = 4 };
+
+/* Contact types of the virtual springs (Section II-C). */
+enum { GS_CONTACT_SELF = 0, GS_CONTACT_SPHERE = 1, GS_CONTACT_PLANE = 2 };
+
+/* Tet mesh M = M_c + M_b (Section II-A).  Host pointers, copied by gs_create. */
+typedef struct {
+  int32_t n_verts, n_tets, n_chambers;
+  int32_t precision;          /* 4 (float) or 8 (double)                          */
+  const double* rest_xyz;     /* [3][n_verts] rest positions X0 (mm)              */
+  const int32_t* tets;        /* [4][n_tets] vertex ids, any orientation          */
+  const uint8_t* tet_mode;    /* [n_tets] GS_BODY / GS_CH_*                       */
+  const int16_t* tet_chamber; /* [n_tets] chamber id in [0, n_chambers), -1 body  */
+  const uint8_t* fixed;       /* [n_verts] 1 = held at its rest position          */
+} gs_mesh_desc;
+
+typedef struct {
+  double c1, c2;          /* Mooney-Rivlin constants of the body (Section IV)     */
+  int32_t hyperelastic;   /* 0: R_w == 1 (as-rigid-as-possible body targets)      */
+  double kappa_col;       /* spring stiffness k_v = kappa_col * A_el[v,v]         */
+  double eps_rel;         /* offset eps of the collided boundary, x h_ref (0.05)  */
+  double ray_rel;         /* length of the inverse-normal search, x h_ref (4)     */
+  int32_t self_collision, obstacle_collision;
+  double tol;             /* outer residual max_v|dx_v| / bbox diagonal (1e-6)    */
+  int32_t max_iter;       /* outer iteration cap                                  */
+  int32_t fixed_iters;    /* > 0: run exactly this many outer iterations          */
+  double pcg_eta;         /* inner CG stop: sqrt(r'z) <= pcg_eta sqrt(b'D^-1 b),
+                             b = right-hand side, CG warm-started at the previous
+                             correction                                           */
+  int32_t pcg_max;        /* inner CG iteration cap per outer iteration           */
+  int32_t check_every;    /* outer iterations between host convergence polls     */
+  int32_t pcg_blocks;     /* workgroups of the cooperative CG kernel (0: auto)    */
+  int32_t trace_len;      /* iterations recorded by gs_trace (workspace grows)    */
+} gs_params;
+
+typedef struct {
+  int32_t iters;           /* outer iterations run                                */
+  int32_t pcg_iters_total; /* inner CG iterations summed over the solve           */
+  int32_t n_contacts;      /* active springs after the last iteration             */
+  int32_t ray_miss;        /* penetrating vertices whose ray found no boundary    */
+  double residual;         /* r_k of the last iteration                           */
+  double energy;           /* Eq. (9) at x_k with the last targets                */
+} gs_stats;
+
+/* Sizes derived by gs_create (set-up step). */
+typedef struct {
+  int32_t n_verts, n_tets, n_surface_faces, n_surface_verts, n_query_verts, nnz;
+  int32_t n_slots;         /* contact slots per query vertex: 1 + spheres + planes */
+  int32_t hash_buckets;
+  double h_ref, eps_off, ray_len, bbox_diag, cell_size;
+} gs_info;
+
+typedef struct gs_problem gs_problem;
+
+int32_t gs_version(void);
+const char* gs_last_error(void);
+
+/* Defaults: Ecoflex 00-30 (c1 = 0.0418, c2 = 0.0106 MPa), hyperelastic on,
+ * kappa_col 1, eps_rel 0.05, ray_rel 4, no collision, tol 1e-6,
+ * max_iter 20000, fixed_iters 0, pcg_eta 1e-3, pcg_max 200, check_every 16,
+ * pcg_blocks 0, trace_len 0. */
+void gs_default_params(gs_params* params);
+
+/* Host set-up for one mesh (done once per mesh; not per iteration): orient
+ * tets to positive rest volume (swapping slots 2 and 3 of negative ones),
+ * rest shapes and weights omega_e = Vol(e)/mean Vol (Eq. 9), boundary faces
+ * (faces of exactly one tet, outward), query vertices (non-fixed boundary
+ * vertices), A_el = sum_e omega_e S_e^T N S_e with N = I - 11^T/4 (below
+ * Eq. 1) as CSR with fixed rows/columns removed, h_ref (mean rest edge
+ * length), eps = eps_rel h_ref, L_ray = ray_rel h_ref and the spatial-hash
+ * geometry.  Errors: GS_EINVAL, GS_EDEGENERATE.  *out is owned by the caller
+ * and released with gs_destroy. */
+gs_status gs_create(const gs_mesh_desc* mesh, const gs_params* params, gs_problem** out);
+
+/* Analytic obstacles O_obs (Eq. 4): n_sph spheres (cx, cy, cz, r) and n_pln
+ * half-spaces (px, py, pz, nx, ny, nz) whose inside is n.(x - p) < 0 (the
+ * normal is normalised here).  Must be called before gs_bind.  GS_EINVAL for
+ * r <= 0, a zero normal or non-finite values. */
+gs_status gs_set_obstacles(gs_problem* p, int32_t n_sph, const double* sph, int32_t n_pln,
+                           const double* pln);
+
+gs_status gs_info_get(const gs_problem* p, gs_info* info);
+
+/* Bytes of device workspace gs_bind needs (256-byte aligned start). */
+gs_status gs_workspace_size(const gs_problem* p, size_t* bytes);
+
+/* Attach a workspace and a stream, and upload the static data.  The
+ * workspace must stay valid until gs_destroy or the next gs_bind.
+ * Errors: GS_EINVAL (null/small/misaligned workspace), GS_EHIP. */
+gs_status gs_bind(gs_problem* p, void* dev_workspace, size_t bytes, void* hip_stream);
+
+/* Replace the solver constants (c1, c2, tolerances, collision switches,
+ * iteration limits).  Obstacles and mesh stay.  GS_EINVAL on bad values. */
+gs_status gs_set_params(gs_problem* p, const gs_params* params);
+
+/* Solve: iterate from dev_x (warm start; fixed vertices are reset to X0) and
+ * the stored active contact set (empty after gs_bind, or the set left by the
+ * previous solve / gs_set_contacts), for the per-chamber volume ratios
+ * dev_alpha[n_chambers], until r_k <= tol with the active set unchanged, or
+ * exactly fixed_iters iterations.  dev_x [3][n] receives the result.
+ * Returns GS_OK, GS_NOT_CONVERGED (last iterate written), GS_EBREAKDOWN,
+ * GS_ESTATE (not bound), GS_EINVAL (null pointers), GS_EHIP.  stats may be
+ * NULL. */
+gs_status gs_solve(gs_problem* p, const void* dev_alpha, void* dev_x, gs_stats* stats);
+
+/* Forget the stored active contact set (the next solve starts from none). */
+gs_status gs_reset_contacts(gs_problem* p);
+
+/* Copy out the stored active set sorted by (vertex, type, prim): prim is the
+ * hit boundary-face id for self contacts and the obstacle index otherwise;
+ * target/normal are [cap][3] (x,y,z per row).  *count receives the number
+ * of contacts; GS_ECAPACITY if it exceeds cap (nothing else written). */
+gs_status gs_contacts(gs_problem* p, int32_t cap, int32_t* v, int32_t* type, int32_t* prim,
+                      double* target, double* normal, int32_t* count);
+
+/* Import an active set (for resuming a solve).  Rows as gs_contacts gives
+ * them; at most one contact per (vertex, type, prim) slot.  GS_EINVAL for a
+ * vertex that is not a query vertex or an out-of-range prim. */
+gs_status gs_set_contacts(gs_problem* p, int32_t count, const int32_t* v, const int32_t* type,
+                          const int32_t* prim, const double* target, const double* normal);
+
+/* Local step alone (Section III-A) at positions dev_x [3][n]: writes the
+ * centred target shapes to dev_targets [3][4][T] (row c, tet slot j, tet e
+ * at ((c*4 + j) * T + e)); slots follow the oriented tets (gs_tets). */
+gs_status gs_local_step_debug(gs_problem* p, const void* dev_x, const void* dev_alpha,
+                              void* dev_targets);
+
+/* Oriented tets [4][T] as used internally (host copy). */
+gs_status gs_tets(const gs_problem* p, int32_t* tets);
+/* Outward boundary faces [3][F] in their id order (host copy). */
+gs_status gs_faces(const gs_problem* p, int32_t* faces);
+
+/* Device scratch bytes gs_collide_debug needs for a candidate capacity cap. */
+size_t gs_collide_debug_scratch(int32_t cap);
+
+/* One collision check (Section II-B/II-C) at positions dev_x [3][n] given the
+ * stored active set as A_{k-1}; the stored set is not modified.  dev_scratch
+ * (gs_collide_debug_scratch(cap) bytes, caller-owned device memory) stages
+ * the candidate lists.  Outputs (host, each sorted ascending and free of
+ * duplicates; row r of a [m][cap] array is at r * cap):
+ *   cand_tet [2][cap]   (v, e) with v a query vertex not in e and x_v inside
+ *                       the min/max box of e (inclusive)
+ *   cand_tri [2][cap]   (v, f) for penetrating v: f a boundary face not
+ *                       containing v whose box meets the box of the segment
+ *                       [x_v, x_v - L_ray n_v]
+ *   contacts [3][cap]   (v, type, prim) of the resulting active set, with
+ *                       target [3][cap]
+ * and the counts.  GS_ECAPACITY if any count exceeds cap (counts still set). */
+gs_status gs_collide_debug(gs_problem* p, const void* dev_x, int32_t cap, void* dev_scratch,
+                           size_t scratch_bytes, int32_t* cand_tet, int32_t* n_cand_tet,
+                           int32_t* cand_tri, int32_t* n_cand_tri, int32_t* contacts,
+                           double* target, int32_t* n_contacts);
+
+/* Per-iteration trace of the last solve: rows of GS_TRACE_COLS doubles
+ * (r_k, E_k, active springs, set changed, inner CG iterations, ray misses)
+ * for the first min(iters, trace_len) iterations; trace_len is fixed at
+ * gs_create.  *count receives the number of rows written (<= cap). */
+#define GS_TRACE_COLS 6
+gs_status gs_trace(gs_problem* p, int32_t cap, double* rows, int32_t* count);
+
+/* Kernel timing.  gs_profile(p, 1) resets the totals and brackets every
+ * kernel that gs_solve launches with a pair of HIP events on the bound
+ * stream; gs_profile_read returns, per kernel id k < GS_N_KERNELS, the summed
+ * duration in milliseconds and the number of launches; gs_kernel_name(k)
+ * names the kernel ("pcg", "local", ...).  gs_profile(p, 0) stops. */
+#define GS_N_KERNELS 11
+gs_status gs_profile(gs_problem* p, int32_t enable);
+gs_status gs_profile_read(const gs_problem* p, double* ms, int64_t* launches);
+const char* gs_kernel_name(int32_t k);
+
+void gs_destroy(gs_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEOSIM_H */

@@ -101,7 +101,14 @@ class Problem:
         e = np.concatenate([np.sort(tets[[a, b]], axis=0) for a in range(4) for b in range(a + 1, 4)], axis=1)
         e = np.unique(e[0] * n + e[1])
         ei, ej = e // n, e % n
-        self.h_ref = float(np.mean(np.linalg.norm(X[:, ei] - X[:, ej], axis=0)))
+        d = X[:, ei] - X[:, ej]
+        lens = np.sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2])
+        # summed in ascending (i, j) edge order, one term at a time, so that the
+        # offsets eps and L_ray derived from h_ref are reproducible bit for bit
+        acc = 0.0
+        for v in lens.tolist():
+            acc += v
+        self.h_ref = acc / lens.size
 
         # orientation: positive rest volume; swap slots 2 and 3 otherwise
         v6 = orient(X[:, tets[0]], X[:, tets[1]], X[:, tets[2]], X[:, tets[3]])

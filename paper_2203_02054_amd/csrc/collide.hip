@@ -1,0 +1,452 @@
+// Collision detection and response (Sections II-B, II-C, III-A.3).
+//
+// Broadphase: a spatial hash of the query vertices (non-fixed boundary
+// vertices), one cell per vertex, rebuilt every iteration by a counting sort
+// (Teschner et al. 2003).  Each tet visits the cells its min/max box covers and
+// tests the vertices found there exactly: the candidate set is
+// C_tet = {(v, e): v not in e, lo_e <= x_v <= hi_e}, the same set a brute-force
+// or BVH search yields, because the cell map is monotone in x.
+// Narrowphase: exact point-in-tet by four FP64 orientation signs (Eq. 3).
+// Response: the inverse-normal ray of every penetrating vertex is cast against
+// the boundary triangles (one wavefront per vertex, Moller-Trumbore), giving
+// the spring target an offset eps past the first hit (Section II-C); obstacle
+// targets are closed form; the active set follows the release rule of Eq. 8.
+// All decisions are made in double precision in the operation order written
+// here, and this file is compiled without floating-point contraction, so
+// identical inputs give identical sets on any conforming implementation.
+#include <climits>
+
+#include "device_common.h"
+
+namespace gs {
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_hash_count(Dev<R> d, Consts c) {
+  if (is_done(d.st)) return;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= c.S) return;
+  const int v = d.qverts[s];
+  const int ix = cell_of(d.xc[v], c.inv_cell);
+  const int iy = cell_of(d.xc[(size_t)c.n + v], c.inv_cell);
+  const int iz = cell_of(d.xc[2 * (size_t)c.n + v], c.inv_cell);
+  const int key = hash_cell(ix, iy, iz, c.H);
+  d.qkey[s] = key;
+  atomicAdd(&d.hcount[key], 1);
+}
+
+// Exclusive scan of the bucket counts (one block); zeroes the counts so that
+// the fill pass can reuse them as cursors.
+constexpr int kScanBlock = 1024;
+template <typename R>
+__global__ __launch_bounds__(kScanBlock) void k_hash_scan(Dev<R> d, Consts c) {
+  __shared__ int wsum[kScanBlock / 64];
+  if (is_done(d.st)) return;
+  const int H = c.H;
+  const int per = (H + kScanBlock - 1) / kScanBlock;
+  const int lo = threadIdx.x * per;
+  const int hi = min(H, lo + per);
+  int acc = 0;
+#pragma unroll 8
+  for (int i = lo; i < hi; ++i) acc += d.hcount[i];
+  // inclusive scan of the per-thread sums: within each wavefront, then across
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int incl = acc;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (wv == 0) {
+    int t = (lane < kScanBlock / 64) ? wsum[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(t, off, 64);
+      if (lane >= off) t += u;
+    }
+    if (lane < kScanBlock / 64) wsum[lane] = t;
+  }
+  __syncthreads();
+  int run = incl - acc + (wv > 0 ? wsum[wv - 1] : 0);
+#pragma unroll 8
+  for (int i = lo; i < hi; ++i) {
+    const int cnt = d.hcount[i];
+    d.hstart[i] = run;
+    d.hcount[i] = 0;
+    run += cnt;
+  }
+  if (threadIdx.x == kScanBlock - 1) d.hstart[H] = run;
+}
+
+// Entries carry the vertex position (x, y, z) and the query index, so the
+// tet query reads one 32-byte record per candidate.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_hash_fill(Dev<R> d, Consts c) {
+  if (is_done(d.st)) return;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= c.S) return;
+  const int key = d.qkey[s];
+  const int pos = d.hstart[key] + atomicAdd(&d.hcount[key], 1);
+  const int v = d.qverts[s];
+  double4 e;
+  e.x = d.xc[v];
+  e.y = d.xc[(size_t)c.n + v];
+  e.z = d.xc[2 * (size_t)c.n + v];
+  e.w = __longlong_as_double((long long)s);
+  reinterpret_cast<double4*>(d.hent)[pos] = e;
+}
+
+template <typename R, bool DEBUG>
+__device__ __forceinline__ void test_point(const Dev<R>& d, int s, const double (&q)[3], int e, const int (&vi)[4],
+                                          const double (&p)[4][3], const double (&lo)[3], const double (&hi)[3]) {
+  if (!(lo[0] <= q[0] && q[0] <= hi[0] && lo[1] <= q[1] && q[1] <= hi[1] && lo[2] <= q[2] && q[2] <= hi[2])) return;
+  const int v = d.qverts[s];
+  if (v == vi[0] || v == vi[1] || v == vi[2] || v == vi[3]) return;
+  if (DEBUG) {
+    const int k = atomicAdd(&d.st->cand_tet, 1);
+    if (k < d.dbg_cap) {
+      d.dbg_tet[k] = v;
+      d.dbg_tet[d.dbg_cap + k] = e;
+    }
+  }
+  if (point_in_tet(q, p[0], p[1], p[2], p[3])) d.pen[s] = 1;
+}
+
+template <typename R, bool DEBUG>
+__global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
+  if (is_done(d.st)) return;
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= c.T) return;
+  int vi[4];
+  double p[4][3];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    vi[j] = d.tets[j * c.T + e];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p[j][k] = d.xc[(size_t)k * c.n + vi[j]];
+  }
+  double lo[3], hi[3];
+  int clo[3], chi[3];
+  long ncell = 1;
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = fmin(fmin(p[0][k], p[1][k]), fmin(p[2][k], p[3][k]));
+    hi[k] = fmax(fmax(p[0][k], p[1][k]), fmax(p[2][k], p[3][k]));
+    finite = finite && isfinite(lo[k]) && isfinite(hi[k]) && fabs(lo[k] * c.inv_cell) < 1e9 &&
+             fabs(hi[k] * c.inv_cell) < 1e9;
+  }
+  if (!finite) return;  // a diverged iterate: no candidates (the finish step reports the breakdown)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    clo[k] = cell_of(lo[k], c.inv_cell);
+    chi[k] = cell_of(hi[k], c.inv_cell);
+    const long ext = (long)chi[k] - (long)clo[k] + 1;
+    ncell = (ext > kCellCap || ncell > kCellCap) ? (long)kCellCap + 1 : ncell * ext;
+  }
+  if (ncell > kCellCap) {
+    // a tet stretched over many cells: test every query vertex (still exact)
+    for (int s = 0; s < c.S; ++s) {
+      const int v = d.qverts[s];
+      const double q[3] = {d.xc[v], d.xc[(size_t)c.n + v], d.xc[2 * (size_t)c.n + v]};
+      test_point<R, DEBUG>(d, s, q, e, vi, p, lo, hi);
+    }
+    return;
+  }
+  const double4* ent = reinterpret_cast<const double4*>(d.hent);
+  for (int ix = clo[0]; ix <= chi[0]; ++ix)
+    for (int iy = clo[1]; iy <= chi[1]; ++iy)
+      for (int iz = clo[2]; iz <= chi[2]; ++iz) {
+        const int key = hash_cell(ix, iy, iz, c.H);
+        const int b0 = d.hstart[key], b1 = d.hstart[key + 1];
+        for (int i = b0; i < b1; ++i) {
+          const double4 en = ent[i];
+          const double q[3] = {en.x, en.y, en.z};
+          test_point<R, DEBUG>(d, (int)__double_as_longlong(en.w), q, e, vi, p, lo, hi);
+        }
+      }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pen_compact(Dev<R> d, Consts c) {
+  if (is_done(d.st)) return;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= c.S) return;
+  if (d.pen[s]) {
+    const int k = atomicAdd(&d.st->n_pen, 1);
+    d.penlist[k] = s;
+  }
+}
+
+__device__ __forceinline__ void load3(const double* xc, size_t n, int v, double* o) {
+  o[0] = xc[v];
+  o[1] = xc[n + v];
+  o[2] = xc[2 * n + v];
+}
+
+// One wavefront per penetrating vertex: vertex normal, then the first hit of
+// [x_v, x_v - L_ray n_v] on a boundary face not containing v.
+template <typename R, bool DEBUG>
+__global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
+  if (is_done(d.st)) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * kBlock) >> 6;
+  const int npen = __hip_atomic_load(&d.st->n_pen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const size_t n = (size_t)c.n;
+  const int F = c.F;
+  for (int i = wave; i < npen; i += nwaves) {
+    const int s = d.penlist[i];
+    const int v = d.qverts[s];
+    // area-weighted normal: sum over incident faces in ascending id
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int j = d.qf_start[s]; j < d.qf_start[s + 1]; ++j) {
+      const int f = d.qf_list[j];
+      double a0[3], a1[3], a2[3], e1[3], e2[3], cr[3];
+      load3(d.xc, n, d.faces[f], a0);
+      load3(d.xc, n, d.faces[F + f], a1);
+      load3(d.xc, n, d.faces[2 * F + f], a2);
+      for (int k = 0; k < 3; ++k) {
+        e1[k] = a1[k] - a0[k];
+        e2[k] = a2[k] - a0[k];
+      }
+      cross3(e1, e2, cr);
+      acc[0] = acc[0] + cr[0];
+      acc[1] = acc[1] + cr[1];
+      acc[2] = acc[2] + cr[2];
+    }
+    double len;
+    {
+      len = sqrt((acc[0] * acc[0] + acc[1] * acc[1]) + acc[2] * acc[2]);
+    }
+    if (!(len > 0.0)) {
+      if (lane == 0) d.fhit[s] = -1;
+      continue;
+    }
+    double o[3], dir[3], end[3], slo[3], shi[3];
+    load3(d.xc, n, v, o);
+    {
+      for (int k = 0; k < 3; ++k) {
+        dir[k] = -(acc[k] / len);
+        end[k] = o[k] + c.Lray * dir[k];
+        slo[k] = fmin(o[k], end[k]);
+        shi[k] = fmax(o[k], end[k]);
+      }
+    }
+    double best_t = INFINITY;
+    int best_f = INT_MAX;
+    for (int f = lane; f < F; f += 64) {
+      const int i0 = d.faces[f], i1 = d.faces[F + f], i2 = d.faces[2 * F + f];
+      if (i0 == v || i1 == v || i2 == v) continue;
+      double a0[3], a1[3], a2[3];
+      load3(d.xc, n, i0, a0);
+      load3(d.xc, n, i1, a1);
+      load3(d.xc, n, i2, a2);
+      bool ov = true;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double flo = fmin(fmin(a0[k], a1[k]), a2[k]);
+        const double fhi = fmax(fmax(a0[k], a1[k]), a2[k]);
+        ov = ov && (flo <= shi[k]) && (slo[k] <= fhi);
+      }
+      if (!ov) continue;
+      if (DEBUG) {
+        const int k = atomicAdd(&d.st->cand_tri, 1);
+        if (k < d.dbg_cap) {
+          d.dbg_tri[k] = v;
+          d.dbg_tri[d.dbg_cap + k] = f;
+        }
+      }
+      double t;
+      if (moller_trumbore(o, dir, a0, a1, a2, c.Lray, &t)) {
+        if (t < best_t || (t == best_t && f < best_f)) {
+          best_t = t;
+          best_f = f;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ot = __shfl_xor(best_t, off, 64);
+      const int of = __shfl_xor(best_f, off, 64);
+      if (ot < best_t || (ot == best_t && of < best_f)) {
+        best_t = ot;
+        best_f = of;
+      }
+    }
+    if (lane == 0) {
+      if (best_f == INT_MAX) {
+        d.fhit[s] = -1;
+      } else {
+        d.fhit[s] = best_f;
+        double a0[3], a1[3], a2[3], e1[3], e2[3], cr[3];
+        load3(d.xc, n, d.faces[best_f], a0);
+        load3(d.xc, n, d.faces[F + best_f], a1);
+        load3(d.xc, n, d.faces[2 * F + best_f], a2);
+        const double te = best_t + c.eps;
+        for (int k = 0; k < 3; ++k) {
+          d.fc[3 * s + k] = o[k] + te * dir[k];
+          e1[k] = a1[k] - a0[k];
+          e2[k] = a2[k] - a0[k];
+        }
+        cross3(e1, e2, cr);
+        const double ln = sqrt((cr[0] * cr[0] + cr[1] * cr[1]) + cr[2] * cr[2]);
+        for (int k = 0; k < 3; ++k) d.fn[3 * s + k] = cr[k] / ln;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ bool released(const double* x, const double* tc, const double* nc, double eps) {
+  const double g = (nc[0] * (x[0] - tc[0]) + nc[1] * (x[1] - tc[1])) + nc[2] * (x[2] - tc[2]);
+  return fabs(g) > eps;
+}
+
+// Active set A_k from A_{k-1} (stored in place), per query vertex.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
+  if (is_done(d.st)) return;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= c.S) return;
+  const int v = d.qverts[s];
+  double x[3];
+  load3(d.xc, (size_t)c.n, v, x);
+  const int base = s * c.slots;
+  bool changed = false;
+  int nact = 0;
+  if (c.self_col) {
+    const bool old = d.cact[base] != 0;
+    const bool pen = d.pen[s] != 0;
+    const int hit = pen ? d.fhit[s] : -1;
+    bool now = false;
+    if (pen && hit >= 0) {
+      now = true;
+      for (int k = 0; k < 3; ++k) {
+        d.ctgt[3 * base + k] = d.fc[3 * s + k];
+        d.cnrm[3 * base + k] = d.fn[3 * s + k];
+      }
+      d.cprim[base] = hit;
+    } else if (old) {
+      now = pen ? true : !released(x, d.ctgt + 3 * base, d.cnrm + 3 * base, c.eps);
+    }
+    if (pen && hit < 0) atomicAdd(&d.st->ray_miss, 1);
+    d.cact[base] = now ? 1 : 0;
+    changed |= (now != old);
+    nact += now;
+    d.pen[s] = 0;
+  }
+  if (c.obst_col) {
+    for (int j = 0; j < c.ns; ++j) {
+      const double* sp = d.obst + 4 * j;
+      const int slot = base + 1 + j;
+      const bool old = d.cact[slot] != 0;
+      const double dx = x[0] - sp[0], dy = x[1] - sp[1], dz = x[2] - sp[2];
+      const double q = (dx * dx + dy * dy) + dz * dz;
+      const bool inside = q < sp[3] * sp[3];
+      bool now = false;
+      if (inside || old) {
+        const double dist = sqrt(q);
+        double nc[3];
+        if (dist > 0.0) {
+          nc[0] = dx / dist;
+          nc[1] = dy / dist;
+          nc[2] = dz / dist;
+        } else {
+          nc[0] = 0.0;
+          nc[1] = 0.0;
+          nc[2] = 1.0;
+        }
+        const double rr = sp[3] + c.eps;
+        const double tc[3] = {sp[0] + rr * nc[0], sp[1] + rr * nc[1], sp[2] + rr * nc[2]};
+        now = inside || !released(x, tc, nc, c.eps);
+        if (now) {
+          for (int k = 0; k < 3; ++k) {
+            d.ctgt[3 * slot + k] = tc[k];
+            d.cnrm[3 * slot + k] = nc[k];
+          }
+          d.cprim[slot] = j;
+        }
+      }
+      d.cact[slot] = now ? 1 : 0;
+      changed |= (now != old);
+      nact += now;
+    }
+    for (int j = 0; j < c.np; ++j) {
+      const double* pl = d.obst + 4 * c.ns + 6 * j;
+      const int slot = base + 1 + c.ns + j;
+      const bool old = d.cact[slot] != 0;
+      const double sd = (pl[3] * (x[0] - pl[0]) + pl[4] * (x[1] - pl[1])) + pl[5] * (x[2] - pl[2]);
+      const bool inside = sd < 0.0;
+      bool now = false;
+      if (inside || old) {
+        const double se = sd - c.eps;
+        const double nc[3] = {pl[3], pl[4], pl[5]};
+        const double tc[3] = {x[0] - se * nc[0], x[1] - se * nc[1], x[2] - se * nc[2]};
+        now = inside || !released(x, tc, nc, c.eps);
+        if (now) {
+          for (int k = 0; k < 3; ++k) {
+            d.ctgt[3 * slot + k] = tc[k];
+            d.cnrm[3 * slot + k] = nc[k];
+          }
+          d.cprim[slot] = j;
+        }
+      }
+      d.cact[slot] = now ? 1 : 0;
+      changed |= (now != old);
+      nact += now;
+    }
+  }
+  if (changed) atomicOr(&d.st->changed, 1);
+  if (nact) atomicAdd(&d.st->n_contacts, nact);
+}
+
+template <typename R>
+hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s) {
+  const int gs = cdiv(c.S, kBlock), gt = cdiv(c.T, kBlock);
+  switch (stage) {
+    case STAGE_HASH_COUNT:
+      k_hash_count<R><<<gs, kBlock, 0, s>>>(d, c);
+      break;
+    case STAGE_HASH_SCAN:
+      k_hash_scan<R><<<1, kScanBlock, 0, s>>>(d, c);
+      break;
+    case STAGE_HASH_FILL:
+      k_hash_fill<R><<<gs, kBlock, 0, s>>>(d, c);
+      break;
+    case STAGE_TET_QUERY:
+      if (debug)
+        k_tet_query<R, true><<<gt, kBlock, 0, s>>>(d, c);
+      else
+        k_tet_query<R, false><<<gt, kBlock, 0, s>>>(d, c);
+      break;
+    case STAGE_PEN_COMPACT:
+      k_pen_compact<R><<<gs, kBlock, 0, s>>>(d, c);
+      break;
+    case STAGE_RAY: {
+      // one wavefront per penetrating vertex on the first pass (up to 8192)
+      const int gr = max(1, min(cdiv(c.S, kBlock / 64), 2048));
+      if (debug)
+        k_ray<R, true><<<gr, kBlock, 0, s>>>(d, c);
+      else
+        k_ray<R, false><<<gr, kBlock, 0, s>>>(d, c);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_contacts(const Dev<R>& d, const Consts& c, hipStream_t s) {
+  k_contacts<R><<<cdiv(c.S, kBlock), kBlock, 0, s>>>(d, c);
+  return hipGetLastError();
+}
+
+template hipError_t launch_collide_stage<float>(const Dev<float>&, const Consts&, int, bool, hipStream_t);
+template hipError_t launch_collide_stage<double>(const Dev<double>&, const Consts&, int, bool, hipStream_t);
+template hipError_t launch_contacts<float>(const Dev<float>&, const Consts&, hipStream_t);
+template hipError_t launch_contacts<double>(const Dev<double>&, const Consts&, hipStream_t);
+
+}  // namespace gs

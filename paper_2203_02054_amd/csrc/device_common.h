@@ -1,0 +1,139 @@
+// Device helpers: wavefront/block reductions, a grid barrier for cooperative
+// launches, and the exact (FP64, fixed order, no contraction) predicates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace gs {
+
+// ---- reductions (64-wide wavefronts) ---------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  `lds` holds one
+// double per wavefront.  Fixed association order (deterministic).
+template <int BLOCK>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) t += lds[i];
+  }
+  __syncthreads();
+  return t;
+}
+template <int BLOCK>
+__device__ __forceinline__ double block_max(double v, double* lds) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) t = fmax(t, lds[i]);
+  }
+  __syncthreads();
+  return t;
+}
+
+// ---- grid barrier (cooperative launch: every block is resident) -------------
+// Arrival counter + generation word.  Thread 0 of each block releases the
+// block's writes at agent scope, arrives, and spins on the generation; the
+// last arrival resets the counter and bumps the generation.
+__device__ __forceinline__ void grid_barrier(unsigned* count, unsigned* gen, unsigned nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// ---- exact predicates -------------------------------------------------------
+// Six times the signed volume det[p1-p0, p2-p0, p3-p0], evaluated in the
+// order written (contraction off), FP64.
+__device__ __forceinline__ double orient(const double* p0, const double* p1, const double* p2, const double* p3) {
+#pragma clang fp contract(off)
+  const double ax = p1[0] - p0[0], ay = p1[1] - p0[1], az = p1[2] - p0[2];
+  const double bx = p2[0] - p0[0], by = p2[1] - p0[1], bz = p2[2] - p0[2];
+  const double cx = p3[0] - p0[0], cy = p3[1] - p0[1], cz = p3[2] - p0[2];
+  return ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+}
+
+// Strictly inside a positively oriented tet (a,b,c,d): all four sub-volumes
+// with one vertex replaced by q are positive (ties are outside).
+__device__ __forceinline__ bool point_in_tet(const double* q, const double* a, const double* b, const double* c,
+                                             const double* d) {
+  return orient(q, b, c, d) > 0.0 && orient(a, q, c, d) > 0.0 && orient(a, b, q, d) > 0.0 &&
+         orient(a, b, c, q) > 0.0;
+}
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* o) {
+#pragma clang fp contract(off)
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double dot3(const double* a, const double* b) {
+#pragma clang fp contract(off)
+  return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+// Segment o + t d (0 < t <= L) against triangle (a0, a1, a2): Moller-Trumbore.
+__device__ __forceinline__ bool moller_trumbore(const double* o, const double* d, const double* a0, const double* a1,
+                                                const double* a2, double L, double* t_out) {
+#pragma clang fp contract(off)
+  double e1[3] = {a1[0] - a0[0], a1[1] - a0[1], a1[2] - a0[2]};
+  double e2[3] = {a2[0] - a0[0], a2[1] - a0[1], a2[2] - a0[2]};
+  double pv[3];
+  cross3(d, e2, pv);
+  const double det = dot3(e1, pv);
+  if (det == 0.0) return false;
+  double tv[3] = {o[0] - a0[0], o[1] - a0[1], o[2] - a0[2]};
+  const double u = dot3(tv, pv) / det;
+  double qv[3];
+  cross3(tv, e1, qv);
+  const double w = dot3(d, qv) / det;
+  const double t = dot3(e2, qv) / det;
+  *t_out = t;
+  return (u >= 0.0) && (w >= 0.0) && (u + w <= 1.0) && (t > 0.0) && (t <= L);
+}
+
+// Spatial-hash cell of a coordinate (monotone in x, so a point inside a box
+// lies in a cell of the box's cell range).
+__device__ __forceinline__ int cell_of(double x, double inv_cell) { return (int)floor(x * inv_cell); }
+
+__device__ __forceinline__ int hash_cell(int ix, int iy, int iz, int H) {
+  const uint32_t h = ((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u);
+  return (int)(h & (uint32_t)(H - 1));
+}
+
+__device__ __forceinline__ bool is_done(const DevStatus* st) {
+  return __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != RUNNING;
+}
+
+}  // namespace gs

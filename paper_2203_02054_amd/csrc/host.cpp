@@ -1,0 +1,1053 @@
+// Host layer of the C ABI: input validation, the once-per-mesh set-up, the
+// device workspace layout, and the outer-iteration driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "geosim.h"
+#include "internal.h"
+
+using namespace gs;
+
+namespace {
+
+thread_local std::string g_err;
+
+gs_status fail(gs_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                             \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return fail(GS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// outward faces of a positively oriented tet: the face opposite each slot
+constexpr int kFaceSlots[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+
+// six times the signed volume det[p1-p0, p2-p0, p3-p0] (same evaluation order
+// as the device predicate; this file is compiled without contraction)
+double orient_h(const double* p0, const double* p1, const double* p2, const double* p3) {
+  const double ax = p1[0] - p0[0], ay = p1[1] - p0[1], az = p1[2] - p0[2];
+  const double bx = p2[0] - p0[0], by = p2[1] - p0[1], bz = p2[2] - p0[2];
+  const double cx = p3[0] - p0[0], cy = p3[1] - p0[1], cz = p3[2] - p0[2];
+  return ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Offsets of every device array inside the workspace.
+struct Layout {
+  size_t X0, tets, tag, inc_start, inc_pos, ell_col, ell_val, ell_scaled, adiag, freem, faces, qverts, vq, qf_start, qf_list, kq,
+      obst;
+  size_t u, xc, res4, r, w, s, dl, p, dg, dsp, pen, hcount, hstart, hent, qkey, penlist, fhit, fc, fn, cact, ctgt,
+      cnrm, cprim, part_a, part_b, part_c, part_d, part_e, st, trace;
+  size_t total;
+};
+
+constexpr int kNKernels = 11;
+const char* const kKernelNames[kNKernels] = {"hash_count", "hash_scan", "hash_fill", "tet_query", "pen_compact",
+                                             "ray_cast",   "contacts",  "local",     "gather",    "pcg",
+                                             "finish"};
+enum { K_CONTACTS = 6, K_LOCAL = 7, K_GATHER = 8, K_PCG = 9, K_FINISH = 10 };
+
+// Optional per-kernel timing: each launch is bracketed by two events on the
+// bound stream; elapsed times are collected whenever the driver synchronises.
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> fam;  // kernel id of each recorded pair
+  double ms[kNKernels] = {};
+  long long cnt[kNKernels] = {};
+
+  hipError_t mark(hipStream_t s, int f, bool start) {
+    const size_t i = 2 * fam.size() + (start ? 0 : 1);
+    while (pool.size() <= i) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      pool.push_back(e);
+    }
+    if (!start) fam.push_back(f);
+    return hipEventRecord(pool[i], s);
+  }
+  hipError_t flush() {
+    for (size_t k = 0; k < fam.size(); ++k) {
+      float t = 0.f;
+      hipError_t r = hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]);
+      if (r != hipSuccess) return r;
+      ms[fam[k]] += t;
+      cnt[fam[k]] += 1;
+    }
+    fam.clear();
+    return hipSuccess;
+  }
+  void reset() {
+    fam.clear();
+    for (int k = 0; k < kNKernels; ++k) {
+      ms[k] = 0;
+      cnt[k] = 0;
+    }
+  }
+  ~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct gs_problem {
+  int prec = 4;
+  int n = 0, T = 0, nch = 0, S = 0, F = 0, slots = 1, H = 0, nnz = 0, nparts = 0;
+  int ns = 0, np = 0;
+  gs_params prm{};
+  std::vector<double> X0;
+  std::vector<int32_t> tets, tag, inc_start, inc_pos, rowptr, col, faces, qverts, vq, qf_start, qf_list, ell_col;
+  std::vector<double> val, adiag, kq, obst, ell_val;
+  int ell_w = 0;
+  std::vector<uint8_t> freem;
+  int n_surf_verts = 0;
+  double h_ref = 0, eps = 0, Lray = 0, diag = 0, cell = 0, inv_mean_vol = 0;
+  // device binding
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  Layout lay{};
+  int pcg_grid = 1;
+  int trace_len = 0;
+  int last_iters = 0;
+  Profiler prof;
+};
+
+namespace {
+
+gs_status check_params(const gs_params* p) {
+  if (!p) return fail(GS_EINVAL, "null params");
+  if (!(p->c1 > 0) || !(p->c2 >= 0) || !std::isfinite(p->c1) || !std::isfinite(p->c2))
+    return fail(GS_EINVAL, "Mooney-Rivlin constants must be c1 > 0, c2 >= 0");
+  if (!(p->kappa_col > 0) || !(p->eps_rel > 0) || !(p->ray_rel > 0))
+    return fail(GS_EINVAL, "kappa_col, eps_rel and ray_rel must be positive");
+  if (!(p->tol >= 0) || p->max_iter < 1 || p->fixed_iters < 0) return fail(GS_EINVAL, "bad tol/max_iter/fixed_iters");
+  if (!(p->pcg_eta > 0 && p->pcg_eta < 1) || p->pcg_max < 1) return fail(GS_EINVAL, "bad pcg_eta/pcg_max");
+  if (p->check_every < 1) return fail(GS_EINVAL, "check_every must be >= 1");
+  if (p->trace_len < 0) return fail(GS_EINVAL, "trace_len must be >= 0");
+  return GS_OK;
+}
+
+Layout make_layout(const gs_problem* p) {
+  Layout L{};
+  size_t off = 0;
+  const size_t W = (size_t)p->prec;
+  auto take = [&](size_t bytes) {
+    off = align256(off);
+    const size_t o = off;
+    off += std::max<size_t>(bytes, 1);
+    return o;
+  };
+  const size_t n = p->n, T = p->T, S = p->S, F = p->F, sl = p->slots, H = p->H;
+  L.X0 = take(3 * n * 8);
+  L.tets = take(4 * T * 4);
+  L.tag = take(T * 4);
+  L.inc_start = take((n + 1) * 4);
+  L.inc_pos = take(4 * T * 4);
+  L.ell_col = take((size_t)p->ell_w * n * 4);
+  L.ell_val = take((size_t)p->ell_w * n * W);
+  L.ell_scaled = take((size_t)p->ell_w * n * W);
+  L.adiag = take(n * W);
+  L.freem = take(n);
+  L.faces = take(3 * F * 4);
+  L.qverts = take(S * 4);
+  L.vq = take(n * 4);
+  L.qf_start = take((S + 1) * 4);
+  L.qf_list = take(p->qf_list.size() * 4);
+  L.kq = take(S * 8);
+  L.obst = take((4 * (size_t)p->ns + 6 * (size_t)p->np) * 8);
+  L.u = take(3 * n * W);
+  L.xc = take(3 * n * 8);
+  L.res4 = take(4 * T * 4 * W);
+  L.r = take(6 * n * W);
+  L.w = take(6 * n * W);
+  L.s = take(6 * n * W);
+  L.dl = take(3 * n * W);
+  L.p = take(3 * n * W);
+  L.dg = take(n * W);
+  L.dsp = take(n * W);
+  L.pen = take(S);
+  L.hcount = take(H * 4);
+  L.hstart = take((H + 1) * 4);
+  L.hent = take(S * 32);
+  L.qkey = take(S * 4);
+  L.penlist = take(S * 4);
+  L.fhit = take(S * 4);
+  L.fc = take(3 * S * 8);
+  L.fn = take(3 * S * 8);
+  L.cact = take(S * sl);
+  L.ctgt = take(3 * S * sl * 8);
+  L.cnrm = take(3 * S * sl * 8);
+  L.cprim = take(S * sl * 4);
+  L.part_a = take((size_t)p->nparts * 8);
+  L.part_b = take((size_t)p->nparts * 8);
+  L.part_c = take((size_t)p->nparts * 8);
+  L.part_d = take((size_t)p->nparts * 8);
+  L.part_e = take((size_t)p->nparts * 8);
+  L.st = take(sizeof(DevStatus));
+  L.trace = take((size_t)p->trace_len * 6 * 8);
+  L.total = align256(off);
+  return L;
+}
+
+template <typename R>
+Dev<R> make_dev(const gs_problem* p) {
+  const Layout& L = p->lay;
+  char* b = p->ws;
+  Dev<R> d{};
+  d.X0 = (const double*)(b + L.X0);
+  d.tets = (const int32_t*)(b + L.tets);
+  d.tag = (const int32_t*)(b + L.tag);
+  d.inc_start = (const int32_t*)(b + L.inc_start);
+  d.inc_pos = (const int32_t*)(b + L.inc_pos);
+  d.ell_col = (const int32_t*)(b + L.ell_col);
+  d.ell_val = (const R*)(b + L.ell_val);
+  d.ell_scaled = (R*)(b + L.ell_scaled);
+  d.adiag = (const R*)(b + L.adiag);
+  d.freem = (const uint8_t*)(b + L.freem);
+  d.faces = (const int32_t*)(b + L.faces);
+  d.qverts = (const int32_t*)(b + L.qverts);
+  d.vq = (const int32_t*)(b + L.vq);
+  d.qf_start = (const int32_t*)(b + L.qf_start);
+  d.qf_list = (const int32_t*)(b + L.qf_list);
+  d.kq = (const double*)(b + L.kq);
+  d.obst = (const double*)(b + L.obst);
+  d.u = (R*)(b + L.u);
+  d.xc = (double*)(b + L.xc);
+  d.res4 = (R*)(b + L.res4);
+  d.r = (R*)(b + L.r);
+  d.w = (R*)(b + L.w);
+  d.s = (R*)(b + L.s);
+  d.dl = (R*)(b + L.dl);
+  d.p = (R*)(b + L.p);
+  d.dg = (R*)(b + L.dg);
+  d.dsp = (R*)(b + L.dsp);
+  d.pen = (uint8_t*)(b + L.pen);
+  d.hcount = (int32_t*)(b + L.hcount);
+  d.hstart = (int32_t*)(b + L.hstart);
+  d.hent = (double*)(b + L.hent);
+  d.qkey = (int32_t*)(b + L.qkey);
+  d.penlist = (int32_t*)(b + L.penlist);
+  d.fhit = (int32_t*)(b + L.fhit);
+  d.fc = (double*)(b + L.fc);
+  d.fn = (double*)(b + L.fn);
+  d.cact = (uint8_t*)(b + L.cact);
+  d.ctgt = (double*)(b + L.ctgt);
+  d.cnrm = (double*)(b + L.cnrm);
+  d.cprim = (int32_t*)(b + L.cprim);
+  d.part_a = (double*)(b + L.part_a);
+  d.part_b = (double*)(b + L.part_b);
+  d.part_c = (double*)(b + L.part_c);
+  d.part_d = (double*)(b + L.part_d);
+  d.part_e = (double*)(b + L.part_e);
+  d.st = (DevStatus*)(b + L.st);
+  d.trace = (double*)(b + L.trace);
+  d.dbg_tet = nullptr;
+  d.dbg_tri = nullptr;
+  d.dbg_cap = 0;
+  return d;
+}
+
+Consts make_consts(const gs_problem* p) {
+  Consts c{};
+  c.n = p->n;
+  c.T = p->T;
+  c.S = p->S;
+  c.F = p->F;
+  c.nch = p->nch;
+  c.slots = p->slots;
+  c.H = p->H;
+  c.ns = p->ns;
+  c.np = p->np;
+  c.self_col = p->prm.self_collision ? 1 : 0;
+  c.obst_col = (p->prm.obstacle_collision && (p->ns + p->np) > 0) ? 1 : 0;
+  c.hyper = p->prm.hyperelastic ? 1 : 0;
+  c.max_iter = p->prm.max_iter;
+  c.fixed_iters = p->prm.fixed_iters;
+  c.pcg_max = p->prm.pcg_max;
+  c.nparts = p->nparts;
+  c.ell_w = p->ell_w;
+  c.trace_len = p->trace_len;
+  c.c1 = p->prm.c1;
+  c.c2 = p->prm.c2;
+  c.kappa = p->prm.kappa_col;
+  c.eps = p->eps;
+  c.Lray = p->Lray;
+  c.diag = p->diag;
+  c.tol = p->prm.tol;
+  c.pcg_eta = p->prm.pcg_eta;
+  c.inv_mean_vol = p->inv_mean_vol;
+  c.inv_cell = 1.0 / p->cell;
+  return c;
+}
+
+template <typename T>
+hipError_t upload(char* base, size_t off, const std::vector<T>& v, hipStream_t s) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+template <typename R>
+std::vector<R> cast_vec(const std::vector<double>& v) {
+  return std::vector<R>(v.begin(), v.end());
+}
+
+// Workgroups of the cooperative CG kernel: about one row per thread, within
+// what can be resident and what the partial-sum arrays hold.
+int pcg_grid_for(const gs_problem* p, int maxg) {
+  int g = p->prm.pcg_blocks > 0 ? p->prm.pcg_blocks : cdiv(p->n, kPcgThreads);
+  return std::max(1, std::min({g, maxg, kMaxPcgGrid, p->nparts / 2}));
+}
+
+template <typename R>
+gs_status bind_impl(gs_problem* p) {
+  char* b = p->ws;
+  const Layout& L = p->lay;
+  hipStream_t s = p->stream;
+  HIPCHK(upload(b, L.X0, p->X0, s));
+  HIPCHK(upload(b, L.tets, p->tets, s));
+  HIPCHK(upload(b, L.tag, p->tag, s));
+  HIPCHK(upload(b, L.inc_start, p->inc_start, s));
+  HIPCHK(upload(b, L.inc_pos, p->inc_pos, s));
+  HIPCHK(upload(b, L.ell_col, p->ell_col, s));
+  const std::vector<R> ell_val = cast_vec<R>(p->ell_val), adiag = cast_vec<R>(p->adiag);
+  HIPCHK(upload(b, L.ell_val, ell_val, s));
+  HIPCHK(upload(b, L.adiag, adiag, s));
+  HIPCHK(upload(b, L.freem, p->freem, s));
+  HIPCHK(upload(b, L.faces, p->faces, s));
+  HIPCHK(upload(b, L.qverts, p->qverts, s));
+  HIPCHK(upload(b, L.vq, p->vq, s));
+  HIPCHK(upload(b, L.qf_start, p->qf_start, s));
+  HIPCHK(upload(b, L.qf_list, p->qf_list, s));
+  HIPCHK(upload(b, L.kq, p->kq, s));
+  HIPCHK(upload(b, L.obst, p->obst, s));
+  HIPCHK(hipMemsetAsync(b + L.cact, 0, (size_t)p->S * p->slots, s));
+  HIPCHK(hipMemsetAsync(b + L.st, 0, sizeof(DevStatus), s));
+  HIPCHK(hipMemsetAsync(b + L.hcount, 0, (size_t)p->H * 4, s));
+  HIPCHK(hipMemsetAsync(b + L.pen, 0, (size_t)std::max(p->S, 1), s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int maxg = pcg_max_grid<R>(0);
+  if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
+  p->pcg_grid = pcg_grid_for(p, maxg);
+  return GS_OK;
+}
+
+// Launch one kernel, bracketed by timing events when profiling is on.
+template <typename F>
+hipError_t timed(gs_problem* p, int k, F&& launch) {
+  hipError_t e;
+  if (p->prof.on && (e = p->prof.mark(p->stream, k, true)) != hipSuccess) return e;
+  if ((e = launch()) != hipSuccess) return e;
+  if (p->prof.on) return p->prof.mark(p->stream, k, false);
+  return hipSuccess;
+}
+
+template <typename R>
+hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, const R* alpha) {
+  hipError_t e;
+  hipStream_t s = p->stream;
+  if (c.self_col) {
+    for (int st = 0; st < N_COLLIDE_STAGES; ++st)
+      if ((e = timed(p, st, [&] { return launch_collide_stage<R>(d, c, st, false, s); })) != hipSuccess) return e;
+  }
+  if (c.self_col || c.obst_col) {
+    if ((e = timed(p, K_CONTACTS, [&] { return launch_contacts<R>(d, c, s); })) != hipSuccess) return e;
+  }
+  if ((e = timed(p, K_LOCAL, [&] { return launch_local<R>(d, c, alpha, s); })) != hipSuccess) return e;
+  if ((e = timed(p, K_GATHER, [&] { return launch_gather<R>(d, c, s); })) != hipSuccess) return e;
+  if ((e = timed(p, K_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s); })) != hipSuccess) return e;
+  return timed(p, K_FINISH, [&] { return launch_finish<R>(d, c, s); });
+}
+
+template <typename R>
+gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
+  const Dev<R> d = make_dev<R>(p);
+  const Consts c = make_consts(p);
+  hipStream_t s = p->stream;
+  HIPCHK(launch_init<R>(d, c, x, s));
+  DevStatus h{};
+  const int limit = p->prm.fixed_iters > 0 ? p->prm.fixed_iters : p->prm.max_iter;
+  int enq = 0;
+  while (true) {
+    const int chunk = std::min(p->prm.check_every, std::max(1, limit - enq));
+    for (int i = 0; i < chunk; ++i) HIPCHK(enqueue_iteration<R>(p, d, c, alpha));
+    enq += chunk;
+    HIPCHK(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (p->prof.on) HIPCHK(p->prof.flush());
+    if (h.done != RUNNING) break;
+    if (enq >= limit + p->prm.check_every) return fail(GS_EHIP, "iteration driver out of step with the device");
+  }
+  HIPCHK(launch_output<R>(d, c, x, s));
+  HIPCHK(hipStreamSynchronize(s));
+  p->last_iters = h.iters;
+  if (stats) {
+    stats->iters = h.iters;
+    stats->pcg_iters_total = h.pcg_total;
+    stats->n_contacts = h.n_contacts_last;
+    stats->ray_miss = h.ray_miss_last;
+    stats->residual = h.residual;
+    stats->energy = h.energy;
+  }
+  if (h.done == BREAKDOWN) return fail(GS_EBREAKDOWN, "non-finite value or CG curvature p'Ap <= 0");
+  if (h.done == MAXITER) {
+    g_err = "max_iter reached";
+    return GS_NOT_CONVERGED;
+  }
+  if (h.done == FIXED_DONE && !(h.residual <= p->prm.tol && !h.changed_last)) {
+    g_err = "fixed iteration count reached above tolerance";
+    return GS_NOT_CONVERGED;
+  }
+  return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// set-up
+
+gs_status setup(gs_problem* p, const gs_mesh_desc* m) {
+  const int n = m->n_verts, T = m->n_tets;
+  p->n = n;
+  p->T = T;
+  p->nch = m->n_chambers;
+  p->prec = m->precision;
+  p->X0.assign(m->rest_xyz, m->rest_xyz + 3 * (size_t)n);
+  for (double v : p->X0)
+    if (!std::isfinite(v)) return fail(GS_EINVAL, "non-finite rest position");
+  p->tets.assign(m->tets, m->tets + 4 * (size_t)T);
+  for (int32_t v : p->tets)
+    if (v < 0 || v >= n) return fail(GS_EINVAL, "tet vertex index out of range");
+  p->tag.resize(T);
+  for (int e = 0; e < T; ++e) {
+    const int mode = m->tet_mode[e], ch = m->tet_chamber[e];
+    if (mode < GS_BODY || mode > GS_CH_AX_Z) return fail(GS_EINVAL, "bad tet_mode");
+    if (mode != GS_BODY && (ch < 0 || ch >= p->nch)) return fail(GS_EINVAL, "chamber element without a valid chamber");
+    p->tag[e] = mode | ((mode != GS_BODY ? ch : 0) << 3);
+  }
+  p->freem.resize(n);
+  for (int v = 0; v < n; ++v) p->freem[v] = m->fixed[v] ? 0 : 1;
+  auto X = [&](int v, int k) { return p->X0[(size_t)k * n + v]; };
+
+  // h_ref: mean rest length of the unique edges
+  {
+    std::vector<uint64_t> ek;
+    ek.reserve(6 * (size_t)T);
+    for (int e = 0; e < T; ++e)
+      for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b) {
+          uint64_t i = (uint32_t)p->tets[a * (size_t)T + e], j = (uint32_t)p->tets[b * (size_t)T + e];
+          if (i > j) std::swap(i, j);
+          ek.push_back((i << 32) | j);
+        }
+    std::sort(ek.begin(), ek.end());
+    ek.erase(std::unique(ek.begin(), ek.end()), ek.end());
+    double sum = 0.0;
+    for (uint64_t k : ek) {
+      const int i = (int)(k >> 32), j = (int)(k & 0xffffffffu);
+      const double dx = X(i, 0) - X(j, 0), dy = X(i, 1) - X(j, 1), dz = X(i, 2) - X(j, 2);
+      sum += std::sqrt((dx * dx + dy * dy) + dz * dz);
+    }
+    p->h_ref = sum / (double)ek.size();
+  }
+
+  // orientation (swap slots 2 and 3 of negative tets), volumes, cell size
+  std::vector<double> vol(T);
+  double vsum = 0.0, cell = 0.0;
+  for (int e = 0; e < T; ++e) {
+    int32_t* t[4];
+    for (int j = 0; j < 4; ++j) t[j] = &p->tets[j * (size_t)T + e];
+    double P[4][3];
+    for (int j = 0; j < 4; ++j)
+      for (int k = 0; k < 3; ++k) P[j][k] = X(*t[j], k);
+    const double v6 = orient_h(P[0], P[1], P[2], P[3]);
+    if (std::fabs(v6) / 6.0 <= 1e-12 * p->h_ref * p->h_ref * p->h_ref)
+      return fail(GS_EDEGENERATE, "degenerate rest tet " + std::to_string(e));
+    if (v6 < 0) std::swap(*t[2], *t[3]);
+    vol[e] = std::fabs(v6) / 6.0;
+    vsum += vol[e];
+    for (int k = 0; k < 3; ++k) {
+      const double lo = std::min(std::min(P[0][k], P[1][k]), std::min(P[2][k], P[3][k]));
+      const double hi = std::max(std::max(P[0][k], P[1][k]), std::max(P[2][k], P[3][k]));
+      cell = std::max(cell, hi - lo);
+    }
+  }
+  const double mean_vol = vsum / T;
+  p->inv_mean_vol = 1.0 / mean_vol;
+  p->cell = cell;
+
+  // bounding box, offsets
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int v = 0; v < n; ++v)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], X(v, k));
+      hi[k] = std::max(hi[k], X(v, k));
+    }
+  p->diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                      (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  p->eps = p->prm.eps_rel * p->h_ref;
+  p->Lray = p->prm.ray_rel * p->h_ref;
+
+  // incidence: vertex -> (tet, slot) in (tet, slot) order
+  p->inc_start.assign(n + 1, 0);
+  for (size_t i = 0; i < 4 * (size_t)T; ++i) p->inc_start[p->tets[i] + 1]++;
+  for (int v = 0; v < n; ++v) p->inc_start[v + 1] += p->inc_start[v];
+  {
+    std::vector<int32_t> cur(p->inc_start.begin(), p->inc_start.end() - 1);
+    p->inc_pos.resize(4 * (size_t)T);
+    for (int e = 0; e < T; ++e)
+      for (int j = 0; j < 4; ++j) p->inc_pos[j * (size_t)T + e] = cur[p->tets[j * (size_t)T + e]]++;
+  }
+
+  // A_el = sum_e omega_e S_e^T N S_e, N = I - 11^T/4; Dirichlet rows/cols removed
+  std::vector<double> full_diag(n, 0.0);
+  {
+    std::vector<std::pair<uint64_t, double>> trip;
+    trip.reserve(16 * (size_t)T);
+    for (int e = 0; e < T; ++e) {
+      const double om = vol[e] / mean_vol;
+      for (int a = 0; a < 4; ++a) {
+        const uint64_t i = (uint32_t)p->tets[a * (size_t)T + e];
+        full_diag[i] += 0.75 * om;
+        for (int b = 0; b < 4; ++b) {
+          const uint64_t j = (uint32_t)p->tets[b * (size_t)T + e];
+          trip.emplace_back((i << 32) | j, (a == b ? 0.75 : -0.25) * om);
+        }
+      }
+    }
+    std::sort(trip.begin(), trip.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    p->rowptr.assign(n + 1, 0);
+    p->col.clear();
+    p->val.clear();
+    size_t i = 0;
+    for (int r = 0; r < n; ++r) {
+      if (!p->freem[r]) {
+        p->col.push_back(r);
+        p->val.push_back(1.0);
+        while (i < trip.size() && (int)(trip[i].first >> 32) == r) ++i;
+      } else {
+        while (i < trip.size() && (int)(trip[i].first >> 32) == r) {
+          const int cj = (int)(trip[i].first & 0xffffffffu);
+          double s = 0.0;
+          while (i < trip.size() && trip[i].first == (((uint64_t)r << 32) | (uint32_t)cj)) s += trip[i++].second;
+          if (p->freem[cj]) {
+            p->col.push_back(cj);
+            p->val.push_back(s);
+          }
+        }
+      }
+      p->rowptr[r + 1] = (int32_t)p->col.size();
+    }
+    p->nnz = (int)p->col.size();
+    // ELL copy of the off-diagonal entries (slot-major, padded with the row
+    // itself and value 0); the diagonal lives in the Jacobi diagonal
+    int wmax = 0;
+    for (int r = 0; r < n; ++r) {
+      int cnt = 0;
+      if (p->freem[r])
+        for (int j = p->rowptr[r]; j < p->rowptr[r + 1]; ++j) cnt += (p->col[j] != r);
+      wmax = std::max(wmax, cnt);
+    }
+    if (wmax > 64) throw std::runtime_error("a vertex has more than 64 neighbours");
+    p->ell_w = wmax <= 16 ? 16 : (wmax <= 32 ? 32 : 64);
+    p->ell_col.assign((size_t)p->ell_w * n, 0);
+    p->ell_val.assign((size_t)p->ell_w * n, 0.0);
+    for (int r = 0; r < n; ++r) {
+      int k = 0;
+      if (p->freem[r])
+        for (int j = p->rowptr[r]; j < p->rowptr[r + 1]; ++j)
+          if (p->col[j] != r) {
+            p->ell_col[(size_t)k * n + r] = p->col[j];
+            p->ell_val[(size_t)k * n + r] = p->val[j];
+            ++k;
+          }
+      for (; k < p->ell_w; ++k) p->ell_col[(size_t)k * n + r] = r;
+    }
+    p->adiag.resize(n);
+    for (int v = 0; v < n; ++v) p->adiag[v] = p->freem[v] ? full_diag[v] : 1.0;
+  }
+
+  // boundary faces: faces of exactly one tet, outward, in (tet, slot) order
+  {
+    struct FK {
+      int32_t a, b, c;
+      int32_t idx;
+    };
+    std::vector<FK> fk(4 * (size_t)T);
+    for (int e = 0; e < T; ++e)
+      for (int m2 = 0; m2 < 4; ++m2) {
+        int32_t v[3];
+        for (int k = 0; k < 3; ++k) v[k] = p->tets[kFaceSlots[m2][k] * (size_t)T + e];
+        std::sort(v, v + 3);
+        fk[4 * (size_t)e + m2] = {v[0], v[1], v[2], (int32_t)(4 * e + m2)};
+      }
+    std::sort(fk.begin(), fk.end(), [](const FK& x, const FK& y) {
+      if (x.a != y.a) return x.a < y.a;
+      if (x.b != y.b) return x.b < y.b;
+      if (x.c != y.c) return x.c < y.c;
+      return x.idx < y.idx;
+    });
+    std::vector<uint8_t> on(4 * (size_t)T, 0);
+    for (size_t i = 0; i < fk.size();) {
+      size_t j = i + 1;
+      while (j < fk.size() && fk[j].a == fk[i].a && fk[j].b == fk[i].b && fk[j].c == fk[i].c) ++j;
+      if (j - i == 1) on[fk[i].idx] = 1;
+      i = j;
+    }
+    std::vector<int32_t> f0, f1, f2;
+    for (size_t i = 0; i < on.size(); ++i)
+      if (on[i]) {
+        const int e = (int)(i / 4), m2 = (int)(i % 4);
+        f0.push_back(p->tets[kFaceSlots[m2][0] * (size_t)T + e]);
+        f1.push_back(p->tets[kFaceSlots[m2][1] * (size_t)T + e]);
+        f2.push_back(p->tets[kFaceSlots[m2][2] * (size_t)T + e]);
+      }
+    p->F = (int)f0.size();
+    p->faces.clear();
+    p->faces.insert(p->faces.end(), f0.begin(), f0.end());
+    p->faces.insert(p->faces.end(), f1.begin(), f1.end());
+    p->faces.insert(p->faces.end(), f2.begin(), f2.end());
+  }
+
+  // query vertices: non-fixed boundary vertices, ascending; incident faces ascending
+  {
+    const int F = p->F;
+    std::vector<uint8_t> surf(n, 0);
+    for (int32_t v : p->faces) surf[v] = 1;
+    p->n_surf_verts = 0;
+    p->qverts.clear();
+    p->vq.assign(n, -1);
+    for (int v = 0; v < n; ++v) {
+      p->n_surf_verts += surf[v];
+      if (surf[v] && p->freem[v]) {
+        p->vq[v] = (int32_t)p->qverts.size();
+        p->qverts.push_back(v);
+      }
+    }
+    p->S = (int)p->qverts.size();
+    p->qf_start.assign(p->S + 1, 0);
+    for (int f = 0; f < F; ++f)
+      for (int k = 0; k < 3; ++k) {
+        const int s = p->vq[p->faces[k * (size_t)F + f]];
+        if (s >= 0) p->qf_start[s + 1]++;
+      }
+    for (int s = 0; s < p->S; ++s) p->qf_start[s + 1] += p->qf_start[s];
+    std::vector<int32_t> cur(p->qf_start.begin(), p->qf_start.end() - 1);
+    p->qf_list.assign(p->qf_start[p->S], 0);
+    for (int f = 0; f < F; ++f)
+      for (int k = 0; k < 3; ++k) {
+        const int s = p->vq[p->faces[k * (size_t)F + f]];
+        if (s >= 0) p->qf_list[cur[s]++] = f;
+      }
+    p->kq.resize(p->S);
+    // spring stiffness k_v = kappa_col * A_el[v, v]
+    for (int s = 0; s < p->S; ++s) p->kq[s] = p->prm.kappa_col * full_diag[p->qverts[s]];
+  }
+
+  int H = 1024;
+  while (H < 2 * p->S) H <<= 1;
+  p->H = H;
+  p->nparts = std::max({cdiv(T, kBlock), cdiv(n, kBlock), 2 * kMaxPcgGrid});
+  p->slots = 1;
+  return GS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+int32_t gs_version(void) { return GEOSIM_VERSION; }
+
+const char* gs_last_error(void) { return g_err.c_str(); }
+
+void gs_default_params(gs_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->c1 = 0.0418;
+  p->c2 = 0.0106;
+  p->hyperelastic = 1;
+  p->kappa_col = 1.0;
+  p->eps_rel = 0.05;
+  p->ray_rel = 4.0;
+  p->self_collision = 0;
+  p->obstacle_collision = 0;
+  p->tol = 1e-6;
+  p->max_iter = 20000;
+  p->fixed_iters = 0;
+  p->pcg_eta = 1e-3;
+  p->pcg_max = 200;
+  p->check_every = 16;
+  p->pcg_blocks = 0;
+  p->trace_len = 0;
+}
+
+gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** out) {
+  if (!out) return fail(GS_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!m || !m->rest_xyz || !m->tets || !m->tet_mode || !m->tet_chamber || !m->fixed)
+    return fail(GS_EINVAL, "null mesh array");
+  if (m->n_verts <= 0 || m->n_tets <= 0 || m->n_chambers < 0) return fail(GS_EINVAL, "empty mesh");
+  if (m->precision != 4 && m->precision != 8) return fail(GS_EINVAL, "precision must be 4 or 8");
+  if ((long)m->n_tets * 4 >= (1L << 31)) return fail(GS_EINVAL, "mesh too large");
+  gs_status st = check_params(prm);
+  if (st != GS_OK) return st;
+  gs_problem* p = new (std::nothrow) gs_problem();
+  if (!p) return fail(GS_EINVAL, "out of host memory");
+  p->prm = *prm;
+  p->trace_len = prm->trace_len;
+  try {
+    st = setup(p, m);
+  } catch (const std::exception& ex) {
+    st = fail(GS_EINVAL, std::string("set-up failed: ") + ex.what());
+  }
+  if (st != GS_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return GS_OK;
+}
+
+gs_status gs_set_obstacles(gs_problem* p, int32_t n_sph, const double* sph, int32_t n_pln, const double* pln) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (p->bound) return fail(GS_ESTATE, "obstacles must be set before gs_bind");
+  if (n_sph < 0 || n_pln < 0 || n_sph > 8 || n_pln > 8) return fail(GS_EINVAL, "at most 8 spheres and 8 planes");
+  if ((n_sph && !sph) || (n_pln && !pln)) return fail(GS_EINVAL, "null obstacle array");
+  std::vector<double> ob;
+  for (int j = 0; j < n_sph; ++j) {
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(sph[4 * j + k])) return fail(GS_EINVAL, "non-finite sphere");
+    if (!(sph[4 * j + 3] > 0)) return fail(GS_EINVAL, "sphere radius must be positive");
+    ob.insert(ob.end(), sph + 4 * j, sph + 4 * j + 4);
+  }
+  for (int j = 0; j < n_pln; ++j) {
+    const double* q = pln + 6 * j;
+    for (int k = 0; k < 6; ++k)
+      if (!std::isfinite(q[k])) return fail(GS_EINVAL, "non-finite plane");
+    const double nr = std::sqrt((q[3] * q[3] + q[4] * q[4]) + q[5] * q[5]);
+    if (!(nr > 0)) return fail(GS_EINVAL, "plane with zero normal");
+    ob.insert(ob.end(), {q[0], q[1], q[2], q[3] / nr, q[4] / nr, q[5] / nr});
+  }
+  p->ns = n_sph;
+  p->np = n_pln;
+  p->obst = ob;
+  p->slots = 1 + n_sph + n_pln;
+  return GS_OK;
+}
+
+gs_status gs_info_get(const gs_problem* p, gs_info* info) {
+  if (!p || !info) return fail(GS_EINVAL, "null argument");
+  info->n_verts = p->n;
+  info->n_tets = p->T;
+  info->n_surface_faces = p->F;
+  info->n_surface_verts = p->n_surf_verts;
+  info->n_query_verts = p->S;
+  info->nnz = p->nnz;
+  info->n_slots = p->slots;
+  info->hash_buckets = p->H;
+  info->h_ref = p->h_ref;
+  info->eps_off = p->eps;
+  info->ray_len = p->Lray;
+  info->bbox_diag = p->diag;
+  info->cell_size = p->cell;
+  return GS_OK;
+}
+
+gs_status gs_workspace_size(const gs_problem* p, size_t* bytes) {
+  if (!p || !bytes) return fail(GS_EINVAL, "null argument");
+  *bytes = make_layout(p).total;
+  return GS_OK;
+}
+
+gs_status gs_bind(gs_problem* p, void* ws, size_t bytes, void* stream) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!ws) return fail(GS_EINVAL, "null workspace");
+  if (((uintptr_t)ws & 255) != 0) return fail(GS_EINVAL, "workspace must be 256-byte aligned");
+  const Layout L = make_layout(p);
+  if (bytes < L.total) return fail(GS_EINVAL, "workspace too small");
+  p->lay = L;
+  p->ws = (char*)ws;
+  p->ws_bytes = bytes;
+  p->stream = (hipStream_t)stream;
+  p->bound = false;
+  const gs_status st = p->prec == 4 ? bind_impl<float>(p) : bind_impl<double>(p);
+  if (st == GS_OK) p->bound = true;
+  return st;
+}
+
+gs_status gs_set_params(gs_problem* p, const gs_params* prm) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  const gs_status st = check_params(prm);
+  if (st != GS_OK) return st;
+  if (prm->kappa_col != p->prm.kappa_col) {
+    for (int s = 0; s < p->S; ++s) p->kq[s] *= prm->kappa_col / p->prm.kappa_col;
+    if (p->bound) HIPCHK(hipMemcpyAsync(p->ws + p->lay.kq, p->kq.data(), p->kq.size() * 8, hipMemcpyHostToDevice,
+                                        p->stream));
+  }
+  const double h = p->h_ref;
+  p->prm = *prm;
+  p->eps = prm->eps_rel * h;
+  p->Lray = prm->ray_rel * h;
+  if (p->bound) {
+    const int maxg = p->prec == 4 ? pcg_max_grid<float>(0) : pcg_max_grid<double>(0);
+    p->pcg_grid = pcg_grid_for(p, maxg);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  }
+  return GS_OK;
+}
+
+gs_status gs_solve(gs_problem* p, const void* alpha, void* x, gs_stats* stats) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "gs_solve before gs_bind");
+  if (!x || (p->nch > 0 && !alpha)) return fail(GS_EINVAL, "null device buffer");
+  if (p->prec == 4) return solve_impl<float>(p, (const float*)alpha, (float*)x, stats);
+  return solve_impl<double>(p, (const double*)alpha, (double*)x, stats);
+}
+
+gs_status gs_reset_contacts(gs_problem* p) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "not bound");
+  HIPCHK(hipMemsetAsync(p->ws + p->lay.cact, 0, (size_t)p->S * p->slots, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return GS_OK;
+}
+
+gs_status gs_contacts(gs_problem* p, int32_t cap, int32_t* v, int32_t* type, int32_t* prim, double* target,
+                      double* normal, int32_t* count) {
+  if (!p || !count) return fail(GS_EINVAL, "null argument");
+  if (!p->bound) return fail(GS_ESTATE, "not bound");
+  const size_t m = (size_t)p->S * p->slots;
+  std::vector<uint8_t> act(m);
+  std::vector<double> tg(3 * m), nr(3 * m);
+  std::vector<int32_t> pr(m);
+  HIPCHK(hipMemcpyAsync(act.data(), p->ws + p->lay.cact, m, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipMemcpyAsync(tg.data(), p->ws + p->lay.ctgt, 3 * m * 8, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipMemcpyAsync(nr.data(), p->ws + p->lay.cnrm, 3 * m * 8, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipMemcpyAsync(pr.data(), p->ws + p->lay.cprim, m * 4, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  int k = 0;
+  for (size_t i = 0; i < m; ++i) k += act[i] ? 1 : 0;
+  *count = k;
+  if (k > cap) return fail(GS_ECAPACITY, "contact capacity too small");
+  int o = 0;
+  for (int s = 0; s < p->S; ++s)
+    for (int sl = 0; sl < p->slots; ++sl) {
+      const size_t i = (size_t)s * p->slots + sl;
+      if (!act[i]) continue;
+      if (v) v[o] = p->qverts[s];
+      if (type) type[o] = sl == 0 ? GS_CONTACT_SELF : (sl <= p->ns ? GS_CONTACT_SPHERE : GS_CONTACT_PLANE);
+      if (prim) prim[o] = pr[i];
+      for (int c = 0; c < 3; ++c) {
+        if (target) target[3 * o + c] = tg[3 * i + c];
+        if (normal) normal[3 * o + c] = nr[3 * i + c];
+      }
+      ++o;
+    }
+  return GS_OK;
+}
+
+gs_status gs_set_contacts(gs_problem* p, int32_t count, const int32_t* v, const int32_t* type, const int32_t* prim,
+                          const double* target, const double* normal) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "not bound");
+  if (count < 0 || (count > 0 && (!v || !type || !prim || !target || !normal))) return fail(GS_EINVAL, "bad arrays");
+  const size_t m = (size_t)p->S * p->slots;
+  std::vector<uint8_t> act(m, 0);
+  std::vector<double> tg(3 * m, 0.0), nr(3 * m, 0.0);
+  std::vector<int32_t> pr(m, -1);
+  for (int i = 0; i < count; ++i) {
+    if (v[i] < 0 || v[i] >= p->n || p->vq[v[i]] < 0) return fail(GS_EINVAL, "contact vertex is not a query vertex");
+    int sl;
+    if (type[i] == GS_CONTACT_SELF) {
+      if (prim[i] < 0 || prim[i] >= p->F) return fail(GS_EINVAL, "self contact face out of range");
+      sl = 0;
+    } else if (type[i] == GS_CONTACT_SPHERE) {
+      if (prim[i] < 0 || prim[i] >= p->ns) return fail(GS_EINVAL, "sphere index out of range");
+      sl = 1 + prim[i];
+    } else if (type[i] == GS_CONTACT_PLANE) {
+      if (prim[i] < 0 || prim[i] >= p->np) return fail(GS_EINVAL, "plane index out of range");
+      sl = 1 + p->ns + prim[i];
+    } else {
+      return fail(GS_EINVAL, "bad contact type");
+    }
+    const size_t j = (size_t)p->vq[v[i]] * p->slots + sl;
+    if (act[j]) return fail(GS_EINVAL, "duplicate contact");
+    act[j] = 1;
+    pr[j] = prim[i];
+    for (int c = 0; c < 3; ++c) {
+      tg[3 * j + c] = target[3 * i + c];
+      nr[3 * j + c] = normal[3 * i + c];
+    }
+  }
+  HIPCHK(hipMemcpyAsync(p->ws + p->lay.cact, act.data(), m, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->ws + p->lay.ctgt, tg.data(), 3 * m * 8, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->ws + p->lay.cnrm, nr.data(), 3 * m * 8, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->ws + p->lay.cprim, pr.data(), m * 4, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return GS_OK;
+}
+
+gs_status gs_local_step_debug(gs_problem* p, const void* x, const void* alpha, void* targets) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "not bound");
+  if (!x || !targets || (p->nch > 0 && !alpha)) return fail(GS_EINVAL, "null device buffer");
+  const Consts c = make_consts(p);
+  if (p->prec == 4) {
+    HIPCHK(launch_local_debug<float>(make_dev<float>(p), c, (const float*)alpha, (const float*)x, (float*)targets,
+                                     p->stream));
+  } else {
+    HIPCHK(launch_local_debug<double>(make_dev<double>(p), c, (const double*)alpha, (const double*)x,
+                                      (double*)targets, p->stream));
+  }
+  return GS_OK;
+}
+
+gs_status gs_tets(const gs_problem* p, int32_t* tets) {
+  if (!p || !tets) return fail(GS_EINVAL, "null argument");
+  std::memcpy(tets, p->tets.data(), p->tets.size() * 4);
+  return GS_OK;
+}
+
+gs_status gs_faces(const gs_problem* p, int32_t* faces) {
+  if (!p || !faces) return fail(GS_EINVAL, "null argument");
+  std::memcpy(faces, p->faces.data(), p->faces.size() * 4);
+  return GS_OK;
+}
+
+size_t gs_collide_debug_scratch(int32_t cap) { return 16 * (size_t)std::max(cap, 0) + 256; }
+
+gs_status gs_collide_debug(gs_problem* p, const void* x, int32_t cap, void* scratch, size_t scratch_bytes,
+                           int32_t* cand_tet, int32_t* n_cand_tet, int32_t* cand_tri, int32_t* n_cand_tri,
+                           int32_t* contacts, double* target, int32_t* n_contacts) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "not bound");
+  if (!x || !scratch || cap < 0 || !n_cand_tet || !n_cand_tri || !n_contacts) return fail(GS_EINVAL, "null argument");
+  if (scratch_bytes < gs_collide_debug_scratch(cap)) return fail(GS_EINVAL, "debug scratch too small");
+  hipStream_t s = p->stream;
+  const size_t m = (size_t)p->S * p->slots;
+  // keep the stored active set: save it, run one check, restore it
+  std::vector<uint8_t> act(m);
+  std::vector<double> tg(3 * m), nr(3 * m);
+  std::vector<int32_t> pr(m);
+  HIPCHK(hipMemcpyAsync(act.data(), p->ws + p->lay.cact, m, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(tg.data(), p->ws + p->lay.ctgt, 3 * m * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(nr.data(), p->ws + p->lay.cnrm, 3 * m * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(pr.data(), p->ws + p->lay.cprim, m * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const Consts c = make_consts(p);
+  DevStatus h{};
+  gs_status st = GS_OK;
+  auto run = [&](auto tag) -> gs_status {
+    using R = decltype(tag);
+    Dev<R> d = make_dev<R>(p);
+    d.dbg_cap = cap;
+    d.dbg_tet = (int32_t*)scratch;
+    d.dbg_tri = (int32_t*)scratch + 2 * (size_t)cap;
+    HIPCHK(launch_set_positions<R>(d, c, (const R*)x, s));
+    if (c.self_col)
+      for (int stg = 0; stg < N_COLLIDE_STAGES; ++stg) HIPCHK(launch_collide_stage<R>(d, c, stg, true, s));
+    if (c.self_col || c.obst_col) HIPCHK(launch_contacts<R>(d, c, s));
+    HIPCHK(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return GS_OK;
+  };
+  st = p->prec == 4 ? run(float{}) : run(double{});
+  if (st != GS_OK) return st;
+  *n_cand_tet = h.cand_tet;
+  *n_cand_tri = h.cand_tri;
+  auto sorted_pairs = [&](const int32_t* dev, int cnt, int32_t* out, int32_t* nout) -> gs_status {
+    const int k = std::min(cnt, cap);
+    std::vector<int32_t> buf(2 * (size_t)cap);
+    if (cap > 0) HIPCHK(hipMemcpy(buf.data(), dev, 2 * (size_t)cap * 4, hipMemcpyDeviceToHost));
+    std::vector<std::pair<int32_t, int32_t>> pr2(k);
+    for (int i = 0; i < k; ++i) pr2[i] = {buf[i], buf[cap + i]};
+    std::sort(pr2.begin(), pr2.end());
+    pr2.erase(std::unique(pr2.begin(), pr2.end()), pr2.end());
+    *nout = (int32_t)pr2.size();
+    if (out)
+      for (size_t i = 0; i < pr2.size(); ++i) {
+        out[i] = pr2[i].first;
+        out[cap + i] = pr2[i].second;
+      }
+    return GS_OK;
+  };
+  const bool over = h.cand_tet > cap || h.cand_tri > cap;
+  if (!over) {
+    if ((st = sorted_pairs((const int32_t*)scratch, h.cand_tet, cand_tet, n_cand_tet)) != GS_OK) return st;
+    if ((st = sorted_pairs((const int32_t*)scratch + 2 * (size_t)cap, h.cand_tri, cand_tri, n_cand_tri)) != GS_OK)
+      return st;
+  }
+  // resulting active set, then restore the stored one
+  std::vector<int32_t> cv(std::max<size_t>(m, 1)), ct(std::max<size_t>(m, 1)), cp(std::max<size_t>(m, 1));
+  std::vector<double> ctg(3 * std::max<size_t>(m, 1)), cnr(3 * std::max<size_t>(m, 1));
+  int32_t cnt = 0;
+  st = gs_contacts(p, (int32_t)m, cv.data(), ct.data(), cp.data(), ctg.data(), cnr.data(), &cnt);
+  HIPCHK(hipMemcpyAsync(p->ws + p->lay.cact, act.data(), m, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->ws + p->lay.ctgt, tg.data(), 3 * m * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->ws + p->lay.cnrm, nr.data(), 3 * m * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(p->ws + p->lay.cprim, pr.data(), m * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st != GS_OK) return st;
+  *n_contacts = cnt;
+  if (cnt <= cap && contacts)
+    for (int i = 0; i < cnt; ++i) {
+      contacts[i] = cv[i];
+      contacts[cap + i] = ct[i];
+      contacts[2 * (size_t)cap + i] = cp[i];
+      if (target)
+        for (int k = 0; k < 3; ++k) target[k * (size_t)cap + i] = ctg[3 * i + k];
+    }
+  if (over || cnt > cap) return fail(GS_ECAPACITY, "candidate or contact capacity too small");
+  return GS_OK;
+}
+
+gs_status gs_trace(gs_problem* p, int32_t cap, double* rows, int32_t* count) {
+  if (!p || !count || (cap > 0 && !rows)) return fail(GS_EINVAL, "null argument");
+  if (!p->bound) return fail(GS_ESTATE, "not bound");
+  const int k = std::min({p->last_iters, p->trace_len, std::max(cap, 0)});
+  *count = k;
+  if (k > 0) {
+    HIPCHK(hipMemcpyAsync(rows, p->ws + p->lay.trace, (size_t)k * 6 * 8, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  }
+  return GS_OK;
+}
+
+gs_status gs_profile(gs_problem* p, int32_t enable) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  p->prof.reset();
+  p->prof.on = enable != 0;
+  return GS_OK;
+}
+
+gs_status gs_profile_read(const gs_problem* p, double* ms, int64_t* launches) {
+  if (!p || !ms || !launches) return fail(GS_EINVAL, "null argument");
+  for (int k = 0; k < kNKernels; ++k) {
+    ms[k] = p->prof.ms[k];
+    launches[k] = p->prof.cnt[k];
+  }
+  return GS_OK;
+}
+
+const char* gs_kernel_name(int32_t k) { return (k >= 0 && k < kNKernels) ? kKernelNames[k] : ""; }
+
+void gs_destroy(gs_problem* p) { delete p; }
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Internal declarations shared by the host layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "geosim.h"
+
+namespace gs {
+
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+constexpr int kCellCap = 64;         // hash cells a tet box may span before the brute-force path
+constexpr int kMaxSlots = 1 + 8 + 8; // self + spheres + planes
+constexpr int kPcgThreads = 512;     // threads per block of the cooperative CG kernel
+constexpr int kMaxPcgGrid = 64;      // workgroups of the cooperative CG kernel at most
+
+// Completion codes kept on the device (DevStatus::done).
+enum { RUNNING = 0, CONVERGED = 1, MAXITER = 2, BREAKDOWN = 3, FIXED_DONE = 4 };
+
+struct DevStatus {
+  int iters;            // outer iterations completed
+  int done;             // RUNNING / CONVERGED / ...
+  int changed;          // active set changed in the current iteration
+  int pcg_total;        // inner CG iterations summed
+  int ray_miss;         // current iteration
+  int ray_miss_last;    // last completed iteration
+  int n_pen;            // penetrating query vertices (current iteration)
+  int ticket;           // last-block ticket of the finish kernel
+  int n_contacts;       // active springs (current iteration)
+  int n_contacts_last;
+  int cand_tet, cand_tri;  // debug candidate counters
+  int pcg_last;         // inner iterations of the last outer iteration
+  int changed_last;
+  double residual;      // r_k of the last completed iteration
+  double energy;        // Eq. 9 at x_k with the iteration's targets
+  unsigned bar_count, bar_gen, pad0, pad1;
+};
+
+// Scalars of one problem (passed by value to kernels).
+struct Consts {
+  int n, T, S, F, nch, slots, H, ns, np;
+  int self_col, obst_col, hyper;
+  int max_iter, fixed_iters, pcg_max;
+  int nparts;           // partial-sum slots per reduction array
+  int ell_w;            // off-diagonal entries per row of the ELL matrix (16, 32 or 64)
+  int trace_len;        // rows of the per-iteration trace
+  double c1, c2, kappa, eps, Lray, diag, tol, pcg_eta, inv_mean_vol, inv_cell;
+};
+
+// Device pointers, all inside the caller's workspace except the in/out buffers.
+template <typename R>
+struct Dev {
+  // static
+  const double* X0;        // [3][n]
+  const int32_t* tets;     // [4][T]
+  const int32_t* tag;      // [T] mode | (chamber << 3)
+  const int32_t* inc_start;  // [n+1]
+  const int32_t* inc_pos;  // [4][T]
+  const int32_t* ell_col;  // [ell_w][n] off-diagonal columns of A_el (free rows/cols; padding: own row)
+  const R* ell_val;        // [ell_w][n] (padding: 0)
+  R* ell_scaled;           // [ell_w][n] ell_val / dg[col], rebuilt by each CG solve
+  const R* adiag;          // [n] diagonal of A_el (1 on fixed rows)
+  const uint8_t* freem;    // [n]
+  const int32_t* faces;    // [3][F]
+  const int32_t* qverts;   // [S]
+  const int32_t* vq;       // [n] query index or -1
+  const int32_t* qf_start; // [S+1]
+  const int32_t* qf_list;  // incident boundary faces of each query vertex, ascending
+  const double* kq;        // [S] spring stiffness
+  const double* obst;      // spheres [ns][4] then planes [np][6]
+  // iteration state
+  R* u;                    // [3][n] displacement from X0
+  double* xc;              // [3][n] X0 + u in double (collision positions)
+  R* res4;                 // [4T][4] element residual columns in incidence order
+  R* r;                    // [2][3][n] right-hand side / CG residual (two buffers)
+  R* w;                    // [2][3][n] CG: A M^-1 r (two buffers)
+  R* s;                    // [2][3][n] CG: A p (two buffers)
+  R* dl;                   // [3][n] correction (kept across iterations: the warm start)
+  R* p;                    // [3][n]
+  R* dg;                   // [n] Jacobi diagonal
+  R* dsp;                  // [n] spring diagonal
+  uint8_t* pen;            // [S]
+  int32_t* hcount;         // [H]
+  int32_t* hstart;         // [H+1]
+  double* hent;            // [S][4] (x, y, z, query index as bits)
+  int32_t* qkey;           // [S]
+  int32_t* penlist;        // [S]
+  int32_t* fhit;           // [S] fresh self hit face or -1
+  double* fc;              // [S][3] fresh self target
+  double* fn;              // [S][3] fresh self normal
+  uint8_t* cact;           // [S][slots]
+  double* ctgt;            // [S][slots][3]
+  double* cnrm;            // [S][slots][3]
+  int32_t* cprim;          // [S][slots]
+  double* part_a;          // [nparts] reductions
+  double* part_b;
+  double* part_c;
+  double* part_d;
+  double* part_e;
+  DevStatus* st;
+  double* trace;           // [trace_len][6]
+  // debug candidate buffers (null outside gs_collide_debug)
+  int32_t* dbg_tet;        // [2][cap]
+  int32_t* dbg_tri;        // [2][cap]
+  int dbg_cap;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (one per kernel family); all enqueue on `s` and return hipError_t
+template <typename R> hipError_t launch_init(const Dev<R>& d, const Consts& c, const R* xin, hipStream_t s);
+template <typename R> hipError_t launch_output(const Dev<R>& d, const Consts& c, R* xout, hipStream_t s);
+// collision stages, in launch order
+enum { STAGE_HASH_COUNT = 0, STAGE_HASH_SCAN, STAGE_HASH_FILL, STAGE_TET_QUERY, STAGE_PEN_COMPACT, STAGE_RAY,
+       N_COLLIDE_STAGES };
+template <typename R>
+hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s);
+template <typename R> hipError_t launch_contacts(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R> hipError_t launch_local(const Dev<R>& d, const Consts& c, const R* alpha, hipStream_t s);
+template <typename R> hipError_t launch_local_debug(const Dev<R>& d, const Consts& c, const R* alpha, const R* x,
+                                                    R* targets, hipStream_t s);
+template <typename R> hipError_t launch_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R> hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s);
+template <typename R> hipError_t launch_finish(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R> hipError_t launch_set_positions(const Dev<R>& d, const Consts& c, const R* x, hipStream_t s);
+template <typename R> int pcg_max_grid(int block);
+
+__host__ __device__ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace gs

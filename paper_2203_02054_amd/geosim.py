@@ -1,0 +1,313 @@
+"""Python binding of libgeosim (argument marshalling only).
+
+Every step of the solve runs in the HIP library; PyTorch provides device
+memory and the stream.  The binding fails loudly when the library is not
+built or no GPU is present: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgeosim.so")
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, EDEGENERATE, EBREAKDOWN, ECAPACITY, ESTATE, EHIP = -1, -2, -3, -4, -5, -6
+BODY, CH_ISO, CH_AX_X, CH_AX_Y, CH_AX_Z = 0, 1, 2, 3, 4
+CONTACT_SELF, CONTACT_SPHERE, CONTACT_PLANE = 0, 1, 2
+
+
+class GeosimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"geosim error {code}: {msg}")
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_verts", ctypes.c_int32), ("n_tets", ctypes.c_int32), ("n_chambers", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("rest_xyz", ctypes.c_void_p), ("tets", ctypes.c_void_p),
+                ("tet_mode", ctypes.c_void_p), ("tet_chamber", ctypes.c_void_p), ("fixed", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("c1", ctypes.c_double), ("c2", ctypes.c_double), ("hyperelastic", ctypes.c_int32),
+                ("kappa_col", ctypes.c_double), ("eps_rel", ctypes.c_double), ("ray_rel", ctypes.c_double),
+                ("self_collision", ctypes.c_int32), ("obstacle_collision", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
+                ("pcg_eta", ctypes.c_double), ("pcg_max", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("pcg_blocks", ctypes.c_int32), ("trace_len", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32), ("n_contacts", ctypes.c_int32),
+                ("ray_miss", ctypes.c_int32), ("residual", ctypes.c_double), ("energy", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_verts", ctypes.c_int32), ("n_tets", ctypes.c_int32), ("n_surface_faces", ctypes.c_int32),
+                ("n_surface_verts", ctypes.c_int32), ("n_query_verts", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("n_slots", ctypes.c_int32), ("hash_buckets", ctypes.c_int32), ("h_ref", ctypes.c_double),
+                ("eps_off", ctypes.c_double), ("ray_len", ctypes.c_double), ("bbox_diag", ctypes.c_double),
+                ("cell_size", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_PI = ctypes.POINTER(ctypes.c_int32)
+_PD = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes); every entry point the header declares
+SIGNATURES = {
+    "gs_version": (_I, []),
+    "gs_last_error": (ctypes.c_char_p, []),
+    "gs_default_params": (None, [ctypes.POINTER(Params)]),
+    "gs_create": (_I, [ctypes.POINTER(MeshDesc), ctypes.POINTER(Params), ctypes.POINTER(_P)]),
+    "gs_set_obstacles": (_I, [_P, _I, _PD, _I, _PD]),
+    "gs_info_get": (_I, [_P, ctypes.POINTER(Info)]),
+    "gs_workspace_size": (_I, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "gs_bind": (_I, [_P, _P, ctypes.c_size_t, _P]),
+    "gs_set_params": (_I, [_P, ctypes.POINTER(Params)]),
+    "gs_solve": (_I, [_P, _P, _P, ctypes.POINTER(Stats)]),
+    "gs_reset_contacts": (_I, [_P]),
+    "gs_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD, _PI]),
+    "gs_set_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD]),
+    "gs_local_step_debug": (_I, [_P, _P, _P, _P]),
+    "gs_tets": (_I, [_P, _PI]),
+    "gs_faces": (_I, [_P, _PI]),
+    "gs_collide_debug_scratch": (ctypes.c_size_t, [_I]),
+    "gs_collide_debug": (_I, [_P, _P, _I, _P, ctypes.c_size_t, _PI, _PI, _PI, _PI, _PI, _PD, _PI]),
+    "gs_trace": (_I, [_P, _I, _PD, _PI]),
+    "gs_profile": (_I, [_P, _I]),
+    "gs_profile_read": (_I, [_P, _PD, ctypes.POINTER(ctypes.c_int64)]),
+    "gs_kernel_name": (ctypes.c_char_p, [_I]),
+    "gs_destroy": (None, [_P]),
+}
+
+N_KERNELS = 11
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2203_02054_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code, allow=(OK,)):
+    if code in allow:
+        return code
+    raise GeosimError(code, lib().gs_last_error().decode())
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().gs_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, type(getattr(p, k))(v))
+    return p
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("geosim needs a HIP GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+class Problem:
+    """One tet mesh bound to a device workspace and a stream."""
+
+    def __init__(self, rest_xyz, tets, tet_mode, tet_chamber, fixed, n_chambers, precision=4, params=None,
+                 spheres=None, planes=None, device=None, stream=None, **kw):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        self.dtype = torch.float32 if precision == 4 else torch.float64
+        self.np_dtype = np.float32 if precision == 4 else np.float64
+        self._X = np.ascontiguousarray(rest_xyz, dtype=np.float64)
+        self._T = np.ascontiguousarray(tets, dtype=np.int32)
+        self._m = np.ascontiguousarray(tet_mode, dtype=np.uint8)
+        self._c = np.ascontiguousarray(tet_chamber, dtype=np.int16)
+        self._f = np.ascontiguousarray(fixed, dtype=np.uint8)
+        self.n, self.T, self.n_chambers = self._X.shape[1], self._T.shape[1], int(n_chambers)
+        desc = MeshDesc(self.n, self.T, self.n_chambers, int(precision), self._X.ctypes.data, self._T.ctypes.data,
+                        self._m.ctypes.data, self._c.ctypes.data, self._f.ctypes.data)
+        self.params = params if params is not None else default_params(**kw)
+        h = _P()
+        _check(lib().gs_create(ctypes.byref(desc), ctypes.byref(self.params), ctypes.byref(h)))
+        self._h = h
+        sph = np.ascontiguousarray(np.zeros((0, 4)) if spheres is None else spheres, dtype=np.float64).reshape(-1, 4)
+        pln = np.ascontiguousarray(np.zeros((0, 6)) if planes is None else planes, dtype=np.float64).reshape(-1, 6)
+        if sph.shape[0] or pln.shape[0]:
+            _check(lib().gs_set_obstacles(h, sph.shape[0], _ptr(sph, ctypes.c_double), pln.shape[0],
+                                          _ptr(pln, ctypes.c_double)))
+        nb = ctypes.c_size_t()
+        _check(lib().gs_workspace_size(h, ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(lib().gs_bind(h, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream))
+        inf = Info()
+        _check(lib().gs_info_get(h, ctypes.byref(inf)))
+        self.info = inf.as_dict()
+
+    @classmethod
+    def from_workload(cls, wl, precision=None, **kw):
+        kw.setdefault("c1", wl.material[0])
+        kw.setdefault("c2", wl.material[1])
+        kw.setdefault("self_collision", int(wl.self_collision))
+        kw.setdefault("obstacle_collision", int(wl.obstacle_collision))
+        kw.setdefault("fixed_iters", wl.fixed_iters)
+        return cls(wl.rest_xyz, wl.tets, wl.tet_mode, wl.tet_chamber, wl.fixed, wl.n_chambers,
+                   precision=precision or wl.precision, spheres=wl.spheres, planes=wl.planes, **kw)
+
+    # -- helpers -----------------------------------------------------------
+    def tensor(self, a):
+        t = self.torch.as_tensor(np.asarray(a), dtype=self.dtype)
+        return t.to(self.device).contiguous()
+
+    def _dev(self, t, shape):
+        if not (t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"expected a contiguous {self.dtype} device tensor of shape {shape}")
+        return t.data_ptr()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points --------------------------------------------------------
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            if not hasattr(self.params, k):
+                raise TypeError(f"unknown parameter {k}")
+            setattr(self.params, k, type(getattr(self.params, k))(v))
+        _check(lib().gs_set_params(self._h, ctypes.byref(self.params)))
+
+    def solve(self, alpha, x=None, allow_not_converged=True):
+        """Solve from x (default: rest positions) with the stored contact set.
+        Returns (x [3,n] device tensor, stats dict with 'status')."""
+        a = alpha if self.torch.is_tensor(alpha) else self.tensor(np.asarray(alpha, dtype=np.float64).reshape(-1))
+        if x is None:
+            x = self.tensor(self._X)
+        st = Stats()
+        allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        code = lib().gs_solve(self._h, self._dev(a, (self.n_chambers,)) if self.n_chambers else None,
+                              self._dev(x, (3, self.n)), ctypes.byref(st))
+        _check(code, allow)
+        d = st.as_dict()
+        d["status"] = code
+        return x, d
+
+    def trace(self):
+        """Per-iteration rows (r_k, E_k, springs, changed, CG its, ray misses) of the last solve."""
+        cap = max(self.params.trace_len, 1)
+        out = np.zeros((cap, 6))
+        cnt = ctypes.c_int32()
+        _check(lib().gs_trace(self._h, cap, _ptr(out, ctypes.c_double), ctypes.byref(cnt)))
+        return out[:cnt.value]
+
+    def profile(self, enable=True):
+        _check(lib().gs_profile(self._h, int(enable)))
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since profiling was enabled."""
+        ms = np.zeros(N_KERNELS)
+        cnt = np.zeros(N_KERNELS, np.int64)
+        _check(lib().gs_profile_read(self._h, _ptr(ms, ctypes.c_double), _ptr(cnt, ctypes.c_int64)))
+        return {lib().gs_kernel_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(N_KERNELS)}
+
+    def reset_contacts(self):
+        _check(lib().gs_reset_contacts(self._h))
+
+    def contacts(self):
+        m = self.info["n_query_verts"] * self.info["n_slots"]
+        cap = max(m, 1)
+        v, t, p = (np.zeros(cap, np.int32) for _ in range(3))
+        tg, nr = np.zeros((cap, 3)), np.zeros((cap, 3))
+        cnt = ctypes.c_int32()
+        _check(lib().gs_contacts(self._h, cap, _ptr(v, ctypes.c_int32), _ptr(t, ctypes.c_int32),
+                                 _ptr(p, ctypes.c_int32), _ptr(tg, ctypes.c_double), _ptr(nr, ctypes.c_double),
+                                 ctypes.byref(cnt)))
+        k = cnt.value
+        return dict(rows=np.stack([v[:k], t[:k], p[:k]], axis=1), target=tg[:k], normal=nr[:k])
+
+    def set_contacts(self, rows, target, normal):
+        rows = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1, 3)
+        v, t, p = (np.ascontiguousarray(rows[:, i]) for i in range(3))
+        tg = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, 3)
+        nr = np.ascontiguousarray(normal, dtype=np.float64).reshape(-1, 3)
+        _check(lib().gs_set_contacts(self._h, rows.shape[0], _ptr(v, ctypes.c_int32), _ptr(t, ctypes.c_int32),
+                                     _ptr(p, ctypes.c_int32), _ptr(tg, ctypes.c_double), _ptr(nr, ctypes.c_double)))
+
+    def local_step(self, x, alpha):
+        """Centred target shapes [3, 4, T] at positions x."""
+        a = alpha if self.torch.is_tensor(alpha) else self.tensor(np.asarray(alpha, dtype=np.float64).reshape(-1))
+        out = self.torch.empty((3, 4, self.T), dtype=self.dtype, device=self.device)
+        _check(lib().gs_local_step_debug(self._h, self._dev(x, (3, self.n)),
+                                         self._dev(a, (self.n_chambers,)) if self.n_chambers else None,
+                                         out.data_ptr()))
+        self.stream.synchronize()
+        return out
+
+    def oriented_tets(self):
+        t = np.zeros((4, self.T), np.int32)
+        _check(lib().gs_tets(self._h, _ptr(t, ctypes.c_int32)))
+        return t
+
+    def faces(self):
+        f = np.zeros((3, self.info["n_surface_faces"]), np.int32)
+        _check(lib().gs_faces(self._h, _ptr(f, ctypes.c_int32)))
+        return f
+
+    def collide(self, x, cap=None):
+        """One collision check at x with the stored set as the previous one."""
+        cap = int(cap or max(4 * self.info["n_query_verts"] * 8, 1024))
+        nbytes = lib().gs_collide_debug_scratch(cap)
+        scratch = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        ct, tr, co = np.zeros((2, cap), np.int32), np.zeros((2, cap), np.int32), np.zeros((3, cap), np.int32)
+        tg = np.zeros((3, cap))
+        nct, ntr, nco = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        code = lib().gs_collide_debug(self._h, self._dev(x, (3, self.n)), cap, scratch.data_ptr(), nbytes,
+                                      _ptr(ct, ctypes.c_int32), ctypes.byref(nct), _ptr(tr, ctypes.c_int32),
+                                      ctypes.byref(ntr), _ptr(co, ctypes.c_int32), _ptr(tg, ctypes.c_double),
+                                      ctypes.byref(nco))
+        if code == ECAPACITY:
+            return self.collide(x, cap=2 * max(cap, nct.value, ntr.value, nco.value))
+        _check(code)
+        a, b, k = nct.value, ntr.value, nco.value
+        return dict(cand_tet=ct[:, :a].T.copy(), cand_tri=tr[:, :b].T.copy(), contacts=co[:, :k].T.copy(),
+                    target=tg[:, :k].T.copy())

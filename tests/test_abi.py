@@ -1,0 +1,110 @@
+"""The C ABI without a GPU: exported symbols, host-side validation and the
+once-per-mesh set-up (orientation, boundary faces, query vertices, sizes),
+checked against the oracle's set-up."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2203_02054_amd import geosim as G
+from paper_2203_02054_amd import meshgen as mg
+import oracle
+from tests.meshes import voxel_box
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "geosim.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = G.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(G.SIGNATURES) == names
+    assert L.gs_version() == 100
+
+
+def _desc(m, precision=4):
+    keep = dict(X=np.ascontiguousarray(m["rest_xyz"], np.float64), T=np.ascontiguousarray(m["tets"], np.int32),
+                M=np.ascontiguousarray(m["tet_mode"], np.uint8), C=np.ascontiguousarray(m["tet_chamber"], np.int16),
+                F=np.ascontiguousarray(m["fixed"], np.uint8))
+    d = G.MeshDesc(keep["X"].shape[1], keep["T"].shape[1], int(m.get("n_chambers", 1)), precision,
+                   keep["X"].ctypes.data, keep["T"].ctypes.data, keep["M"].ctypes.data, keep["C"].ctypes.data,
+                   keep["F"].ctypes.data)
+    return d, keep
+
+
+def _create(m, **kw):
+    d, keep = _desc(m)
+    p = G.default_params(**kw)
+    h = ctypes.c_void_p()
+    code = G.lib().gs_create(ctypes.byref(d), ctypes.byref(p), ctypes.byref(h))
+    return code, h, keep
+
+
+def test_create_rejects_bad_input():
+    m = voxel_box(2, 1, 1)
+    bad = dict(m, tets=m["tets"].copy())
+    bad["tets"][0, 0] = 10_000
+    assert _create(bad)[0] == G.EINVAL
+    nan = dict(m, rest_xyz=m["rest_xyz"].copy())
+    nan["rest_xyz"][1, 3] = np.nan
+    assert _create(nan)[0] == G.EINVAL
+    flat = dict(m, rest_xyz=m["rest_xyz"].copy())
+    flat["rest_xyz"][2] = 0.0                      # every tet flat
+    assert _create(flat)[0] == G.EDEGENERATE
+    ch = dict(m, tet_mode=np.full(m["tets"].shape[1], G.CH_ISO, np.uint8))   # chamber id -1
+    assert _create(ch)[0] == G.EINVAL
+    assert _create(m, pcg_eta=0.0)[0] == G.EINVAL
+    assert _create(m, c1=-1.0)[0] == G.EINVAL
+    code, h, _ = _create(m)
+    assert code == G.OK
+    st = G.Stats()
+    assert G.lib().gs_solve(h, None, None, ctypes.byref(st)) == G.ESTATE       # not bound
+    sph = np.array([0.0, 0.0, 0.0, -1.0])
+    assert G.lib().gs_set_obstacles(h, 1, sph.ctypes.data_as(G._PD), 0, None) == G.EINVAL
+    pl = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    assert G.lib().gs_set_obstacles(h, 0, None, 1, pl.ctypes.data_as(G._PD)) == G.EINVAL
+    assert "normal" in G.lib().gs_last_error().decode()
+    G.lib().gs_destroy(h)
+
+
+@pytest.mark.parametrize("name", ["block", "finger_small"])
+def test_host_setup_matches_oracle(name):
+    wl = mg.make("block") if name == "block" else mg.finger(4.0, 3, 2.0)
+    prob = oracle.Problem.from_workload(wl)
+    m = dict(rest_xyz=wl.rest_xyz, tets=wl.tets, tet_mode=wl.tet_mode, tet_chamber=wl.tet_chamber,
+             fixed=wl.fixed, n_chambers=wl.n_chambers)
+    code, h, keep = _create(m)
+    assert code == G.OK
+    info = G.Info()
+    G.lib().gs_info_get(h, ctypes.byref(info))
+    assert info.n_tets == prob.T and info.n_verts == prob.n
+    assert info.n_surface_faces == prob.faces.shape[0]
+    assert info.n_surface_verts == prob.surf_verts.size
+    assert info.n_query_verts == prob.query_verts.size
+    assert info.h_ref == pytest.approx(prob.h_ref, rel=1e-12)
+    assert info.bbox_diag == pytest.approx(prob.diag, rel=1e-12)
+    assert info.eps_off == pytest.approx(prob.eps_off, rel=1e-12)
+    # Dirichlet-reduced CSR: free-free entries of A_el plus one diagonal per fixed row
+    F = prob.free
+    red = prob.A_el[F][:, F]
+    assert info.nnz == red.nnz + int(prob.fixed.sum())
+    t = np.zeros((4, prob.T), np.int32)
+    G.lib().gs_tets(h, t.ctypes.data_as(G._PI))
+    np.testing.assert_array_equal(t, prob.tets)
+    f = np.zeros((3, info.n_surface_faces), np.int32)
+    G.lib().gs_faces(h, f.ctypes.data_as(G._PI))
+    np.testing.assert_array_equal(f.T, prob.faces)
+    nb = ctypes.c_size_t()
+    G.lib().gs_workspace_size(h, ctypes.byref(nb))
+    assert nb.value > 0
+    G.lib().gs_destroy(h)

@@ -1,0 +1,274 @@
+"""GPU (HIP library through the C ABI) against the FP64 oracle.
+
+Bars: collision candidate and contact index sets bit-exact on identical FP32
+inputs; FP64 runs within 1e-9 of the bounding-box diagonal at matched
+iteration counts; FP32 converged positions within 1e-5 of the diagonal.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2203_02054_amd import meshgen as mg
+import oracle
+from oracle import solver as osolver
+from oracle.collision import Contacts
+from tests.meshes import voxel_box
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2203_02054_amd import geosim
+    geosim.lib()
+    return geosim
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _deformed(prob, seed=0, amp=0.15):
+    rng = np.random.default_rng(seed)
+    X = prob.X0
+    c = X.mean(axis=1, keepdims=True)
+    bend = 0.02 * (X[0:1] - c[0:1]) ** 2 / max(prob.diag, 1.0)
+    x = X + amp * prob.h_ref * rng.normal(size=X.shape)
+    x[2] += bend[0]
+    x[:, prob.fixed] = X[:, prob.fixed]
+    return x
+
+
+def _contacts_rows(prob, A):
+    rows, tg = A.listing(prob)
+    s, slot = np.nonzero(A.active)
+    return rows, tg, A.normal[s, slot]
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_local_step_matches_oracle(G, precision):
+    wl = mg.finger(3.0, 4, 2.0)
+    prob = oracle.Problem.from_workload(wl)
+    gp = G.Problem.from_workload(wl, precision=precision)
+    x = _deformed(prob, 1)
+    xr = x.astype(gp.np_dtype).astype(np.float64)
+    say("local step", precision, prob.T)
+    Tg = gp.local_step(gp.tensor(xr), gp.tensor(wl.alpha)).cpu().numpy().astype(np.float64)
+    Tg = np.transpose(Tg, (2, 0, 1))
+    To = oracle.local_step(prob, xr, wl.alpha)
+    err = np.abs(Tg - To).max() / prob.h_ref
+    say("  max |T_gpu - T_oracle| / h_ref =", err)
+    assert err < (1e-10 if precision == 8 else 2e-5)
+
+
+def test_collision_sets_bit_exact_on_identical_inputs(G):
+    wl = mg.finger(3.0, 4, 2.0)
+    prob = oracle.Problem.from_workload(wl)
+    # a deformed state with live contacts, from the oracle's own iteration
+    x, A, st = oracle.solve(prob, wl.alpha, fixed_iters=6)
+    assert A.count > 0
+    x32 = x.astype(np.float32)
+    x64 = x32.astype(np.float64)
+    gp = G.Problem.from_workload(wl, precision=4)
+    rows, tg, nr = _contacts_rows(prob, A)
+    gp.set_contacts(rows, tg, nr)
+    say("collide", prob.T, "contacts in", A.count)
+    got = gp.collide(gp.tensor(x32))
+    Ao, info = oracle.collide(prob, x64, A)
+    v, e = info["cand_tet"]
+    exp_tet = np.unique(np.stack([v, e], axis=1), axis=0)
+    np.testing.assert_array_equal(got["cand_tet"], exp_tet)
+    cv, cf = info["cand_tri"]
+    exp_tri = np.unique(np.stack([cv, cf], axis=1), axis=0) if cv.size else np.zeros((0, 2), np.int64)
+    np.testing.assert_array_equal(got["cand_tri"], exp_tri)
+    orows, otg = Ao.listing(prob)
+    np.testing.assert_array_equal(got["contacts"], orows)
+    # targets are continuous values: the bar is 1e-6 of the diagonal
+    np.testing.assert_allclose(got["target"], otg, rtol=0, atol=1e-6 * prob.diag)
+    say("  max target difference", np.abs(got["target"] - otg).max() if len(otg) else 0.0)
+    say("  tet candidates", len(exp_tet), "tri candidates", len(exp_tri), "contacts", len(orows))
+    # the stored set is untouched by the check
+    after = gp.contacts()
+    np.testing.assert_array_equal(after["rows"], rows)
+
+
+def test_fp64_block_matches_oracle_at_50_iterations(G):
+    wl = mg.make("block")
+    prob = oracle.Problem.from_workload(wl)
+    gp = G.Problem.from_workload(wl, precision=8, pcg_eta=1e-13, pcg_max=5000)
+    say("block fp64", prob.T)
+    xg, st = gp.solve(wl.alpha)
+    xo, _, sto = oracle.solve(prob, wl.alpha)
+    err = np.abs(xg.cpu().numpy() - xo).max() / prob.diag
+    say("  iters", st["iters"], "max err / diag", err, "energy", st["energy"], sto["energy"])
+    assert st["iters"] == 50
+    assert err < 1e-9
+    assert st["energy"] == pytest.approx(sto["energy"], rel=1e-8)
+
+
+def test_fp64_finger_with_self_collision_matches_oracle(G):
+    wl = mg.finger(4.0, 4, 2.0)
+    prob = oracle.Problem.from_workload(wl)
+    K = 40
+    gp = G.Problem.from_workload(wl, precision=8, pcg_eta=1e-13, pcg_max=5000, fixed_iters=K)
+    say("finger fp64 collision", prob.T)
+    xg, st = gp.solve(wl.alpha)
+    xo, Ao, sto = oracle.solve(prob, wl.alpha, fixed_iters=K)
+    err = np.abs(xg.cpu().numpy() - xo).max() / prob.diag
+    cg = gp.contacts()
+    orows, _ = Ao.listing(prob)
+    say("  max err / diag", err, "contacts", len(cg["rows"]), len(orows))
+    np.testing.assert_array_equal(cg["rows"], orows)
+    assert err < 1e-9
+
+
+def test_fp32_finger_matches_oracle_at_matched_iterations(G):
+    """FP32 kernels with a tight inner solve follow the FP64 oracle's trajectory."""
+    wl = mg.finger(4.0, 4, 2.0)
+    prob = oracle.Problem.from_workload(wl)
+    K = 150
+    gp = G.Problem.from_workload(wl, precision=4, pcg_eta=1e-7, pcg_max=3000, fixed_iters=K)
+    say("finger fp32 matched", prob.T)
+    xg, st = gp.solve(wl.alpha)
+    xo, Ao, sto = oracle.solve(prob, wl.alpha, fixed_iters=K)
+    err = np.abs(xg.cpu().numpy().astype(np.float64) - xo).max() / prob.diag
+    orows, _ = Ao.listing(prob)
+    say("  iters", st["iters"], "err/diag", err, "contacts", st["n_contacts"], len(orows))
+    np.testing.assert_array_equal(gp.contacts()["rows"], orows)
+    assert err < 1e-5
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "finger_h4_c4_fixed_point.npz")
+
+
+def _oracle_contacts(prob, cg):
+    A = Contacts.empty(prob.query_verts.size, prob.n_slots)
+    ns = prob.spheres.shape[0]
+    for (v, typ, prim), t, nrm in zip(cg["rows"], cg["target"], cg["normal"]):
+        si = int(np.searchsorted(prob.query_verts, v))
+        slot = 0 if typ == 0 else (1 + prim if typ == 1 else 1 + ns + prim)
+        A.active[si, slot] = True
+        A.target[si, slot] = t
+        A.normal[si, slot] = nrm
+        A.prim[si, slot] = prim
+    return A
+
+
+def test_fp32_finger_converges_to_the_oracle_fixed_point(G):
+    """FP32 kernels, inner solve tight enough to follow the oracle's path,
+    converged to r <= 2e-8: within 1e-5 of the diagonal of the oracle's fixed
+    point (stored, r <= 1e-11), with the same active set."""
+    g = np.load(GOLDEN)
+    wl = mg.finger(4.0, 4, 2.0)
+    prob = oracle.Problem.from_workload(wl)
+    say("finger fp32 converge (tight inner solve)", prob.T)
+    gp = G.Problem.from_workload(wl, precision=4, pcg_eta=1e-7, pcg_max=3000, tol=2e-8)
+    xt, st = gp.solve(wl.alpha)
+    err = np.abs(xt.cpu().numpy().astype(np.float64) - g["x"]).max() / prob.diag
+    say("  ", st, "err/diag vs fixed point", err)
+    assert st["status"] == G.OK
+    np.testing.assert_array_equal(gp.contacts()["rows"], g["contacts"])
+    assert err < 1e-5
+
+
+def test_fp32_default_solve_reaches_a_fixed_point_of_the_oracle_map(G):
+    """The default inexact (warm-started, eta = 1e-3) inner solve takes another
+    path; springs keep the targets they were created with (Eq. 8), so the
+    fixed point reached is the oracle's fixed point for the GPU's final active
+    set: iterating the oracle from the GPU result with that set moves it by
+    less than 1e-5 of the diagonal."""
+    wl = mg.finger(4.0, 4, 2.0)
+    prob = oracle.Problem.from_workload(wl)
+    gp = G.Problem.from_workload(wl, precision=4)
+    x6, st6 = gp.solve(wl.alpha)
+    say("  default tol 1e-6:", st6)
+    assert st6["status"] == G.OK
+    gp.reset_contacts()
+    gp.set_params(tol=2e-8)
+    xt, st = gp.solve(wl.alpha)
+    say("  tol 2e-8:", st)
+    assert st["status"] == G.OK
+    xg = xt.cpu().numpy().astype(np.float64)
+    A = _oracle_contacts(prob, gp.contacts())
+    xo, Ao, sto = oracle.solve(prob, wl.alpha, x0=xg, contacts0=A, tol=1e-11, max_iter=20000)
+    err = np.abs(xg - xo).max() / prob.diag
+    e6 = np.abs(x6.cpu().numpy().astype(np.float64) - xo).max() / prob.diag
+    say("  oracle from gpu state:", sto["iters"], "iterations; err/diag", err, "(tol 1e-6 result:", e6, ")")
+    assert sto["converged"] and Ao.same_set(A)
+    assert err < 1e-5
+
+
+def test_rest_state_and_closed_form_expansion(G):
+    wl = mg.make("block")
+    gp = G.Problem.from_workload(wl, precision=4, fixed_iters=0)
+    prob = oracle.Problem.from_workload(wl)
+    xg, st = gp.solve(np.ones(1))
+    assert st["iters"] == 1 and st["status"] == G.OK
+    assert np.abs(xg.cpu().numpy() - prob.X0).max() < 1e-6 * prob.diag
+    m = voxel_box(3, 2, 2, h=1.0, mode=mg.CH_ISO, chamber=0)
+    m["fixed"][5] = 1
+    gq = G.Problem(m["rest_xyz"], m["tets"], m["tet_mode"], m["tet_chamber"], m["fixed"], 1, precision=8,
+                   fixed_iters=1, pcg_eta=1e-14, pcg_max=1000)
+    alpha = 1.7
+    xg, _ = gq.solve(np.array([alpha]))
+    xf = m["rest_xyz"][:, 5:6]
+    np.testing.assert_allclose(xg.cpu().numpy(), xf + alpha ** (1 / 3) * (m["rest_xyz"] - xf), atol=1e-11)
+
+
+def test_solve_is_deterministic(G):
+    wl = mg.finger(4.0, 4, 2.0)
+    gp = G.Problem.from_workload(wl, precision=4)
+    x1, s1 = gp.solve(wl.alpha)
+    c1 = gp.contacts()
+    gp.reset_contacts()
+    x2, s2 = gp.solve(wl.alpha)
+    c2 = gp.contacts()
+    assert s1 == s2
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    np.testing.assert_array_equal(c1["rows"], c2["rows"])
+
+
+def test_full_finger_fixed_point_and_collision_sets(G):
+    """Full-size finger (26,880 tets) in the benchmark configuration: the FP32 GPU
+    result is a fixed point of the oracle's iteration, its collision sets match the
+    oracle's brute force bit for bit, and sampled local targets agree."""
+    wl = mg.make("finger")
+    prob = oracle.Problem.from_workload(wl)
+    gp = G.Problem.from_workload(wl, precision=4)
+    say("full finger fp32", prob.T)
+    xg_t, st = gp.solve(wl.alpha)
+    say("  ", st)
+    assert st["status"] == G.OK
+    xg = xg_t.cpu().numpy().astype(np.float64)
+    cg = gp.contacts()
+    # oracle's view of the GPU active set
+    A = Contacts.empty(prob.query_verts.size, prob.n_slots)
+    qidx = np.searchsorted(prob.query_verts, cg["rows"][:, 0])
+    A.active[qidx, 0] = True
+    A.target[qidx, 0] = cg["target"]
+    A.normal[qidx, 0] = cg["normal"]
+    A.prim[qidx, 0] = cg["rows"][:, 2]
+    # one oracle iteration from the GPU fixed point barely moves it
+    xn, A2, _, info = osolver.step(prob, xg, wl.alpha, A)
+    move = np.abs(xn - xg).max() / prob.diag
+    say("  oracle step from gpu x*: r =", info["r"], "max move/diag", move, "set changed", info["changed"])
+    assert move < 2e-5
+    # collision sets at the GPU positions, bit-exact
+    gp.set_contacts(cg["rows"], cg["target"], cg["normal"])
+    got = gp.collide(xg_t)
+    Ao, cinfo = oracle.collide(prob, xg, A)
+    v, e = cinfo["cand_tet"]
+    np.testing.assert_array_equal(got["cand_tet"], np.unique(np.stack([v, e], axis=1), axis=0))
+    orows, _ = Ao.listing(prob)
+    np.testing.assert_array_equal(got["contacts"], orows)
+    # sampled local targets at the GPU positions
+    Tg = np.transpose(gp.local_step(xg_t, gp.tensor(wl.alpha)).cpu().numpy().astype(np.float64), (2, 0, 1))
+    To = oracle.local_step(prob, xg, wl.alpha)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(prob.T, 2000, replace=False)
+    assert np.abs(Tg[idx] - To[idx]).max() / prob.h_ref < 2e-5
