@@ -21,27 +21,38 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
-def kernel_bytes(info, W, n_launch, pcg_iters, stats_per_step, steps):
-    """Algorithmic bytes per launch of each kernel (what the method must move).
+def kernel_bytes(info, W, n_launch, pcg_iters):
+    """Algorithmic bytes per launch of each kernel: the data the method must
+    move, each array element counted once per launch (W = 4 or 8 bytes per
+    real, int32 indices, collision positions in double).
 
-    Per-unit figures: positions W bytes per component, int32 indices.
-      local  : per tet, connectivity 16 + tag 4 + residual slot index 16 + four
-               residual columns written 4*4W; per vertex, X0 24 + u 3W read once.
-      pcg    : per inner iteration (W+4) nnz + 4 (n+1) + 36 W n (CSR once; p, q,
-               r, d, diagonal streams), plus 10 W n for the start-up pass.
-      gather : per vertex, residual slots read 4W * incidences + 3W written + 2W.
-      finish : per vertex, d read 3W, u read+written 6W, collision positions 24.
-      tet_query: per tet, connectivity 16 + positions of 4 vertices (24 each,
-               counted per vertex once: 24 n).
+      pcg        per CG iteration: per row the CG state (r, w, s: 3 vectors of
+                 4 reals) read and written, p and the correction read and
+                 written, the Jacobi diagonal; per off-diagonal entry its column
+                 and value.  Plus the two start-up passes and the end-of-iteration
+                 update (u read/written, correction read, collision positions
+                 written).
+      local      per tet connectivity 16, tag 4, residual slot index 16, residual
+                 columns written 4 x 4W; per vertex rest position 24 and
+                 displacement 3W read once.
+      gather     per incidence one residual column 4W; per vertex the
+                 incidence range 4, right-hand side 4W and two diagonals 2W.
+      tet_query  per tet connectivity 16; per vertex its collision position 24.
+      hash_insert per query vertex its id 4, position 24, entry written 32.
     """
     n, T, nnz = info["n_verts"], info["n_tets"], info["nnz"]
+    S = info["n_query_verts"]
+    off = nnz - n
     out = {}
-    out["local"] = T * (36 + 16 * W) + n * (24 + 3 * W)
     m = pcg_iters / max(n_launch.get("pcg", 1), 1)
-    out["pcg"] = m * ((W + 4) * nnz + 4 * (n + 1) + 36 * W * n) + 10 * W * n
-    out["gather"] = 4 * T * 4 * W + n * (4 + 5 * W)
-    out["finish"] = n * (9 * W + 24)
+    per_it = n * (12 * W * 2 + 8 * W + 8 * W + W) + off * (4 + W)
+    startup = n * (17 * W) + off * (4 + 2 * W) + n * (9 * W) + off * (4 + W)
+    finish = n * (3 * W + 4 * W + 24) + 4 * info["hash_buckets"]
+    out["pcg"] = m * per_it + startup + finish
+    out["local"] = T * (36 + 16 * W) + n * (24 + 3 * W)
+    out["gather"] = 4 * T * 4 * W + n * (4 + 6 * W)
     out["tet_query"] = 16 * T + 24 * n
+    out["hash_insert"] = S * 60
     return out
 
 
@@ -122,7 +133,7 @@ def main():
     pcg_iters = sum(s["pcg_iters_total"] for s in stats)
     value = wl.n_tets * iters / (ms / 1e3)
     n_launch = {k: v[1] for k, v in prof.items()}
-    kb = kernel_bytes(gp.info, W, n_launch, pcg_iters, stats, a.steps)
+    kb = kernel_bytes(gp.info, W, n_launch, pcg_iters)
     dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
     avg_ms = prof[dom][0] / prof[dom][1]
     roof = None

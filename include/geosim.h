@@ -235,8 +235,9 @@ gs_status gs_trace(gs_problem* p, int32_t cap, double* rows, int32_t* count);
  * kernel that gs_solve launches with a pair of HIP events on the bound
  * stream; gs_profile_read returns, per kernel id k < GS_N_KERNELS, the summed
  * duration in milliseconds and the number of launches; gs_kernel_name(k)
- * names the kernel ("pcg", "local", ...).  gs_profile(p, 0) stops. */
-#define GS_N_KERNELS 11
+ * names the kernel ("pcg", "local", ...); the CG kernel also applies the
+ * correction and takes the convergence decision.  gs_profile(p, 0) stops. */
+#define GS_N_KERNELS 7
 gs_status gs_profile(gs_problem* p, int32_t enable);
 gs_status gs_profile_read(const gs_problem* p, double* ms, int64_t* launches);
 const char* gs_kernel_name(int32_t k);

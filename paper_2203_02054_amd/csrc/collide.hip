@@ -1,8 +1,8 @@
 // Collision detection and response (Sections II-B, II-C, III-A.3).
 //
 // Broadphase: a spatial hash of the query vertices (non-fixed boundary
-// vertices), one cell per vertex, rebuilt every iteration by a counting sort
-// (Teschner et al. 2003).  Each tet visits the cells its min/max box covers and
+// vertices), one cell per vertex, rebuilt every iteration (Teschner et al.
+// 2003) into fixed-capacity buckets with an overflow list.  Each tet visits the cells its min/max box covers and
 // tests the vertices found there exactly: the candidate set is
 // C_tet = {(v, e): v not in e, lo_e <= x_v <= hi_e}, the same set a brute-force
 // or BVH search yields, because the cell map is monotone in x.
@@ -20,87 +20,37 @@
 
 namespace gs {
 
+// Insert every query vertex into the bucket of its cell.  A bucket keeps its
+// first kHashCap entries; further entries go to an overflow list that every
+// tet scans, so no candidate is ever lost.  Entries carry the position, so a
+// candidate costs one 32-byte read.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_hash_count(Dev<R> d, Consts c) {
+__global__ __launch_bounds__(kBlock) void k_hash_insert(Dev<R> d, Consts c) {
   if (is_done(d.st)) return;
   const int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= c.S) return;
-  const int v = d.qverts[s];
-  const int ix = cell_of(d.xc[v], c.inv_cell);
-  const int iy = cell_of(d.xc[(size_t)c.n + v], c.inv_cell);
-  const int iz = cell_of(d.xc[2 * (size_t)c.n + v], c.inv_cell);
-  const int key = hash_cell(ix, iy, iz, c.H);
-  d.qkey[s] = key;
-  atomicAdd(&d.hcount[key], 1);
-}
-
-// Exclusive scan of the bucket counts (one block); zeroes the counts so that
-// the fill pass can reuse them as cursors.
-constexpr int kScanBlock = 1024;
-template <typename R>
-__global__ __launch_bounds__(kScanBlock) void k_hash_scan(Dev<R> d, Consts c) {
-  __shared__ int wsum[kScanBlock / 64];
-  if (is_done(d.st)) return;
-  const int H = c.H;
-  const int per = (H + kScanBlock - 1) / kScanBlock;
-  const int lo = threadIdx.x * per;
-  const int hi = min(H, lo + per);
-  int acc = 0;
-#pragma unroll 8
-  for (int i = lo; i < hi; ++i) acc += d.hcount[i];
-  // inclusive scan of the per-thread sums: within each wavefront, then across
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int incl = acc;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += t;
-  }
-  if (lane == 63) wsum[wv] = incl;
-  __syncthreads();
-  if (wv == 0) {
-    int t = (lane < kScanBlock / 64) ? wsum[lane] : 0;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int u = __shfl_up(t, off, 64);
-      if (lane >= off) t += u;
-    }
-    if (lane < kScanBlock / 64) wsum[lane] = t;
-  }
-  __syncthreads();
-  int run = incl - acc + (wv > 0 ? wsum[wv - 1] : 0);
-#pragma unroll 8
-  for (int i = lo; i < hi; ++i) {
-    const int cnt = d.hcount[i];
-    d.hstart[i] = run;
-    d.hcount[i] = 0;
-    run += cnt;
-  }
-  if (threadIdx.x == kScanBlock - 1) d.hstart[H] = run;
-}
-
-// Entries carry the vertex position (x, y, z) and the query index, so the
-// tet query reads one 32-byte record per candidate.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_hash_fill(Dev<R> d, Consts c) {
-  if (is_done(d.st)) return;
-  const int s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= c.S) return;
-  const int key = d.qkey[s];
-  const int pos = d.hstart[key] + atomicAdd(&d.hcount[key], 1);
   const int v = d.qverts[s];
   double4 e;
   e.x = d.xc[v];
   e.y = d.xc[(size_t)c.n + v];
   e.z = d.xc[2 * (size_t)c.n + v];
   e.w = __longlong_as_double((long long)s);
-  reinterpret_cast<double4*>(d.hent)[pos] = e;
+  const int key = hash_cell(cell_of(e.x, c.inv_cell), cell_of(e.y, c.inv_cell), cell_of(e.z, c.inv_cell), c.H);
+  const int slot = atomicAdd(&d.hcount[key], 1);
+  if (slot < kHashCap) {
+    reinterpret_cast<double4*>(d.hslot)[(size_t)key * kHashCap + slot] = e;
+  } else {
+    const int o = atomicAdd(&d.st->n_over, 1);
+    reinterpret_cast<double4*>(d.hover)[o] = e;
+  }
 }
 
 template <typename R, bool DEBUG>
-__device__ __forceinline__ void test_point(const Dev<R>& d, int s, const double (&q)[3], int e, const int (&vi)[4],
+__device__ __forceinline__ void test_point(const Dev<R>& d, const double4& en, int e, const int (&vi)[4],
                                           const double (&p)[4][3], const double (&lo)[3], const double (&hi)[3]) {
+  const double q[3] = {en.x, en.y, en.z};
   if (!(lo[0] <= q[0] && q[0] <= hi[0] && lo[1] <= q[1] && q[1] <= hi[1] && lo[2] <= q[2] && q[2] <= hi[2])) return;
+  const int s = (int)__double_as_longlong(en.w);
   const int v = d.qverts[s];
   if (v == vi[0] || v == vi[1] || v == vi[2] || v == vi[3]) return;
   if (DEBUG) {
@@ -110,7 +60,10 @@ __device__ __forceinline__ void test_point(const Dev<R>& d, int s, const double 
       d.dbg_tet[d.dbg_cap + k] = e;
     }
   }
-  if (point_in_tet(q, p[0], p[1], p[2], p[3])) d.pen[s] = 1;
+  if (point_in_tet(q, p[0], p[1], p[2], p[3])) {
+    // the first tet to find the vertex inside lists it for the ray cast
+    if (atomicOr(&d.pen[s], 1) == 0) d.penlist[atomicAdd(&d.st->n_pen, 1)] = s;
+  }
 }
 
 template <typename R, bool DEBUG>
@@ -137,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
     finite = finite && isfinite(lo[k]) && isfinite(hi[k]) && fabs(lo[k] * c.inv_cell) < 1e9 &&
              fabs(hi[k] * c.inv_cell) < 1e9;
   }
-  if (!finite) return;  // a diverged iterate: no candidates (the finish step reports the breakdown)
+  if (!finite) return;  // a diverged iterate: no candidates (the CG reports the breakdown)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     clo[k] = cell_of(lo[k], c.inv_cell);
@@ -145,38 +98,54 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
     const long ext = (long)chi[k] - (long)clo[k] + 1;
     ncell = (ext > kCellCap || ncell > kCellCap) ? (long)kCellCap + 1 : ncell * ext;
   }
+  const double4* slots = reinterpret_cast<const double4*>(d.hslot);
   if (ncell > kCellCap) {
     // a tet stretched over many cells: test every query vertex (still exact)
     for (int s = 0; s < c.S; ++s) {
       const int v = d.qverts[s];
-      const double q[3] = {d.xc[v], d.xc[(size_t)c.n + v], d.xc[2 * (size_t)c.n + v]};
-      test_point<R, DEBUG>(d, s, q, e, vi, p, lo, hi);
+      double4 en;
+      en.x = d.xc[v];
+      en.y = d.xc[(size_t)c.n + v];
+      en.z = d.xc[2 * (size_t)c.n + v];
+      en.w = __longlong_as_double((long long)s);
+      test_point<R, DEBUG>(d, en, e, vi, p, lo, hi);
     }
     return;
   }
-  const double4* ent = reinterpret_cast<const double4*>(d.hent);
-  for (int ix = clo[0]; ix <= chi[0]; ++ix)
-    for (int iy = clo[1]; iy <= chi[1]; ++iy)
-      for (int iz = clo[2]; iz <= chi[2]; ++iz) {
-        const int key = hash_cell(ix, iy, iz, c.H);
-        const int b0 = d.hstart[key], b1 = d.hstart[key + 1];
-        for (int i = b0; i < b1; ++i) {
-          const double4 en = ent[i];
-          const double q[3] = {en.x, en.y, en.z};
-          test_point<R, DEBUG>(d, (int)__double_as_longlong(en.w), q, e, vi, p, lo, hi);
+  const bool small = (chi[0] - clo[0] <= 1) && (chi[1] - clo[1] <= 1) && (chi[2] - clo[2] <= 1);
+  if (small) {
+    // common case (at most 2 cells per axis): bucket counts and first entries
+    // of all cells are fetched in one round trip
+    int keys[8], cnt[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int ix = clo[0] + (k & 1), iy = clo[1] + ((k >> 1) & 1), iz = clo[2] + ((k >> 2) & 1);
+      const bool ok = ix <= chi[0] && iy <= chi[1] && iz <= chi[2];
+      keys[k] = ok ? hash_cell(ix, iy, iz, c.H) : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cnt[k] = (keys[k] >= 0) ? min(d.hcount[keys[k]], kHashCap) : 0;
+    double4 e0[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (cnt[k] > 0) e0[k] = slots[(size_t)keys[k] * kHashCap];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (cnt[k] > 0) test_point<R, DEBUG>(d, e0[k], e, vi, p, lo, hi);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      for (int i = 1; i < cnt[k]; ++i) test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, vi, p, lo, hi);
+  } else {
+    for (int ix = clo[0]; ix <= chi[0]; ++ix)
+      for (int iy = clo[1]; iy <= chi[1]; ++iy)
+        for (int iz = clo[2]; iz <= chi[2]; ++iz) {
+          const int key = hash_cell(ix, iy, iz, c.H);
+          const int cn = min(d.hcount[key], kHashCap);
+          for (int i = 0; i < cn; ++i) test_point<R, DEBUG>(d, slots[(size_t)key * kHashCap + i], e, vi, p, lo, hi);
         }
-      }
-}
-
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_pen_compact(Dev<R> d, Consts c) {
-  if (is_done(d.st)) return;
-  const int s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= c.S) return;
-  if (d.pen[s]) {
-    const int k = atomicAdd(&d.st->n_pen, 1);
-    d.penlist[k] = s;
   }
+  const int nover = __hip_atomic_load(&d.st->n_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = 0; i < nover; ++i) test_point<R, DEBUG>(d, reinterpret_cast<const double4*>(d.hover)[i], e, vi, p, lo, hi);
 }
 
 __device__ __forceinline__ void load3(const double* xc, size_t n, int v, double* o) {
@@ -405,23 +374,14 @@ template <typename R>
 hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s) {
   const int gs = cdiv(c.S, kBlock), gt = cdiv(c.T, kBlock);
   switch (stage) {
-    case STAGE_HASH_COUNT:
-      k_hash_count<R><<<gs, kBlock, 0, s>>>(d, c);
-      break;
-    case STAGE_HASH_SCAN:
-      k_hash_scan<R><<<1, kScanBlock, 0, s>>>(d, c);
-      break;
-    case STAGE_HASH_FILL:
-      k_hash_fill<R><<<gs, kBlock, 0, s>>>(d, c);
+    case STAGE_HASH_INSERT:
+      k_hash_insert<R><<<gs, kBlock, 0, s>>>(d, c);
       break;
     case STAGE_TET_QUERY:
       if (debug)
         k_tet_query<R, true><<<gt, kBlock, 0, s>>>(d, c);
       else
         k_tet_query<R, false><<<gt, kBlock, 0, s>>>(d, c);
-      break;
-    case STAGE_PEN_COMPACT:
-      k_pen_compact<R><<<gs, kBlock, 0, s>>>(d, c);
       break;
     case STAGE_RAY: {
       // one wavefront per penetrating vertex on the first pass (up to 8192)

@@ -49,16 +49,15 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   size_t X0, tets, tag, inc_start, inc_pos, ell_col, ell_val, ell_scaled, adiag, freem, faces, qverts, vq, qf_start, qf_list, kq,
       obst;
-  size_t u, xc, res4, r, w, s, dl, p, dg, dsp, pen, hcount, hstart, hent, qkey, penlist, fhit, fc, fn, cact, ctgt,
-      cnrm, cprim, part_a, part_b, part_c, part_d, part_e, st, trace;
+  size_t u, xc, res4, cg, dl, p, dg, dsp, pen, hcount, hslot, hover, penlist, fhit, fc, fn, cact, ctgt, cnrm,
+      cprim, part_a, part_b, part_c, part_d, part_e, part_f, st, trace;
   size_t total;
 };
 
-constexpr int kNKernels = 11;
-const char* const kKernelNames[kNKernels] = {"hash_count", "hash_scan", "hash_fill", "tet_query", "pen_compact",
-                                             "ray_cast",   "contacts",  "local",     "gather",    "pcg",
-                                             "finish"};
-enum { K_CONTACTS = 6, K_LOCAL = 7, K_GATHER = 8, K_PCG = 9, K_FINISH = 10 };
+constexpr int kNKernels = 7;
+const char* const kKernelNames[kNKernels] = {"hash_insert", "tet_query", "ray_cast", "contacts",
+                                             "local",       "gather",    "pcg"};
+enum { K_CONTACTS = 3, K_LOCAL = 4, K_GATHER = 5, K_PCG = 6 };
 
 // Optional per-kernel timing: each launch is bracketed by two events on the
 // bound stream; elapsed times are collected whenever the driver synchronises.
@@ -175,18 +174,15 @@ Layout make_layout(const gs_problem* p) {
   L.u = take(3 * n * W);
   L.xc = take(3 * n * 8);
   L.res4 = take(4 * T * 4 * W);
-  L.r = take(6 * n * W);
-  L.w = take(6 * n * W);
-  L.s = take(6 * n * W);
-  L.dl = take(3 * n * W);
-  L.p = take(3 * n * W);
+  L.cg = take(24 * n * W);
+  L.dl = take(4 * n * W);
+  L.p = take(4 * n * W);
   L.dg = take(n * W);
   L.dsp = take(n * W);
-  L.pen = take(S);
+  L.pen = take(S * 4);
   L.hcount = take(H * 4);
-  L.hstart = take((H + 1) * 4);
-  L.hent = take(S * 32);
-  L.qkey = take(S * 4);
+  L.hslot = take(H * kHashCap * 32);
+  L.hover = take(S * 32);
   L.penlist = take(S * 4);
   L.fhit = take(S * 4);
   L.fc = take(3 * S * 8);
@@ -200,6 +196,7 @@ Layout make_layout(const gs_problem* p) {
   L.part_c = take((size_t)p->nparts * 8);
   L.part_d = take((size_t)p->nparts * 8);
   L.part_e = take((size_t)p->nparts * 8);
+  L.part_f = take((size_t)p->nparts * 8);
   L.st = take(sizeof(DevStatus));
   L.trace = take((size_t)p->trace_len * 6 * 8);
   L.total = align256(off);
@@ -231,18 +228,15 @@ Dev<R> make_dev(const gs_problem* p) {
   d.u = (R*)(b + L.u);
   d.xc = (double*)(b + L.xc);
   d.res4 = (R*)(b + L.res4);
-  d.r = (R*)(b + L.r);
-  d.w = (R*)(b + L.w);
-  d.s = (R*)(b + L.s);
+  d.cg = (R*)(b + L.cg);
   d.dl = (R*)(b + L.dl);
   d.p = (R*)(b + L.p);
   d.dg = (R*)(b + L.dg);
   d.dsp = (R*)(b + L.dsp);
-  d.pen = (uint8_t*)(b + L.pen);
+  d.pen = (int32_t*)(b + L.pen);
   d.hcount = (int32_t*)(b + L.hcount);
-  d.hstart = (int32_t*)(b + L.hstart);
-  d.hent = (double*)(b + L.hent);
-  d.qkey = (int32_t*)(b + L.qkey);
+  d.hslot = (double*)(b + L.hslot);
+  d.hover = (double*)(b + L.hover);
   d.penlist = (int32_t*)(b + L.penlist);
   d.fhit = (int32_t*)(b + L.fhit);
   d.fc = (double*)(b + L.fc);
@@ -256,6 +250,7 @@ Dev<R> make_dev(const gs_problem* p) {
   d.part_c = (double*)(b + L.part_c);
   d.part_d = (double*)(b + L.part_d);
   d.part_e = (double*)(b + L.part_e);
+  d.part_f = (double*)(b + L.part_f);
   d.st = (DevStatus*)(b + L.st);
   d.trace = (double*)(b + L.trace);
   d.dbg_tet = nullptr;
@@ -340,7 +335,7 @@ gs_status bind_impl(gs_problem* p) {
   HIPCHK(hipMemsetAsync(b + L.cact, 0, (size_t)p->S * p->slots, s));
   HIPCHK(hipMemsetAsync(b + L.st, 0, sizeof(DevStatus), s));
   HIPCHK(hipMemsetAsync(b + L.hcount, 0, (size_t)p->H * 4, s));
-  HIPCHK(hipMemsetAsync(b + L.pen, 0, (size_t)std::max(p->S, 1), s));
+  HIPCHK(hipMemsetAsync(b + L.pen, 0, (size_t)std::max(p->S, 1) * 4, s));
   HIPCHK(hipStreamSynchronize(s));
   const int maxg = pcg_max_grid<R>(0);
   if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
@@ -371,8 +366,7 @@ hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, co
   }
   if ((e = timed(p, K_LOCAL, [&] { return launch_local<R>(d, c, alpha, s); })) != hipSuccess) return e;
   if ((e = timed(p, K_GATHER, [&] { return launch_gather<R>(d, c, s); })) != hipSuccess) return e;
-  if ((e = timed(p, K_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s); })) != hipSuccess) return e;
-  return timed(p, K_FINISH, [&] { return launch_finish<R>(d, c, s); });
+  return timed(p, K_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s); });
 }
 
 template <typename R>

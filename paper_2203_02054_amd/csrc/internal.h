@@ -10,6 +10,7 @@ namespace gs {
 
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
 constexpr int kCellCap = 64;         // hash cells a tet box may span before the brute-force path
+constexpr int kHashCap = 8;          // entries stored in a hash bucket before the overflow list
 constexpr int kMaxSlots = 1 + 8 + 8; // self + spheres + planes
 constexpr int kPcgThreads = 512;     // threads per block of the cooperative CG kernel
 constexpr int kMaxPcgGrid = 64;      // workgroups of the cooperative CG kernel at most
@@ -29,6 +30,7 @@ struct DevStatus {
   int n_contacts;       // active springs (current iteration)
   int n_contacts_last;
   int cand_tet, cand_tri;  // debug candidate counters
+  int n_over;           // hash entries in the overflow list (current iteration)
   int pcg_last;         // inner iterations of the last outer iteration
   int changed_last;
   double residual;      // r_k of the last completed iteration
@@ -72,19 +74,17 @@ struct Dev {
   R* u;                    // [3][n] displacement from X0
   double* xc;              // [3][n] X0 + u in double (collision positions)
   R* res4;                 // [4T][4] element residual columns in incidence order
-  R* r;                    // [2][3][n] right-hand side / CG residual (two buffers)
-  R* w;                    // [2][3][n] CG: A M^-1 r (two buffers)
-  R* s;                    // [2][3][n] CG: A p (two buffers)
-  R* dl;                   // [3][n] correction (kept across iterations: the warm start)
-  R* p;                    // [3][n]
+  R* cg;                   // [2][n][3][4] CG state per row, two buffers: r, w = A M^-1 r, s = A p
+                           //   (each as x, y, z, pad); buffer 0 holds the right-hand side on entry
+  R* dl;                   // [n][4] correction (kept across iterations: the warm start)
+  R* p;                    // [n][4]
   R* dg;                   // [n] Jacobi diagonal
   R* dsp;                  // [n] spring diagonal
-  uint8_t* pen;            // [S]
-  int32_t* hcount;         // [H]
-  int32_t* hstart;         // [H+1]
-  double* hent;            // [S][4] (x, y, z, query index as bits)
-  int32_t* qkey;           // [S]
-  int32_t* penlist;        // [S]
+  int32_t* pen;            // [S] penetration flag of each query vertex (this iteration)
+  int32_t* hcount;         // [H] entries inserted per bucket (may exceed kHashCap)
+  double* hslot;           // [H][kHashCap][4] bucket entries (x, y, z, query index as bits)
+  double* hover;           // [S][4] entries of full buckets (scanned by every tet)
+  int32_t* penlist;        // [S] penetrating query vertices (unordered)
   int32_t* fhit;           // [S] fresh self hit face or -1
   double* fc;              // [S][3] fresh self target
   double* fn;              // [S][3] fresh self normal
@@ -97,6 +97,7 @@ struct Dev {
   double* part_c;
   double* part_d;
   double* part_e;
+  double* part_f;
   DevStatus* st;
   double* trace;           // [trace_len][6]
   // debug candidate buffers (null outside gs_collide_debug)
@@ -110,8 +111,7 @@ struct Dev {
 template <typename R> hipError_t launch_init(const Dev<R>& d, const Consts& c, const R* xin, hipStream_t s);
 template <typename R> hipError_t launch_output(const Dev<R>& d, const Consts& c, R* xout, hipStream_t s);
 // collision stages, in launch order
-enum { STAGE_HASH_COUNT = 0, STAGE_HASH_SCAN, STAGE_HASH_FILL, STAGE_TET_QUERY, STAGE_PEN_COMPACT, STAGE_RAY,
-       N_COLLIDE_STAGES };
+enum { STAGE_HASH_INSERT = 0, STAGE_TET_QUERY, STAGE_RAY, N_COLLIDE_STAGES };
 template <typename R>
 hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s);
 template <typename R> hipError_t launch_contacts(const Dev<R>& d, const Consts& c, hipStream_t s);
@@ -120,7 +120,6 @@ template <typename R> hipError_t launch_local_debug(const Dev<R>& d, const Const
                                                     R* targets, hipStream_t s);
 template <typename R> hipError_t launch_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s);
-template <typename R> hipError_t launch_finish(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_set_positions(const Dev<R>& d, const Consts& c, const R* x, hipStream_t s);
 template <typename R> int pcg_max_grid(int block);
 

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
       const R uu = fr ? (R)((double)xin[k * n + v] - X) : R(0);
       d.u[k * n + v] = uu;
       d.xc[k * n + v] = X + (double)uu;
-      d.dl[k * n + v] = R(0);
+      d.dl[4 * (size_t)v + k] = R(0);
     }
   }
   const int stride = gridDim.x * kBlock;
@@ -57,6 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
     st->ray_miss = 0;
     st->ray_miss_last = 0;
     st->n_pen = 0;
+    st->n_over = 0;
     st->ticket = 0;
     st->n_contacts = 0;
     st->n_contacts_last = 0;
@@ -89,6 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_set_positions(Dev<R> d, Consts c, co
     st->changed = 0;
     st->ray_miss = 0;
     st->n_pen = 0;
+    st->n_over = 0;
     st->n_contacts = 0;
     st->cand_tet = 0;
     st->cand_tri = 0;
@@ -144,9 +146,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(Dev<R> d, Consts c) {
         }
       }
     }
-    d.r[v] = (R)r0;
-    d.r[n + v] = (R)r1;
-    d.r[2 * n + v] = (R)r2;
+    W4<R> rb;
+    rb.x = (R)r0;
+    rb.y = (R)r1;
+    rb.z = (R)r2;
+    rb.w = R(0);
+    reinterpret_cast<W4<R>*>(d.cg)[3 * (size_t)v] = rb;
     d.dsp[v] = (R)ds;
     d.dg[v] = d.freem[v] ? (R)((double)d.adiag[v] + ds) : R(1);
   }
@@ -156,245 +161,77 @@ __global__ __launch_bounds__(kBlock) void k_gather(Dev<R> d, Consts c) {
 
 constexpr int kPcgBlock = kPcgThreads;
 
-// Sum of the G <= 64 block partials: one wavefront, fixed shuffle tree (every
-// block obtains the same bits).
-__device__ __forceinline__ double grid_sum(const double* part, int G, double* sh) {
-  if (threadIdx.x < 64) {
-    double t = (threadIdx.x < G) ? part[threadIdx.x] : 0.0;
+// Sums of the G <= 64 block partials of two arrays in one round trip: wave 0
+// reduces `a`, wave 1 reduces `b`, each with a fixed shuffle tree (every block
+// obtains the same bits).
+__device__ __forceinline__ void grid_sum2(const double* a, const double* b, int G, double* sh, double& ra,
+                                          double& rb) {
+  if (threadIdx.x < 128) {
+    const double* src = threadIdx.x < 64 ? a : b;
+    const int l = threadIdx.x & 63;
+    double t = (l < G) ? src[l] : 0.0;
     t = wave_sum(t);
-    if (threadIdx.x == 0) sh[0] = t;
+    if (l == 0) sh[threadIdx.x >> 6] = t;
   }
   __syncthreads();
-  const double t = sh[0];
+  ra = sh[0];
+  rb = sh[1];
   __syncthreads();
-  return t;
+}
+
+template <typename R>
+__device__ __forceinline__ W4<R> w4(R x, R y, R z) {
+  W4<R> o;
+  o.x = x;
+  o.y = y;
+  o.z = z;
+  o.w = R(0);
+  return o;
 }
 
 // Preconditioned conjugate gradient in the Chronopoulos-Gear arrangement:
 // both inner products of an iteration are taken after its single
 // matrix-vector product, so one grid-wide reduction (one barrier) per
-// iteration suffices.  The product w_{i+1} = A M^-1 r_{i+1} needs
-// r_{i+1} at neighbouring rows; each block recomputes those values from the
-// neighbours' previous state (r_i, w_i, s_{i-1}, kept in the other half of a
-// double buffer) instead of waiting for a second barrier.
+// iteration suffices.  The product w_{i+1} = A M^-1 r_{i+1} needs r_{i+1} at
+// neighbouring rows; each block rebuilds those values from the neighbours'
+// previous state (r_i, w_i, s_{i-1}: three 16-byte vectors per row, in the
+// other half of a double buffer) instead of waiting for a second barrier.
 //
 //   p_i = u_i + b_i p_{i-1}        s_i = w_i + b_i s_{i-1}      (s_i = A p_i)
 //   x_{i+1} = x_i + a_i p_i        r_{i+1} = r_i - a_i s_i      u = M^-1 r
 //   w_{i+1} = A u_{i+1}            g = (r, u), d = (w, u)
 //   b_{i+1} = g_{i+1} / g_i        a_{i+1} = g_{i+1} / (d_{i+1} - b_{i+1} g_{i+1} / a_i)
-template <typename R, int MW>
-__global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
-  __shared__ double lds[kPcgBlock / 64];
-  __shared__ double sh[1];
-  if (is_done(d.st)) return;
-  const int G = gridDim.x;
-  const int stride = G * kPcgBlock;
-  const int tid0 = blockIdx.x * kPcgBlock + threadIdx.x;
-  const size_t n = (size_t)c.n;
-  const size_t n3 = 3 * n;
-  unsigned* bc = &d.st->bar_count;
-  unsigned* bg = &d.st->bar_gen;
-  R* __restrict__ x = d.dl;
-  R* __restrict__ p = d.p;
-  const R* __restrict__ dg = d.dg;
-  const int32_t* __restrict__ ecol = d.ell_col;
-  const R* __restrict__ evl = d.ell_val;
-
-  // (A) r_0 = b - A x_0 with the warm start x_0 = previous correction;
-  //     p_{-1} = s_{-1} = 0; right-hand-side norm b' M^-1 b
-  double acc_b = 0.0;
-  {
-    R* r0 = d.r;
-    R* s0 = d.s;
-    R* __restrict__ evs = d.ell_scaled;
-    for (int v = tid0; v < c.n; v += stride) {
-      const R dv = dg[v], idg = R(1) / dv;
-      int jj[MW];
-      R aa[MW];
-#pragma unroll
-      for (int k = 0; k < MW; ++k) {
-        jj[k] = ecol[(size_t)k * n + v];
-        aa[k] = evl[(size_t)k * n + v];
-      }
-      R ax0 = dv * x[v], ax1 = dv * x[n + v], ax2 = dv * x[2 * n + v];
-#pragma unroll
-      for (int k = 0; k < MW; ++k) {
-        const int j = jj[k];
-        ax0 += aa[k] * x[j];
-        ax1 += aa[k] * x[n + j];
-        ax2 += aa[k] * x[2 * n + j];
-        evs[(size_t)k * n + v] = aa[k] / dg[j];  // a_vj / dg_j, fixed during this solve
-      }
-      const R ax[3] = {ax0, ax1, ax2};
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const R b = r0[k * n + v];
-        acc_b += (double)b * (double)(b * idg);
-        r0[k * n + v] = b - ax[k];
-        p[k * n + v] = R(0);
-        s0[k * n + v] = R(0);
-      }
-    }
-  }
-  double bs = block_sum<kPcgBlock>(acc_b, lds);
-  if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
-  grid_barrier(bc, bg, G);
-  // (B) w_0 = A u_0, g_0 = (r_0, u_0), d_0 = (w_0, u_0)
-  double acc_g = 0.0, acc_d = 0.0;
-  {
-    const R* r0 = d.r;
-    R* w0 = d.w;
-    for (int v = tid0; v < c.n; v += stride) {
-      const R dv = dg[v], idg = R(1) / dv;
-      const R u0 = r0[v] * idg, u1 = r0[n + v] * idg, u2 = r0[2 * n + v] * idg;
-      R a0 = dv * u0, a1 = dv * u1, a2 = dv * u2;
-      int jj[MW];
-      R aa[MW];
-#pragma unroll
-      for (int k = 0; k < MW; ++k) {
-        jj[k] = ecol[(size_t)k * n + v];
-        aa[k] = d.ell_scaled[(size_t)k * n + v];
-      }
-#pragma unroll
-      for (int k = 0; k < MW; ++k) {
-        const int j = jj[k];
-        a0 += aa[k] * r0[j];
-        a1 += aa[k] * r0[n + j];
-        a2 += aa[k] * r0[2 * n + j];
-      }
-      w0[v] = a0;
-      w0[n + v] = a1;
-      w0[2 * n + v] = a2;
-      acc_g += (double)r0[v] * u0 + (double)r0[n + v] * u1 + (double)r0[2 * n + v] * u2;
-      acc_d += (double)a0 * u0 + (double)a1 * u1 + (double)a2 * u2;
-    }
-  }
-  bs = block_sum<kPcgBlock>(acc_g, lds);
-  if (threadIdx.x == 0) d.part_c[blockIdx.x] = bs;
-  bs = block_sum<kPcgBlock>(acc_d, lds);
-  if (threadIdx.x == 0) d.part_e[blockIdx.x] = bs;
-  grid_barrier(bc, bg, G);
-  const double rhs = grid_sum(d.part_d, G, sh);
-  double gam = grid_sum(d.part_c, G, sh);
-  const double del = grid_sum(d.part_e, G, sh);
-  const double stop = c.pcg_eta * c.pcg_eta * rhs;
-  int it = 0;
-  bool broke = !(rhs >= 0.0) || isinf(rhs) || !(gam >= 0.0) || isinf(gam);
-  bool run = !broke && gam > stop;
-  if (run && !(del > 0.0 && !isinf(del))) {
-    broke = true;
-    run = false;
-  }
-  double al = run ? gam / del : 0.0, be = 0.0;
-  int cur = 0;
-  while (run && it < c.pcg_max) {
-    const R* rc = d.r + cur * n3;
-    const R* wc = d.w + cur * n3;
-    const R* sc = d.s + cur * n3;
-    R* rn = d.r + (cur ^ 1) * n3;
-    R* wn = d.w + (cur ^ 1) * n3;
-    R* sn = d.s + (cur ^ 1) * n3;
-    const R ra = (R)al, rb = (R)be;
-    acc_g = 0.0;
-    acc_d = 0.0;
-    for (int v = tid0; v < c.n; v += stride) {
-      const R dv = dg[v], idg = R(1) / dv;
-      R rv[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const size_t o = k * n + v;
-        const R pv = rc[o] * idg + rb * p[o];
-        p[o] = pv;
-        const R sv = wc[o] + rb * sc[o];
-        sn[o] = sv;
-        x[o] += ra * pv;
-        rv[k] = rc[o] - ra * sv;
-        rn[o] = rv[k];
-      }
-      // w_{i+1} at this row from neighbours' r_{i+1}, rebuilt from their state
-      R a0 = rv[0], a1 = rv[1], a2 = rv[2];  // dg_v * (r_v / dg_v)
-      int jj[MW];
-      R aa[MW];
-#pragma unroll
-      for (int k = 0; k < MW; ++k) {
-        jj[k] = ecol[(size_t)k * n + v];
-        aa[k] = d.ell_scaled[(size_t)k * n + v];
-      }
-#pragma unroll
-      for (int k = 0; k < MW; ++k) {
-        const int j = jj[k];
-        a0 += aa[k] * (rc[j] - ra * (wc[j] + rb * sc[j]));
-        a1 += aa[k] * (rc[n + j] - ra * (wc[n + j] + rb * sc[n + j]));
-        a2 += aa[k] * (rc[2 * n + j] - ra * (wc[2 * n + j] + rb * sc[2 * n + j]));
-      }
-      wn[v] = a0;
-      wn[n + v] = a1;
-      wn[2 * n + v] = a2;
-      const R u0 = rv[0] * idg, u1 = rv[1] * idg, u2 = rv[2] * idg;
-      acc_g += (double)rv[0] * u0 + (double)rv[1] * u1 + (double)rv[2] * u2;
-      acc_d += (double)a0 * u0 + (double)a1 * u1 + (double)a2 * u2;
-    }
-    // partial sums alternate halves so a slow block still reading the previous
-    // iteration's sums is never overwritten
-    const int half = (it & 1) ? 0 : G;
-    bs = block_sum<kPcgBlock>(acc_g, lds);
-    if (threadIdx.x == 0) d.part_c[half + blockIdx.x] = bs;
-    bs = block_sum<kPcgBlock>(acc_d, lds);
-    if (threadIdx.x == 0) d.part_e[half + blockIdx.x] = bs;
-    grid_barrier(bc, bg, G);
-    const double gn = grid_sum(d.part_c + half, G, sh);
-    const double dn = grid_sum(d.part_e + half, G, sh);
-    ++it;
-    cur ^= 1;
-    if (!(gn >= 0.0) || isinf(gn) || !(dn == dn) || isinf(dn)) {
-      broke = true;
-      break;
-    }
-    if (gn <= stop) break;
-    const double bn = gn / gam;
-    const double den = dn - bn * gn / al;
-    if (!(den > 0.0)) {
-      broke = true;
-      break;
-    }
-    al = gn / den;
-    be = bn;
-    gam = gn;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    d.st->pcg_total += it;
-    d.st->pcg_last = it;
-    if (broke) __hip_atomic_store(&d.st->done, (int)BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// u += d on free vertices, collision positions refreshed, r_k = max|d|/diag,
-// convergence decision by the last block to finish.
+//
+// The matrix is A_el (fixed rows removed) plus the spring diagonal: its
+// diagonal is the Jacobi diagonal dg, its off-diagonal part is stored as a
+// fixed-width ELL array (padded with the row itself and value 0) so every
+// neighbour load of a row is issued at once.
+// End of an outer iteration, run by the CG kernel after its last reduction:
+// u += d on the rows each block owns, collision positions refreshed, hash
+// buckets cleared for the next iteration; r_k = max|d| / diag and the
+// convergence decision are taken by the last block to arrive (ticket).
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_finish(Dev<R> d, Consts c) {
-  __shared__ double lds[kBlock / 64];
+__device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, int tid0, int stride, double* lds) {
   __shared__ int last;
-  if (is_done(d.st)) return;
-  const int v = blockIdx.x * kBlock + threadIdx.x;
   const size_t n = (size_t)c.n;
+  const W4<R>* x = reinterpret_cast<const W4<R>*>(d.dl);
   double dm = 0.0;
-  if (v < c.n && d.freem[v]) {
-    double dd[3];
+  for (int v = tid0; v < c.n; v += stride) {
+    if (!d.freem[v]) continue;
+    const W4<R> dv = x[v];
+    const R dd[3] = {dv.x, dv.y, dv.z};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const R dk = d.dl[k * n + v];
-      const R uu = d.u[k * n + v] + dk;
+      const R uu = d.u[k * n + v] + dd[k];
       d.u[k * n + v] = uu;
       d.xc[k * n + v] = d.X0[k * n + v] + (double)uu;
-      dd[k] = (double)dk;
     }
-    dm = sqrt((dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]);
+    dm = fmax(dm, sqrt(((double)dv.x * dv.x + (double)dv.y * dv.y) + (double)dv.z * dv.z));
   }
-  const int stride = gridDim.x * kBlock;
-  for (int i = v; i < c.H; i += stride) d.hcount[i] = 0;
-  const double bm = block_max<kBlock>(dm, lds);
+  for (int i = tid0; i < c.H; i += stride) d.hcount[i] = 0;
+  const double bm = block_max<kPcgBlock>(dm, lds);
   if (threadIdx.x == 0) {
-    d.part_d[blockIdx.x] = bm;
+    d.part_f[blockIdx.x] = bm;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const int t = __hip_atomic_fetch_add(&d.st->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     last = (t == (int)gridDim.x - 1);
@@ -406,11 +243,11 @@ __global__ __launch_bounds__(kBlock) void k_finish(Dev<R> d, Consts c) {
   // then a fixed tree: deterministic)
   double mloc = 0.0, eloc = 0.0;
   const int gl = cdiv(c.T, kBlock), gg = cdiv(c.n, kBlock);
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) mloc = fmax(mloc, d.part_d[b]);
-  for (int b = threadIdx.x; b < gl; b += kBlock) eloc += d.part_a[b];
-  for (int b = threadIdx.x; b < gg; b += kBlock) eloc += d.part_b[b];
-  const double m = block_max<kBlock>(mloc, lds);
-  const double E = block_sum<kBlock>(eloc, lds);
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += kPcgBlock) mloc = fmax(mloc, d.part_f[b]);
+  for (int b = threadIdx.x; b < gl; b += kPcgBlock) eloc += d.part_a[b];
+  for (int b = threadIdx.x; b < gg; b += kPcgBlock) eloc += d.part_b[b];
+  const double m = block_max<kPcgBlock>(mloc, lds);
+  const double E = block_sum<kPcgBlock>(eloc, lds);
   if (threadIdx.x != 0) return;
   DevStatus* st = d.st;
   const double res = m / c.diag;
@@ -444,8 +281,215 @@ __global__ __launch_bounds__(kBlock) void k_finish(Dev<R> d, Consts c) {
   st->n_contacts_last = st->n_contacts;
   st->n_contacts = 0;
   st->n_pen = 0;
+  st->n_over = 0;
   st->ticket = 0;
   __hip_atomic_store(&st->done, code, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Neighbour gathers are issued in chunks of CH rows of 16-byte vectors (so the
+// loads of a chunk are in flight together without exhausting registers); the
+// column indices and scaled values of a row are preloaded when they fit.
+template <typename R> struct Chunk { static constexpr int n = 8; };
+template <> struct Chunk<double> { static constexpr int n = 4; };
+
+template <typename R, int MW>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
+  constexpr int CH = Chunk<R>::n;
+  constexpr bool PRE = MW <= 16;
+  __shared__ double lds[kPcgBlock / 64];
+  __shared__ double sh[2];
+  if (is_done(d.st)) return;
+  const int G = gridDim.x;
+  const int stride = G * kPcgBlock;
+  const int tid0 = blockIdx.x * kPcgBlock + threadIdx.x;
+  const size_t n = (size_t)c.n;
+  unsigned* bc = &d.st->bar_count;
+  unsigned* bg = &d.st->bar_gen;
+  W4<R>* __restrict__ x = reinterpret_cast<W4<R>*>(d.dl);
+  W4<R>* __restrict__ p = reinterpret_cast<W4<R>*>(d.p);
+  W4<R>* const cg0 = reinterpret_cast<W4<R>*>(d.cg);
+  const R* __restrict__ dg = d.dg;
+  const int32_t* __restrict__ ecol = d.ell_col;
+  const R* __restrict__ evl = d.ell_val;
+  R* __restrict__ evs = d.ell_scaled;
+
+  // (A) r_0 = b - A x_0 with the warm start x_0 = previous correction;
+  //     p_{-1} = s_{-1} = 0; right-hand-side norm b' M^-1 b; a_vj / dg_j
+  double acc_b = 0.0;
+  for (int v = tid0; v < c.n; v += stride) {
+    const R dv = dg[v], idg = R(1) / dv;
+    const W4<R> xv = x[v];
+    R ax0 = dv * xv.x, ax1 = dv * xv.y, ax2 = dv * xv.z;
+#pragma unroll 1
+    for (int k0 = 0; k0 < MW; k0 += CH) {
+      int jj[CH];
+      R aa[CH], dgn[CH];
+      W4<R> xn[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        jj[k] = ecol[(size_t)(k0 + k) * n + v];
+        aa[k] = evl[(size_t)(k0 + k) * n + v];
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        xn[k] = x[jj[k]];
+        dgn[k] = dg[jj[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        ax0 += aa[k] * xn[k].x;
+        ax1 += aa[k] * xn[k].y;
+        ax2 += aa[k] * xn[k].z;
+        evs[(size_t)(k0 + k) * n + v] = aa[k] / dgn[k];
+      }
+    }
+    const W4<R> b = cg0[3 * (size_t)v];
+    acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
+    cg0[3 * (size_t)v] = w4<R>(b.x - ax0, b.y - ax1, b.z - ax2);
+    cg0[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
+    p[v] = w4<R>(R(0), R(0), R(0));
+  }
+  double bs = block_sum<kPcgBlock>(acc_b, lds);
+  if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
+  grid_barrier(bc, bg, G);
+  // (B) w_0 = A u_0, g_0 = (r_0, u_0), d_0 = (w_0, u_0)
+  double acc_g = 0.0, acc_d = 0.0;
+  for (int v = tid0; v < c.n; v += stride) {
+    const R idg = R(1) / dg[v];
+    const W4<R> rv = cg0[3 * (size_t)v];
+    R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
+#pragma unroll 1
+    for (int k0 = 0; k0 < MW; k0 += CH) {
+      int jj[CH];
+      R aa[CH];
+      W4<R> rn[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        jj[k] = ecol[(size_t)(k0 + k) * n + v];
+        aa[k] = evs[(size_t)(k0 + k) * n + v];
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) rn[k] = cg0[3 * (size_t)jj[k]];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        a0 += aa[k] * rn[k].x;
+        a1 += aa[k] * rn[k].y;
+        a2 += aa[k] * rn[k].z;
+      }
+    }
+    cg0[3 * (size_t)v + 1] = w4<R>(a0, a1, a2);
+    const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
+    acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
+    acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
+  }
+  bs = block_sum<kPcgBlock>(acc_g, lds);
+  if (threadIdx.x == 0) d.part_c[blockIdx.x] = bs;
+  bs = block_sum<kPcgBlock>(acc_d, lds);
+  if (threadIdx.x == 0) d.part_e[blockIdx.x] = bs;
+  grid_barrier(bc, bg, G);
+  double gam, del, rhs, dummy;
+  grid_sum2(d.part_c, d.part_e, G, sh, gam, del);
+  grid_sum2(d.part_d, d.part_d, G, sh, rhs, dummy);
+  const double stop = c.pcg_eta * c.pcg_eta * rhs;
+  int it = 0;
+  bool broke = !(rhs >= 0.0) || isinf(rhs) || !(gam >= 0.0) || isinf(gam);
+  bool run = !broke && gam > stop;
+  if (run && !(del > 0.0 && !isinf(del))) {
+    broke = true;
+    run = false;
+  }
+  double al = run ? gam / del : 0.0, be = 0.0;
+  int cur = 0;
+  while (run && it < c.pcg_max) {
+    const W4<R>* cs = cg0 + cur * 3 * n;
+    W4<R>* ns = cg0 + (cur ^ 1) * 3 * n;
+    const R ra = (R)al, rb = (R)be;
+    acc_g = 0.0;
+    acc_d = 0.0;
+    for (int v = tid0; v < c.n; v += stride) {
+      const R idg = R(1) / dg[v];
+      int jpre[PRE ? MW : 1];
+      R apre[PRE ? MW : 1];
+      if (PRE) {
+#pragma unroll
+        for (int k = 0; k < MW; ++k) {
+          jpre[k] = ecol[(size_t)k * n + v];
+          apre[k] = evs[(size_t)k * n + v];
+        }
+      }
+      const W4<R> rc = cs[3 * (size_t)v], wc = cs[3 * (size_t)v + 1], sc = cs[3 * (size_t)v + 2];
+      const W4<R> pv0 = p[v];
+      const W4<R> xv = x[v];
+      const W4<R> pv = w4<R>(rc.x * idg + rb * pv0.x, rc.y * idg + rb * pv0.y, rc.z * idg + rb * pv0.z);
+      const W4<R> sv = w4<R>(wc.x + rb * sc.x, wc.y + rb * sc.y, wc.z + rb * sc.z);
+      const W4<R> rv = w4<R>(rc.x - ra * sv.x, rc.y - ra * sv.y, rc.z - ra * sv.z);
+      p[v] = pv;
+      x[v] = w4<R>(xv.x + ra * pv.x, xv.y + ra * pv.y, xv.z + ra * pv.z);
+      R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
+#pragma unroll 1
+      for (int k0 = 0; k0 < MW; k0 += CH) {
+        int jj[CH];
+        R aa[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          jj[k] = PRE ? jpre[k0 + k] : ecol[(size_t)(k0 + k) * n + v];
+          aa[k] = PRE ? apre[k0 + k] : evs[(size_t)(k0 + k) * n + v];
+        }
+        W4<R> nr[CH], nw[CH], nsv[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const size_t b3 = 3 * (size_t)jj[k];
+          nr[k] = cs[b3];
+          nw[k] = cs[b3 + 1];
+          nsv[k] = cs[b3 + 2];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          a0 += aa[k] * (nr[k].x - ra * (nw[k].x + rb * nsv[k].x));
+          a1 += aa[k] * (nr[k].y - ra * (nw[k].y + rb * nsv[k].y));
+          a2 += aa[k] * (nr[k].z - ra * (nw[k].z + rb * nsv[k].z));
+        }
+      }
+      ns[3 * (size_t)v] = rv;
+      ns[3 * (size_t)v + 1] = w4<R>(a0, a1, a2);
+      ns[3 * (size_t)v + 2] = sv;
+      const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
+      acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
+      acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
+    }
+    // partial sums alternate halves so a slow block still reading the previous
+    // iteration's sums is never overwritten
+    const int half = (it & 1) ? 0 : G;
+    bs = block_sum<kPcgBlock>(acc_g, lds);
+    if (threadIdx.x == 0) d.part_c[half + blockIdx.x] = bs;
+    bs = block_sum<kPcgBlock>(acc_d, lds);
+    if (threadIdx.x == 0) d.part_e[half + blockIdx.x] = bs;
+    grid_barrier(bc, bg, G);
+    double gn, dn;
+    grid_sum2(d.part_c + half, d.part_e + half, G, sh, gn, dn);
+    ++it;
+    cur ^= 1;
+    if (!(gn >= 0.0) || isinf(gn) || !(dn == dn) || isinf(dn)) {
+      broke = true;
+      break;
+    }
+    if (gn <= stop) break;
+    const double bn = gn / gam;
+    const double den = dn - bn * gn / al;
+    if (!(den > 0.0)) {
+      broke = true;
+      break;
+    }
+    al = gn / den;
+    be = bn;
+    gam = gn;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.st->pcg_total += it;
+    d.st->pcg_last = it;
+    if (broke) __hip_atomic_store(&d.st->done, (int)BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (!broke) finish_tail<R>(d, c, tid0, stride, lds);
 }
 
 template <typename R>
@@ -480,11 +524,6 @@ hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s)
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
 }
 
-template <typename R>
-hipError_t launch_finish(const Dev<R>& d, const Consts& c, hipStream_t s) {
-  k_finish<R><<<cdiv(c.n, kBlock), kBlock, 0, s>>>(d, c);
-  return hipGetLastError();
-}
 
 template <typename R>
 int pcg_max_grid(int block) {
@@ -508,7 +547,6 @@ int pcg_max_grid(int block) {
   template hipError_t launch_output<R>(const Dev<R>&, const Consts&, R*, hipStream_t);          \
   template hipError_t launch_gather<R>(const Dev<R>&, const Consts&, hipStream_t);              \
   template hipError_t launch_pcg<R>(const Dev<R>&, const Consts&, int, hipStream_t);            \
-  template hipError_t launch_finish<R>(const Dev<R>&, const Consts&, hipStream_t);              \
   template int pcg_max_grid<R>(int);
 INST(float)
 INST(double)

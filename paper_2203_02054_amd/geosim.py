@@ -92,7 +92,7 @@ SIGNATURES = {
     "gs_destroy": (None, [_P]),
 }
 
-N_KERNELS = 11
+N_KERNELS = 7
 
 _lib = None
 
