@@ -145,6 +145,28 @@ void gs_default_params(gs_params* params);
  * and released with gs_destroy. */
 gs_status gs_create(const gs_mesh_desc* mesh, const gs_params* params, gs_problem** out);
 
+/* Batch of meshes solved together (one problem): the arrays of all calls are
+ * the meshes' arrays concatenated in order (positions [3][sum n], alpha
+ * [sum n_chambers]); chamber ids, vertex ids and boundary-face ids are offset
+ * per mesh; there are no contacts between meshes.  Each mesh keeps its own
+ * h_ref, eps, L_ray, weights and residual scale (its bounding-box diagonal);
+ * in a convergence solve a mesh whose r_k <= tol with an unchanged active set
+ * is frozen (its correction is zero from then on) and the solve ends when
+ * every mesh is frozen.  All meshes share one precision.  Errors as
+ * gs_create, prefixed with the mesh number. */
+gs_status gs_create_batch(int32_t n_mesh, const gs_mesh_desc* meshes, const gs_params* params,
+                          gs_problem** out);
+
+/* Offsets of mesh m's vertices, tets and chambers in the concatenated arrays:
+ * entries m and m + 1 of each array (cap >= n_mesh + 1).  A single mesh is a
+ * batch of one. */
+gs_status gs_batch_layout(const gs_problem* p, int32_t cap, int32_t* vert_offset,
+                          int32_t* tet_offset, int32_t* chamber_offset, int32_t* n_mesh);
+
+/* Iteration at which each mesh of the last convergence solve converged (0:
+ * did not converge), cap >= n_mesh. */
+gs_status gs_mesh_iters(gs_problem* p, int32_t cap, int32_t* iters);
+
 /* Analytic obstacles O_obs (Eq. 4): n_sph spheres (cx, cy, cz, r) and n_pln
  * half-spaces (px, py, pz, nx, ny, nz) whose inside is n.(x - p) < 0 (the
  * normal is normalised here).  Must be called before gs_bind.  GS_EINVAL for

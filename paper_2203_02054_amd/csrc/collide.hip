@@ -30,12 +30,16 @@ __global__ __launch_bounds__(kBlock) void k_hash_insert(Dev<R> d, Consts c) {
   const int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= c.S) return;
   const int v = d.qverts[s];
+  const int m = d.vmesh[v];
+  if (mesh_frozen(d, c.mask_done, m)) return;
+  const double ic = d.mesh[m].inv_cell;
   double4 e;
   e.x = d.xc[v];
   e.y = d.xc[(size_t)c.n + v];
   e.z = d.xc[2 * (size_t)c.n + v];
   e.w = __longlong_as_double((long long)s);
-  const int key = hash_cell(cell_of(e.x, c.inv_cell), cell_of(e.y, c.inv_cell), cell_of(e.z, c.inv_cell), c.H);
+  if (!(fabs(e.x * ic) < 1e9 && fabs(e.y * ic) < 1e9 && fabs(e.z * ic) < 1e9)) return;  // diverged iterate
+  const int key = hash_cell(cell_of(e.x, ic), cell_of(e.y, ic), cell_of(e.z, ic), m, c.H);
   const int slot = atomicAdd(&d.hcount[key], 1);
   if (slot < kHashCap) {
     reinterpret_cast<double4*>(d.hslot)[(size_t)key * kHashCap + slot] = e;
@@ -46,13 +50,13 @@ __global__ __launch_bounds__(kBlock) void k_hash_insert(Dev<R> d, Consts c) {
 }
 
 template <typename R, bool DEBUG>
-__device__ __forceinline__ void test_point(const Dev<R>& d, const double4& en, int e, const int (&vi)[4],
+__device__ __forceinline__ void test_point(const Dev<R>& d, const double4& en, int e, int m, const int (&vi)[4],
                                           const double (&p)[4][3], const double (&lo)[3], const double (&hi)[3]) {
   const double q[3] = {en.x, en.y, en.z};
   if (!(lo[0] <= q[0] && q[0] <= hi[0] && lo[1] <= q[1] && q[1] <= hi[1] && lo[2] <= q[2] && q[2] <= hi[2])) return;
   const int s = (int)__double_as_longlong(en.w);
   const int v = d.qverts[s];
-  if (v == vi[0] || v == vi[1] || v == vi[2] || v == vi[3]) return;
+  if (v == vi[0] || v == vi[1] || v == vi[2] || v == vi[3] || d.vmesh[v] != m) return;
   if (DEBUG) {
     const int k = atomicAdd(&d.st->cand_tet, 1);
     if (k < d.dbg_cap) {
@@ -71,6 +75,9 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
   if (is_done(d.st)) return;
   const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= c.T) return;
+  const int m = d.tmesh[e];
+  if (mesh_frozen(d, c.mask_done, m)) return;
+  const double ic = d.mesh[m].inv_cell;
   int vi[4];
   double p[4][3];
 #pragma unroll
@@ -87,28 +94,27 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
   for (int k = 0; k < 3; ++k) {
     lo[k] = fmin(fmin(p[0][k], p[1][k]), fmin(p[2][k], p[3][k]));
     hi[k] = fmax(fmax(p[0][k], p[1][k]), fmax(p[2][k], p[3][k]));
-    finite = finite && isfinite(lo[k]) && isfinite(hi[k]) && fabs(lo[k] * c.inv_cell) < 1e9 &&
-             fabs(hi[k] * c.inv_cell) < 1e9;
+    finite = finite && isfinite(lo[k]) && isfinite(hi[k]) && fabs(lo[k] * ic) < 1e9 && fabs(hi[k] * ic) < 1e9;
   }
   if (!finite) return;  // a diverged iterate: no candidates (the CG reports the breakdown)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    clo[k] = cell_of(lo[k], c.inv_cell);
-    chi[k] = cell_of(hi[k], c.inv_cell);
+    clo[k] = cell_of(lo[k], ic);
+    chi[k] = cell_of(hi[k], ic);
     const long ext = (long)chi[k] - (long)clo[k] + 1;
     ncell = (ext > kCellCap || ncell > kCellCap) ? (long)kCellCap + 1 : ncell * ext;
   }
   const double4* slots = reinterpret_cast<const double4*>(d.hslot);
   if (ncell > kCellCap) {
-    // a tet stretched over many cells: test every query vertex (still exact)
-    for (int s = 0; s < c.S; ++s) {
+    // a tet stretched over many cells: test every query vertex of its mesh (still exact)
+    for (int s = d.mesh[m].sbeg; s < d.mesh[m].send; ++s) {
       const int v = d.qverts[s];
       double4 en;
       en.x = d.xc[v];
       en.y = d.xc[(size_t)c.n + v];
       en.z = d.xc[2 * (size_t)c.n + v];
       en.w = __longlong_as_double((long long)s);
-      test_point<R, DEBUG>(d, en, e, vi, p, lo, hi);
+      test_point<R, DEBUG>(d, en, e, m, vi, p, lo, hi);
     }
     return;
   }
@@ -121,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
     for (int k = 0; k < 8; ++k) {
       const int ix = clo[0] + (k & 1), iy = clo[1] + ((k >> 1) & 1), iz = clo[2] + ((k >> 2) & 1);
       const bool ok = ix <= chi[0] && iy <= chi[1] && iz <= chi[2];
-      keys[k] = ok ? hash_cell(ix, iy, iz, c.H) : -1;
+      keys[k] = ok ? hash_cell(ix, iy, iz, m, c.H) : -1;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) cnt[k] = (keys[k] >= 0) ? min(d.hcount[keys[k]], kHashCap) : 0;
@@ -131,21 +137,23 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
       if (cnt[k] > 0) e0[k] = slots[(size_t)keys[k] * kHashCap];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (cnt[k] > 0) test_point<R, DEBUG>(d, e0[k], e, vi, p, lo, hi);
+      if (cnt[k] > 0) test_point<R, DEBUG>(d, e0[k], e, m, vi, p, lo, hi);
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      for (int i = 1; i < cnt[k]; ++i) test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, vi, p, lo, hi);
+      for (int i = 1; i < cnt[k]; ++i)
+        test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, m, vi, p, lo, hi);
   } else {
     for (int ix = clo[0]; ix <= chi[0]; ++ix)
       for (int iy = clo[1]; iy <= chi[1]; ++iy)
         for (int iz = clo[2]; iz <= chi[2]; ++iz) {
-          const int key = hash_cell(ix, iy, iz, c.H);
+          const int key = hash_cell(ix, iy, iz, m, c.H);
           const int cn = min(d.hcount[key], kHashCap);
-          for (int i = 0; i < cn; ++i) test_point<R, DEBUG>(d, slots[(size_t)key * kHashCap + i], e, vi, p, lo, hi);
+          for (int i = 0; i < cn; ++i) test_point<R, DEBUG>(d, slots[(size_t)key * kHashCap + i], e, m, vi, p, lo, hi);
         }
   }
   const int nover = __hip_atomic_load(&d.st->n_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int i = 0; i < nover; ++i) test_point<R, DEBUG>(d, reinterpret_cast<const double4*>(d.hover)[i], e, vi, p, lo, hi);
+  for (int i = 0; i < nover; ++i)
+    test_point<R, DEBUG>(d, reinterpret_cast<const double4*>(d.hover)[i], e, m, vi, p, lo, hi);
 }
 
 __device__ __forceinline__ void load3(const double* xc, size_t n, int v, double* o) {
@@ -168,6 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
   for (int i = wave; i < npen; i += nwaves) {
     const int s = d.penlist[i];
     const int v = d.qverts[s];
+    const MeshConst mc = d.mesh[d.vmesh[v]];
     // area-weighted normal: sum over incident faces in ascending id
     double acc[3] = {0.0, 0.0, 0.0};
     for (int j = d.qf_start[s]; j < d.qf_start[s + 1]; ++j) {
@@ -198,14 +207,14 @@ __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
     {
       for (int k = 0; k < 3; ++k) {
         dir[k] = -(acc[k] / len);
-        end[k] = o[k] + c.Lray * dir[k];
+        end[k] = o[k] + mc.Lray * dir[k];
         slo[k] = fmin(o[k], end[k]);
         shi[k] = fmax(o[k], end[k]);
       }
     }
     double best_t = INFINITY;
     int best_f = INT_MAX;
-    for (int f = lane; f < F; f += 64) {
+    for (int f = mc.fbeg + lane; f < mc.fend; f += 64) {
       const int i0 = d.faces[f], i1 = d.faces[F + f], i2 = d.faces[2 * F + f];
       if (i0 == v || i1 == v || i2 == v) continue;
       double a0[3], a1[3], a2[3];
@@ -228,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
         }
       }
       double t;
-      if (moller_trumbore(o, dir, a0, a1, a2, c.Lray, &t)) {
+      if (moller_trumbore(o, dir, a0, a1, a2, mc.Lray, &t)) {
         if (t < best_t || (t == best_t && f < best_f)) {
           best_t = t;
           best_f = f;
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
         load3(d.xc, n, d.faces[best_f], a0);
         load3(d.xc, n, d.faces[F + best_f], a1);
         load3(d.xc, n, d.faces[2 * F + best_f], a2);
-        const double te = best_t + c.eps;
+        const double te = best_t + mc.eps;
         for (int k = 0; k < 3; ++k) {
           d.fc[3 * s + k] = o[k] + te * dir[k];
           e1[k] = a1[k] - a0[k];
@@ -279,6 +288,9 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
   const int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= c.S) return;
   const int v = d.qverts[s];
+  const int m = d.vmesh[v];
+  if (mesh_frozen(d, c.mask_done, m)) return;
+  const double eps = d.mesh[m].eps;
   double x[3];
   load3(d.xc, (size_t)c.n, v, x);
   const int base = s * c.slots;
@@ -297,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
       }
       d.cprim[base] = hit;
     } else if (old) {
-      now = pen ? true : !released(x, d.ctgt + 3 * base, d.cnrm + 3 * base, c.eps);
+      now = pen ? true : !released(x, d.ctgt + 3 * base, d.cnrm + 3 * base, eps);
     }
     if (pen && hit < 0) atomicAdd(&d.st->ray_miss, 1);
     d.cact[base] = now ? 1 : 0;
@@ -326,9 +338,9 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
           nc[1] = 0.0;
           nc[2] = 1.0;
         }
-        const double rr = sp[3] + c.eps;
+        const double rr = sp[3] + eps;
         const double tc[3] = {sp[0] + rr * nc[0], sp[1] + rr * nc[1], sp[2] + rr * nc[2]};
-        now = inside || !released(x, tc, nc, c.eps);
+        now = inside || !released(x, tc, nc, eps);
         if (now) {
           for (int k = 0; k < 3; ++k) {
             d.ctgt[3 * slot + k] = tc[k];
@@ -349,10 +361,10 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
       const bool inside = sd < 0.0;
       bool now = false;
       if (inside || old) {
-        const double se = sd - c.eps;
+        const double se = sd - eps;
         const double nc[3] = {pl[3], pl[4], pl[5]};
         const double tc[3] = {x[0] - se * nc[0], x[1] - se * nc[1], x[2] - se * nc[2]};
-        now = inside || !released(x, tc, nc, c.eps);
+        now = inside || !released(x, tc, nc, eps);
         if (now) {
           for (int k = 0; k < 3; ++k) {
             d.ctgt[3 * slot + k] = tc[k];
@@ -366,7 +378,10 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
       nact += now;
     }
   }
-  if (changed) atomicOr(&d.st->changed, 1);
+  if (changed) {
+    atomicOr(&d.st->changed, 1);
+    d.mchanged[m] = 1;
+  }
   if (nact) atomicAdd(&d.st->n_contacts, nact);
 }
 

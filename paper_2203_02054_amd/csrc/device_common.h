@@ -127,9 +127,17 @@ __device__ __forceinline__ bool moller_trumbore(const double* o, const double* d
 // lies in a cell of the box's cell range).
 __device__ __forceinline__ int cell_of(double x, double inv_cell) { return (int)floor(x * inv_cell); }
 
-__device__ __forceinline__ int hash_cell(int ix, int iy, int iz, int H) {
-  const uint32_t h = ((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u);
+// Bucket of cell (ix, iy, iz) of mesh m (meshes of a batch share the table).
+__device__ __forceinline__ int hash_cell(int ix, int iy, int iz, int m, int H) {
+  const uint32_t h = ((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u) ^
+                     ((uint32_t)m * 2654435761u);
   return (int)(h & (uint32_t)(H - 1));
+}
+
+// Mesh of a vertex / tet is frozen once it has converged (batched solves).
+template <typename DevT>
+__device__ __forceinline__ bool mesh_frozen(const DevT& d, int mask, int m) {
+  return mask && d.mdone[m] != 0;
 }
 
 __device__ __forceinline__ bool is_done(const DevStatus* st) {

@@ -50,7 +50,7 @@ struct Layout {
   size_t X0, tets, tag, inc_start, inc_pos, ell_col, ell_val, ell_scaled, adiag, freem, faces, qverts, vq, qf_start, qf_list, kq,
       obst;
   size_t u, xc, res4, cg, dl, p, dg, dsp, pen, hcount, hslot, hover, penlist, fhit, fc, fn, cact, ctgt, cnrm,
-      cprim, part_a, part_b, part_c, part_d, part_e, part_f, st, trace;
+      cprim, part_a, part_b, part_c, part_d, part_e, part_f, st, trace, mesh, vmesh, tmesh, mres, mchanged, mdone;
   size_t total;
 };
 
@@ -115,7 +115,12 @@ struct gs_problem {
   int ell_w = 0;
   std::vector<uint8_t> freem;
   int n_surf_verts = 0;
-  double h_ref = 0, eps = 0, Lray = 0, diag = 0, cell = 0, inv_mean_vol = 0;
+  double h_ref = 0, eps = 0, Lray = 0, diag = 0, cell = 0, inv_mean_vol = 0;  // of a single mesh (mesh 0)
+  // meshes (a single mesh is a batch of one)
+  int M = 1;
+  std::vector<double> mh_ref, mdiag, mcell, minv_mean_vol;
+  std::vector<int32_t> vbeg, tbeg, chbeg, fbeg, sbeg;  // [M+1] offsets
+  std::vector<int32_t> vmesh, tmesh;
   // device binding
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -199,6 +204,12 @@ Layout make_layout(const gs_problem* p) {
   L.part_f = take((size_t)p->nparts * 8);
   L.st = take(sizeof(DevStatus));
   L.trace = take((size_t)p->trace_len * 6 * 8);
+  L.mesh = take((size_t)p->M * sizeof(MeshConst));
+  L.vmesh = take(n * 4);
+  L.tmesh = take(T * 4);
+  L.mres = take((size_t)p->M * 8);
+  L.mchanged = take((size_t)p->M * 4);
+  L.mdone = take((size_t)p->M * 4);
   L.total = align256(off);
   return L;
 }
@@ -253,6 +264,12 @@ Dev<R> make_dev(const gs_problem* p) {
   d.part_f = (double*)(b + L.part_f);
   d.st = (DevStatus*)(b + L.st);
   d.trace = (double*)(b + L.trace);
+  d.mesh = (const MeshConst*)(b + L.mesh);
+  d.vmesh = (const int32_t*)(b + L.vmesh);
+  d.tmesh = (const int32_t*)(b + L.tmesh);
+  d.mres = (unsigned long long*)(b + L.mres);
+  d.mchanged = (int32_t*)(b + L.mchanged);
+  d.mdone = (int32_t*)(b + L.mdone);
   d.dbg_tet = nullptr;
   d.dbg_tri = nullptr;
   d.dbg_cap = 0;
@@ -282,13 +299,10 @@ Consts make_consts(const gs_problem* p) {
   c.c1 = p->prm.c1;
   c.c2 = p->prm.c2;
   c.kappa = p->prm.kappa_col;
-  c.eps = p->eps;
-  c.Lray = p->Lray;
-  c.diag = p->diag;
   c.tol = p->prm.tol;
   c.pcg_eta = p->prm.pcg_eta;
-  c.inv_mean_vol = p->inv_mean_vol;
-  c.inv_cell = 1.0 / p->cell;
+  c.M = p->M;
+  c.mask_done = p->prm.fixed_iters > 0 ? 0 : 1;
   return c;
 }
 
@@ -308,6 +322,22 @@ std::vector<R> cast_vec(const std::vector<double>& v) {
 int pcg_grid_for(const gs_problem* p, int maxg) {
   int g = p->prm.pcg_blocks > 0 ? p->prm.pcg_blocks : cdiv(p->n, kPcgThreads);
   return std::max(1, std::min({g, maxg, kMaxPcgGrid, p->nparts / 2}));
+}
+
+std::vector<MeshConst> mesh_table(const gs_problem* p) {
+  std::vector<MeshConst> t(p->M);
+  for (int m = 0; m < p->M; ++m) {
+    t[m].eps = p->prm.eps_rel * p->mh_ref[m];
+    t[m].Lray = p->prm.ray_rel * p->mh_ref[m];
+    t[m].inv_cell = 1.0 / p->mcell[m];
+    t[m].inv_diag = 1.0 / p->mdiag[m];
+    t[m].inv_mean_vol = p->minv_mean_vol[m];
+    t[m].fbeg = p->fbeg[m];
+    t[m].fend = p->fbeg[m + 1];
+    t[m].sbeg = p->sbeg[m];
+    t[m].send = p->sbeg[m + 1];
+  }
+  return t;
 }
 
 template <typename R>
@@ -332,6 +362,13 @@ gs_status bind_impl(gs_problem* p) {
   HIPCHK(upload(b, L.qf_list, p->qf_list, s));
   HIPCHK(upload(b, L.kq, p->kq, s));
   HIPCHK(upload(b, L.obst, p->obst, s));
+  const std::vector<MeshConst> mt = mesh_table(p);
+  HIPCHK(upload(b, L.mesh, mt, s));
+  HIPCHK(upload(b, L.vmesh, p->vmesh, s));
+  HIPCHK(upload(b, L.tmesh, p->tmesh, s));
+  HIPCHK(hipMemsetAsync(b + L.mres, 0, (size_t)p->M * 8, s));
+  HIPCHK(hipMemsetAsync(b + L.mchanged, 0, (size_t)p->M * 4, s));
+  HIPCHK(hipMemsetAsync(b + L.mdone, 0, (size_t)p->M * 4, s));
   HIPCHK(hipMemsetAsync(b + L.cact, 0, (size_t)p->S * p->slots, s));
   HIPCHK(hipMemsetAsync(b + L.st, 0, sizeof(DevStatus), s));
   HIPCHK(hipMemsetAsync(b + L.hcount, 0, (size_t)p->H * 4, s));
@@ -547,30 +584,6 @@ gs_status setup(gs_problem* p, const gs_mesh_desc* m) {
       p->rowptr[r + 1] = (int32_t)p->col.size();
     }
     p->nnz = (int)p->col.size();
-    // ELL copy of the off-diagonal entries (slot-major, padded with the row
-    // itself and value 0); the diagonal lives in the Jacobi diagonal
-    int wmax = 0;
-    for (int r = 0; r < n; ++r) {
-      int cnt = 0;
-      if (p->freem[r])
-        for (int j = p->rowptr[r]; j < p->rowptr[r + 1]; ++j) cnt += (p->col[j] != r);
-      wmax = std::max(wmax, cnt);
-    }
-    if (wmax > 64) throw std::runtime_error("a vertex has more than 64 neighbours");
-    p->ell_w = wmax <= 16 ? 16 : (wmax <= 32 ? 32 : 64);
-    p->ell_col.assign((size_t)p->ell_w * n, 0);
-    p->ell_val.assign((size_t)p->ell_w * n, 0.0);
-    for (int r = 0; r < n; ++r) {
-      int k = 0;
-      if (p->freem[r])
-        for (int j = p->rowptr[r]; j < p->rowptr[r + 1]; ++j)
-          if (p->col[j] != r) {
-            p->ell_col[(size_t)k * n + r] = p->col[j];
-            p->ell_val[(size_t)k * n + r] = p->val[j];
-            ++k;
-          }
-      for (; k < p->ell_w; ++k) p->ell_col[(size_t)k * n + r] = r;
-    }
     p->adiag.resize(n);
     for (int v = 0; v < n; ++v) p->adiag[v] = p->freem[v] ? full_diag[v] : 1.0;
   }
@@ -652,12 +665,168 @@ gs_status setup(gs_problem* p, const gs_mesh_desc* m) {
     for (int s = 0; s < p->S; ++s) p->kq[s] = p->prm.kappa_col * full_diag[p->qverts[s]];
   }
 
+  // a single mesh: one entry in the per-mesh tables
+  p->M = 1;
+  p->mh_ref = {p->h_ref};
+  p->mdiag = {p->diag};
+  p->mcell = {p->cell};
+  p->minv_mean_vol = {p->inv_mean_vol};
+  p->vbeg = {0, n};
+  p->tbeg = {0, T};
+  p->chbeg = {0, p->nch};
+  p->fbeg = {0, p->F};
+  p->sbeg = {0, p->S};
+  p->vmesh.assign(n, 0);
+  p->tmesh.assign(T, 0);
+  return GS_OK;
+}
+
+// Sizes and structures derived from the (possibly merged) arrays: the ELL
+// copy of the off-diagonal entries (slot-major, padded with the row itself
+// and value 0; the diagonal lives in the Jacobi diagonal), hash table size,
+// partial-sum slots.
+void finalize(gs_problem* p) {
+  const int n = p->n;
+  int wmax = 0;
+  for (int r = 0; r < n; ++r) {
+    int cnt = 0;
+    if (p->freem[r])
+      for (int j = p->rowptr[r]; j < p->rowptr[r + 1]; ++j) cnt += (p->col[j] != r);
+    wmax = std::max(wmax, cnt);
+  }
+  if (wmax > 64) throw std::runtime_error("a vertex has more than 64 neighbours");
+  p->ell_w = wmax <= 16 ? 16 : (wmax <= 32 ? 32 : 64);
+  p->ell_col.assign((size_t)p->ell_w * n, 0);
+  p->ell_val.assign((size_t)p->ell_w * n, 0.0);
+  for (int r = 0; r < n; ++r) {
+    int k = 0;
+    if (p->freem[r])
+      for (int j = p->rowptr[r]; j < p->rowptr[r + 1]; ++j)
+        if (p->col[j] != r) {
+          p->ell_col[(size_t)k * n + r] = p->col[j];
+          p->ell_val[(size_t)k * n + r] = p->val[j];
+          ++k;
+        }
+    for (; k < p->ell_w; ++k) p->ell_col[(size_t)k * n + r] = r;
+  }
   int H = 1024;
   while (H < 2 * p->S) H <<= 1;
   p->H = H;
-  p->nparts = std::max({cdiv(T, kBlock), cdiv(n, kBlock), 2 * kMaxPcgGrid});
-  p->slots = 1;
-  return GS_OK;
+  p->nparts = std::max({cdiv(p->T, kBlock), cdiv(n, kBlock), 2 * kMaxPcgGrid});
+  p->slots = 1 + p->ns + p->np;
+}
+
+// Concatenate single-mesh set-ups into one problem: vertex, tet, chamber,
+// face and query-vertex ids are offset; the system matrix is block diagonal.
+void merge(gs_problem* p, const std::vector<gs_problem*>& parts) {
+  const int M = (int)parts.size();
+  int n = 0, T = 0, nch = 0, F = 0, S = 0, inc = 0, qf = 0;
+  for (auto* q : parts) {
+    n += q->n;
+    T += q->T;
+    nch += q->nch;
+    F += q->F;
+    S += q->S;
+    inc += q->inc_start[q->n];
+    qf += (int)q->qf_list.size();
+  }
+  p->M = M;
+  p->n = n;
+  p->T = T;
+  p->nch = nch;
+  p->F = F;
+  p->S = S;
+  p->X0.assign(3 * (size_t)n, 0.0);
+  p->tets.assign(4 * (size_t)T, 0);
+  p->inc_pos.assign(4 * (size_t)T, 0);
+  p->faces.assign(3 * (size_t)F, 0);
+  p->tag.clear();
+  p->freem.clear();
+  p->adiag.clear();
+  p->kq.clear();
+  p->qverts.clear();
+  p->vq.assign(n, -1);
+  p->inc_start.assign(1, 0);
+  p->rowptr.assign(1, 0);
+  p->col.clear();
+  p->val.clear();
+  p->qf_start.assign(1, 0);
+  p->qf_list.clear();
+  p->vmesh.clear();
+  p->tmesh.clear();
+  p->mh_ref.clear();
+  p->mdiag.clear();
+  p->mcell.clear();
+  p->minv_mean_vol.clear();
+  p->vbeg.assign(1, 0);
+  p->tbeg.assign(1, 0);
+  p->chbeg.assign(1, 0);
+  p->fbeg.assign(1, 0);
+  p->sbeg.assign(1, 0);
+  p->n_surf_verts = 0;
+  p->nnz = 0;
+  int vo = 0, to = 0, co = 0, fo = 0, so = 0, io = 0;
+  for (int m = 0; m < M; ++m) {
+    const gs_problem* q = parts[m];
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < q->n; ++i) p->X0[(size_t)k * n + vo + i] = q->X0[(size_t)k * q->n + i];
+    for (int j = 0; j < 4; ++j)
+      for (int e = 0; e < q->T; ++e) {
+        p->tets[(size_t)j * T + to + e] = q->tets[(size_t)j * q->T + e] + vo;
+        p->inc_pos[(size_t)j * T + to + e] = q->inc_pos[(size_t)j * q->T + e] + io;
+      }
+    for (int e = 0; e < q->T; ++e) {
+      const int tg = q->tag[e], mode = tg & 7;
+      p->tag.push_back(mode == GS_BODY ? tg : (mode | (((tg >> 3) + co) << 3)));
+      p->tmesh.push_back(m);
+    }
+    for (int k = 0; k < 3; ++k)
+      for (int f = 0; f < q->F; ++f) p->faces[(size_t)k * F + fo + f] = q->faces[(size_t)k * q->F + f] + vo;
+    for (int i = 0; i < q->n; ++i) {
+      p->freem.push_back(q->freem[i]);
+      p->adiag.push_back(q->adiag[i]);
+      p->vmesh.push_back(m);
+      p->inc_start.push_back(q->inc_start[i + 1] + io);
+      for (int j = q->rowptr[i]; j < q->rowptr[i + 1]; ++j) {
+        p->col.push_back(q->col[j] + vo);
+        p->val.push_back(q->val[j]);
+      }
+      p->rowptr.push_back((int32_t)p->col.size());
+      if (q->vq[i] >= 0) p->vq[vo + i] = q->vq[i] + so;
+    }
+    const int qbase = (int)p->qf_list.size();
+    for (int s2 = 0; s2 < q->S; ++s2) {
+      p->qverts.push_back(q->qverts[s2] + vo);
+      p->kq.push_back(q->kq[s2]);
+      p->qf_start.push_back(q->qf_start[s2 + 1] + qbase);
+    }
+    for (int32_t f : q->qf_list) p->qf_list.push_back(f + fo);
+    p->n_surf_verts += q->n_surf_verts;
+    p->mh_ref.push_back(q->h_ref);
+    p->mdiag.push_back(q->diag);
+    p->mcell.push_back(q->cell);
+    p->minv_mean_vol.push_back(q->inv_mean_vol);
+    vo += q->n;
+    to += q->T;
+    co += q->nch;
+    fo += q->F;
+    so += q->S;
+    io += q->inc_start[q->n];
+    p->vbeg.push_back(vo);
+    p->tbeg.push_back(to);
+    p->chbeg.push_back(co);
+    p->fbeg.push_back(fo);
+    p->sbeg.push_back(so);
+  }
+  p->nnz = (int)p->col.size();
+  p->h_ref = p->mh_ref[0];
+  p->diag = p->mdiag[0];
+  p->cell = p->mcell[0];
+  p->inv_mean_vol = p->minv_mean_vol[0];
+  p->eps = p->prm.eps_rel * p->h_ref;
+  p->Lray = p->prm.ray_rel * p->h_ref;
+  (void)inc;
+  (void)qf;
 }
 
 }  // namespace
@@ -708,6 +877,7 @@ gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** ou
   p->trace_len = prm->trace_len;
   try {
     st = setup(p, m);
+    if (st == GS_OK) finalize(p);
   } catch (const std::exception& ex) {
     st = fail(GS_EINVAL, std::string("set-up failed: ") + ex.what());
   }
@@ -716,6 +886,77 @@ gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** ou
     return st;
   }
   *out = p;
+  return GS_OK;
+}
+
+gs_status gs_create_batch(int32_t n_mesh, const gs_mesh_desc* meshes, const gs_params* prm, gs_problem** out) {
+  if (!out) return fail(GS_EINVAL, "null output handle");
+  *out = nullptr;
+  if (n_mesh < 1 || !meshes) return fail(GS_EINVAL, "need at least one mesh");
+  gs_status st = check_params(prm);
+  if (st != GS_OK) return st;
+  long nt = 0, nv = 0;
+  for (int m = 0; m < n_mesh; ++m) {
+    const gs_mesh_desc* d = &meshes[m];
+    if (!d->rest_xyz || !d->tets || !d->tet_mode || !d->tet_chamber || !d->fixed)
+      return fail(GS_EINVAL, "null mesh array in mesh " + std::to_string(m));
+    if (d->n_verts <= 0 || d->n_tets <= 0 || d->n_chambers < 0)
+      return fail(GS_EINVAL, "empty mesh " + std::to_string(m));
+    if (d->precision != meshes[0].precision || (d->precision != 4 && d->precision != 8))
+      return fail(GS_EINVAL, "meshes of a batch share one precision (4 or 8)");
+    nt += d->n_tets;
+    nv += d->n_verts;
+  }
+  if (nt * 4 >= (1L << 31) || nv * 64 >= (1L << 31)) return fail(GS_EINVAL, "batch too large");
+  std::vector<gs_problem*> parts;
+  gs_problem* p = nullptr;
+  try {
+    for (int m = 0; m < n_mesh && st == GS_OK; ++m) {
+      gs_problem* q = new gs_problem();
+      q->prm = *prm;
+      parts.push_back(q);
+      st = setup(q, &meshes[m]);
+      if (st != GS_OK) g_err = "mesh " + std::to_string(m) + ": " + g_err;
+    }
+    if (st == GS_OK) {
+      p = new gs_problem();
+      p->prm = *prm;
+      p->prec = meshes[0].precision;
+      p->trace_len = prm->trace_len;
+      merge(p, parts);
+      finalize(p);
+    }
+  } catch (const std::exception& ex) {
+    st = fail(GS_EINVAL, std::string("set-up failed: ") + ex.what());
+  }
+  for (auto* q : parts) delete q;
+  if (st != GS_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return GS_OK;
+}
+
+gs_status gs_batch_layout(const gs_problem* p, int32_t cap, int32_t* vert_offset, int32_t* tet_offset,
+                          int32_t* chamber_offset, int32_t* n_mesh) {
+  if (!p || !n_mesh) return fail(GS_EINVAL, "null argument");
+  *n_mesh = p->M;
+  if (cap < p->M + 1) return fail(GS_ECAPACITY, "offset arrays need n_mesh + 1 entries");
+  for (int m = 0; m <= p->M; ++m) {
+    if (vert_offset) vert_offset[m] = p->vbeg[m];
+    if (tet_offset) tet_offset[m] = p->tbeg[m];
+    if (chamber_offset) chamber_offset[m] = p->chbeg[m];
+  }
+  return GS_OK;
+}
+
+gs_status gs_mesh_iters(gs_problem* p, int32_t cap, int32_t* iters) {
+  if (!p || !iters) return fail(GS_EINVAL, "null argument");
+  if (!p->bound) return fail(GS_ESTATE, "not bound");
+  if (cap < p->M) return fail(GS_ECAPACITY, "iteration array needs n_mesh entries");
+  HIPCHK(hipMemcpyAsync(iters, p->ws + p->lay.mdone, (size_t)p->M * 4, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
   return GS_OK;
 }
 
@@ -799,6 +1040,10 @@ gs_status gs_set_params(gs_problem* p, const gs_params* prm) {
   p->prm = *prm;
   p->eps = prm->eps_rel * h;
   p->Lray = prm->ray_rel * h;
+  if (p->bound) {
+    const std::vector<MeshConst> mt = mesh_table(p);
+    HIPCHK(upload(p->ws, p->lay.mesh, mt, p->stream));
+  }
   if (p->bound) {
     const int maxg = p->prec == 4 ? pcg_max_grid<float>(0) : pcg_max_grid<double>(0);
     p->pcg_grid = pcg_grid_for(p, maxg);

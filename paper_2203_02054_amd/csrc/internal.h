@@ -13,7 +13,7 @@ constexpr int kCellCap = 64;         // hash cells a tet box may span before the
 constexpr int kHashCap = 8;          // entries stored in a hash bucket before the overflow list
 constexpr int kMaxSlots = 1 + 8 + 8; // self + spheres + planes
 constexpr int kPcgThreads = 512;     // threads per block of the cooperative CG kernel
-constexpr int kMaxPcgGrid = 64;      // workgroups of the cooperative CG kernel at most
+constexpr int kMaxPcgGrid = 1024;     // workgroups of the cooperative CG kernel at most
 
 // Completion codes kept on the device (DevStatus::done).
 enum { RUNNING = 0, CONVERGED = 1, MAXITER = 2, BREAKDOWN = 3, FIXED_DONE = 4 };
@@ -33,20 +33,34 @@ struct DevStatus {
   int n_over;           // hash entries in the overflow list (current iteration)
   int pcg_last;         // inner iterations of the last outer iteration
   int changed_last;
+  int n_active;         // meshes still iterating
   double residual;      // r_k of the last completed iteration
   double energy;        // Eq. 9 at x_k with the iteration's targets
   unsigned bar_count, bar_gen, pad0, pad1;
 };
 
+// Per-mesh constants of a problem made of one or several meshes.
+struct MeshConst {
+  double eps;       // offset of the collided boundary (eps_rel * h_ref)
+  double Lray;      // length of the inverse-normal search (ray_rel * h_ref)
+  double inv_cell;  // 1 / hash cell size
+  double inv_diag;  // 1 / bounding-box diagonal (residual scale)
+  double inv_mean_vol;  // 1 / mean rest tet volume (omega_e = Vol(e) / mean Vol)
+  int fbeg, fend;   // boundary faces of the mesh
+  int sbeg, send;   // query vertices of the mesh
+};
+
 // Scalars of one problem (passed by value to kernels).
 struct Consts {
   int n, T, S, F, nch, slots, H, ns, np;
+  int M;                // meshes
+  int mask_done;        // freeze meshes once they converge (not with fixed_iters)
   int self_col, obst_col, hyper;
   int max_iter, fixed_iters, pcg_max;
   int nparts;           // partial-sum slots per reduction array
   int ell_w;            // off-diagonal entries per row of the ELL matrix (16, 32 or 64)
   int trace_len;        // rows of the per-iteration trace
-  double c1, c2, kappa, eps, Lray, diag, tol, pcg_eta, inv_mean_vol, inv_cell;
+  double c1, c2, kappa, tol, pcg_eta;
 };
 
 // Device pointers, all inside the caller's workspace except the in/out buffers.
@@ -70,6 +84,9 @@ struct Dev {
   const int32_t* qf_list;  // incident boundary faces of each query vertex, ascending
   const double* kq;        // [S] spring stiffness
   const double* obst;      // spheres [ns][4] then planes [np][6]
+  const MeshConst* mesh;   // [M]
+  const int32_t* vmesh;    // [n] mesh of each vertex
+  const int32_t* tmesh;    // [T] mesh of each tet
   // iteration state
   R* u;                    // [3][n] displacement from X0
   double* xc;              // [3][n] X0 + u in double (collision positions)
@@ -98,6 +115,9 @@ struct Dev {
   double* part_d;
   double* part_e;
   double* part_f;
+  unsigned long long* mres;  // [M] max |d| per mesh (double bits; non-negative, so integer max works)
+  int32_t* mchanged;       // [M] active set of the mesh changed this iteration
+  int32_t* mdone;          // [M] iteration at which the mesh converged (0: still running)
   DevStatus* st;
   double* trace;           // [trace_len][6]
   // debug candidate buffers (null outside gs_collide_debug)

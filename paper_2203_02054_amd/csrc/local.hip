@@ -276,27 +276,36 @@ __global__ __launch_bounds__(kBlock) void k_local(Dev<R> d, Consts c, const R* _
   const int e = blockIdx.x * kBlock + threadIdx.x;
   double eloc = 0.0;
   if (e < c.T) {
-    int vi[4];
-    R P[3][4], D[3][4], Dminv[3][3];
-    double vol;
-    load_tet<R, false>(d, c, e, nullptr, vi, P, D, Dminv, vol);
-    const int tag = d.tag[e];
-    const int mode = tag & 7, ch = tag >> 3;
-    const R a = (mode != GS_BODY) ? alpha[ch] : R(1);
-    R Tt[3][4];
-    tet_target<R>(mode, a, P, D, Dminv, (R)vol, c, Tt);
-    const R om = (R)(vol * c.inv_mean_vol);
+    const int m = d.tmesh[e];
     V4<R>* res = reinterpret_cast<V4<R>*>(d.res4);
+    if (mesh_frozen(d, c.mask_done, m)) {
+      // a converged mesh of a batch: no residual, so its correction stays zero
+      V4<R> z;
+      z.x = z.y = z.z = z.w = R(0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const R r0 = Tt[0][j] - D[0][j], r1 = Tt[1][j] - D[1][j], r2 = Tt[2][j] - D[2][j];
-      V4<R> v;
-      v.x = om * r0;
-      v.y = om * r1;
-      v.z = om * r2;
-      v.w = R(0);
-      res[d.inc_pos[j * c.T + e]] = v;
-      eloc += (double)om * ((double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2);
+      for (int j = 0; j < 4; ++j) res[d.inc_pos[j * c.T + e]] = z;
+    } else {
+      int vi[4];
+      R P[3][4], D[3][4], Dminv[3][3];
+      double vol;
+      load_tet<R, false>(d, c, e, nullptr, vi, P, D, Dminv, vol);
+      const int tag = d.tag[e];
+      const int mode = tag & 7, ch = tag >> 3;
+      const R a = (mode != GS_BODY) ? alpha[ch] : R(1);
+      R Tt[3][4];
+      tet_target<R>(mode, a, P, D, Dminv, (R)vol, c, Tt);
+      const R om = (R)(vol * d.mesh[m].inv_mean_vol);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const R r0 = Tt[0][j] - D[0][j], r1 = Tt[1][j] - D[1][j], r2 = Tt[2][j] - D[2][j];
+        V4<R> v;
+        v.x = om * r0;
+        v.y = om * r1;
+        v.z = om * r2;
+        v.w = R(0);
+        res[d.inc_pos[j * c.T + e]] = v;
+        eloc += (double)om * ((double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2);
+      }
     }
   }
   const double bs = block_sum<kBlock>(eloc, lds);

@@ -48,8 +48,14 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
   const int stride = gridDim.x * kBlock;
   for (int i = v; i < c.H; i += stride) d.hcount[i] = 0;
   for (int i = v; i < c.S; i += stride) d.pen[i] = 0;
+  for (int i = v; i < c.M; i += stride) {
+    d.mdone[i] = 0;
+    d.mres[i] = 0ull;
+    d.mchanged[i] = 0;
+  }
   if (v == 0) {
     DevStatus* st = d.st;
+    st->n_active = c.M;
     st->iters = 0;
     st->done = RUNNING;
     st->changed = 0;
@@ -84,6 +90,10 @@ __global__ __launch_bounds__(kBlock) void k_set_positions(Dev<R> d, Consts c, co
   const int stride = gridDim.x * kBlock;
   for (int i = v; i < c.H; i += stride) d.hcount[i] = 0;
   for (int i = v; i < c.S; i += stride) d.pen[i] = 0;
+  for (int i = v; i < c.M; i += stride) {
+    d.mdone[i] = 0;
+    d.mchanged[i] = 0;
+  }
   if (v == 0) {
     DevStatus* st = d.st;
     st->done = RUNNING;
@@ -127,7 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(Dev<R> d, Consts c) {
       r2 += (double)t.z;
     }
     double ds = 0.0;
-    if (!d.freem[v]) {
+    const bool frozen = mesh_frozen(d, c.mask_done, d.vmesh[v]);
+    if (!d.freem[v] || frozen) {
       r0 = r1 = r2 = 0.0;
     } else {
       const int s = d.vq[v];
@@ -161,15 +172,17 @@ __global__ __launch_bounds__(kBlock) void k_gather(Dev<R> d, Consts c) {
 
 constexpr int kPcgBlock = kPcgThreads;
 
-// Sums of the G <= 64 block partials of two arrays in one round trip: wave 0
-// reduces `a`, wave 1 reduces `b`, each with a fixed shuffle tree (every block
-// obtains the same bits).
+// Sums of the G <= kMaxPcgGrid block partials of two arrays in one round
+// trip: wave 0 reduces `a`, wave 1 reduces `b`; lane l first adds entries
+// l, l+64, l+128, ... in that order, then a fixed shuffle tree combines the
+// lanes (every block obtains the same bits).
 __device__ __forceinline__ void grid_sum2(const double* a, const double* b, int G, double* sh, double& ra,
                                           double& rb) {
   if (threadIdx.x < 128) {
     const double* src = threadIdx.x < 64 ? a : b;
     const int l = threadIdx.x & 63;
     double t = (l < G) ? src[l] : 0.0;
+    for (int k = l + 64; k < G; k += 64) t += src[k];
     t = wave_sum(t);
     if (l == 0) sh[threadIdx.x >> 6] = t;
   }
@@ -215,21 +228,40 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   __shared__ int last;
   const size_t n = (size_t)c.n;
   const W4<R>* x = reinterpret_cast<const W4<R>*>(d.dl);
-  double dm = 0.0;
-  for (int v = tid0; v < c.n; v += stride) {
-    if (!d.freem[v]) continue;
-    const W4<R> dv = x[v];
-    const R dd[3] = {dv.x, dv.y, dv.z};
+  double dmax = 0.0;
+  for (int v0 = tid0 - (int)(threadIdx.x & 63); v0 < c.n; v0 += stride) {
+    // one wavefront handles 64 consecutive rows: the per-mesh maximum of |d|
+    // is reduced in the wavefront when all its rows share a mesh
+    const int v = v0 + (int)(threadIdx.x & 63);
+    double dm = 0.0;
+    int m = -1;
+    if (v < c.n) {
+      m = d.vmesh[v];
+      if (d.freem[v]) {
+        const W4<R> dv = x[v];
+        const R dd[3] = {dv.x, dv.y, dv.z};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const R uu = d.u[k * n + v] + dd[k];
-      d.u[k * n + v] = uu;
-      d.xc[k * n + v] = d.X0[k * n + v] + (double)uu;
+        for (int k = 0; k < 3; ++k) {
+          const R uu = d.u[k * n + v] + dd[k];
+          d.u[k * n + v] = uu;
+          d.xc[k * n + v] = d.X0[k * n + v] + (double)uu;
+        }
+        dm = sqrt(((double)dv.x * dv.x + (double)dv.y * dv.y) + (double)dv.z * dv.z);
+      }
     }
-    dm = fmax(dm, sqrt(((double)dv.x * dv.x + (double)dv.y * dv.y) + (double)dv.z * dv.z));
+    dmax = fmax(dmax, dm);
+    const int m0 = __shfl(m, 0, 64);
+    const bool uniform = __all(m == m0 || m < 0);
+    if (uniform) {
+      const double wm = wave_max(dm);
+      if ((threadIdx.x & 63) == 0 && m0 >= 0 && wm > 0.0)
+        atomicMax(&d.mres[m0], (unsigned long long)__double_as_longlong(wm));
+    } else if (m >= 0 && dm > 0.0) {
+      atomicMax(&d.mres[m], (unsigned long long)__double_as_longlong(dm));
+    }
   }
   for (int i = tid0; i < c.H; i += stride) d.hcount[i] = 0;
-  const double bm = block_max<kPcgBlock>(dm, lds);
+  const double bm = block_max<kPcgBlock>(dmax, lds);
   if (threadIdx.x == 0) {
     d.part_f[blockIdx.x] = bm;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -239,29 +271,42 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   }
   __syncthreads();
   if (!last) return;
-  // the last block reduces every block's partials (fixed order per thread,
-  // then a fixed tree: deterministic)
-  double mloc = 0.0, eloc = 0.0;
+  // the last block: energy (fixed order per thread, then a fixed tree), and the
+  // per-mesh convergence decisions (r = max|d| / diag, active set unchanged)
+  DevStatus* st = d.st;
+  const int it = st->iters + 1;
+  double eloc = 0.0, rloc = 0.0, active = 0.0, bad = 0.0;
   const int gl = cdiv(c.T, kBlock), gg = cdiv(c.n, kBlock);
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kPcgBlock) mloc = fmax(mloc, d.part_f[b]);
   for (int b = threadIdx.x; b < gl; b += kPcgBlock) eloc += d.part_a[b];
   for (int b = threadIdx.x; b < gg; b += kPcgBlock) eloc += d.part_b[b];
-  const double m = block_max<kPcgBlock>(mloc, lds);
+  for (int mi = threadIdx.x; mi < c.M; mi += kPcgBlock) {
+    const double r = __longlong_as_double((long long)d.mres[mi]) * d.mesh[mi].inv_diag;
+    const bool was_running = d.mdone[mi] == 0;
+    if (!(r == r) || isinf(r)) bad = 1.0;
+    if (was_running) {
+      rloc = fmax(rloc, r);
+      if (c.fixed_iters <= 0 && r <= c.tol && !d.mchanged[mi]) d.mdone[mi] = it;
+      if (d.mdone[mi] == 0) active += 1.0;
+    }
+    d.mres[mi] = 0ull;
+    d.mchanged[mi] = 0;
+  }
   const double E = block_sum<kPcgBlock>(eloc, lds);
+  const double res = block_max<kPcgBlock>(rloc, lds);
+  const double n_act = block_sum<kPcgBlock>(active, lds);
+  const double nbad = block_sum<kPcgBlock>(bad, lds);
   if (threadIdx.x != 0) return;
-  DevStatus* st = d.st;
-  const double res = m / c.diag;
   st->residual = res;
   st->energy = E;
-  const int it = st->iters + 1;
   st->iters = it;
+  st->n_active = (int)n_act;
   const int changed = st->changed;
   int code = RUNNING;
-  if (!(res == res) || isinf(res) || !(E == E))
+  if (nbad > 0.0 || !(E == E))
     code = BREAKDOWN;
   else if (c.fixed_iters > 0)
     code = (it >= c.fixed_iters) ? FIXED_DONE : RUNNING;
-  else if (res <= c.tol && !changed)
+  else if (n_act == 0.0)
     code = CONVERGED;
   else if (it >= c.max_iter)
     code = MAXITER;

@@ -86,6 +86,9 @@ SIGNATURES = {
     "gs_collide_debug_scratch": (ctypes.c_size_t, [_I]),
     "gs_collide_debug": (_I, [_P, _P, _I, _P, ctypes.c_size_t, _PI, _PI, _PI, _PI, _PI, _PD, _PI]),
     "gs_trace": (_I, [_P, _I, _PD, _PI]),
+    "gs_create_batch": (_I, [_I, ctypes.POINTER(MeshDesc), ctypes.POINTER(Params), ctypes.POINTER(_P)]),
+    "gs_batch_layout": (_I, [_P, _I, _PI, _PI, _PI, _PI]),
+    "gs_mesh_iters": (_I, [_P, _I, _PI]),
     "gs_profile": (_I, [_P, _I]),
     "gs_profile_read": (_I, [_P, _PD, ctypes.POINTER(ctypes.c_int64)]),
     "gs_kernel_name": (ctypes.c_char_p, [_I]),
@@ -144,22 +147,51 @@ class Problem:
 
     def __init__(self, rest_xyz, tets, tet_mode, tet_chamber, fixed, n_chambers, precision=4, params=None,
                  spheres=None, planes=None, device=None, stream=None, **kw):
+        self._setup([dict(rest_xyz=rest_xyz, tets=tets, tet_mode=tet_mode, tet_chamber=tet_chamber, fixed=fixed,
+                          n_chambers=n_chambers)], precision, params, spheres, planes, device, stream, kw)
+
+    @classmethod
+    def batch(cls, meshes, precision=4, params=None, spheres=None, planes=None, device=None, stream=None, **kw):
+        """Several meshes solved together (dicts with the Problem arguments, or
+        workloads); arrays are concatenated in mesh order."""
+        self = cls.__new__(cls)
+        ms = []
+        for m in meshes:
+            if not isinstance(m, dict):
+                m = dict(rest_xyz=m.rest_xyz, tets=m.tets, tet_mode=m.tet_mode, tet_chamber=m.tet_chamber,
+                         fixed=m.fixed, n_chambers=m.n_chambers)
+            ms.append(m)
+        self._setup(ms, precision, params, spheres, planes, device, stream, kw, batch=True)
+        return self
+
+    def _setup(self, meshes, precision, params, spheres, planes, device, stream, kw, batch=False):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device or "cuda")
         self.dtype = torch.float32 if precision == 4 else torch.float64
         self.np_dtype = np.float32 if precision == 4 else np.float64
-        self._X = np.ascontiguousarray(rest_xyz, dtype=np.float64)
-        self._T = np.ascontiguousarray(tets, dtype=np.int32)
-        self._m = np.ascontiguousarray(tet_mode, dtype=np.uint8)
-        self._c = np.ascontiguousarray(tet_chamber, dtype=np.int16)
-        self._f = np.ascontiguousarray(fixed, dtype=np.uint8)
-        self.n, self.T, self.n_chambers = self._X.shape[1], self._T.shape[1], int(n_chambers)
-        desc = MeshDesc(self.n, self.T, self.n_chambers, int(precision), self._X.ctypes.data, self._T.ctypes.data,
-                        self._m.ctypes.data, self._c.ctypes.data, self._f.ctypes.data)
+        self._keep = []
+        descs = (MeshDesc * len(meshes))()
+        for i, m in enumerate(meshes):
+            X = np.ascontiguousarray(m["rest_xyz"], dtype=np.float64)
+            T = np.ascontiguousarray(m["tets"], dtype=np.int32)
+            md = np.ascontiguousarray(m["tet_mode"], dtype=np.uint8)
+            ch = np.ascontiguousarray(m["tet_chamber"], dtype=np.int16)
+            fx = np.ascontiguousarray(m["fixed"], dtype=np.uint8)
+            self._keep += [X, T, md, ch, fx]
+            descs[i] = MeshDesc(X.shape[1], T.shape[1], int(m["n_chambers"]), int(precision), X.ctypes.data,
+                                T.ctypes.data, md.ctypes.data, ch.ctypes.data, fx.ctypes.data)
+        self._X = np.concatenate([np.asarray(m["rest_xyz"], dtype=np.float64) for m in meshes], axis=1)
+        self.n = self._X.shape[1]
+        self.T = sum(int(np.asarray(m["tets"]).shape[1]) for m in meshes)
+        self.n_chambers = sum(int(m["n_chambers"]) for m in meshes)
+        self.n_mesh = len(meshes)
         self.params = params if params is not None else default_params(**kw)
         h = _P()
-        _check(lib().gs_create(ctypes.byref(desc), ctypes.byref(self.params), ctypes.byref(h)))
+        if batch:
+            _check(lib().gs_create_batch(len(meshes), descs, ctypes.byref(self.params), ctypes.byref(h)))
+        else:
+            _check(lib().gs_create(ctypes.byref(descs[0]), ctypes.byref(self.params), ctypes.byref(h)))
         self._h = h
         sph = np.ascontiguousarray(np.zeros((0, 4)) if spheres is None else spheres, dtype=np.float64).reshape(-1, 4)
         pln = np.ascontiguousarray(np.zeros((0, 6)) if planes is None else planes, dtype=np.float64).reshape(-1, 6)
@@ -177,6 +209,20 @@ class Problem:
         inf = Info()
         _check(lib().gs_info_get(h, ctypes.byref(inf)))
         self.info = inf.as_dict()
+
+    def layout(self):
+        """Per-mesh offsets: dict of vert/tet/chamber offset arrays [n_mesh + 1]."""
+        cap = self.n_mesh + 1
+        v, t, c = (np.zeros(cap, np.int32) for _ in range(3))
+        nm = ctypes.c_int32()
+        _check(lib().gs_batch_layout(self._h, cap, _ptr(v, ctypes.c_int32), _ptr(t, ctypes.c_int32),
+                                     _ptr(c, ctypes.c_int32), ctypes.byref(nm)))
+        return dict(vert=v, tet=t, chamber=c)
+
+    def mesh_iters(self):
+        it = np.zeros(self.n_mesh, np.int32)
+        _check(lib().gs_mesh_iters(self._h, self.n_mesh, _ptr(it, ctypes.c_int32)))
+        return it
 
     @classmethod
     def from_workload(cls, wl, precision=None, **kw):

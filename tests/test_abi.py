@@ -108,3 +108,46 @@ def test_host_setup_matches_oracle(name):
     G.lib().gs_workspace_size(h, ctypes.byref(nb))
     assert nb.value > 0
     G.lib().gs_destroy(h)
+
+
+def test_batch_setup_concatenates_meshes():
+    """A batch is the meshes concatenated: its sizes are the sums of the single-mesh
+    set-ups and each mesh's oriented tets and faces are offset copies."""
+    wls = [mg.finger(4.0, 3, 2.0), mg.make("block"), mg.finger(4.0, 4, 1.5)]
+    probs = [oracle.Problem.from_workload(w) for w in wls]
+    keep = []
+    descs = (G.MeshDesc * len(wls))()
+    for i, w in enumerate(wls):
+        d, k = _desc(dict(rest_xyz=w.rest_xyz, tets=w.tets, tet_mode=w.tet_mode, tet_chamber=w.tet_chamber,
+                          fixed=w.fixed, n_chambers=w.n_chambers))
+        keep.append(k)
+        descs[i] = d
+    p = G.default_params()
+    h = ctypes.c_void_p()
+    assert G.lib().gs_create_batch(len(wls), descs, ctypes.byref(p), ctypes.byref(h)) == G.OK
+    info = G.Info()
+    G.lib().gs_info_get(h, ctypes.byref(info))
+    assert info.n_tets == sum(q.T for q in probs)
+    assert info.n_verts == sum(q.n for q in probs)
+    assert info.n_surface_faces == sum(q.faces.shape[0] for q in probs)
+    assert info.n_query_verts == sum(q.query_verts.size for q in probs)
+    vo = np.zeros(4, np.int32)
+    to = np.zeros(4, np.int32)
+    co = np.zeros(4, np.int32)
+    nm = ctypes.c_int32()
+    assert G.lib().gs_batch_layout(h, 4, vo.ctypes.data_as(G._PI), to.ctypes.data_as(G._PI),
+                                   co.ctypes.data_as(G._PI), ctypes.byref(nm)) == G.OK
+    assert nm.value == 3
+    np.testing.assert_array_equal(np.diff(vo), [q.n for q in probs])
+    np.testing.assert_array_equal(np.diff(co), [w.n_chambers for w in wls])
+    t = np.zeros((4, info.n_tets), np.int32)
+    G.lib().gs_tets(h, t.ctypes.data_as(G._PI))
+    f = np.zeros((3, info.n_surface_faces), np.int32)
+    G.lib().gs_faces(h, f.ctypes.data_as(G._PI))
+    fo = 0
+    for m, q in enumerate(probs):
+        np.testing.assert_array_equal(t[:, to[m]:to[m + 1]], q.tets + vo[m])
+        nf = q.faces.shape[0]
+        np.testing.assert_array_equal(f[:, fo:fo + nf].T, q.faces + vo[m])
+        fo += nf
+    G.lib().gs_destroy(h)
