@@ -262,7 +262,9 @@ def _released(x, c, n, eps) -> bool:
 def collide(prob, x: np.ndarray, prev: Contacts | None = None, want_candidates: bool = False):
     """Active set A_k at positions x given A_{k-1} = prev (Algorithm 1, CollisionCheck).
 
-    Returns (Contacts, info) with info = dict(pen_self, ray_miss, cand_tet, cand_tri).
+    Returns (Contacts, info) with info = dict(pen_self, self_fresh, ray_miss,
+    cand_tet, cand_tri); self_fresh marks the self contacts given a new target
+    at x (the others keep a stored one).
     """
     p = prob.params
     qv = prob.query_verts
@@ -272,7 +274,8 @@ def collide(prob, x: np.ndarray, prev: Contacts | None = None, want_candidates: 
         prev = Contacts.empty(S, prob.n_slots)
     eps = prob.eps_off
     x = np.asarray(x, dtype=np.float64)
-    info = dict(ray_miss=0, pen_self=np.zeros(S, bool), cand_tet=None, cand_tri=None)
+    info = dict(ray_miss=0, pen_self=np.zeros(S, bool), self_fresh=np.zeros(S, bool), cand_tet=None,
+                cand_tri=None)
 
     if p.self_collision:
         v, e, inside = tet_candidates(prob, x, qv)
@@ -299,6 +302,7 @@ def collide(prob, x: np.ndarray, prev: Contacts | None = None, want_candidates: 
                 c, n, f = fresh[s]
                 out.active[s, 0] = True
                 out.target[s, 0], out.normal[s, 0], out.prim[s, 0] = c, n, f
+                info["self_fresh"][s] = True
             elif prev.active[s, 0]:
                 keep = True if pen[s] else not _released(x[:, qv[s]], prev.target[s, 0],
                                                          prev.normal[s, 0], eps)

@@ -61,10 +61,12 @@ def _det3(A: torch.Tensor) -> torch.Tensor:
 
 def targets_torch(xe: torch.Tensor, alpha: torch.Tensor, P: torch.Tensor, Dm_inv: torch.Tensor,
                   vol: torch.Tensor, mode: torch.Tensor, chamber: torch.Tensor,
-                  c1: float, c2: float, hyperelastic: bool):
+                  c1: float, c2: float, hyperelastic: bool, rotation=None):
     """Target shapes T_e (T,3,4) and rotations R_e for current positions xe (T,3,4).
 
-    Differentiable in xe and alpha (float64 tensors).
+    Differentiable in xe and alpha (float64 tensors).  ``rotation`` replaces
+    ``kabsch`` (same values; the gradient oracle passes one with an explicit
+    derivative).
     """
     Nm = torch.as_tensor(centring(), dtype=xe.dtype)
     D = xe @ Nm
@@ -79,7 +81,7 @@ def targets_torch(xe: torch.Tensor, alpha: torch.Tensor, P: torch.Tensor, Dm_inv
     S = torch.stack([sx, sy, sz], dim=-1)
     S = torch.where(is_ch[:, None], S, torch.ones_like(S))
     Q = S[:, :, None] * P                                      # diag(s) P; body: P
-    R = kabsch(D @ Q.transpose(1, 2))
+    R = (rotation or kabsch)(D @ Q.transpose(1, 2))
     RQ = R @ Q
 
     # body blend (Eq. 6) and volume scaling (Eq. 7)
