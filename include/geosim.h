@@ -104,6 +104,8 @@ typedef struct {
   int32_t check_every;    /* outer iterations between host convergence polls     */
   int32_t pcg_blocks;     /* workgroups of the cooperative CG kernel (0: auto)    */
   int32_t trace_len;      /* iterations recorded by gs_trace (workspace grows)    */
+  double adj_tol;         /* adjoint stop: max|d mu| <= adj_tol max|mu| per mesh  */
+  int32_t adj_max_iter;   /* adjoint iteration cap                                */
 } gs_params;
 
 typedef struct {
@@ -131,7 +133,7 @@ const char* gs_last_error(void);
 /* Defaults: Ecoflex 00-30 (c1 = 0.0418, c2 = 0.0106 MPa), hyperelastic on,
  * kappa_col 1, eps_rel 0.05, ray_rel 4, no collision, tol 1e-6,
  * max_iter 20000, fixed_iters 0, pcg_eta 1e-3, pcg_max 200, check_every 16,
- * pcg_blocks 0, trace_len 0. */
+ * pcg_blocks 0, trace_len 0, adj_tol 1e-6, adj_max_iter 20000. */
 void gs_default_params(gs_params* params);
 
 /* Host set-up for one mesh (done once per mesh; not per iteration): orient
@@ -203,16 +205,42 @@ gs_status gs_reset_contacts(gs_problem* p);
 
 /* Copy out the stored active set sorted by (vertex, type, prim): prim is the
  * hit boundary-face id for self contacts and the obstacle index otherwise;
- * target/normal are [cap][3] (x,y,z per row).  *count receives the number
- * of contacts; GS_ECAPACITY if it exceeds cap (nothing else written). */
+ * target/normal are [cap][3] (x,y,z per row); fresh[i] is 1 for a self
+ * contact whose target was recomputed from the current positions in the
+ * last collision check (its vertex penetrates and its ray hit prim), 0 for
+ * one kept with its stored target (Eq. 8) and for obstacle contacts.  Any
+ * output pointer may be NULL.  *count receives the number of contacts;
+ * GS_ECAPACITY if it exceeds cap (nothing else written). */
 gs_status gs_contacts(gs_problem* p, int32_t cap, int32_t* v, int32_t* type, int32_t* prim,
-                      double* target, double* normal, int32_t* count);
+                      double* target, double* normal, int32_t* fresh, int32_t* count);
 
-/* Import an active set (for resuming a solve).  Rows as gs_contacts gives
- * them; at most one contact per (vertex, type, prim) slot.  GS_EINVAL for a
- * vertex that is not a query vertex or an out-of-range prim. */
+/* Import an active set (for resuming a solve, or to fix the state an adjoint
+ * linearises).  Rows as gs_contacts gives them (fresh may be NULL: all 0); at
+ * most one contact per (vertex, type, prim) slot.  GS_EINVAL for a vertex
+ * that is not a query vertex, an out-of-range prim, or fresh set on an
+ * obstacle contact. */
 gs_status gs_set_contacts(gs_problem* p, int32_t count, const int32_t* v, const int32_t* type,
-                          const int32_t* prim, const double* target, const double* normal);
+                          const int32_t* prim, const double* target, const double* normal,
+                          const int32_t* fresh);
+
+/* Implicit adjoint of the last gs_solve (not in the paper: the gradient of
+ * its fixed point).  At the positions x the solve returned, with the stored
+ * active set held fixed and the volume ratios alpha of that solve, the free
+ * coordinates satisfy M_FF x_F = b_F(x, alpha) - M_FC x_C (M = A_el +
+ * springs, b = element targets of Section III-A plus spring targets of
+ * Section II-C); for dev_dLdx [3][n] = dL/dx this computes
+ *   dev_dLdalpha[n_chambers] = (db_F/dalpha)^T mu,  (M_FF - db_F/dx_F)^T mu = g_F
+ * by the iteration mu <- M^-1 (g + (db/dx)^T mu) in correction form (same CG
+ * as the solve, pcg_eta / pcg_max apply), until max|d mu| <= adj_tol max|mu|
+ * on every mesh or adj_max_iter iterations.  Self contacts flagged fresh
+ * (gs_contacts) follow x through the ray target; kept self contacts are
+ * constant; obstacle targets follow x in closed form.  dev_mu [3][n] (may be
+ * NULL) receives mu (zero on fixed vertices).  Both outputs use the
+ * problem's width.  stats (may be NULL): iters = adjoint iterations,
+ * pcg_iters_total, residual = the largest max|d mu| / max|mu|.  Returns
+ * GS_OK, GS_NOT_CONVERGED (gradient of the last iterate written),
+ * GS_ESTATE (no solve since gs_bind), GS_EINVAL, GS_EBREAKDOWN, GS_EHIP. */
+gs_status gs_adjoint(gs_problem* p, const void* dev_dLdx, void* dev_dLdalpha, void* dev_mu, gs_stats* stats);
 
 /* Local step alone (Section III-A) at positions dev_x [3][n]: writes the
  * centred target shapes to dev_targets [3][4][T] (row c, tet slot j, tet e
@@ -255,11 +283,12 @@ gs_status gs_trace(gs_problem* p, int32_t cap, double* rows, int32_t* count);
 
 /* Kernel timing.  gs_profile(p, 1) resets the totals and brackets every
  * kernel that gs_solve launches with a pair of HIP events on the bound
- * stream; gs_profile_read returns, per kernel id k < GS_N_KERNELS, the summed
+ * stream (gs_adjoint likewise: its kernels are named "adj_*");
+ * gs_profile_read returns, per kernel id k < GS_N_KERNELS, the summed
  * duration in milliseconds and the number of launches; gs_kernel_name(k)
  * names the kernel ("pcg", "local", ...); the CG kernel also applies the
  * correction and takes the convergence decision.  gs_profile(p, 0) stops. */
-#define GS_N_KERNELS 7
+#define GS_N_KERNELS 11
 gs_status gs_profile(gs_problem* p, int32_t enable);
 gs_status gs_profile_read(const gs_problem* p, double* ms, int64_t* launches);
 const char* gs_kernel_name(int32_t k);

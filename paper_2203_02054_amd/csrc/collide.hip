@@ -156,12 +156,6 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
     test_point<R, DEBUG>(d, reinterpret_cast<const double4*>(d.hover)[i], e, m, vi, p, lo, hi);
 }
 
-__device__ __forceinline__ void load3(const double* xc, size_t n, int v, double* o) {
-  o[0] = xc[v];
-  o[1] = xc[n + v];
-  o[2] = xc[2 * n + v];
-}
-
 // One wavefront per penetrating vertex: vertex normal, then the first hit of
 // [x_v, x_v - L_ray n_v] on a boundary face not containing v.
 template <typename R, bool DEBUG>
@@ -312,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
       now = pen ? true : !released(x, d.ctgt + 3 * base, d.cnrm + 3 * base, eps);
     }
     if (pen && hit < 0) atomicAdd(&d.st->ray_miss, 1);
-    d.cact[base] = now ? 1 : 0;
+    d.cact[base] = now ? ((pen && hit >= 0) ? 2 : 1) : 0;
     changed |= (now != old);
     nact += now;
     d.pen[s] = 0;

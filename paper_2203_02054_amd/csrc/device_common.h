@@ -123,6 +123,13 @@ __device__ __forceinline__ bool moller_trumbore(const double* o, const double* d
   return (u >= 0.0) && (w >= 0.0) && (u + w <= 1.0) && (t > 0.0) && (t <= L);
 }
 
+// Vertex v of an SoA [3][n] double array.
+__device__ __forceinline__ void load3(const double* xc, size_t n, int v, double* o) {
+  o[0] = xc[v];
+  o[1] = xc[n + v];
+  o[2] = xc[2 * n + v];
+}
+
 // Spatial-hash cell of a coordinate (monotone in x, so a point inside a box
 // lies in a cell of the box's cell range).
 __device__ __forceinline__ int cell_of(double x, double inv_cell) { return (int)floor(x * inv_cell); }

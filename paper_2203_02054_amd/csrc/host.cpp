@@ -51,13 +51,16 @@ struct Layout {
       obst;
   size_t u, xc, res4, cg, dl, p, dg, dsp, pen, hcount, hslot, hover, penlist, fhit, fc, fn, cact, ctgt, cnrm,
       cprim, part_a, part_b, part_c, part_d, part_e, part_f, st, trace, mesh, vmesh, tmesh, mres, mchanged, mdone;
+  size_t mu, acc3, ga, ch_start, ch_tets, mmax, mdone2, st2, alpha_last;
   size_t total;
 };
 
-constexpr int kNKernels = 7;
-const char* const kKernelNames[kNKernels] = {"hash_insert", "tet_query", "ray_cast", "contacts",
-                                             "local",       "gather",    "pcg"};
-enum { K_CONTACTS = 3, K_LOCAL = 4, K_GATHER = 5, K_PCG = 6 };
+constexpr int kNKernels = 11;
+const char* const kKernelNames[kNKernels] = {"hash_insert", "tet_query", "ray_cast",  "contacts",
+                                             "local",       "gather",    "pcg",       "adj_springs",
+                                             "adj_local",   "adj_gather", "adj_pcg"};
+enum { K_CONTACTS = 3, K_LOCAL = 4, K_GATHER = 5, K_PCG = 6, K_ADJ_SPRINGS = 7, K_ADJ_LOCAL = 8, K_ADJ_GATHER = 9,
+       K_ADJ_PCG = 10 };
 
 // Optional per-kernel timing: each launch is bracketed by two events on the
 // bound stream; elapsed times are collected whenever the driver synchronises.
@@ -121,6 +124,7 @@ struct gs_problem {
   std::vector<double> mh_ref, mdiag, mcell, minv_mean_vol;
   std::vector<int32_t> vbeg, tbeg, chbeg, fbeg, sbeg;  // [M+1] offsets
   std::vector<int32_t> vmesh, tmesh;
+  std::vector<int32_t> ch_start, ch_tets;  // chamber -> tets (ascending)
   // device binding
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -130,6 +134,7 @@ struct gs_problem {
   int pcg_grid = 1;
   int trace_len = 0;
   int last_iters = 0;
+  bool solved = false;  // a solve has run since gs_bind (the adjoint's state exists)
   Profiler prof;
 };
 
@@ -145,6 +150,7 @@ gs_status check_params(const gs_params* p) {
   if (!(p->pcg_eta > 0 && p->pcg_eta < 1) || p->pcg_max < 1) return fail(GS_EINVAL, "bad pcg_eta/pcg_max");
   if (p->check_every < 1) return fail(GS_EINVAL, "check_every must be >= 1");
   if (p->trace_len < 0) return fail(GS_EINVAL, "trace_len must be >= 0");
+  if (!(p->adj_tol >= 0) || p->adj_max_iter < 1) return fail(GS_EINVAL, "bad adj_tol/adj_max_iter");
   return GS_OK;
 }
 
@@ -210,6 +216,15 @@ Layout make_layout(const gs_problem* p) {
   L.mres = take((size_t)p->M * 8);
   L.mchanged = take((size_t)p->M * 4);
   L.mdone = take((size_t)p->M * 4);
+  L.mu = take(3 * n * W);
+  L.acc3 = take(3 * n * 8);
+  L.ga = take(T * 8);
+  L.ch_start = take(((size_t)p->nch + 1) * 4);
+  L.ch_tets = take(p->ch_tets.size() * 4);
+  L.mmax = take((size_t)p->M * 8);
+  L.mdone2 = take((size_t)p->M * 4);
+  L.st2 = take(sizeof(DevStatus));
+  L.alpha_last = take((size_t)p->nch * W);
   L.total = align256(off);
   return L;
 }
@@ -270,6 +285,14 @@ Dev<R> make_dev(const gs_problem* p) {
   d.mres = (unsigned long long*)(b + L.mres);
   d.mchanged = (int32_t*)(b + L.mchanged);
   d.mdone = (int32_t*)(b + L.mdone);
+  d.mu = (R*)(b + L.mu);
+  d.gL = nullptr;
+  d.acc3 = (double*)(b + L.acc3);
+  d.ga = (double*)(b + L.ga);
+  d.ch_start = (const int32_t*)(b + L.ch_start);
+  d.ch_tets = (const int32_t*)(b + L.ch_tets);
+  d.mmax = (unsigned long long*)(b + L.mmax);
+  d.alpha_last = (R*)(b + L.alpha_last);
   d.dbg_tet = nullptr;
   d.dbg_tri = nullptr;
   d.dbg_cap = 0;
@@ -366,6 +389,8 @@ gs_status bind_impl(gs_problem* p) {
   HIPCHK(upload(b, L.mesh, mt, s));
   HIPCHK(upload(b, L.vmesh, p->vmesh, s));
   HIPCHK(upload(b, L.tmesh, p->tmesh, s));
+  HIPCHK(upload(b, L.ch_start, p->ch_start, s));
+  HIPCHK(upload(b, L.ch_tets, p->ch_tets, s));
   HIPCHK(hipMemsetAsync(b + L.mres, 0, (size_t)p->M * 8, s));
   HIPCHK(hipMemsetAsync(b + L.mchanged, 0, (size_t)p->M * 4, s));
   HIPCHK(hipMemsetAsync(b + L.mdone, 0, (size_t)p->M * 4, s));
@@ -411,6 +436,8 @@ gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
   const Dev<R> d = make_dev<R>(p);
   const Consts c = make_consts(p);
   hipStream_t s = p->stream;
+  if (p->nch > 0)
+    HIPCHK(hipMemcpyAsync(d.alpha_last, alpha, (size_t)p->nch * sizeof(R), hipMemcpyDeviceToDevice, s));
   HIPCHK(launch_init<R>(d, c, x, s));
   DevStatus h{};
   const int limit = p->prm.fixed_iters > 0 ? p->prm.fixed_iters : p->prm.max_iter;
@@ -428,6 +455,7 @@ gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
   HIPCHK(launch_output<R>(d, c, x, s));
   HIPCHK(hipStreamSynchronize(s));
   p->last_iters = h.iters;
+  p->solved = true;
   if (stats) {
     stats->iters = h.iters;
     stats->pcg_iters_total = h.pcg_total;
@@ -443,6 +471,60 @@ gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
   }
   if (h.done == FIXED_DONE && !(h.residual <= p->prm.tol && !h.changed_last)) {
     g_err = "fixed iteration count reached above tolerance";
+    return GS_NOT_CONVERGED;
+  }
+  return GS_OK;
+}
+
+// Implicit adjoint: mu <- M^-1 (g + (db/dx)^T mu) in correction form with its
+// own status block and per-mesh done flags, then dL/dalpha per chamber.
+template <typename R>
+gs_status adjoint_impl(gs_problem* p, const R* gL, R* dalpha, R* mu_out, gs_stats* stats) {
+  Dev<R> d = make_dev<R>(p);
+  d.st = (DevStatus*)(p->ws + p->lay.st2);
+  d.mdone = (int32_t*)(p->ws + p->lay.mdone2);
+  d.gL = gL;
+  Consts c = make_consts(p);
+  c.fixed_iters = 0;
+  c.mask_done = 1;
+  c.tol = p->prm.adj_tol;
+  c.max_iter = p->prm.adj_max_iter;
+  c.trace_len = 0;
+  hipStream_t s = p->stream;
+  HIPCHK(launch_adj_init<R>(d, c, s));
+  DevStatus h{};
+  const int limit = c.max_iter;
+  int enq = 0;
+  while (true) {
+    const int chunk = std::min(p->prm.check_every, std::max(1, limit - enq));
+    for (int i = 0; i < chunk; ++i) {
+      HIPCHK(timed(p, K_ADJ_SPRINGS, [&] { return launch_adj_springs<R>(d, c, s); }));
+      HIPCHK(timed(p, K_ADJ_LOCAL, [&] { return launch_adj_local<R>(d, c, false, s); }));
+      HIPCHK(timed(p, K_ADJ_GATHER, [&] { return launch_adj_gather<R>(d, c, s); }));
+      HIPCHK(timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, true); }));
+    }
+    enq += chunk;
+    HIPCHK(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (p->prof.on) HIPCHK(p->prof.flush());
+    if (h.done != RUNNING) break;
+    if (enq >= limit + p->prm.check_every) return fail(GS_EHIP, "adjoint driver out of step with the device");
+  }
+  HIPCHK(launch_adj_local<R>(d, c, true, s));
+  HIPCHK(launch_adj_chamber_sum<R>(d, c, dalpha, s));
+  if (mu_out) HIPCHK(hipMemcpyAsync(mu_out, d.mu, 3 * (size_t)p->n * sizeof(R), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (stats) {
+    stats->iters = h.iters;
+    stats->pcg_iters_total = h.pcg_total;
+    stats->n_contacts = 0;
+    stats->ray_miss = 0;
+    stats->residual = h.residual;
+    stats->energy = 0.0;
+  }
+  if (h.done == BREAKDOWN) return fail(GS_EBREAKDOWN, "non-finite value or CG curvature p'Ap <= 0 in the adjoint");
+  if (h.done == MAXITER) {
+    g_err = "adj_max_iter reached";
     return GS_NOT_CONVERGED;
   }
   return GS_OK;
@@ -714,6 +796,15 @@ void finalize(gs_problem* p) {
   p->H = H;
   p->nparts = std::max({cdiv(p->T, kBlock), cdiv(n, kBlock), 2 * kMaxPcgGrid});
   p->slots = 1 + p->ns + p->np;
+  // chamber -> tets, ascending tet id within a chamber
+  p->ch_start.assign(p->nch + 1, 0);
+  for (int e = 0; e < p->T; ++e)
+    if ((p->tag[e] & 7) != GS_BODY) p->ch_start[(p->tag[e] >> 3) + 1]++;
+  for (int c = 0; c < p->nch; ++c) p->ch_start[c + 1] += p->ch_start[c];
+  p->ch_tets.assign(p->ch_start[p->nch], 0);
+  std::vector<int32_t> cur(p->ch_start.begin(), p->ch_start.end() - 1);
+  for (int e = 0; e < p->T; ++e)
+    if ((p->tag[e] & 7) != GS_BODY) p->ch_tets[cur[p->tag[e] >> 3]++] = e;
 }
 
 // Concatenate single-mesh set-ups into one problem: vertex, tet, chamber,
@@ -859,6 +950,8 @@ void gs_default_params(gs_params* p) {
   p->check_every = 16;
   p->pcg_blocks = 0;
   p->trace_len = 0;
+  p->adj_tol = 1e-6;
+  p->adj_max_iter = 20000;
 }
 
 gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** out) {
@@ -1022,6 +1115,7 @@ gs_status gs_bind(gs_problem* p, void* ws, size_t bytes, void* stream) {
   p->ws_bytes = bytes;
   p->stream = (hipStream_t)stream;
   p->bound = false;
+  p->solved = false;
   const gs_status st = p->prec == 4 ? bind_impl<float>(p) : bind_impl<double>(p);
   if (st == GS_OK) p->bound = true;
   return st;
@@ -1060,6 +1154,15 @@ gs_status gs_solve(gs_problem* p, const void* alpha, void* x, gs_stats* stats) {
   return solve_impl<double>(p, (const double*)alpha, (double*)x, stats);
 }
 
+gs_status gs_adjoint(gs_problem* p, const void* dLdx, void* dLdalpha, void* mu, gs_stats* stats) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "gs_adjoint before gs_bind");
+  if (!p->solved) return fail(GS_ESTATE, "gs_adjoint needs a gs_solve first");
+  if (!dLdx || (p->nch > 0 && !dLdalpha)) return fail(GS_EINVAL, "null device buffer");
+  if (p->prec == 4) return adjoint_impl<float>(p, (const float*)dLdx, (float*)dLdalpha, (float*)mu, stats);
+  return adjoint_impl<double>(p, (const double*)dLdx, (double*)dLdalpha, (double*)mu, stats);
+}
+
 gs_status gs_reset_contacts(gs_problem* p) {
   if (!p) return fail(GS_EINVAL, "null problem");
   if (!p->bound) return fail(GS_ESTATE, "not bound");
@@ -1069,7 +1172,7 @@ gs_status gs_reset_contacts(gs_problem* p) {
 }
 
 gs_status gs_contacts(gs_problem* p, int32_t cap, int32_t* v, int32_t* type, int32_t* prim, double* target,
-                      double* normal, int32_t* count) {
+                      double* normal, int32_t* fresh, int32_t* count) {
   if (!p || !count) return fail(GS_EINVAL, "null argument");
   if (!p->bound) return fail(GS_ESTATE, "not bound");
   const size_t m = (size_t)p->S * p->slots;
@@ -1093,6 +1196,7 @@ gs_status gs_contacts(gs_problem* p, int32_t cap, int32_t* v, int32_t* type, int
       if (v) v[o] = p->qverts[s];
       if (type) type[o] = sl == 0 ? GS_CONTACT_SELF : (sl <= p->ns ? GS_CONTACT_SPHERE : GS_CONTACT_PLANE);
       if (prim) prim[o] = pr[i];
+      if (fresh) fresh[o] = act[i] == 2 ? 1 : 0;
       for (int c = 0; c < 3; ++c) {
         if (target) target[3 * o + c] = tg[3 * i + c];
         if (normal) normal[3 * o + c] = nr[3 * i + c];
@@ -1103,7 +1207,7 @@ gs_status gs_contacts(gs_problem* p, int32_t cap, int32_t* v, int32_t* type, int
 }
 
 gs_status gs_set_contacts(gs_problem* p, int32_t count, const int32_t* v, const int32_t* type, const int32_t* prim,
-                          const double* target, const double* normal) {
+                          const double* target, const double* normal, const int32_t* fresh) {
   if (!p) return fail(GS_EINVAL, "null problem");
   if (!p->bound) return fail(GS_ESTATE, "not bound");
   if (count < 0 || (count > 0 && (!v || !type || !prim || !target || !normal))) return fail(GS_EINVAL, "bad arrays");
@@ -1128,7 +1232,9 @@ gs_status gs_set_contacts(gs_problem* p, int32_t count, const int32_t* v, const 
     }
     const size_t j = (size_t)p->vq[v[i]] * p->slots + sl;
     if (act[j]) return fail(GS_EINVAL, "duplicate contact");
-    act[j] = 1;
+    const bool fr = fresh && fresh[i];
+    if (fr && sl != 0) return fail(GS_EINVAL, "only self contacts can be fresh");
+    act[j] = fr ? 2 : 1;
     pr[j] = prim[i];
     for (int c = 0; c < 3; ++c) {
       tg[3 * j + c] = target[3 * i + c];
@@ -1237,7 +1343,7 @@ gs_status gs_collide_debug(gs_problem* p, const void* x, int32_t cap, void* scra
   std::vector<int32_t> cv(std::max<size_t>(m, 1)), ct(std::max<size_t>(m, 1)), cp(std::max<size_t>(m, 1));
   std::vector<double> ctg(3 * std::max<size_t>(m, 1)), cnr(3 * std::max<size_t>(m, 1));
   int32_t cnt = 0;
-  st = gs_contacts(p, (int32_t)m, cv.data(), ct.data(), cp.data(), ctg.data(), cnr.data(), &cnt);
+  st = gs_contacts(p, (int32_t)m, cv.data(), ct.data(), cp.data(), ctg.data(), cnr.data(), nullptr, &cnt);
   HIPCHK(hipMemcpyAsync(p->ws + p->lay.cact, act.data(), m, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->ws + p->lay.ctgt, tg.data(), 3 * m * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(p->ws + p->lay.cnrm, nr.data(), 3 * m * 8, hipMemcpyHostToDevice, s));

@@ -105,7 +105,7 @@ struct Dev {
   int32_t* fhit;           // [S] fresh self hit face or -1
   double* fc;              // [S][3] fresh self target
   double* fn;              // [S][3] fresh self normal
-  uint8_t* cact;           // [S][slots]
+  uint8_t* cact;           // [S][slots] 0 inactive, 1 active, 2 self contact given a new target this iteration
   double* ctgt;            // [S][slots][3]
   double* cnrm;            // [S][slots][3]
   int32_t* cprim;          // [S][slots]
@@ -120,6 +120,16 @@ struct Dev {
   int32_t* mdone;          // [M] iteration at which the mesh converged (0: still running)
   DevStatus* st;
   double* trace;           // [trace_len][6]
+  // implicit adjoint (gs_adjoint); the adjoint iteration runs with its own
+  // status block and per-mesh done flags in place of st / mdone
+  R* mu;                   // [3][n] adjoint iterate
+  const R* gL;             // [3][n] dL/dx (caller's buffer)
+  double* acc3;            // [3][n] adjoint of the new self-contact targets, scattered (cleared by the gather)
+  double* ga;              // [T] per-tet contribution to dL/dalpha
+  const int32_t* ch_start; // [nch+1] chamber -> tets
+  const int32_t* ch_tets;  // chamber tets grouped by chamber, ascending
+  unsigned long long* mmax;  // [M] max |mu| per mesh (double bits)
+  R* alpha_last;           // [nch] volume ratios of the last solve
   // debug candidate buffers (null outside gs_collide_debug)
   int32_t* dbg_tet;        // [2][cap]
   int32_t* dbg_tri;        // [2][cap]
@@ -139,7 +149,15 @@ template <typename R> hipError_t launch_local(const Dev<R>& d, const Consts& c, 
 template <typename R> hipError_t launch_local_debug(const Dev<R>& d, const Consts& c, const R* alpha, const R* x,
                                                     R* targets, hipStream_t s);
 template <typename R> hipError_t launch_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
-template <typename R> hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s);
+template <typename R>
+hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint = false);
+// implicit adjoint
+template <typename R> hipError_t launch_adj_init(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R> hipError_t launch_adj_springs(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R>
+hipError_t launch_adj_local(const Dev<R>& d, const Consts& c, bool alpha_grad, hipStream_t s);
+template <typename R> hipError_t launch_adj_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R> hipError_t launch_adj_chamber_sum(const Dev<R>& d, const Consts& c, R* out, hipStream_t s);
 template <typename R> hipError_t launch_set_positions(const Dev<R>& d, const Consts& c, const R* x, hipStream_t s);
 template <typename R> int pcg_max_grid(int block);
 

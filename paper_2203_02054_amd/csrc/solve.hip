@@ -19,6 +19,8 @@
 // participating blocks, so the solve uses few, wide blocks.  Dot products are
 // accumulated in double; block partials are summed in block order by every
 // block, so all blocks take identical decisions.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace gs {
@@ -223,7 +225,9 @@ __device__ __forceinline__ W4<R> w4(R x, R y, R z) {
 // u += d on the rows each block owns, collision positions refreshed, hash
 // buckets cleared for the next iteration; r_k = max|d| / diag and the
 // convergence decision are taken by the last block to arrive (ticket).
-template <typename R>
+// In the adjoint iteration (ADJ) the update is mu += d and a mesh is done once
+// max|d| <= tol max|mu| over its vertices.
+template <typename R, bool ADJ>
 __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, int tid0, int stride, double* lds) {
   __shared__ int last;
   const size_t n = (size_t)c.n;
@@ -233,20 +237,28 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
     // one wavefront handles 64 consecutive rows: the per-mesh maximum of |d|
     // is reduced in the wavefront when all its rows share a mesh
     const int v = v0 + (int)(threadIdx.x & 63);
-    double dm = 0.0;
+    double dm = 0.0, um = 0.0;
     int m = -1;
     if (v < c.n) {
       m = d.vmesh[v];
       if (d.freem[v]) {
         const W4<R> dv = x[v];
         const R dd[3] = {dv.x, dv.y, dv.z};
+        double uq = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const R uu = d.u[k * n + v] + dd[k];
-          d.u[k * n + v] = uu;
-          d.xc[k * n + v] = d.X0[k * n + v] + (double)uu;
+          if (ADJ) {
+            const R mm = d.mu[k * n + v] + dd[k];
+            d.mu[k * n + v] = mm;
+            uq += (double)mm * (double)mm;
+          } else {
+            const R uu = d.u[k * n + v] + dd[k];
+            d.u[k * n + v] = uu;
+            d.xc[k * n + v] = d.X0[k * n + v] + (double)uu;
+          }
         }
         dm = sqrt(((double)dv.x * dv.x + (double)dv.y * dv.y) + (double)dv.z * dv.z);
+        um = sqrt(uq);
       }
     }
     dmax = fmax(dmax, dm);
@@ -256,11 +268,18 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
       const double wm = wave_max(dm);
       if ((threadIdx.x & 63) == 0 && m0 >= 0 && wm > 0.0)
         atomicMax(&d.mres[m0], (unsigned long long)__double_as_longlong(wm));
-    } else if (m >= 0 && dm > 0.0) {
-      atomicMax(&d.mres[m], (unsigned long long)__double_as_longlong(dm));
+      if (ADJ) {
+        const double wu = wave_max(um);
+        if ((threadIdx.x & 63) == 0 && m0 >= 0 && wu > 0.0)
+          atomicMax(&d.mmax[m0], (unsigned long long)__double_as_longlong(wu));
+      }
+    } else if (m >= 0) {
+      if (dm > 0.0) atomicMax(&d.mres[m], (unsigned long long)__double_as_longlong(dm));
+      if (ADJ && um > 0.0) atomicMax(&d.mmax[m], (unsigned long long)__double_as_longlong(um));
     }
   }
-  for (int i = tid0; i < c.H; i += stride) d.hcount[i] = 0;
+  if (!ADJ)
+    for (int i = tid0; i < c.H; i += stride) d.hcount[i] = 0;
   const double bm = block_max<kPcgBlock>(dmax, lds);
   if (threadIdx.x == 0) {
     d.part_f[blockIdx.x] = bm;
@@ -276,20 +295,30 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   DevStatus* st = d.st;
   const int it = st->iters + 1;
   double eloc = 0.0, rloc = 0.0, active = 0.0, bad = 0.0;
-  const int gl = cdiv(c.T, kBlock), gg = cdiv(c.n, kBlock);
-  for (int b = threadIdx.x; b < gl; b += kPcgBlock) eloc += d.part_a[b];
-  for (int b = threadIdx.x; b < gg; b += kPcgBlock) eloc += d.part_b[b];
+  if (!ADJ) {
+    const int gl = cdiv(c.T, kBlock), gg = cdiv(c.n, kBlock);
+    for (int b = threadIdx.x; b < gl; b += kPcgBlock) eloc += d.part_a[b];
+    for (int b = threadIdx.x; b < gg; b += kPcgBlock) eloc += d.part_b[b];
+  }
   for (int mi = threadIdx.x; mi < c.M; mi += kPcgBlock) {
-    const double r = __longlong_as_double((long long)d.mres[mi]) * d.mesh[mi].inv_diag;
+    const double dmx = __longlong_as_double((long long)d.mres[mi]);
+    double r;
+    if (ADJ) {
+      const double umx = __longlong_as_double((long long)d.mmax[mi]);
+      r = umx > 0.0 ? dmx / umx : (dmx > 0.0 ? INFINITY : 0.0);
+      d.mmax[mi] = 0ull;
+    } else {
+      r = dmx * d.mesh[mi].inv_diag;
+    }
     const bool was_running = d.mdone[mi] == 0;
-    if (!(r == r) || isinf(r)) bad = 1.0;
+    if (!(r == r) || (isinf(r) && !ADJ)) bad = 1.0;
     if (was_running) {
       rloc = fmax(rloc, r);
-      if (c.fixed_iters <= 0 && r <= c.tol && !d.mchanged[mi]) d.mdone[mi] = it;
+      if (c.fixed_iters <= 0 && r <= c.tol && (ADJ || !d.mchanged[mi])) d.mdone[mi] = it;
       if (d.mdone[mi] == 0) active += 1.0;
     }
     d.mres[mi] = 0ull;
-    d.mchanged[mi] = 0;
+    if (!ADJ) d.mchanged[mi] = 0;
   }
   const double E = block_sum<kPcgBlock>(eloc, lds);
   const double res = block_max<kPcgBlock>(rloc, lds);
@@ -337,7 +366,7 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
 template <typename R> struct Chunk { static constexpr int n = 8; };
 template <> struct Chunk<double> { static constexpr int n = 4; };
 
-template <typename R, int MW>
+template <typename R, int MW, bool ADJ>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   constexpr int CH = Chunk<R>::n;
   constexpr bool PRE = MW <= 16;
@@ -534,7 +563,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     d.st->pcg_last = it;
     if (broke) __hip_atomic_store(&d.st->done, (int)BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (!broke) finish_tail<R>(d, c, tid0, stride, lds);
+  if (!broke) finish_tail<R, ADJ>(d, c, tid0, stride, lds);
 }
 
 template <typename R>
@@ -562,10 +591,15 @@ hipError_t launch_gather(const Dev<R>& d, const Consts& c, hipStream_t s) {
 }
 
 template <typename R>
-hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s) {
+hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint) {
   void* args[] = {(void*)&d, (void*)&c};
-  const void* f = c.ell_w <= 16 ? (const void*)k_pcg<R, 16> : c.ell_w <= 32 ? (const void*)k_pcg<R, 32>
-                                                                             : (const void*)k_pcg<R, 64>;
+  const void* f;
+  if (adjoint)
+    f = c.ell_w <= 16 ? (const void*)k_pcg<R, 16, true>
+                      : c.ell_w <= 32 ? (const void*)k_pcg<R, 32, true> : (const void*)k_pcg<R, 64, true>;
+  else
+    f = c.ell_w <= 16 ? (const void*)k_pcg<R, 16, false>
+                      : c.ell_w <= 32 ? (const void*)k_pcg<R, 32, false> : (const void*)k_pcg<R, 64, false>;
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
 }
 
@@ -574,11 +608,15 @@ template <typename R>
 int pcg_max_grid(int block) {
   int occ = 0;
   int o16 = 0, o32 = 0, o64 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o16, k_pcg<R, 16>, kPcgBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&o32, k_pcg<R, 32>, kPcgBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&o64, k_pcg<R, 64>, kPcgBlock, 0) != hipSuccess)
+  int a16 = 0, a32 = 0, a64 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o16, k_pcg<R, 16, false>, kPcgBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&o32, k_pcg<R, 32, false>, kPcgBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&o64, k_pcg<R, 64, false>, kPcgBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&a16, k_pcg<R, 16, true>, kPcgBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&a32, k_pcg<R, 32, true>, kPcgBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&a64, k_pcg<R, 64, true>, kPcgBlock, 0) != hipSuccess)
     return 0;
-  occ = std::min(o16, std::min(o32, o64));
+  occ = std::min({o16, o32, o64, a16, a32, a64});
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
@@ -591,7 +629,7 @@ int pcg_max_grid(int block) {
   template hipError_t launch_set_positions<R>(const Dev<R>&, const Consts&, const R*, hipStream_t); \
   template hipError_t launch_output<R>(const Dev<R>&, const Consts&, R*, hipStream_t);          \
   template hipError_t launch_gather<R>(const Dev<R>&, const Consts&, hipStream_t);              \
-  template hipError_t launch_pcg<R>(const Dev<R>&, const Consts&, int, hipStream_t);            \
+  template hipError_t launch_pcg<R>(const Dev<R>&, const Consts&, int, hipStream_t, bool);      \
   template int pcg_max_grid<R>(int);
 INST(float)
 INST(double)

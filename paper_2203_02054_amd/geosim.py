@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
                 ("self_collision", ctypes.c_int32), ("obstacle_collision", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("pcg_eta", ctypes.c_double), ("pcg_max", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("pcg_blocks", ctypes.c_int32), ("trace_len", ctypes.c_int32)]
+                ("pcg_blocks", ctypes.c_int32), ("trace_len", ctypes.c_int32), ("adj_tol", ctypes.c_double),
+                ("adj_max_iter", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -78,8 +79,9 @@ SIGNATURES = {
     "gs_set_params": (_I, [_P, ctypes.POINTER(Params)]),
     "gs_solve": (_I, [_P, _P, _P, ctypes.POINTER(Stats)]),
     "gs_reset_contacts": (_I, [_P]),
-    "gs_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD, _PI]),
-    "gs_set_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD]),
+    "gs_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD, _PI, _PI]),
+    "gs_set_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD, _PI]),
+    "gs_adjoint": (_I, [_P, _P, _P, _P, ctypes.POINTER(Stats)]),
     "gs_local_step_debug": (_I, [_P, _P, _P, _P]),
     "gs_tets": (_I, [_P, _PI]),
     "gs_faces": (_I, [_P, _PI]),
@@ -95,7 +97,7 @@ SIGNATURES = {
     "gs_destroy": (None, [_P]),
 }
 
-N_KERNELS = 7
+N_KERNELS = 11
 
 _lib = None
 
@@ -302,22 +304,39 @@ class Problem:
     def contacts(self):
         m = self.info["n_query_verts"] * self.info["n_slots"]
         cap = max(m, 1)
-        v, t, p = (np.zeros(cap, np.int32) for _ in range(3))
+        v, t, p, fr = (np.zeros(cap, np.int32) for _ in range(4))
         tg, nr = np.zeros((cap, 3)), np.zeros((cap, 3))
         cnt = ctypes.c_int32()
         _check(lib().gs_contacts(self._h, cap, _ptr(v, ctypes.c_int32), _ptr(t, ctypes.c_int32),
                                  _ptr(p, ctypes.c_int32), _ptr(tg, ctypes.c_double), _ptr(nr, ctypes.c_double),
-                                 ctypes.byref(cnt)))
+                                 _ptr(fr, ctypes.c_int32), ctypes.byref(cnt)))
         k = cnt.value
-        return dict(rows=np.stack([v[:k], t[:k], p[:k]], axis=1), target=tg[:k], normal=nr[:k])
+        return dict(rows=np.stack([v[:k], t[:k], p[:k]], axis=1), target=tg[:k], normal=nr[:k],
+                    fresh=fr[:k].astype(bool))
 
-    def set_contacts(self, rows, target, normal):
+    def set_contacts(self, rows, target, normal, fresh=None):
         rows = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1, 3)
         v, t, p = (np.ascontiguousarray(rows[:, i]) for i in range(3))
         tg = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, 3)
         nr = np.ascontiguousarray(normal, dtype=np.float64).reshape(-1, 3)
+        fr = None if fresh is None else np.ascontiguousarray(fresh, dtype=np.int32).reshape(-1)
         _check(lib().gs_set_contacts(self._h, rows.shape[0], _ptr(v, ctypes.c_int32), _ptr(t, ctypes.c_int32),
-                                     _ptr(p, ctypes.c_int32), _ptr(tg, ctypes.c_double), _ptr(nr, ctypes.c_double)))
+                                     _ptr(p, ctypes.c_int32), _ptr(tg, ctypes.c_double), _ptr(nr, ctypes.c_double),
+                                     None if fr is None else _ptr(fr, ctypes.c_int32)))
+
+    def adjoint(self, dLdx, want_mu=False, allow_not_converged=True):
+        """Implicit adjoint of the last solve for dL/dx [3, n] (device tensor or
+        array): returns (dL/dalpha [n_chambers] device tensor, stats dict[, mu])."""
+        g = dLdx if self.torch.is_tensor(dLdx) else self.tensor(np.asarray(dLdx, dtype=np.float64))
+        out = self.torch.zeros(max(self.n_chambers, 1), dtype=self.dtype, device=self.device)[:self.n_chambers]
+        mu = self.torch.empty((3, self.n), dtype=self.dtype, device=self.device) if want_mu else None
+        st = Stats()
+        code = lib().gs_adjoint(self._h, self._dev(g, (3, self.n)), out.data_ptr() if self.n_chambers else None,
+                                mu.data_ptr() if want_mu else None, ctypes.byref(st))
+        _check(code, (OK, NOT_CONVERGED) if allow_not_converged else (OK,))
+        d = st.as_dict()
+        d["status"] = code
+        return (out, d, mu) if want_mu else (out, d)
 
     def local_step(self, x, alpha):
         """Centred target shapes [3, 4, T] at positions x."""
@@ -357,3 +376,36 @@ class Problem:
         a, b, k = nct.value, ntr.value, nco.value
         return dict(cand_tet=ct[:, :a].T.copy(), cand_tri=tr[:, :b].T.copy(), contacts=co[:, :k].T.copy(),
                     target=tg[:, :k].T.copy())
+
+
+class _SolveFn:
+    """Holder for the autograd function (built lazily so importing this module
+    does not import torch)."""
+    fn = None
+
+
+def solve_fn():
+    """torch.autograd.Function: x = SolveFn.apply(alpha, problem, x0).
+
+    Forward runs gs_solve from x0 (rest positions when None) with the stored
+    contact set; backward runs gs_adjoint on the incoming dL/dx and returns
+    dL/dalpha (implicit gradient at the solve's fixed point with its contact
+    set held fixed)."""
+    if _SolveFn.fn is None:
+        import torch
+
+        class SolveFn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, alpha, problem, x0=None):
+                x = problem.tensor(problem._X) if x0 is None else x0.detach().clone().contiguous()
+                problem.solve(alpha.detach().contiguous(), x)
+                ctx.problem = problem
+                return x
+
+            @staticmethod
+            def backward(ctx, gx):
+                ga, _ = ctx.problem.adjoint(gx.detach().to(ctx.problem.dtype).contiguous())
+                return ga, None, None
+
+        _SolveFn.fn = SolveFn
+    return _SolveFn.fn

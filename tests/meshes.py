@@ -32,3 +32,16 @@ def random_rotation(rng):
     return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
                      [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
                      [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def pressed_finger():
+    """A small finger (h = 4 mm, 3 chambers, alpha 2) with a sphere above its
+    tip and a plane 0.6 mm above its base face: its iterations carry self
+    contacts with new ray targets, kept self contacts, sphere and plane
+    contacts."""
+    import dataclasses
+    w = mg.finger(4.0, 3, 2.0)
+    X = w.rest_xyz
+    sph = np.array([[X[0].max() - 8.0, 10.0, X[2].max() + 3.0, 6.0]])
+    pl = np.array([[0.0, 0.0, 0.6, 0.0, 0.0, 1.0]])
+    return dataclasses.replace(w, spheres=sph, planes=pl, obstacle_collision=True, self_collision=True)

@@ -1,0 +1,141 @@
+"""GPU implicit adjoint (gs_adjoint through the C ABI) against the oracle's
+implicit gradient (oracle.adjoint.grad) at the same state: the positions and
+the contact set (with its new/kept self-contact flags) the GPU solve left.
+
+Bars: FP64 gradient within 1e-8 relative and mu within 1e-8 of its largest
+entry; FP32 gradient within 1e-3 relative (the FP32 iterate mu carries the
+rounding of a slowly contracting fixed-point iteration, about 1e-4).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2203_02054_amd import meshgen as mg
+import oracle
+from oracle import adjoint as oa
+from oracle.collision import Contacts
+from tests.meshes import pressed_finger, voxel_box
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2203_02054_amd import geosim
+    geosim.lib()
+    return geosim
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_contacts(prob, cg):
+    """Oracle Contacts (and new-target flags per query vertex) from gs_contacts rows."""
+    A = Contacts.empty(prob.query_verts.size, prob.n_slots)
+    fresh = np.zeros(prob.query_verts.size, bool)
+    ns = prob.spheres.shape[0]
+    for (v, typ, prim), t, nrm, fr in zip(cg["rows"], cg["target"], cg["normal"], cg["fresh"]):
+        s = int(np.searchsorted(prob.query_verts, v))
+        assert prob.query_verts[s] == v
+        sl = 0 if typ == 0 else (1 + prim if typ == 1 else 1 + ns + prim)
+        A.active[s, sl] = True
+        A.target[s, sl], A.normal[s, sl], A.prim[s, sl] = t, nrm, prim
+        if sl == 0:
+            fresh[s] = bool(fr)
+    return A, fresh
+
+
+def _seeded_loss_grad(prob, seed=3):
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((3, prob.n))
+    g[:, prob.fixed] = 0.0
+    return g
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_adjoint_matches_oracle_at_contact_state(G, precision):
+    w = pressed_finger()
+    prob = oracle.Problem.from_workload(w)
+    kw = dict(pcg_eta=1e-13, pcg_max=5000, adj_tol=1e-13) if precision == 8 else dict(adj_tol=1e-6)
+    # 62 iterations: the stored set is the one found at x_61, which holds new
+    # self-contact targets (the set cycles with a period of about 20 iterations)
+    gp = G.Problem.from_workload(w, precision=precision, fixed_iters=62, **kw)
+    x, st = gp.solve(w.alpha)
+    cg = gp.contacts()
+    say("adjoint", precision, "solve", st, "contacts", len(cg["rows"]), "fresh", int(cg["fresh"].sum()),
+        "types", np.bincount(cg["rows"][:, 1], minlength=3))
+    assert len(cg["rows"]) > 0
+    if precision == 8:
+        assert cg["fresh"].sum() >= 1 and np.any(cg["rows"][:, 1] == 1) and np.any(cg["rows"][:, 1] == 2)
+    xs = x.cpu().numpy().astype(np.float64)
+    A, fresh = _oracle_contacts(prob, cg)
+    g = _seeded_loss_grad(prob)
+    ga_o, mu_o, info = oa.grad(prob, xs, w.alpha, A, fresh, g)
+    ga, ast, mu = gp.adjoint(g, want_mu=True)
+    ga = ga.cpu().numpy().astype(np.float64)
+    mu = mu.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(ga - ga_o) / np.linalg.norm(ga_o)
+    mu_err = np.abs(mu - mu_o).max() / np.abs(mu_o).max()
+    say("  adjoint stats", ast, "grad", ga, "oracle", ga_o, "rel", rel, "mu err", mu_err)
+    assert ast["status"] == G.OK
+    if precision == 8:
+        assert rel < 1e-8 and mu_err < 1e-8
+    else:
+        assert rel < 1e-3
+
+
+@pytest.mark.parametrize("mode,alpha", [(mg.CH_ISO, 1.5), (mg.CH_AX_X, 1.7)])
+def test_adjoint_closed_form_all_chamber(G, mode, alpha):
+    """All-chamber box, one fixed vertex: L = sum |x - x_f|^2 has the
+    closed-form gradient (2/3) alpha^(-1/3) sum |X - x_f|^2 (isotropic) or
+    2 alpha sum (X - x_f)_x^2 (axis)."""
+    mesh = voxel_box(3, 2, 2, h=1.0, mode=mode, chamber=0)
+    mesh["fixed"][5] = 1
+    gp = G.Problem(mesh["rest_xyz"], mesh["tets"], mesh["tet_mode"], mesh["tet_chamber"], mesh["fixed"], 1,
+                   precision=8, tol=1e-13, pcg_eta=1e-13, pcg_max=5000, adj_tol=1e-12, max_iter=4000)
+    x, st = gp.solve([alpha])
+    X = mesh["rest_xyz"]
+    xf = X[:, 5:6]
+    s = np.full((3, 1), alpha ** (1.0 / 3.0)) if mode == mg.CH_ISO else np.array([[alpha], [1.0], [1.0]])
+    xs = x.cpu().numpy()
+    # the fixed point is the scaled rest shape up to a rotation about x_f
+    L, L_exact = ((xs - xf) ** 2).sum(), ((s * (X - xf)) ** 2).sum()
+    say("closed form", mode, st, "L", L, L_exact)
+    assert L == pytest.approx(L_exact, rel=1e-10)
+    ga, ast = gp.adjoint(2.0 * (xs - xf))
+    exact = ((2.0 / 3.0) * alpha ** (-1.0 / 3.0) * ((X - xf) ** 2).sum() if mode == mg.CH_ISO
+             else 2.0 * alpha * ((X[0] - xf[0]) ** 2).sum())
+    say("  adjoint", ast, float(ga[0]), exact)
+    assert float(ga[0]) == pytest.approx(exact, rel=1e-9)
+
+
+def test_autograd_function_matches_adjoint(G):
+    """SolveFn: loss.backward() through the solve gives gs_adjoint's gradient."""
+    import torch
+    w = mg.finger(4.0, 3, 2.0)
+    gp = G.Problem.from_workload(w, precision=8, tol=1e-8, pcg_eta=1e-10, pcg_max=5000, adj_tol=1e-10,
+                                 self_collision=1)
+    alpha = torch.tensor(w.alpha, dtype=torch.float64, device="cuda", requires_grad=True)
+    target = torch.tensor(w.rest_xyz, dtype=torch.float64, device="cuda") + 1.0
+    x = G.solve_fn().apply(alpha, gp)
+    loss = ((x - target) ** 2).sum()
+    loss.backward()
+    gp2 = G.Problem.from_workload(w, precision=8, tol=1e-8, pcg_eta=1e-10, pcg_max=5000, adj_tol=1e-10,
+                                  self_collision=1)
+    x2, _ = gp2.solve(w.alpha)
+    ga, _ = gp2.adjoint(2.0 * (x2 - target))
+    say("autograd", alpha.grad.cpu().numpy(), ga.cpu().numpy())
+    np.testing.assert_allclose(alpha.grad.cpu().numpy(), ga.cpu().numpy(), rtol=1e-9, atol=0)
+
+
+def test_adjoint_requires_a_solve(G):
+    w = mg.finger(4.0, 3, 2.0)
+    gp = G.Problem.from_workload(w, precision=4)
+    with pytest.raises(G.GeosimError) as e:
+        gp.adjoint(np.zeros((3, gp.n)))
+    assert e.value.code == G.ESTATE

@@ -3,8 +3,6 @@ derivative against finite differences, the closed-form gradient of an
 all-chamber mesh, every part of db/dx against finite differences at a state
 with new self contacts, sphere and plane contacts, and the implicit gradient
 against central differences of the frozen-set fixed point."""
-import dataclasses
-
 import numpy as np
 import pytest
 import torch
@@ -15,7 +13,7 @@ from oracle import adjoint as oa
 from oracle import collision as oc
 from oracle import solver as so
 from oracle.collision import Contacts
-from tests.meshes import voxel_box
+from tests.meshes import pressed_finger, voxel_box
 
 
 def test_polar_rotation_derivative_matches_finite_differences():
@@ -78,11 +76,7 @@ def contact_state():
     """A small finger (h = 4 mm, 3 chambers) pressed by a sphere and a plane,
     after 61 iterations from rest: the active set holds self contacts with new
     ray targets, kept self contacts, sphere and plane contacts."""
-    w = mg.finger(4.0, 3, 2.0)
-    X = w.rest_xyz
-    sph = np.array([[X[0].max() - 8.0, 10.0, X[2].max() + 3.0, 6.0]])
-    pl = np.array([[0.0, 0.0, 0.6, 0.0, 0.0, 1.0]])
-    w = dataclasses.replace(w, spheres=sph, planes=pl, obstacle_collision=True, self_collision=True)
+    w = pressed_finger()
     prob = oracle.Problem.from_workload(w)
     x, prev, fac = prob.X0.copy(), None, so._Factor()
     for _ in range(61):
