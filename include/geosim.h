@@ -106,6 +106,9 @@ typedef struct {
   int32_t trace_len;      /* iterations recorded by gs_trace (workspace grows)    */
   double adj_tol;         /* adjoint stop: max|d mu| <= adj_tol max|mu| per mesh  */
   int32_t adj_max_iter;   /* adjoint iteration cap                                */
+  int32_t adj_aa_m;       /* Anderson memory of the adjoint iteration, 0..16 (0:
+                             plain fixed-point iteration); the workspace holds
+                             the value given at gs_create                         */
 } gs_params;
 
 typedef struct {
@@ -133,7 +136,7 @@ const char* gs_last_error(void);
 /* Defaults: Ecoflex 00-30 (c1 = 0.0418, c2 = 0.0106 MPa), hyperelastic on,
  * kappa_col 1, eps_rel 0.05, ray_rel 4, no collision, tol 1e-6,
  * max_iter 20000, fixed_iters 0, pcg_eta 1e-3, pcg_max 200, check_every 16,
- * pcg_blocks 0, trace_len 0, adj_tol 1e-6, adj_max_iter 20000. */
+ * pcg_blocks 0, trace_len 0, adj_tol 1e-6, adj_max_iter 20000, adj_aa_m 16. */
 void gs_default_params(gs_params* params);
 
 /* Host set-up for one mesh (done once per mesh; not per iteration): orient
@@ -231,8 +234,11 @@ gs_status gs_set_contacts(gs_problem* p, int32_t count, const int32_t* v, const 
  * Section II-C); for dev_dLdx [3][n] = dL/dx this computes
  *   dev_dLdalpha[n_chambers] = (db_F/dalpha)^T mu,  (M_FF - db_F/dx_F)^T mu = g_F
  * by the iteration mu <- M^-1 (g + (db/dx)^T mu) in correction form (same CG
- * as the solve, pcg_eta / pcg_max apply), until max|d mu| <= adj_tol max|mu|
- * on every mesh or adj_max_iter iterations.  Self contacts flagged fresh
+ * as the solve, pcg_eta / pcg_max apply), with Anderson acceleration of
+ * memory adj_aa_m (Walker & Ni 2011) when it is > 0, until
+ * max|d mu| <= adj_tol max|mu| (d the correction of the last iteration; per
+ * mesh, and on every mesh at once when accelerated) or adj_max_iter
+ * iterations.  Self contacts flagged fresh
  * (gs_contacts) follow x through the ray target; kept self contacts are
  * constant; obstacle targets follow x in closed form.  dev_mu [3][n] (may be
  * NULL) receives mu (zero on fixed vertices).  Both outputs use the

@@ -295,6 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(Dev<R> d, Consts c) {
     d.mres[i] = 0ull;
     d.mmax[i] = 0ull;
   }
+  if (v == 0 && c.aa_m > 0) d.aa_k[0] = 0;
   if (v == 0) {
     DevStatus* st = d.st;
     st->n_active = c.M;
@@ -593,6 +594,161 @@ __global__ __launch_bounds__(kBlock) void k_adj_chamber_sum(Dev<R> d, Consts c, 
   if (threadIdx.x == 0) out[ch] = (R)t;
 }
 
+// ---------------------------------------------------------------------------
+// Anderson acceleration of the adjoint iteration (Walker & Ni 2011, type II,
+// memory m): with f_k = G(mu_k) - mu_k the correction the CG kernel left in
+// dl, and the last m differences dX_j = mu_{j+1} - mu_j, dF_j = f_{j+1} - f_j,
+//   gamma = argmin |f_k - dF gamma|,   mu_{k+1} = mu_k + f_k - (dX + dF) gamma.
+// For a linear fixed-point map this is a Krylov method on (I - G') (it
+// matches GMRES in exact arithmetic with full memory), so the slow modes of
+// the iteration no longer set the iteration count.  The normal equations
+// (dF^T dF + ridge) gamma = dF^T f are solved in double by one thread; the
+// dot products are block partials summed in a fixed order.
+
+constexpr int kAaMax = 16;
+constexpr int kAaBlock = 256;
+
+// New difference column (k >= 1), previous iterate / residual, and the
+// block partials of dF_j . dF_new and dF_j . f_k.
+template <typename R>
+__global__ __launch_bounds__(kAaBlock) void k_aa_diff_dots(Dev<R> d, Consts c) {
+  __shared__ double lds[kAaBlock / 64];
+  if (is_done(d.st)) return;
+  const int k = d.aa_k[0];
+  const int m = c.aa_m;
+  const int mk = min(k, m);
+  const int col = (k - 1 + m) % m;
+  const size_t n3 = 3 * (size_t)c.n;
+  const size_t n = (size_t)c.n;
+  double a[kAaMax], b[kAaMax];
+#pragma unroll
+  for (int j = 0; j < kAaMax; ++j) a[j] = b[j] = 0.0;
+  for (size_t e = (size_t)blockIdx.x * kAaBlock + threadIdx.x; e < n3; e += (size_t)gridDim.x * kAaBlock) {
+    const size_t v = e % n, kc = e / n;
+    const R f = d.dl[4 * v + kc];
+    const R mu = d.mu[e];
+    if (k >= 1) {
+      const R df = f - d.aa_fp[e];
+      d.aa_df[col * n3 + e] = df;
+      d.aa_dx[col * n3 + e] = mu - d.aa_xp[e];
+#pragma unroll
+      for (int j = 0; j < kAaMax; ++j) {
+        if (j < mk) {
+          const double dj = (j == col) ? (double)df : (double)d.aa_df[j * n3 + e];
+          a[j] += dj * (double)df;
+          b[j] += dj * (double)f;
+        }
+      }
+    }
+    d.aa_xp[e] = mu;
+    d.aa_fp[e] = f;
+  }
+  if (k < 1) return;
+#pragma unroll
+  for (int j = 0; j < kAaMax; ++j) {
+    if (j < mk) {  // uniform over the block
+      const double ta = block_sum<kAaBlock>(a[j], lds);
+      const double tb = block_sum<kAaBlock>(b[j], lds);
+      if (threadIdx.x == 0) {
+        d.aa_part[(2 * j) * (size_t)gridDim.x + blockIdx.x] = ta;
+        d.aa_part[(2 * j + 1) * (size_t)gridDim.x + blockIdx.x] = tb;
+      }
+    }
+  }
+}
+
+// Sum the partials (one wavefront per value), update the Gram matrix, solve
+// for gamma (thread 0, Cholesky with a relative ridge; on failure gamma = 0,
+// a plain step), count the iteration.
+template <typename R>
+__global__ __launch_bounds__(1024) void k_aa_solve(Dev<R> d, Consts c, int G) {
+  __shared__ double val[2 * kAaMax];
+  __shared__ double L[kAaMax][kAaMax];
+  __shared__ double y[kAaMax];
+  if (is_done(d.st)) return;
+  const int k = d.aa_k[0];
+  const int m = c.aa_m;
+  const int mk = min(k, m);
+  const int col = (k - 1 + m) % m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = wave; q < 2 * mk; q += 16) {
+    double t = 0.0;
+    for (int b = lane; b < G; b += 64) t += d.aa_part[(size_t)q * G + b];
+    t = wave_sum(t);
+    if (lane == 0) val[q] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (mk > 0) {
+    for (int j = 0; j < mk; ++j) {
+      d.aa_h[j * m + col] = val[2 * j];
+      d.aa_h[col * m + j] = val[2 * j];
+      d.aa_v[j] = val[2 * j + 1];
+    }
+    double dmax = 0.0;
+    for (int i = 0; i < mk; ++i) dmax = fmax(dmax, d.aa_h[i * m + i]);
+    const double ridge = 1e-10 * dmax;
+    bool ok = dmax > 0.0;
+    for (int i = 0; i < mk && ok; ++i) {
+      for (int j = 0; j <= i; ++j) {
+        double sum = d.aa_h[i * m + j] + (i == j ? ridge : 0.0);
+        for (int q = 0; q < j; ++q) sum -= L[i][q] * L[j][q];
+        if (i == j) {
+          if (!(sum > 0.0)) {
+            ok = false;
+            break;
+          }
+          L[i][i] = sqrt(sum);
+        } else {
+          L[i][j] = sum / L[j][j];
+        }
+      }
+    }
+    for (int i = 0; i < mk; ++i) {
+      double sum = ok ? d.aa_v[i] : 0.0;
+      for (int q = 0; q < i && ok; ++q) sum -= L[i][q] * y[q];
+      y[i] = ok ? sum / L[i][i] : 0.0;
+    }
+    for (int i = mk - 1; i >= 0; --i) {
+      double sum = y[i];
+      for (int q = i + 1; q < mk && ok; ++q) sum -= L[q][i] * d.aa_gamma[q];
+      d.aa_gamma[i] = ok ? sum / L[i][i] : 0.0;
+    }
+  }
+  d.aa_k[0] = k + 1;
+}
+
+// mu_{k+1} = mu_k + f_k - sum_j gamma_j (dX_j + dF_j)
+template <typename R>
+__global__ __launch_bounds__(kAaBlock) void k_aa_update(Dev<R> d, Consts c) {
+  if (is_done(d.st)) return;
+  const int k = d.aa_k[0] - 1;  // k_aa_solve counted this iteration already
+  const int mk = min(k, c.aa_m);
+  const size_t n3 = 3 * (size_t)c.n;
+  const size_t n = (size_t)c.n;
+  double g[kAaMax];
+#pragma unroll
+  for (int j = 0; j < kAaMax; ++j) g[j] = j < mk ? d.aa_gamma[j] : 0.0;
+  for (size_t e = (size_t)blockIdx.x * kAaBlock + threadIdx.x; e < n3; e += (size_t)gridDim.x * kAaBlock) {
+    const size_t v = e % n, kc = e / n;
+    double x = (double)d.mu[e] + (double)d.dl[4 * v + kc];
+#pragma unroll
+    for (int j = 0; j < kAaMax; ++j)
+      if (j < mk) x -= g[j] * ((double)d.aa_dx[j * n3 + e] + (double)d.aa_df[j * n3 + e]);
+    d.mu[e] = (R)x;
+  }
+}
+
+template <typename R>
+hipError_t launch_adj_anderson(const Dev<R>& d, const Consts& c, hipStream_t s) {
+  if (c.aa_m <= 0) return hipSuccess;
+  const int G = max(1, min(cdiv(3L * c.n, kAaBlock), min(c.nparts, 1024)));
+  k_aa_diff_dots<R><<<G, kAaBlock, 0, s>>>(d, c);
+  k_aa_solve<R><<<1, 1024, 0, s>>>(d, c, G);
+  k_aa_update<R><<<G, kAaBlock, 0, s>>>(d, c);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_adj_init(const Dev<R>& d, const Consts& c, hipStream_t s) {
   k_adj_init<R><<<max(1, cdiv(c.n, kBlock)), kBlock, 0, s>>>(d, c);
@@ -626,7 +782,8 @@ hipError_t launch_adj_chamber_sum(const Dev<R>& d, const Consts& c, R* out, hipS
   template hipError_t launch_adj_springs<R>(const Dev<R>&, const Consts&, hipStream_t);          \
   template hipError_t launch_adj_local<R>(const Dev<R>&, const Consts&, bool, hipStream_t);      \
   template hipError_t launch_adj_gather<R>(const Dev<R>&, const Consts&, hipStream_t);           \
-  template hipError_t launch_adj_chamber_sum<R>(const Dev<R>&, const Consts&, R*, hipStream_t);
+  template hipError_t launch_adj_chamber_sum<R>(const Dev<R>&, const Consts&, R*, hipStream_t); \
+  template hipError_t launch_adj_anderson<R>(const Dev<R>&, const Consts&, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -52,6 +52,7 @@ struct Layout {
   size_t u, xc, res4, cg, dl, p, dg, dsp, pen, hcount, hslot, hover, penlist, fhit, fc, fn, cact, ctgt, cnrm,
       cprim, part_a, part_b, part_c, part_d, part_e, part_f, st, trace, mesh, vmesh, tmesh, mres, mchanged, mdone;
   size_t mu, acc3, ga, ch_start, ch_tets, mmax, mdone2, st2, alpha_last;
+  size_t aa_dx, aa_df, aa_xp, aa_fp, aa_h, aa_v, aa_gamma, aa_part, aa_k;
   size_t total;
 };
 
@@ -135,6 +136,7 @@ struct gs_problem {
   int trace_len = 0;
   int last_iters = 0;
   bool solved = false;  // a solve has run since gs_bind (the adjoint's state exists)
+  int aa_cap = 0;       // Anderson memory the workspace holds (adj_aa_m at gs_create)
   Profiler prof;
 };
 
@@ -151,6 +153,7 @@ gs_status check_params(const gs_params* p) {
   if (p->check_every < 1) return fail(GS_EINVAL, "check_every must be >= 1");
   if (p->trace_len < 0) return fail(GS_EINVAL, "trace_len must be >= 0");
   if (!(p->adj_tol >= 0) || p->adj_max_iter < 1) return fail(GS_EINVAL, "bad adj_tol/adj_max_iter");
+  if (p->adj_aa_m < 0 || p->adj_aa_m > 16) return fail(GS_EINVAL, "adj_aa_m must be in [0, 16]");
   return GS_OK;
 }
 
@@ -225,6 +228,16 @@ Layout make_layout(const gs_problem* p) {
   L.mdone2 = take((size_t)p->M * 4);
   L.st2 = take(sizeof(DevStatus));
   L.alpha_last = take((size_t)p->nch * W);
+  const size_t am = (size_t)p->aa_cap;
+  L.aa_dx = take(am * 3 * n * W);
+  L.aa_df = take(am * 3 * n * W);
+  L.aa_xp = take(am ? 3 * n * W : 0);
+  L.aa_fp = take(am ? 3 * n * W : 0);
+  L.aa_h = take(am * am * 8);
+  L.aa_v = take(am * 8);
+  L.aa_gamma = take(am * 8);
+  L.aa_part = take(2 * am * (size_t)p->nparts * 8);
+  L.aa_k = take(4);
   L.total = align256(off);
   return L;
 }
@@ -293,6 +306,15 @@ Dev<R> make_dev(const gs_problem* p) {
   d.ch_tets = (const int32_t*)(b + L.ch_tets);
   d.mmax = (unsigned long long*)(b + L.mmax);
   d.alpha_last = (R*)(b + L.alpha_last);
+  d.aa_dx = (R*)(b + L.aa_dx);
+  d.aa_df = (R*)(b + L.aa_df);
+  d.aa_xp = (R*)(b + L.aa_xp);
+  d.aa_fp = (R*)(b + L.aa_fp);
+  d.aa_h = (double*)(b + L.aa_h);
+  d.aa_v = (double*)(b + L.aa_v);
+  d.aa_gamma = (double*)(b + L.aa_gamma);
+  d.aa_part = (double*)(b + L.aa_part);
+  d.aa_k = (int32_t*)(b + L.aa_k);
   d.dbg_tet = nullptr;
   d.dbg_tri = nullptr;
   d.dbg_cap = 0;
@@ -490,6 +512,8 @@ gs_status adjoint_impl(gs_problem* p, const R* gL, R* dalpha, R* mu_out, gs_stat
   c.tol = p->prm.adj_tol;
   c.max_iter = p->prm.adj_max_iter;
   c.trace_len = 0;
+  c.aa_m = std::min(p->prm.adj_aa_m, p->aa_cap);
+  if (c.aa_m > 0) c.mask_done = 0;  // the accelerated update mixes meshes: converge all at once
   hipStream_t s = p->stream;
   HIPCHK(launch_adj_init<R>(d, c, s));
   DevStatus h{};
@@ -502,6 +526,7 @@ gs_status adjoint_impl(gs_problem* p, const R* gL, R* dalpha, R* mu_out, gs_stat
       HIPCHK(timed(p, K_ADJ_LOCAL, [&] { return launch_adj_local<R>(d, c, false, s); }));
       HIPCHK(timed(p, K_ADJ_GATHER, [&] { return launch_adj_gather<R>(d, c, s); }));
       HIPCHK(timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, true); }));
+      HIPCHK(launch_adj_anderson<R>(d, c, s));
     }
     enq += chunk;
     HIPCHK(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
@@ -952,6 +977,7 @@ void gs_default_params(gs_params* p) {
   p->trace_len = 0;
   p->adj_tol = 1e-6;
   p->adj_max_iter = 20000;
+  p->adj_aa_m = 16;
 }
 
 gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** out) {
@@ -968,6 +994,7 @@ gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** ou
   if (!p) return fail(GS_EINVAL, "out of host memory");
   p->prm = *prm;
   p->trace_len = prm->trace_len;
+  p->aa_cap = prm->adj_aa_m;
   try {
     st = setup(p, m);
     if (st == GS_OK) finalize(p);
@@ -1016,6 +1043,7 @@ gs_status gs_create_batch(int32_t n_mesh, const gs_mesh_desc* meshes, const gs_p
       p->prm = *prm;
       p->prec = meshes[0].precision;
       p->trace_len = prm->trace_len;
+      p->aa_cap = prm->adj_aa_m;
       merge(p, parts);
       finalize(p);
     }

@@ -60,6 +60,7 @@ struct Consts {
   int nparts;           // partial-sum slots per reduction array
   int ell_w;            // off-diagonal entries per row of the ELL matrix (16, 32 or 64)
   int trace_len;        // rows of the per-iteration trace
+  int aa_m;             // adjoint: Anderson memory (0: plain fixed-point iteration)
   double c1, c2, kappa, tol, pcg_eta;
 };
 
@@ -130,6 +131,16 @@ struct Dev {
   const int32_t* ch_tets;  // chamber tets grouped by chamber, ascending
   unsigned long long* mmax;  // [M] max |mu| per mesh (double bits)
   R* alpha_last;           // [nch] volume ratios of the last solve
+  // Anderson acceleration of the adjoint iteration (memory m = Consts::aa_m)
+  R* aa_dx;                // [m][3][n] differences of successive iterates
+  R* aa_df;                // [m][3][n] differences of successive residuals (corrections)
+  R* aa_xp;                // [3][n] previous iterate
+  R* aa_fp;                // [3][n] previous residual
+  double* aa_h;            // [m][m] Gram matrix of aa_df
+  double* aa_v;            // [m] aa_df^T f
+  double* aa_gamma;        // [m] least-squares coefficients
+  double* aa_part;         // [2m][nparts] block partials of the dot products
+  int32_t* aa_k;           // [1] iterations taken by the accelerated loop
   // debug candidate buffers (null outside gs_collide_debug)
   int32_t* dbg_tet;        // [2][cap]
   int32_t* dbg_tri;        // [2][cap]
@@ -158,6 +169,7 @@ template <typename R>
 hipError_t launch_adj_local(const Dev<R>& d, const Consts& c, bool alpha_grad, hipStream_t s);
 template <typename R> hipError_t launch_adj_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_adj_chamber_sum(const Dev<R>& d, const Consts& c, R* out, hipStream_t s);
+template <typename R> hipError_t launch_adj_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_set_positions(const Dev<R>& d, const Consts& c, const R* x, hipStream_t s);
 template <typename R> int pcg_max_grid(int block);
 

@@ -248,8 +248,9 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           if (ADJ) {
+            // with Anderson acceleration the update is taken by its own kernels
             const R mm = d.mu[k * n + v] + dd[k];
-            d.mu[k * n + v] = mm;
+            if (!c.aa_m) d.mu[k * n + v] = mm;
             uq += (double)mm * (double)mm;
           } else {
             const R uu = d.u[k * n + v] + dd[k];

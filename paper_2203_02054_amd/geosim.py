@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("pcg_eta", ctypes.c_double), ("pcg_max", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("pcg_blocks", ctypes.c_int32), ("trace_len", ctypes.c_int32), ("adj_tol", ctypes.c_double),
-                ("adj_max_iter", ctypes.c_int32)]
+                ("adj_max_iter", ctypes.c_int32), ("adj_aa_m", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -57,17 +57,19 @@ def _seeded_loss_grad(prob, seed=3):
     return g
 
 
-@pytest.mark.parametrize("precision", [8, 4])
-def test_adjoint_matches_oracle_at_contact_state(G, precision):
+@pytest.mark.parametrize("precision,aa_m", [(8, 0), (8, 16), (4, 0), (4, 16)])
+def test_adjoint_matches_oracle_at_contact_state(G, precision, aa_m):
+    """Plain fixed-point adjoint iteration (aa_m = 0) and Anderson-accelerated."""
     w = pressed_finger()
     prob = oracle.Problem.from_workload(w)
     kw = dict(pcg_eta=1e-13, pcg_max=5000, adj_tol=1e-13) if precision == 8 else dict(adj_tol=1e-6)
+    kw["adj_aa_m"] = aa_m
     # 62 iterations: the stored set is the one found at x_61, which holds new
     # self-contact targets (the set cycles with a period of about 20 iterations)
     gp = G.Problem.from_workload(w, precision=precision, fixed_iters=62, **kw)
     x, st = gp.solve(w.alpha)
     cg = gp.contacts()
-    say("adjoint", precision, "solve", st, "contacts", len(cg["rows"]), "fresh", int(cg["fresh"].sum()),
+    say("adjoint", precision, aa_m, "solve", st, "contacts", len(cg["rows"]), "fresh", int(cg["fresh"].sum()),
         "types", np.bincount(cg["rows"][:, 1], minlength=3))
     assert len(cg["rows"]) > 0
     if precision == 8:
