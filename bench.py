@@ -1,11 +1,26 @@
 """Benchmark: tet-iterations per second of the collision-aware local/global
-solve to the 1e-6 residual on one GPU.
+solve to the 1e-6 residual on one GPU, plain and batched, and adjoint
+gradients per second.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload finger]
 
-A step is one complete solve of the workload from its rest shape (all
-iterations until r_k <= 1e-6 with an unchanged active set).  Inputs are
-resident on the device before the timed region.  Prints one JSON line.
+Headline (``value``): a step is one complete solve of the workload (default:
+the 26,880-tet, 8-chamber finger) from its rest shape, all iterations until
+r_k <= 1e-6 with an unchanged active set.  Inputs are resident on the device
+before the timed region; the K steps are timed with HIP events on the
+library's stream, without per-kernel events.  The same K steps are then run
+again with per-kernel events for the kernel table and the roofline of the
+dominant kernel.
+
+Extra legs (same JSON line):
+  batched  256 finger meshes of uneven size in one problem, solved once from
+           rest (iterations capped); throughput sum_i T_i K_i / t and the
+           speedup over solving a sample of the meshes one by one.
+  adjoint  gs_adjoint on the converged finger for a fingertip loss: gradients
+           per second, and the speedup over a finite-difference gradient by
+           plain solves (2 solves per chamber).
+  cpu_baseline  the FP64 oracle on the host cores for a bounded sample.
+Prints one JSON line.
 """
 import argparse
 import json
@@ -56,6 +71,24 @@ def kernel_bytes(info, W, n_launch, pcg_iters):
     return out
 
 
+def roofline_of(prof, info, W, pcg_iters):
+    n_launch = {k: v[1] for k, v in prof.items()}
+    kb = kernel_bytes(info, W, n_launch, pcg_iters)
+    dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
+    avg_ms = prof[dom][0] / prof[dom][1]
+    if dom not in kb:
+        return None
+    achieved = kb[dom] / (avg_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": None, "kernel": dom,
+            "avg_launch_us": round(1e3 * avg_ms, 3), "algorithmic_bytes_per_launch": int(kb[dom])}
+
+
+def kernel_table(prof):
+    return {k: {"total_ms": round(v[0], 3), "launches": v[1], "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else None}
+            for k, v in prof.items() if v[1]}
+
+
 def run_cpu_baseline(wl, budget_s=15.0):
     import torch
     import oracle
@@ -78,6 +111,110 @@ def run_cpu_baseline(wl, budget_s=15.0):
                       f"(FP64 oracle: brute-force collision, sparse direct global step), {dt:.1f} s"}
 
 
+def timed_on(stream, fn):
+    """Run fn() between two HIP events recorded on `stream`; return (ms, result)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    r = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), r
+
+
+def run_batched(G, mg, n_mesh, max_iter, sample):
+    import torch
+    wls = mg.batched(n_mesh)
+    Ts = np.array([w.n_tets for w in wls], dtype=np.int64)
+    print(f"# batched: {n_mesh} meshes, {int(Ts.sum())} tets", file=sys.stderr, flush=True)
+    gb = G.Problem.batch(wls, precision=4, self_collision=1, max_iter=max_iter)
+    alpha = gb.tensor(np.concatenate([w.alpha for w in wls]))
+    x0 = gb.tensor(gb._X)
+    x = x0.clone()
+
+    def solve():
+        x.copy_(x0)
+        gb.reset_contacts()
+        return gb.solve(alpha, x)[1]
+
+    solve()                                                   # warm-up
+    torch.cuda.synchronize()
+    ms, st = timed_on(gb.stream, solve)
+    its = gb.mesh_iters().astype(np.int64)
+    K = np.where(its > 0, its, st["iters"])                  # capped meshes ran every iteration
+    value = float((Ts * K).sum() / (ms / 1e3))
+    # kernel averages and the CG roofline from a profiled prefix of the same solve
+    gb.set_params(max_iter=min(200, max_iter))
+    gb.profile(True)
+    x.copy_(x0)
+    gb.reset_contacts()
+    _, st_p = gb.solve(alpha, x)
+    prof = gb.profile_read()
+    gb.profile(False)
+    roof = roofline_of(prof, gb.info, 4, st_p["pcg_iters_total"])
+    # plain path on a sample of the meshes (every n_mesh/sample-th), one by one
+    idx = list(range(0, n_mesh, max(1, n_mesh // sample)))[:sample]
+    t_plain, work_plain = 0.0, 0
+    for i in idx:
+        w = wls[i]
+        gp = G.Problem.from_workload(w, precision=4, max_iter=max_iter)
+        a = gp.tensor(w.alpha)
+        xx0 = gp.tensor(w.rest_xyz)
+        xx = xx0.clone()
+
+        def solve1():
+            xx.copy_(xx0)
+            gp.reset_contacts()
+            return gp.solve(a, xx)[1]
+
+        solve1()
+        torch.cuda.synchronize()
+        ms1, st1 = timed_on(gp.stream, solve1)
+        t_plain += ms1 / 1e3
+        work_plain += w.n_tets * st1["iters"]
+        gp.close()
+    rate_plain = work_plain / t_plain
+    out = {"value": round(value, 1), "unit": "tet-iterations/s", "ms_per_step": round(ms, 3),
+           "meshes": n_mesh, "tets": int(Ts.sum()), "chambers": int(sum(w.n_chambers for w in wls)),
+           "max_iter": max_iter, "outer_iters": st["iters"], "pcg_iters": st["pcg_iters_total"],
+           "converged_meshes": int((its > 0).sum()),
+           "plain_sample": {"meshes": len(idx), "value": round(rate_plain, 1), "unit": "tet-iterations/s"},
+           "speedup_vs_plain": round(value / rate_plain, 3), "roofline": roof, "kernels": kernel_table(prof)}
+    gb.close()
+    return out
+
+
+def run_adjoint(G, mg, wl, gp, x, alpha, t_solve_ms, reps=3):
+    """Adjoint of the converged solve left in gp (positions x)."""
+    import torch
+    verts, y = mg.finger_tip_targets(wl)
+    xs = x.double().cpu().numpy()
+    g = np.zeros((3, wl.n_verts))
+    g[:, verts] = 2.0 * (xs[:, verts] - y.T)
+    gt = gp.tensor(g)
+    gp.set_params(adj_tol=1e-6, adj_aa_m=16)
+    ga, st = gp.adjoint(gt)                                   # warm-up
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        ms, (ga, st) = timed_on(gp.stream, lambda: gp.adjoint(gt))
+        times.append(ms)
+    gp.profile(True)
+    gp.adjoint(gt)
+    prof = gp.profile_read()
+    gp.profile(False)
+    t = float(np.median(times))
+    fd_ms = 2 * wl.n_chambers * t_solve_ms
+    return {"value": round(1e3 / t, 3), "unit": "gradients/s", "ms_per_gradient": round(t, 3),
+            "params": wl.n_chambers, "adjoint_iters": st["iters"], "pcg_iters": st["pcg_iters_total"],
+            "residual": st["residual"], "status": st["status"], "anderson_memory": 16,
+            "loss": "sum of squared distances of 10 fingertip vertices to seeded targets",
+            "forward_plus_adjoint_ms": round(t_solve_ms + t, 3),
+            "fd_plain_ms": round(fd_ms, 3), "speedup_vs_fd": round(fd_ms / t, 2),
+            "grad_norm": float(torch.linalg.norm(ga.double()).item()),
+            "kernels": {k: v for k, v in kernel_table(prof).items() if k.startswith("adj_")}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +223,13 @@ def main():
     ap.add_argument("--workload", default="finger")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-meshes", type=int, default=256)
+    ap.add_argument("--batched-max-iter", type=int, default=1000)
+    ap.add_argument("--plain-sample", type=int, default=8)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 20 device-to-device copies of MIB MiB (reference traffic for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -95,6 +239,16 @@ def main():
     import torch
     from paper_2203_02054_amd import geosim as G
     from paper_2203_02054_amd import meshgen as mg
+
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": 4 * n, "copies": 20}), flush=True)
+        return
 
     wl = mg.make(a.workload)
     gp = G.Problem.from_workload(wl, precision=wl.precision)
@@ -114,36 +268,32 @@ def main():
     for _ in range(a.warmup):
         st = step()
     torch.cuda.synchronize()
-    gp.profile(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     stats = []
+
+    def timed_steps():
+        for i in range(a.steps):
+            stats.append(step())
+            print(f"# step {i}: {stats[-1]}", file=sys.stderr, flush=True)
+
     t_host = time.perf_counter()
-    e0.record(stream)
-    for i in range(a.steps):
-        stats.append(step())
-        print(f"# step {i}: {stats[-1]}", file=sys.stderr, flush=True)
-    e1.record(stream)
-    torch.cuda.synchronize()
+    ms, _ = timed_on(stream, timed_steps)
     t_host = time.perf_counter() - t_host
-    ms = e0.elapsed_time(e1)
+
+    # the same steps again with per-kernel events (kernel table, roofline)
+    gp.profile(True)
+    pstats = []
+    for _ in range(a.steps):
+        x.copy_(x0)
+        gp.reset_contacts()
+        pstats.append(gp.solve(alpha, x)[1])
+    torch.cuda.synchronize()
     prof = gp.profile_read()
     gp.profile(False)
 
     iters = sum(s["iters"] for s in stats)
     pcg_iters = sum(s["pcg_iters_total"] for s in stats)
     value = wl.n_tets * iters / (ms / 1e3)
-    n_launch = {k: v[1] for k, v in prof.items()}
-    kb = kernel_bytes(gp.info, W, n_launch, pcg_iters)
-    dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
-    avg_ms = prof[dom][0] / prof[dom][1]
-    roof = None
-    if dom in kb:
-        achieved = kb[dom] / (avg_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": None, "kernel": dom,
-                "avg_launch_us": round(1e3 * avg_ms, 3), "algorithmic_bytes_per_launch": int(kb[dom])}
-    kernels = {k: {"total_ms": round(v[0], 3), "launches": v[1],
-                   "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else None} for k, v in prof.items() if v[1]}
+    roof = roofline_of(prof, gp.info, W, sum(s["pcg_iters_total"] for s in pstats))
     out = {
         "metric": "tet-iterations/sec to 1e-6 residual (plain solve)",
         "value": round(value, 1),
@@ -163,9 +313,15 @@ def main():
                    "pcg_iters_per_step": pcg_iters / a.steps, "contacts": stats[-1]["n_contacts"],
                    "residual": stats[-1]["residual"]},
         "roofline": roof,
-        "kernels": kernels,
+        "kernels": kernel_table(prof),
         "host_s": round(t_host, 3),
     }
+    if not a.no_adjoint:
+        print("# adjoint", file=sys.stderr, flush=True)
+        out["adjoint"] = run_adjoint(G, mg, wl, gp, x, alpha, ms / a.steps)
+    gp.close()
+    if not a.no_batched:
+        out["batched"] = run_batched(G, mg, a.batched_meshes, a.batched_max_iter, a.plain_sample)
     if not a.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = run_cpu_baseline(wl, a.cpu_budget)

@@ -341,6 +341,26 @@ def adjoint_targets(wl: Workload, seed: int = 5, per_finger: int = 10, radius: f
     return verts, y
 
 
+def finger_tip_targets(wl: Workload, seed: int = 5, n: int = 10, radius: float = 10.0):
+    """Loss vertices and targets for a single finger (tip face at x = max):
+    the ``n`` tip-face vertices nearest the tip-face centre (ties to the lower
+    id), targets X0[v] + radius * u with u uniform in the unit ball (seed 5),
+    the single-finger form of ``adjoint_targets``."""
+    X = wl.rest_xyz
+    xmax = X[0].max()
+    tip = np.nonzero(np.abs(X[0] - xmax) < 1e-9)[0]
+    ctr = X[:, tip].mean(axis=1)
+    d = np.linalg.norm(X[:, tip] - ctr[:, None], axis=0)
+    order = np.lexsort((tip, np.round(d, 9)))
+    verts = tip[order[:n]].astype(np.int64)
+    rng = np.random.default_rng(seed)
+    g = rng.normal(size=(verts.size, 3))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    u = rng.uniform(size=verts.size) ** (1.0 / 3.0)
+    y = X[:, verts].T + radius * g * u[:, None]
+    return verts, y
+
+
 CONFIGS = {
     "block": lambda: block(),
     "finger": lambda: finger(2.0, 8, 2.0, name="finger"),
