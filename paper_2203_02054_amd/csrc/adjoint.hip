@@ -657,65 +657,88 @@ __global__ __launch_bounds__(kAaBlock) void k_aa_diff_dots(Dev<R> d, Consts c) {
   }
 }
 
-// Sum the partials (one wavefront per value), update the Gram matrix, solve
-// for gamma (thread 0, Cholesky with a relative ridge; on failure gamma = 0,
-// a plain step), count the iteration.
+// Sum the partials (one wavefront per value), update the Gram matrix, and
+// solve for gamma: right-looking Cholesky with a relative ridge, one LDS
+// entry per thread, then the two triangular solves by wavefront 0 (one
+// shuffle-reduced dot product per row).  A non-positive pivot gives
+// gamma = 0 (a plain step).  Counts the iteration.
+constexpr int kAaSolveBlock = kAaMax * kAaMax;
+
 template <typename R>
-__global__ __launch_bounds__(1024) void k_aa_solve(Dev<R> d, Consts c, int G) {
+__global__ __launch_bounds__(kAaSolveBlock) void k_aa_solve(Dev<R> d, Consts c, int G) {
   __shared__ double val[2 * kAaMax];
-  __shared__ double L[kAaMax][kAaMax];
+  __shared__ double A[kAaMax][kAaMax];
   __shared__ double y[kAaMax];
+  __shared__ int ok;
   if (is_done(d.st)) return;
   const int k = d.aa_k[0];
   const int m = c.aa_m;
   const int mk = min(k, m);
   const int col = (k - 1 + m) % m;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q = wave; q < 2 * mk; q += 16) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int nw = kAaSolveBlock / 64;
+  for (int q = wave; q < 2 * mk; q += nw) {
     double t = 0.0;
     for (int b = lane; b < G; b += 64) t += d.aa_part[(size_t)q * G + b];
     t = wave_sum(t);
     if (lane == 0) val[q] = t;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  const int i = mk > 0 ? tid / mk : 0, j = mk > 0 ? tid % mk : 0;
+  const bool mine = tid < mk * mk;
+  if (mine) {
+    // Gram matrix: the new column from the partial sums, the rest as stored
+    double h;
+    if (i == col) h = val[2 * j];
+    else if (j == col) h = val[2 * i];
+    else h = d.aa_h[i * m + j];
+    d.aa_h[i * m + j] = h;
+    A[i][j] = h;
+  }
+  if (tid == 0) ok = mk > 0 ? 1 : 0;
+  __syncthreads();
   if (mk > 0) {
-    for (int j = 0; j < mk; ++j) {
-      d.aa_h[j * m + col] = val[2 * j];
-      d.aa_h[col * m + j] = val[2 * j];
-      d.aa_v[j] = val[2 * j + 1];
+    if (tid == 0) {
+      double dmax = 0.0;
+      for (int q = 0; q < mk; ++q) dmax = fmax(dmax, A[q][q]);
+      if (!(dmax > 0.0)) ok = 0;
+      val[0] = 1e-10 * dmax;  // the partials are no longer needed
     }
-    double dmax = 0.0;
-    for (int i = 0; i < mk; ++i) dmax = fmax(dmax, d.aa_h[i * m + i]);
-    const double ridge = 1e-10 * dmax;
-    bool ok = dmax > 0.0;
-    for (int i = 0; i < mk && ok; ++i) {
-      for (int j = 0; j <= i; ++j) {
-        double sum = d.aa_h[i * m + j] + (i == j ? ridge : 0.0);
-        for (int q = 0; q < j; ++q) sum -= L[i][q] * L[j][q];
-        if (i == j) {
-          if (!(sum > 0.0)) {
-            ok = false;
-            break;
-          }
-          L[i][i] = sqrt(sum);
-        } else {
-          L[i][j] = sum / L[j][j];
-        }
+    __syncthreads();
+    if (mine && i == j) A[i][i] += val[0];
+    __syncthreads();
+    for (int kk = 0; kk < mk; ++kk) {
+      if (tid == 0) {
+        if (ok && A[kk][kk] > 0.0) A[kk][kk] = sqrt(A[kk][kk]);
+        else ok = 0;
       }
+      __syncthreads();
+      if (!ok) break;
+      if (tid > kk && tid < mk) A[tid][kk] /= A[kk][kk];
+      __syncthreads();
+      if (mine && i > kk && j > kk && j <= i) A[i][j] -= A[i][kk] * A[j][kk];
+      __syncthreads();
     }
-    for (int i = 0; i < mk; ++i) {
-      double sum = ok ? d.aa_v[i] : 0.0;
-      for (int q = 0; q < i && ok; ++q) sum -= L[i][q] * y[q];
-      y[i] = ok ? sum / L[i][i] : 0.0;
-    }
-    for (int i = mk - 1; i >= 0; --i) {
-      double sum = y[i];
-      for (int q = i + 1; q < mk && ok; ++q) sum -= L[q][i] * d.aa_gamma[q];
-      d.aa_gamma[i] = ok ? sum / L[i][i] : 0.0;
+    if (wave == 0) {
+      // L y = v, then L^T gamma = y (lower triangle of A holds L); lane r
+      // keeps y_r and gamma_r, the row dot products are shuffle-reduced
+      double yl = 0.0, gl = 0.0;
+      for (int r = 0; r < mk; ++r) {
+        double t = (lane < r) ? A[r][lane] * yl : 0.0;
+        t = wave_sum(t);
+        const double yr = (val[2 * r + 1] - t) / A[r][r];
+        if (lane == r) yl = yr;
+      }
+      for (int r = mk - 1; r >= 0; --r) {
+        double t = (lane > r && lane < mk) ? A[lane][r] * gl : 0.0;
+        t = wave_sum(t);
+        const double gr = (__shfl(yl, r, 64) - t) / A[r][r];
+        if (lane == r) gl = gr;
+      }
+      if (lane < mk) d.aa_gamma[lane] = ok ? gl : 0.0;
     }
   }
-  d.aa_k[0] = k + 1;
+  if (tid == 0) d.aa_k[0] = k + 1;
 }
 
 // mu_{k+1} = mu_k + f_k - sum_j gamma_j (dX_j + dF_j)
@@ -744,7 +767,7 @@ hipError_t launch_adj_anderson(const Dev<R>& d, const Consts& c, hipStream_t s) 
   if (c.aa_m <= 0) return hipSuccess;
   const int G = max(1, min(cdiv(3L * c.n, kAaBlock), min(c.nparts, 1024)));
   k_aa_diff_dots<R><<<G, kAaBlock, 0, s>>>(d, c);
-  k_aa_solve<R><<<1, 1024, 0, s>>>(d, c, G);
+  k_aa_solve<R><<<1, kAaSolveBlock, 0, s>>>(d, c, G);
   k_aa_update<R><<<G, kAaBlock, 0, s>>>(d, c);
   return hipGetLastError();
 }

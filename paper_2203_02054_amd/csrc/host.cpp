@@ -52,7 +52,7 @@ struct Layout {
   size_t u, xc, res4, cg, dl, p, dg, dsp, pen, hcount, hslot, hover, penlist, fhit, fc, fn, cact, ctgt, cnrm,
       cprim, part_a, part_b, part_c, part_d, part_e, part_f, st, trace, mesh, vmesh, tmesh, mres, mchanged, mdone;
   size_t mu, acc3, ga, ch_start, ch_tets, mmax, mdone2, st2, alpha_last;
-  size_t aa_dx, aa_df, aa_xp, aa_fp, aa_h, aa_v, aa_gamma, aa_part, aa_k;
+  size_t aa_dx, aa_df, aa_xp, aa_fp, aa_h, aa_gamma, aa_part, aa_k;
   size_t total;
 };
 
@@ -234,7 +234,6 @@ Layout make_layout(const gs_problem* p) {
   L.aa_xp = take(am ? 3 * n * W : 0);
   L.aa_fp = take(am ? 3 * n * W : 0);
   L.aa_h = take(am * am * 8);
-  L.aa_v = take(am * 8);
   L.aa_gamma = take(am * 8);
   L.aa_part = take(2 * am * (size_t)p->nparts * 8);
   L.aa_k = take(4);
@@ -311,7 +310,6 @@ Dev<R> make_dev(const gs_problem* p) {
   d.aa_xp = (R*)(b + L.aa_xp);
   d.aa_fp = (R*)(b + L.aa_fp);
   d.aa_h = (double*)(b + L.aa_h);
-  d.aa_v = (double*)(b + L.aa_v);
   d.aa_gamma = (double*)(b + L.aa_gamma);
   d.aa_part = (double*)(b + L.aa_part);
   d.aa_k = (int32_t*)(b + L.aa_k);

@@ -137,7 +137,6 @@ struct Dev {
   R* aa_xp;                // [3][n] previous iterate
   R* aa_fp;                // [3][n] previous residual
   double* aa_h;            // [m][m] Gram matrix of aa_df
-  double* aa_v;            // [m] aa_df^T f
   double* aa_gamma;        // [m] least-squares coefficients
   double* aa_part;         // [2m][nparts] block partials of the dot products
   int32_t* aa_k;           // [1] iterations taken by the accelerated loop
