@@ -35,6 +35,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel measured with rocprofv3 counters
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a 256 MiB copy);
+# see profiles/finger_pcg_hbm_traffic.md.  Only valid for the kernel build the
+# counters were taken on: remove an entry when its kernel changes.
+PMC_TRAFFIC = {("finger", "pcg"): 34204953}
+
 
 def kernel_bytes(info, W, n_launch, pcg_iters):
     """Algorithmic bytes per launch of each kernel: the data the method must
@@ -71,7 +77,7 @@ def kernel_bytes(info, W, n_launch, pcg_iters):
     return out
 
 
-def roofline_of(prof, info, W, pcg_iters):
+def roofline_of(prof, info, W, pcg_iters, workload=None):
     n_launch = {k: v[1] for k, v in prof.items()}
     kb = kernel_bytes(info, W, n_launch, pcg_iters)
     dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
@@ -80,7 +86,7 @@ def roofline_of(prof, info, W, pcg_iters):
         return None
     achieved = kb[dom] / (avg_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": None, "kernel": dom,
+            "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": PMC_TRAFFIC.get((workload, dom)), "kernel": dom,
             "avg_launch_us": round(1e3 * avg_ms, 3), "algorithmic_bytes_per_launch": int(kb[dom])}
 
 
@@ -293,7 +299,7 @@ def main():
     iters = sum(s["iters"] for s in stats)
     pcg_iters = sum(s["pcg_iters_total"] for s in stats)
     value = wl.n_tets * iters / (ms / 1e3)
-    roof = roofline_of(prof, gp.info, W, sum(s["pcg_iters_total"] for s in pstats))
+    roof = roofline_of(prof, gp.info, W, sum(s["pcg_iters_total"] for s in pstats), wl.name)
     out = {
         "metric": "tet-iterations/sec to 1e-6 residual (plain solve)",
         "value": round(value, 1),
