@@ -37,9 +37,9 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 counters
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a 256 MiB copy);
-# see profiles/finger_pcg_hbm_traffic.md.  Only valid for the kernel build the
-# counters were taken on: remove an entry when its kernel changes.
-PMC_TRAFFIC = {("finger", "pcg"): 34204953}
+# see profiles/*_hbm_traffic.md.  Only valid for the kernel build the counters
+# were taken on: remove an entry when its kernel changes.
+PMC_TRAFFIC = {}
 
 
 def kernel_bytes(info, W, n_launch, pcg_iters):

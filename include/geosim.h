@@ -126,6 +126,8 @@ typedef struct {
   int32_t n_slots;         /* contact slots per query vertex: 1 + spheres + planes */
   int32_t hash_buckets;
   double h_ref, eps_off, ray_len, bbox_diag, cell_size;
+  int32_t ell_width;       /* off-diagonal slots per row of the stored matrix      */
+  int32_t pcg_grid;        /* workgroups of the CG kernel (0 before gs_bind)       */
 } gs_info;
 
 typedef struct gs_problem gs_problem;

@@ -419,7 +419,7 @@ gs_status bind_impl(gs_problem* p) {
   HIPCHK(hipMemsetAsync(b + L.hcount, 0, (size_t)p->H * 4, s));
   HIPCHK(hipMemsetAsync(b + L.pen, 0, (size_t)std::max(p->S, 1) * 4, s));
   HIPCHK(hipStreamSynchronize(s));
-  const int maxg = pcg_max_grid<R>(0);
+  const int maxg = pcg_max_grid<R>(p->ell_w);
   if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
   p->pcg_grid = pcg_grid_for(p, maxg);
   return GS_OK;
@@ -1121,6 +1121,8 @@ gs_status gs_info_get(const gs_problem* p, gs_info* info) {
   info->ray_len = p->Lray;
   info->bbox_diag = p->diag;
   info->cell_size = p->cell;
+  info->ell_width = p->ell_w;
+  info->pcg_grid = p->bound ? p->pcg_grid : 0;
   return GS_OK;
 }
 
@@ -1165,7 +1167,7 @@ gs_status gs_set_params(gs_problem* p, const gs_params* prm) {
     HIPCHK(upload(p->ws, p->lay.mesh, mt, p->stream));
   }
   if (p->bound) {
-    const int maxg = p->prec == 4 ? pcg_max_grid<float>(0) : pcg_max_grid<double>(0);
+    const int maxg = p->prec == 4 ? pcg_max_grid<float>(p->ell_w) : pcg_max_grid<double>(p->ell_w);
     p->pcg_grid = pcg_grid_for(p, maxg);
     HIPCHK(hipStreamSynchronize(p->stream));
   }

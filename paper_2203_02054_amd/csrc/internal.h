@@ -170,7 +170,7 @@ template <typename R> hipError_t launch_adj_gather(const Dev<R>& d, const Consts
 template <typename R> hipError_t launch_adj_chamber_sum(const Dev<R>& d, const Consts& c, R* out, hipStream_t s);
 template <typename R> hipError_t launch_adj_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_set_positions(const Dev<R>& d, const Consts& c, const R* x, hipStream_t s);
-template <typename R> int pcg_max_grid(int block);
+template <typename R> int pcg_max_grid(int ell_w);
 
 __host__ __device__ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 

@@ -361,16 +361,16 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   __hip_atomic_store(&st->done, code, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Neighbour gathers are issued in chunks of CH rows of 16-byte vectors (so the
-// loads of a chunk are in flight together without exhausting registers); the
-// column indices and scaled values of a row are preloaded when they fit.
-template <typename R> struct Chunk { static constexpr int n = 8; };
+// Neighbour gathers are issued in chunks of CH rows of 16-byte vectors, all
+// loads of a chunk in flight together.  In FP32 one chunk covers a 16-wide row
+// (one dependent round of neighbour loads per row: faster than two rounds at
+// twice the occupancy); FP64 rows use chunks of 4 to stay within registers.
+template <typename R> struct Chunk { static constexpr int n = 16; };
 template <> struct Chunk<double> { static constexpr int n = 4; };
 
 template <typename R, int MW, bool ADJ>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   constexpr int CH = Chunk<R>::n;
-  constexpr bool PRE = MW <= 16;
   __shared__ double lds[kPcgBlock / 64];
   __shared__ double sh[2];
   if (is_done(d.st)) return;
@@ -483,15 +483,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     acc_d = 0.0;
     for (int v = tid0; v < c.n; v += stride) {
       const R idg = R(1) / dg[v];
-      int jpre[PRE ? MW : 1];
-      R apre[PRE ? MW : 1];
-      if (PRE) {
-#pragma unroll
-        for (int k = 0; k < MW; ++k) {
-          jpre[k] = ecol[(size_t)k * n + v];
-          apre[k] = evs[(size_t)k * n + v];
-        }
-      }
       const W4<R> rc = cs[3 * (size_t)v], wc = cs[3 * (size_t)v + 1], sc = cs[3 * (size_t)v + 2];
       const W4<R> pv0 = p[v];
       const W4<R> xv = x[v];
@@ -507,8 +498,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         R aa[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-          jj[k] = PRE ? jpre[k0 + k] : ecol[(size_t)(k0 + k) * n + v];
-          aa[k] = PRE ? apre[k0 + k] : evs[(size_t)(k0 + k) * n + v];
+          jj[k] = ecol[(size_t)(k0 + k) * n + v];
+          aa[k] = evs[(size_t)(k0 + k) * n + v];
         }
         W4<R> nr[CH], nw[CH], nsv[CH];
 #pragma unroll
@@ -605,24 +596,22 @@ hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s,
 }
 
 
+// Workgroups of the CG kernel that can be resident at once for a matrix of
+// ELL width ell_w: the smaller occupancy of its forward and adjoint variants
+// times the compute units (0 on a runtime error).
 template <typename R>
-int pcg_max_grid(int block) {
-  int occ = 0;
-  int o16 = 0, o32 = 0, o64 = 0;
-  int a16 = 0, a32 = 0, a64 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o16, k_pcg<R, 16, false>, kPcgBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&o32, k_pcg<R, 32, false>, kPcgBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&o64, k_pcg<R, 64, false>, kPcgBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&a16, k_pcg<R, 16, true>, kPcgBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&a32, k_pcg<R, 32, true>, kPcgBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&a64, k_pcg<R, 64, true>, kPcgBlock, 0) != hipSuccess)
+int pcg_max_grid(int ell_w) {
+  const void* f = ell_w <= 16 ? (const void*)k_pcg<R, 16, false>
+                              : ell_w <= 32 ? (const void*)k_pcg<R, 32, false> : (const void*)k_pcg<R, 64, false>;
+  const void* a = ell_w <= 16 ? (const void*)k_pcg<R, 16, true>
+                              : ell_w <= 32 ? (const void*)k_pcg<R, 32, true> : (const void*)k_pcg<R, 64, true>;
+  int of = 0, oa = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&of, f, kPcgBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&oa, a, kPcgBlock, 0) != hipSuccess)
     return 0;
-  occ = std::min({o16, o32, o64, a16, a32, a64});
-  int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  (void)block;
-  return occ * cus;
+  return std::min(of, oa) * cus;
 }
 
 #define INST(R)                                                                                  \

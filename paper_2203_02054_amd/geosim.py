@@ -55,7 +55,7 @@ class Info(ctypes.Structure):
                 ("n_surface_verts", ctypes.c_int32), ("n_query_verts", ctypes.c_int32), ("nnz", ctypes.c_int32),
                 ("n_slots", ctypes.c_int32), ("hash_buckets", ctypes.c_int32), ("h_ref", ctypes.c_double),
                 ("eps_off", ctypes.c_double), ("ray_len", ctypes.c_double), ("bbox_diag", ctypes.c_double),
-                ("cell_size", ctypes.c_double)]
+                ("cell_size", ctypes.c_double), ("ell_width", ctypes.c_int32), ("pcg_grid", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -264,6 +264,9 @@ class Problem:
                 raise TypeError(f"unknown parameter {k}")
             setattr(self.params, k, type(getattr(self.params, k))(v))
         _check(lib().gs_set_params(self._h, ctypes.byref(self.params)))
+        inf = Info()
+        _check(lib().gs_info_get(self._h, ctypes.byref(inf)))
+        self.info = inf.as_dict()
 
     def solve(self, alpha, x=None, allow_not_converged=True):
         """Solve from x (default: rest positions) with the stored contact set.
