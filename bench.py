@@ -137,6 +137,7 @@ def run_batched(G, mg, n_mesh, max_iter, sample):
     alpha = gb.tensor(np.concatenate([w.alpha for w in wls]))
     x0 = gb.tensor(gb._X)
     x = x0.clone()
+    grid, _ = gb.autotune(alpha, x, iters=8)
 
     def solve():
         x.copy_(x0)
@@ -182,7 +183,7 @@ def run_batched(G, mg, n_mesh, max_iter, sample):
     rate_plain = work_plain / t_plain
     out = {"value": round(value, 1), "unit": "tet-iterations/s", "ms_per_step": round(ms, 3),
            "meshes": n_mesh, "tets": int(Ts.sum()), "chambers": int(sum(w.n_chambers for w in wls)),
-           "max_iter": max_iter, "outer_iters": st["iters"], "pcg_iters": st["pcg_iters_total"],
+           "max_iter": max_iter, "outer_iters": st["iters"], "pcg_iters": st["pcg_iters_total"], "pcg_grid": grid,
            "converged_meshes": int((its > 0).sum()),
            "plain_sample": {"meshes": len(idx), "value": round(rate_plain, 1), "unit": "tet-iterations/s"},
            "speedup_vs_plain": round(value / rate_plain, 3), "roofline": roof, "kernels": kernel_table(prof)}
@@ -263,6 +264,7 @@ def main():
     alpha = gp.tensor(wl.alpha)
     x = x0.clone()
     stream = gp.stream
+    grid, _ = gp.autotune(alpha, x, iters=20)
 
     def step():
         x.copy_(x0)
@@ -316,7 +318,7 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.n_tets} tets, {wl.n_verts} verts, {wl.n_chambers} chambers, "
                                f"self-collision {'on' if wl.self_collision else 'off'}, plain solve to 1e-6",
                    "tets": wl.n_tets, "outer_iters_per_step": iters / a.steps,
-                   "pcg_iters_per_step": pcg_iters / a.steps, "contacts": stats[-1]["n_contacts"],
+                   "pcg_iters_per_step": pcg_iters / a.steps, "pcg_grid": grid, "contacts": stats[-1]["n_contacts"],
                    "residual": stats[-1]["residual"]},
         "roofline": roof,
         "kernels": kernel_table(prof),

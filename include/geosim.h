@@ -228,6 +228,17 @@ gs_status gs_set_contacts(gs_problem* p, int32_t count, const int32_t* v, const 
                           const int32_t* prim, const double* target, const double* normal,
                           const int32_t* fresh);
 
+/* Choose the CG kernel's grid for this problem: times `iters` fixed
+ * iterations from dev_x (with the stored contact set) for the default grid
+ * (about one row per thread) and every power-of-two grid that can be
+ * resident, keeps the fastest in params.pcg_blocks, and restores dev_x and
+ * the stored contact set.  *chosen (may be NULL) receives the grid,
+ * *ms_per_iter (may be NULL) its time per outer iteration.  Errors as
+ * gs_solve; the last solve's adjoint state is discarded (gs_adjoint then
+ * needs a new gs_solve). */
+gs_status gs_autotune(gs_problem* p, const void* dev_alpha, void* dev_x, int32_t iters, int32_t* chosen,
+                      double* ms_per_iter);
+
 /* Implicit adjoint of the last gs_solve (not in the paper: the gradient of
  * its fixed point).  At the positions x the solve returned, with the stored
  * active set held fixed and the volume ratios alpha of that solve, the free

@@ -1182,6 +1182,87 @@ gs_status gs_solve(gs_problem* p, const void* alpha, void* x, gs_stats* stats) {
   return solve_impl<double>(p, (const double*)alpha, (double*)x, stats);
 }
 
+gs_status gs_autotune(gs_problem* p, const void* alpha, void* x, int32_t iters, int32_t* chosen, double* ms_per_iter) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "gs_autotune before gs_bind");
+  if (!x || (p->nch > 0 && !alpha) || iters < 1) return fail(GS_EINVAL, "bad argument");
+  hipStream_t s = p->stream;
+  const size_t W = (size_t)p->prec, xb = 3 * (size_t)p->n * W;
+  const size_t m = (size_t)p->S * p->slots;
+  // keep the caller's start positions (in the adjoint iterate's storage, free
+  // between calls) and the stored contact set; each trial starts from both
+  char* xs = p->ws + p->lay.mu;
+  std::vector<uint8_t> act(m);
+  std::vector<double> tg(3 * m), nr(3 * m);
+  std::vector<int32_t> pr(m);
+  HIPCHK(hipMemcpyAsync(xs, x, xb, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(act.data(), p->ws + p->lay.cact, m, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(tg.data(), p->ws + p->lay.ctgt, 3 * m * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(nr.data(), p->ws + p->lay.cnrm, 3 * m * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(pr.data(), p->ws + p->lay.cprim, m * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  auto restore = [&]() -> gs_status {
+    HIPCHK(hipMemcpyAsync(x, xs, xb, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->ws + p->lay.cact, act.data(), m, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->ws + p->lay.ctgt, tg.data(), 3 * m * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->ws + p->lay.cnrm, nr.data(), 3 * m * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(p->ws + p->lay.cprim, pr.data(), m * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return GS_OK;
+  };
+  const int maxg = p->prec == 4 ? pcg_max_grid<float>(p->ell_w) : pcg_max_grid<double>(p->ell_w);
+  if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
+  const gs_params saved = p->prm;
+  const bool prof = p->prof.on;
+  p->prof.on = false;
+  // candidates: the default (about one row per thread) and every power of two
+  std::vector<int> cand = {std::max(1, std::min({cdiv(p->n, kPcgThreads), maxg, kMaxPcgGrid, p->nparts / 2}))};
+  for (int g = 1; g <= std::min({maxg, kMaxPcgGrid, p->nparts / 2}); g *= 2)
+    if (g != cand[0]) cand.push_back(g);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best_ms = INFINITY;
+  int best = cand[0];
+  gs_status st = GS_OK;
+  for (int g : cand) {
+    p->prm.fixed_iters = iters;
+    p->prm.pcg_blocks = g;
+    p->pcg_grid = g;
+    for (int rep = 0; rep < 2 && st == GS_OK; ++rep) {  // the first run warms up
+      if ((st = restore()) != GS_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) st = fail(GS_EHIP, "event record");
+      gs_stats sts{};
+      const gs_status r = p->prec == 4 ? solve_impl<float>(p, (const float*)alpha, (float*)x, &sts)
+                                       : solve_impl<double>(p, (const double*)alpha, (double*)x, &sts);
+      if (r < 0) st = r;
+      if (st == GS_OK && hipEventRecord(e1, s) != hipSuccess) st = fail(GS_EHIP, "event record");
+      if (st == GS_OK && hipEventSynchronize(e1) != hipSuccess) st = fail(GS_EHIP, "event sync");
+      float ms = 0.f;
+      if (st == GS_OK && rep == 1 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best = g;
+      }
+    }
+    if (st != GS_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->prm = saved;
+  p->prof.on = prof;
+  if (st == GS_OK) st = restore();
+  p->solved = false;
+  if (st != GS_OK) {
+    p->pcg_grid = pcg_grid_for(p, maxg);
+    return st;
+  }
+  p->prm.pcg_blocks = best;
+  p->pcg_grid = pcg_grid_for(p, maxg);
+  if (chosen) *chosen = p->pcg_grid;
+  if (ms_per_iter) *ms_per_iter = best_ms / iters;
+  return GS_OK;
+}
+
 gs_status gs_adjoint(gs_problem* p, const void* dLdx, void* dLdalpha, void* mu, gs_stats* stats) {
   if (!p) return fail(GS_EINVAL, "null problem");
   if (!p->bound) return fail(GS_ESTATE, "gs_adjoint before gs_bind");

@@ -82,6 +82,7 @@ SIGNATURES = {
     "gs_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD, _PI, _PI]),
     "gs_set_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD, _PI]),
     "gs_adjoint": (_I, [_P, _P, _P, _P, ctypes.POINTER(Stats)]),
+    "gs_autotune": (_I, [_P, _P, _P, _I, _PI, _PD]),
     "gs_local_step_debug": (_I, [_P, _P, _P, _P]),
     "gs_tets": (_I, [_P, _PI]),
     "gs_faces": (_I, [_P, _PI]),
@@ -282,6 +283,22 @@ class Problem:
         d = st.as_dict()
         d["status"] = code
         return x, d
+
+    def autotune(self, alpha, x=None, iters=20):
+        """Pick the CG grid by timing `iters` fixed iterations per candidate from
+        x (default: rest positions); returns (grid, ms per outer iteration)."""
+        a = alpha if self.torch.is_tensor(alpha) else self.tensor(np.asarray(alpha, dtype=np.float64).reshape(-1))
+        if x is None:
+            x = self.tensor(self._X)
+        g = ctypes.c_int32()
+        ms = ctypes.c_double()
+        _check(lib().gs_autotune(self._h, self._dev(a, (self.n_chambers,)) if self.n_chambers else None,
+                                 self._dev(x, (3, self.n)), int(iters), ctypes.byref(g), ctypes.byref(ms)))
+        self.params.pcg_blocks = g.value
+        inf = Info()
+        _check(lib().gs_info_get(self._h, ctypes.byref(inf)))
+        self.info = inf.as_dict()
+        return g.value, ms.value
 
     def trace(self):
         """Per-iteration rows (r_k, E_k, springs, changed, CG its, ray misses) of the last solve."""
