@@ -15,9 +15,10 @@ the inner loop of Algorithm 1) in double precision:
                  active set (Sections II-B, II-C, III-A.3; Eqs. 3-5, 8).
 * ``solve``    - right-hand side, exact sparse direct global step, energy
                  (Eq. 9) and the local/global iteration.
-* ``adjoint``  - the implicit-function gradient w.r.t. the per-chamber
-                 volume ratios at a fixed point with the contact set frozen,
-                 by automatic differentiation of the plain definitions.
+* ``adjoint``  - gradients w.r.t. the per-chamber volume ratios: implicit
+                 (at a fixed point with the contact set frozen) and unrolled
+                 (through K recorded iterations), by automatic
+                 differentiation of the plain definitions.
 
 Readings of passages the paper leaves open are listed where they are used.
 """
@@ -25,7 +26,8 @@ from .mesh import Params, Problem, orient, ORIENT_SWAP
 from .local import local_step, mooney_rivlin_weight
 from .collision import collide, Contacts
 from .solver import solve, global_step, energy, residual_rhs
-from .adjoint import grad
+from .adjoint import grad, unrolled_grad, record_path
 
 __all__ = ["Params", "Problem", "orient", "ORIENT_SWAP", "local_step", "mooney_rivlin_weight",
-           "collide", "Contacts", "solve", "global_step", "energy", "residual_rhs", "grad"]
+           "collide", "Contacts", "solve", "global_step", "energy", "residual_rhs", "grad",
+           "unrolled_grad", "record_path"]

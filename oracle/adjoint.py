@@ -1,5 +1,5 @@
-"""Oracle gradient of the converged shape with respect to the chamber volume
-ratios (implicit function theorem at the local/global fixed point).
+"""Oracle gradients with respect to the chamber volume ratios: implicit
+(at the local/global fixed point) and unrolled (through K iterations).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -247,3 +247,71 @@ def frozen_solve(prob, alpha, x0, contacts, fresh, tol: float = 1e-13, max_iter:
         x = gx.copy()
         x[:, F] = xf.reshape(3, F.size)
     return x, max_iter, step
+
+
+# ---------------------------------------------------------------------------
+# Unrolled gradient over a fixed number of iterations
+#
+# For K iterations from x_0 the k-th global step is
+#     x_{k+1,F} = M_k,FF^-1 (b_k,F(x_k, alpha) - M_k,FC x_C),
+# with A_k the contact set the collision check found at x_k (its decisions are
+# piecewise constant in x and held as recorded; targets of self contacts
+# created at iteration k follow x_k, kept ones are constants, obstacle targets
+# follow x_k).  Reverse mode: lambda_K = g, and for k = K-1 ... 0
+#     nu = M_k,FF^-1 lambda_{k+1},  dL/dalpha += (db_k/dalpha)^T nu,
+#     lambda_k = (db_k/dx_k)^T nu   (free rows).
+# The exact global step is the one this definition differentiates; a solver
+# whose inner solves are inexact follows a slightly different path.
+
+
+def record_path(prob, alpha, x0, contacts0, K):
+    """K oracle iterations from x0 (and the set contacts0 as A_{-1}), keeping
+    (x_k, A_k, fresh_k) for every k and the final x_K."""
+    from .collision import collide
+    from .local import local_step
+    from .solver import _Factor, global_step
+    S = prob.query_verts.size
+    prev = Contacts.empty(S, prob.n_slots) if contacts0 is None else contacts0.copy()
+    x = np.array(x0, dtype=np.float64, copy=True)
+    x[:, prob.fixed] = prob.X0[:, prob.fixed]
+    fac = _Factor()
+    path = []
+    for _ in range(K):
+        if prob.params.self_collision or prob.params.obstacle_collision:
+            A, info = collide(prob, x, prev)
+            fresh = info["self_fresh"]
+        else:
+            A, fresh = Contacts.empty(S, prob.n_slots), np.zeros(S, bool)
+        path.append((x.copy(), A, fresh))
+        x = global_step(prob, local_step(prob, x, alpha), A, x, fac)
+        prev = A
+    return path, x
+
+
+def replay(prob, alpha, path):
+    """x_K of the recorded path's contact schedule for another alpha (the
+    frozen-schedule map the unrolled gradient differentiates)."""
+    x = path[0][0].copy()
+    for _, A, fresh in path:
+        x = frozen_map(prob, x, alpha, A, fresh)
+    return x
+
+
+def unrolled_grad(prob, alpha, path, dLdx):
+    """dL/dalpha and dL/dx_0 of L(x_K) through the recorded path."""
+    F = np.nonzero(prob.free)[0]
+    lam = np.zeros((3, prob.n))
+    lam[:, F] = np.asarray(dLdx, dtype=np.float64)[:, F]
+    ga = np.zeros(np.asarray(alpha).size)
+    for xk, A, fresh in reversed(path):
+        fz = _Frozen(prob, A)
+        nu = np.zeros((3, prob.n))
+        nu[:, F] = fz.lu.solve(np.ascontiguousarray(lam[:, F].T)).T
+        xt = torch.tensor(xk, requires_grad=True)
+        at = torch.tensor(np.asarray(alpha, dtype=np.float64).reshape(-1), requires_grad=True)
+        b = rhs(prob, xt, at, A, fresh)
+        gx, gal = torch.autograd.grad(b, (xt, at), grad_outputs=torch.from_numpy(nu))
+        ga += gal.numpy()
+        lam = np.zeros((3, prob.n))
+        lam[:, F] = gx.numpy()[:, F]
+    return ga, lam

@@ -146,3 +146,38 @@ def test_implicit_gradient_matches_central_differences(contact_state):
         assert sp_ <= 1e-14 and sm_ <= 1e-14
         fd[c] = ((g * xp).sum() - (g * xm).sum()) / (2 * h)
     assert np.linalg.norm(ga - fd) <= 1e-5 * np.linalg.norm(fd)
+
+
+def test_unrolled_gradient_matches_central_differences():
+    """Unrolled gradient through 30 iterations from rest (new and kept self
+    contacts, sphere and plane springs along the way) against central
+    differences of the same contact schedule replayed for alpha +- h."""
+    w = pressed_finger()
+    prob = oracle.Problem.from_workload(w)
+    path, xK = oa.record_path(prob, w.alpha, prob.X0, None, 30)
+    assert sum(int(f.sum()) for _, _, f in path) > 0
+    assert np.abs(oa.replay(prob, w.alpha, path) - xK).max() < 1e-12 * prob.diag * 100
+    rng = np.random.default_rng(0)
+    g = rng.standard_normal((3, prob.n))
+    g[:, prob.fixed] = 0.0
+    ga, _ = oa.unrolled_grad(prob, w.alpha, path, g)
+    h = 1e-5
+    fd = np.zeros(w.n_chambers)
+    for c in range(w.n_chambers):
+        ap, am = w.alpha.copy(), w.alpha.copy()
+        ap[c] += h
+        am[c] -= h
+        fd[c] = ((g * oa.replay(prob, ap, path)).sum() - (g * oa.replay(prob, am, path)).sum()) / (2 * h)
+    assert np.linalg.norm(ga - fd) <= 1e-8 * np.linalg.norm(fd)
+
+
+def test_unrolled_gradient_closed_form():
+    """All-chamber box from rest: one iteration reaches the scaled shape, which
+    is then a fixed point for every alpha, so the unrolled gradient of
+    L = sum |x - x_f|^2 is the closed form for any K >= 1."""
+    prob, xf = _closed_form_case(mg.CH_ISO)
+    alpha = np.array([1.8])
+    path, xK = oa.record_path(prob, alpha, prob.X0, None, 4)
+    ga, _ = oa.unrolled_grad(prob, alpha, path, 2.0 * (xK - xf))
+    exact = (2.0 / 3.0) * alpha[0] ** (-1.0 / 3.0) * ((prob.X0 - xf) ** 2).sum()
+    assert ga[0] == pytest.approx(exact, rel=1e-10)
