@@ -228,6 +228,32 @@ gs_status gs_set_contacts(gs_problem* p, int32_t count, const int32_t* v, const 
                           const int32_t* prim, const double* target, const double* normal,
                           const int32_t* fresh);
 
+/* Unrolled adjoint over a fixed iteration budget (the differentiable form of
+ * a K-iteration solve; not in the paper).  Runs K local/global iterations
+ * from dev_x0 [3][n] with the stored contact set as the previous one (as
+ * gs_solve with fixed_iters = K), then the reverse sweep: with the contact
+ * set A_k each iteration found held as recorded (new self-contact targets
+ * follow x_k, kept ones are constants, obstacle targets follow x_k),
+ * x_{k+1} = M_k^-1 b_k(x_k, alpha) is differentiated exactly:
+ *   lambda_K = g;  for k = K-1..0:  nu = M_k^-1 lambda_{k+1},
+ *   dL/dalpha += (db_k/dalpha)^T nu,  lambda_k = (db_k/dx_k)^T nu.
+ * Each M_k^-1 is the solve's CG (pcg_eta / pcg_max apply; a small pcg_eta
+ * keeps the forward path close to exact global steps).  States are
+ * checkpointed every ceil(sqrt(K)) iterations in dev_scratch (caller-owned,
+ * 256-byte aligned, gs_unrolled_scratch_size(p, K) bytes) and each segment
+ * is recomputed once.  Outputs (device, problem width): dev_dLdalpha
+ * [n_chambers]; dev_dLdx0 [3][n] = lambda_0 (may be NULL); dev_xK [3][n]
+ * the positions after K iterations (may be NULL).  The stored contact set
+ * afterwards is the one the K-th iteration found, as after gs_solve.
+ * stats (may be NULL): iters = K, pcg_iters_total = forward + reverse CG
+ * iterations, residual / energy of the last forward iteration.  Errors:
+ * GS_EINVAL (bad sizes, null or small scratch), GS_ESTATE, GS_EBREAKDOWN,
+ * GS_EHIP.  The implicit adjoint state of an earlier gs_solve is discarded. */
+size_t gs_unrolled_scratch_size(const gs_problem* p, int32_t K);
+gs_status gs_adjoint_unrolled(gs_problem* p, const void* dev_alpha, const void* dev_x0, int32_t K,
+                              const void* dev_dLdx, void* dev_dLdalpha, void* dev_dLdx0, void* dev_xK,
+                              void* dev_scratch, size_t scratch_bytes, gs_stats* stats);
+
 /* Choose the CG kernel's grid for this problem: times `iters` fixed
  * iterations from dev_x (with the stored contact set) for the default grid
  * (about one row per thread) and every power-of-two grid that can be

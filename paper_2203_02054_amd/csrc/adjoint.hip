@@ -442,7 +442,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_springs(Dev<R> d, Consts c) {
 // Per-tet adjoint columns omega_e ((dT_e/dx_e)^T mu_e - mu_e N) in incidence
 // order; with alpha_grad, the per-tet term of dL/dalpha instead (all meshes).
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_adj_local(Dev<R> d, Consts c, int alpha_grad) {
+__global__ __launch_bounds__(kBlock) void k_adj_local(Dev<R> d, Consts c, int mode_out) {
+  const bool alpha_grad = mode_out == ADJ_ALPHA, jt_only = mode_out == ADJ_JT;
   if (!alpha_grad && is_done(d.st)) return;
   const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= c.T) return;
@@ -484,12 +485,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_local(Dev<R> d, Consts c, int al
     d.ga[e] = (double)om * (double)ga;
     return;
   }
+  const R keep = jt_only ? R(0) : R(1);  // the residual form also subtracts A_el mu
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     V4<R> v;
-    v.x = om * (Xbar[0][j] - MU[0][j]);
-    v.y = om * (Xbar[1][j] - MU[1][j]);
-    v.z = om * (Xbar[2][j] - MU[2][j]);
+    v.x = om * (Xbar[0][j] - keep * MU[0][j]);
+    v.y = om * (Xbar[1][j] - keep * MU[1][j]);
+    v.z = om * (Xbar[2][j] - keep * MU[2][j]);
     v.w = R(0);
     res[d.inc_pos[j * c.T + e]] = v;
   }
@@ -567,9 +569,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_gather(Dev<R> d, Consts c) {
         r2 += k * jt[2];
       }
     }
-    r0 += (double)d.gL[v] - ds * mu[0];
-    r1 += (double)d.gL[n + v] - ds * mu[1];
-    r2 += (double)d.gL[2 * n + v] - ds * mu[2];
+    if (!c.adj_jt) {
+      r0 += (double)d.gL[v] - ds * mu[0];
+      r1 += (double)d.gL[n + v] - ds * mu[1];
+      r2 += (double)d.gL[2 * n + v] - ds * mu[2];
+    }
+  }
+  if (c.adj_jt) {
+    d.lam[v] = (R)r0;
+    d.lam[n + v] = (R)r1;
+    d.lam[2 * n + v] = (R)r2;
+    return;
   }
   A4<R> rb;
   rb.x = (R)r0;
@@ -772,6 +782,102 @@ hipError_t launch_adj_anderson(const Dev<R>& d, const Consts& c, hipStream_t s) 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Unrolled adjoint (reverse sweep over recorded iterations)
+//
+// For K iterations x_{k+1} = M_k^-1 b_k(x_k, alpha) (contact set A_k as the
+// forward found it): lambda_K = g; for k = K-1 ... 0, nu = M_k^-1 lambda_{k+1}
+// (the CG kernel on right-hand side lambda from a zero start, mu = nu),
+// dL/dalpha += (db_k/dalpha)^T nu, lambda_k = (db_k/dx_k)^T nu.
+
+// State x_k restored from u: collision positions, and the status block of
+// the recomputed forward iterations set running.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_unr_restore(Dev<R> d, Consts c, DevStatus* run) {
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  const size_t n = (size_t)c.n;
+  if (v < c.n) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d.xc[k * n + v] = d.X0[k * n + v] + (double)d.u[k * n + v];
+  }
+  if (v == 0) {
+    DevStatus* st = d.st;
+    st->done = RUNNING;
+    st->changed = 0;
+    st->ray_miss = 0;
+    st->n_pen = 0;
+    st->n_over = 0;
+    st->ticket = 0;
+    st->n_contacts = 0;
+    st->bar_count = 0;
+    st->bar_gen = 0;
+    run->done = RUNNING;
+  }
+}
+
+// Right-hand side lambda_{k+1} of the reverse CG solve (zero rows for fixed
+// vertices), the Jacobi diagonal of M_k for the restored contact set, a zero
+// start, and a fresh status block for the solve.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_unr_rhs(Dev<R> d, Consts c) {
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  const size_t n = (size_t)c.n;
+  if (v < c.n) {
+    const bool fr = d.freem[v] != 0;
+    double ds = 0.0;
+    const int s = d.vq[v];
+    if (fr && s >= 0)
+      for (int sl = 0; sl < c.slots; ++sl)
+        if (d.cact[s * c.slots + sl]) ds += d.kq[s];
+    A4<R> rb;
+    rb.x = fr ? d.lam[v] : R(0);
+    rb.y = fr ? d.lam[n + v] : R(0);
+    rb.z = fr ? d.lam[2 * n + v] : R(0);
+    rb.w = R(0);
+    reinterpret_cast<A4<R>*>(d.cg)[3 * (size_t)v] = rb;
+    d.dg[v] = fr ? (R)((double)d.adiag[v] + ds) : R(1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      d.mu[k * n + v] = R(0);
+      d.dl[4 * (size_t)v + k] = R(0);
+    }
+  }
+  for (int i = v; i < c.M; i += gridDim.x * kBlock) {
+    d.mdone[i] = 0;
+    d.mres[i] = 0ull;
+    d.mmax[i] = 0ull;
+  }
+  if (v == 0) {
+    DevStatus* st = d.st;
+    st->iters = 0;
+    st->done = RUNNING;
+    st->ticket = 0;
+    st->bar_count = 0;
+    st->bar_gen = 0;
+    st->pcg_last = 0;
+  }
+}
+
+// dL/dalpha += this step's per-chamber sums (one block per chamber, fixed order).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_unr_accumulate(Dev<R> d, Consts c) {
+  __shared__ double lds[kBlock / 64];
+  const int ch = blockIdx.x;
+  if (ch >= c.nch) return;
+  double acc = 0.0;
+  const int b = d.ch_start[ch], e = d.ch_start[ch + 1];
+  for (int i = b + threadIdx.x; i < e; i += kBlock) acc += d.ga[d.ch_tets[i]];
+  const double t = block_sum<kBlock>(acc, lds);
+  if (threadIdx.x == 0) d.ga_acc[ch] += t;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_unr_finish(Dev<R> d, Consts c, R* dalpha, R* dx0) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (dalpha && i < c.nch) dalpha[i] = (R)d.ga_acc[i];
+  if (dx0 && i < 3 * c.n) dx0[i] = d.lam[i];
+}
+
 template <typename R>
 hipError_t launch_adj_init(const Dev<R>& d, const Consts& c, hipStream_t s) {
   k_adj_init<R><<<max(1, cdiv(c.n, kBlock)), kBlock, 0, s>>>(d, c);
@@ -785,7 +891,12 @@ hipError_t launch_adj_springs(const Dev<R>& d, const Consts& c, hipStream_t s) {
 }
 template <typename R>
 hipError_t launch_adj_local(const Dev<R>& d, const Consts& c, bool alpha_grad, hipStream_t s) {
-  k_adj_local<R><<<cdiv(c.T, kBlock), kBlock, 0, s>>>(d, c, alpha_grad ? 1 : 0);
+  k_adj_local<R><<<cdiv(c.T, kBlock), kBlock, 0, s>>>(d, c, alpha_grad ? ADJ_ALPHA : ADJ_RESIDUAL);
+  return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_adj_local_mode(const Dev<R>& d, const Consts& c, int mode, hipStream_t s) {
+  k_adj_local<R><<<cdiv(c.T, kBlock), kBlock, 0, s>>>(d, c, mode);
   return hipGetLastError();
 }
 template <typename R>
@@ -800,13 +911,40 @@ hipError_t launch_adj_chamber_sum(const Dev<R>& d, const Consts& c, R* out, hipS
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_unr_restore(const Dev<R>& d, const Consts& c, DevStatus* run, hipStream_t s) {
+  k_unr_restore<R><<<max(1, cdiv(c.n, kBlock)), kBlock, 0, s>>>(d, c, run);
+  return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_unr_rhs(const Dev<R>& d, const Consts& c, hipStream_t s) {
+  k_unr_rhs<R><<<max(1, cdiv(c.n, kBlock)), kBlock, 0, s>>>(d, c);
+  return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_unr_accumulate(const Dev<R>& d, const Consts& c, hipStream_t s) {
+  if (c.nch == 0) return hipSuccess;
+  k_unr_accumulate<R><<<c.nch, kBlock, 0, s>>>(d, c);
+  return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_unr_finish(const Dev<R>& d, const Consts& c, R* dalpha, R* dx0, hipStream_t s) {
+  k_unr_finish<R><<<max(1, cdiv(max(3 * c.n, c.nch), kBlock)), kBlock, 0, s>>>(d, c, dalpha, dx0);
+  return hipGetLastError();
+}
+
 #define INST(R)                                                                                  \
   template hipError_t launch_adj_init<R>(const Dev<R>&, const Consts&, hipStream_t);             \
   template hipError_t launch_adj_springs<R>(const Dev<R>&, const Consts&, hipStream_t);          \
   template hipError_t launch_adj_local<R>(const Dev<R>&, const Consts&, bool, hipStream_t);      \
   template hipError_t launch_adj_gather<R>(const Dev<R>&, const Consts&, hipStream_t);           \
   template hipError_t launch_adj_chamber_sum<R>(const Dev<R>&, const Consts&, R*, hipStream_t); \
-  template hipError_t launch_adj_anderson<R>(const Dev<R>&, const Consts&, hipStream_t);
+  template hipError_t launch_adj_anderson<R>(const Dev<R>&, const Consts&, hipStream_t);       \
+  template hipError_t launch_adj_local_mode<R>(const Dev<R>&, const Consts&, int, hipStream_t);  \
+  template hipError_t launch_unr_restore<R>(const Dev<R>&, const Consts&, DevStatus*, hipStream_t); \
+  template hipError_t launch_unr_rhs<R>(const Dev<R>&, const Consts&, hipStream_t);             \
+  template hipError_t launch_unr_accumulate<R>(const Dev<R>&, const Consts&, hipStream_t);      \
+  template hipError_t launch_unr_finish<R>(const Dev<R>&, const Consts&, R*, R*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

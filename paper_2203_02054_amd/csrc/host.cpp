@@ -53,6 +53,7 @@ struct Layout {
       cprim, part_a, part_b, part_c, part_d, part_e, part_f, st, trace, mesh, vmesh, tmesh, mres, mchanged, mdone;
   size_t mu, acc3, ga, ch_start, ch_tets, mmax, mdone2, st2, alpha_last;
   size_t aa_dx, aa_df, aa_xp, aa_fp, aa_h, aa_gamma, aa_part, aa_k;
+  size_t lam, ga_acc, st3, st4;
   size_t total;
 };
 
@@ -237,6 +238,10 @@ Layout make_layout(const gs_problem* p) {
   L.aa_gamma = take(am * 8);
   L.aa_part = take(2 * am * (size_t)p->nparts * 8);
   L.aa_k = take(4);
+  L.lam = take(3 * n * W);
+  L.ga_acc = take((size_t)p->nch * 8);
+  L.st3 = take(sizeof(DevStatus));
+  L.st4 = take(sizeof(DevStatus));
   L.total = align256(off);
   return L;
 }
@@ -313,6 +318,8 @@ Dev<R> make_dev(const gs_problem* p) {
   d.aa_gamma = (double*)(b + L.aa_gamma);
   d.aa_part = (double*)(b + L.aa_part);
   d.aa_k = (int32_t*)(b + L.aa_k);
+  d.lam = (R*)(b + L.lam);
+  d.ga_acc = (double*)(b + L.ga_acc);
   d.dbg_tet = nullptr;
   d.dbg_tri = nullptr;
   d.dbg_cap = 0;
@@ -946,6 +953,173 @@ void merge(gs_problem* p, const std::vector<gs_problem*>& parts) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Unrolled adjoint with checkpoints
+//
+// A record is the state before iteration k: displacement u_k, CG warm start,
+// and the contact set A_{k-1} (flags, targets, normals, prims).  Checkpoints
+// are kept every C = ceil(sqrt(K)) iterations; each segment is recomputed
+// from its checkpoint into C + 1 segment records before its reverse steps.
+
+namespace {
+
+struct RecordLayout {
+  size_t u, dl, cact, ctgt, cnrm, cprim, bytes;
+};
+
+RecordLayout record_layout(const gs_problem* p) {
+  RecordLayout r{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    off = align256(off);
+    const size_t o = off;
+    off += std::max<size_t>(b, 1);
+    return o;
+  };
+  const size_t W = (size_t)p->prec, n = p->n, m = (size_t)p->S * p->slots;
+  r.u = take(3 * n * W);
+  r.dl = take(4 * n * W);
+  r.cact = take(m);
+  r.ctgt = take(3 * m * 8);
+  r.cnrm = take(3 * m * 8);
+  r.cprim = take(m * 4);
+  r.bytes = align256(off);
+  return r;
+}
+
+int ckpt_stride(int K) {
+  int c = 1;
+  while ((long)c * c < K) ++c;
+  return c;
+}
+
+size_t unrolled_records(int K) {
+  const int C = ckpt_stride(K);
+  return (size_t)cdiv(K, C) + (size_t)C + 2;  // checkpoints, segment records, final contact set
+}
+
+hipError_t copy_record(gs_problem* p, char* rec, bool save, bool state, bool contacts) {
+  const RecordLayout R = record_layout(p);
+  const size_t W = (size_t)p->prec, n = p->n, m = (size_t)p->S * p->slots;
+  char* ws = p->ws;
+  const Layout& L = p->lay;
+  struct Item {
+    size_t ws_off, rec_off, bytes;
+    bool is_state;
+  } items[] = {{L.u, R.u, 3 * n * W, true},       {L.dl, R.dl, 4 * n * W, true},
+               {L.cact, R.cact, m, false},        {L.ctgt, R.ctgt, 3 * m * 8, false},
+               {L.cnrm, R.cnrm, 3 * m * 8, false}, {L.cprim, R.cprim, m * 4, false}};
+  for (const Item& it : items) {
+    if ((it.is_state && !state) || (!it.is_state && !contacts)) continue;
+    char* a = ws + it.ws_off;
+    char* b = rec + it.rec_off;
+    hipError_t e = save ? hipMemcpyAsync(b, a, it.bytes, hipMemcpyDeviceToDevice, p->stream)
+                        : hipMemcpyAsync(a, b, it.bytes, hipMemcpyDeviceToDevice, p->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename R>
+gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const R* gL, R* dalpha, R* dx0, R* xK,
+                        char* scratch, gs_stats* stats) {
+  hipStream_t s = p->stream;
+  const RecordLayout RL = record_layout(p);
+  const int C = ckpt_stride(K);
+  const int nck = cdiv(K, C);
+  char* ck = scratch;                                  // nck checkpoint records
+  char* seg = scratch + (size_t)nck * RL.bytes;        // C + 1 segment records
+  char* fin = seg + (size_t)(C + 1) * RL.bytes;        // final contact set
+  const Dev<R> d = make_dev<R>(p);
+  Consts cf = make_consts(p);                          // forward iterations: never stop early
+  cf.fixed_iters = 1 << 30;
+  cf.mask_done = 0;
+  if (p->nch > 0)
+    HIPCHK(hipMemcpyAsync(d.alpha_last, alpha, (size_t)p->nch * sizeof(R), hipMemcpyDeviceToDevice, s));
+  // forward sweep with checkpoints
+  HIPCHK(launch_init<R>(d, cf, x0, s));
+  for (int k = 0; k < K; ++k) {
+    if (k % C == 0) HIPCHK(copy_record(p, ck + (size_t)(k / C) * RL.bytes, true, true, true));
+    HIPCHK(enqueue_iteration<R>(p, d, cf, alpha));
+  }
+  DevStatus h{};
+  HIPCHK(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h.done == BREAKDOWN) return fail(GS_EBREAKDOWN, "non-finite value or CG curvature p'Ap <= 0");
+  if (xK) HIPCHK(launch_output<R>(d, cf, xK, s));
+  HIPCHK(copy_record(p, fin, true, false, true));
+  const int fwd_iters = h.iters, fwd_pcg = h.pcg_total;
+  // reverse sweep
+  DevStatus* run = (DevStatus*)(p->ws + p->lay.st4);
+  Dev<R> dv = d;                                       // VJP kernels: never "done", no frozen meshes
+  dv.st = run;
+  dv.mdone = (int32_t*)(p->ws + p->lay.mdone2);
+  Dev<R> dc = d;                                       // reverse CG solves: their own status block
+  dc.st = (DevStatus*)(p->ws + p->lay.st3);
+  dc.mdone = (int32_t*)(p->ws + p->lay.mdone2);
+  Consts cv = make_consts(p);
+  cv.mask_done = 0;
+  cv.adj_jt = 1;
+  cv.aa_m = 0;
+  Consts cc = make_consts(p);
+  cc.mask_done = 0;
+  cc.fixed_iters = 0;
+  cc.max_iter = 1;
+  cc.tol = 0.0;
+  cc.aa_m = 0;
+  cc.trace_len = 0;
+  HIPCHK(hipMemsetAsync(d.ga_acc, 0, (size_t)std::max(p->nch, 1) * 8, s));
+  HIPCHK(hipMemcpyAsync(d.lam, gL, 3 * (size_t)p->n * sizeof(R), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemsetAsync(d.acc3, 0, 3 * (size_t)p->n * 8, s));
+  int rev_pcg = 0;
+  for (int sg = nck - 1; sg >= 0; --sg) {
+    const int k0 = sg * C, k1 = std::min(k0 + C, K);
+    // recompute the segment from its checkpoint
+    HIPCHK(copy_record(p, ck + (size_t)sg * RL.bytes, false, true, true));
+    HIPCHK(launch_unr_restore<R>(d, cf, run, s));
+    for (int k = k0; k < k1; ++k) {
+      HIPCHK(copy_record(p, seg + (size_t)(k - k0) * RL.bytes, true, true, true));
+      HIPCHK(enqueue_iteration<R>(p, d, cf, alpha));
+    }
+    HIPCHK(copy_record(p, seg + (size_t)(k1 - k0) * RL.bytes, true, true, true));
+    for (int k = k1 - 1; k >= k0; --k) {
+      // x_k from record k, A_k from record k + 1
+      HIPCHK(copy_record(p, seg + (size_t)(k - k0) * RL.bytes, false, true, false));
+      HIPCHK(copy_record(p, seg + (size_t)(k + 1 - k0) * RL.bytes, false, false, true));
+      HIPCHK(launch_unr_restore<R>(d, cf, run, s));
+      HIPCHK(launch_unr_rhs<R>(dc, cc, s));
+      HIPCHK(timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(dc, cc, p->pcg_grid, s, true); }));
+      HIPCHK(timed(p, K_ADJ_SPRINGS, [&] { return launch_adj_springs<R>(dv, cv, s); }));
+      HIPCHK(timed(p, K_ADJ_LOCAL, [&] { return launch_adj_local_mode<R>(dv, cv, ADJ_JT, s); }));
+      HIPCHK(timed(p, K_ADJ_GATHER, [&] { return launch_adj_gather<R>(dv, cv, s); }));
+      HIPCHK(launch_adj_local_mode<R>(dv, cv, ADJ_ALPHA, s));
+      HIPCHK(launch_unr_accumulate<R>(dv, cv, s));
+    }
+    DevStatus hc{};
+    HIPCHK(hipMemcpyAsync(&hc, dc.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (p->prof.on) HIPCHK(p->prof.flush());
+    if (hc.done == BREAKDOWN) return fail(GS_EBREAKDOWN, "breakdown in a reverse CG solve");
+    rev_pcg += hc.pcg_total;
+  }
+  HIPCHK(launch_unr_finish<R>(d, cf, dalpha, dx0, s));
+  // leave the contact set the forward sweep ended with
+  HIPCHK(copy_record(p, fin, false, false, true));
+  HIPCHK(hipStreamSynchronize(s));
+  p->solved = false;
+  if (stats) {
+    stats->iters = fwd_iters;
+    stats->pcg_iters_total = fwd_pcg + rev_pcg;
+    stats->n_contacts = h.n_contacts_last;
+    stats->ray_miss = h.ray_miss_last;
+    stats->residual = h.residual;
+    stats->energy = h.energy;
+  }
+  return GS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 
 extern "C" {
@@ -1261,6 +1435,27 @@ gs_status gs_autotune(gs_problem* p, const void* alpha, void* x, int32_t iters, 
   if (chosen) *chosen = p->pcg_grid;
   if (ms_per_iter) *ms_per_iter = best_ms / iters;
   return GS_OK;
+}
+
+size_t gs_unrolled_scratch_size(const gs_problem* p, int32_t K) {
+  if (!p || K < 1) return 0;
+  return unrolled_records(K) * record_layout(p).bytes;
+}
+
+gs_status gs_adjoint_unrolled(gs_problem* p, const void* alpha, const void* x0, int32_t K, const void* dLdx,
+                              void* dLdalpha, void* dLdx0, void* xK, void* scratch, size_t scratch_bytes,
+                              gs_stats* stats) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "gs_adjoint_unrolled before gs_bind");
+  if (K < 1 || !x0 || !dLdx || !scratch || (p->nch > 0 && (!alpha || !dLdalpha)))
+    return fail(GS_EINVAL, "bad argument");
+  if (((uintptr_t)scratch & 255) != 0) return fail(GS_EINVAL, "scratch must be 256-byte aligned");
+  if (scratch_bytes < gs_unrolled_scratch_size(p, K)) return fail(GS_EINVAL, "scratch too small");
+  if (p->prec == 4)
+    return unrolled_impl<float>(p, (const float*)alpha, (const float*)x0, K, (const float*)dLdx, (float*)dLdalpha,
+                                (float*)dLdx0, (float*)xK, (char*)scratch, stats);
+  return unrolled_impl<double>(p, (const double*)alpha, (const double*)x0, K, (const double*)dLdx,
+                               (double*)dLdalpha, (double*)dLdx0, (double*)xK, (char*)scratch, stats);
 }
 
 gs_status gs_adjoint(gs_problem* p, const void* dLdx, void* dLdalpha, void* mu, gs_stats* stats) {

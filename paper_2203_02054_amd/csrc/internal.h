@@ -61,6 +61,7 @@ struct Consts {
   int ell_w;            // off-diagonal entries per row of the ELL matrix (16, 32 or 64)
   int trace_len;        // rows of the per-iteration trace
   int aa_m;             // adjoint: Anderson memory (0: plain fixed-point iteration)
+  int adj_jt;           // adjoint gather writes (db/dx)^T mu alone to `lam` (unrolled reverse sweep)
   double c1, c2, kappa, tol, pcg_eta;
 };
 
@@ -140,6 +141,9 @@ struct Dev {
   double* aa_gamma;        // [m] least-squares coefficients
   double* aa_part;         // [2m][nparts] block partials of the dot products
   int32_t* aa_k;           // [1] iterations taken by the accelerated loop
+  // unrolled reverse sweep
+  R* lam;                  // [3][n] adjoint of the positions
+  double* ga_acc;          // [nch] dL/dalpha accumulated over the reverse steps
   // debug candidate buffers (null outside gs_collide_debug)
   int32_t* dbg_tet;        // [2][cap]
   int32_t* dbg_tri;        // [2][cap]
@@ -169,6 +173,15 @@ hipError_t launch_adj_local(const Dev<R>& d, const Consts& c, bool alpha_grad, h
 template <typename R> hipError_t launch_adj_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_adj_chamber_sum(const Dev<R>& d, const Consts& c, R* out, hipStream_t s);
 template <typename R> hipError_t launch_adj_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
+// unrolled adjoint helpers
+enum { ADJ_RESIDUAL = 0, ADJ_ALPHA = 1, ADJ_JT = 2 };
+template <typename R> hipError_t launch_adj_local_mode(const Dev<R>& d, const Consts& c, int mode, hipStream_t s);
+template <typename R> hipError_t launch_unr_restore(const Dev<R>& d, const Consts& c, DevStatus* run, hipStream_t s);
+template <typename R> hipError_t launch_unr_rhs(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R>
+hipError_t launch_unr_accumulate(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R>
+hipError_t launch_unr_finish(const Dev<R>& d, const Consts& c, R* dalpha, R* dx0, hipStream_t s);
 template <typename R> hipError_t launch_set_positions(const Dev<R>& d, const Consts& c, const R* x, hipStream_t s);
 template <typename R> int pcg_max_grid(int ell_w);
 

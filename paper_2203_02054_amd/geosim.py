@@ -83,6 +83,8 @@ SIGNATURES = {
     "gs_set_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD, _PI]),
     "gs_adjoint": (_I, [_P, _P, _P, _P, ctypes.POINTER(Stats)]),
     "gs_autotune": (_I, [_P, _P, _P, _I, _PI, _PD]),
+    "gs_unrolled_scratch_size": (ctypes.c_size_t, [_P, _I]),
+    "gs_adjoint_unrolled": (_I, [_P, _P, _P, _I, _P, _P, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(Stats)]),
     "gs_local_step_debug": (_I, [_P, _P, _P, _P]),
     "gs_tets": (_I, [_P, _PI]),
     "gs_faces": (_I, [_P, _PI]),
@@ -283,6 +285,27 @@ class Problem:
         d = st.as_dict()
         d["status"] = code
         return x, d
+
+    def adjoint_unrolled(self, alpha, K, dLdx, x0=None):
+        """Unrolled gradient of L(x_K) over K iterations from x0 (default: rest)
+        with the stored contact set as the previous one.  Returns
+        (dL/dalpha, dL/dx0, x_K, stats dict) as device tensors."""
+        a = alpha if self.torch.is_tensor(alpha) else self.tensor(np.asarray(alpha, dtype=np.float64).reshape(-1))
+        if x0 is None:
+            x0 = self.tensor(self._X)
+        g = dLdx if self.torch.is_tensor(dLdx) else self.tensor(np.asarray(dLdx, dtype=np.float64))
+        nb = int(lib().gs_unrolled_scratch_size(self._h, int(K)))
+        scratch = self.torch.empty(nb + 256, dtype=self.torch.uint8, device=self.device)
+        sp = (scratch.data_ptr() + 255) & ~255
+        ga = self.torch.zeros(max(self.n_chambers, 1), dtype=self.dtype, device=self.device)[:self.n_chambers]
+        gx0 = self.torch.empty((3, self.n), dtype=self.dtype, device=self.device)
+        xK = self.torch.empty((3, self.n), dtype=self.dtype, device=self.device)
+        st = Stats()
+        _check(lib().gs_adjoint_unrolled(self._h, self._dev(a, (self.n_chambers,)) if self.n_chambers else None,
+                                         self._dev(x0, (3, self.n)), int(K), self._dev(g, (3, self.n)),
+                                         ga.data_ptr() if self.n_chambers else None, gx0.data_ptr(),
+                                         xK.data_ptr(), sp, nb, ctypes.byref(st)))
+        return ga, gx0, xK, st.as_dict()
 
     def autotune(self, alpha, x=None, iters=20):
         """Pick the CG grid by timing `iters` fixed iterations per candidate from

@@ -141,3 +141,51 @@ def test_adjoint_requires_a_solve(G):
     with pytest.raises(G.GeosimError) as e:
         gp.adjoint(np.zeros((3, gp.n)))
     assert e.value.code == G.ESTATE
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_unrolled_adjoint_matches_oracle(G, precision):
+    """Unrolled gradient through 30 iterations from rest (new and kept self
+    contacts, sphere and plane springs) against the oracle's reverse sweep over
+    its own recorded path; FP64 within 1e-8 (the GPU's exact-step forward
+    follows the same path), FP32 within 2e-3."""
+    w = pressed_finger()
+    prob = oracle.Problem.from_workload(w)
+    K = 30
+    path, xK_o = oa.record_path(prob, w.alpha, prob.X0, None, K)
+    g = _seeded_loss_grad(prob, seed=4)
+    ga_o, gx0_o = oa.unrolled_grad(prob, w.alpha, path, g)
+    kw = dict(pcg_eta=1e-13, pcg_max=5000) if precision == 8 else dict(pcg_eta=1e-5, pcg_max=2000)
+    gp = G.Problem.from_workload(w, precision=precision, **kw)
+    ga, gx0, xK, st = gp.adjoint_unrolled(w.alpha, K, g)
+    ga = ga.cpu().numpy().astype(np.float64)
+    xK = xK.cpu().numpy().astype(np.float64)
+    gx0 = gx0.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(ga - ga_o) / np.linalg.norm(ga_o)
+    xerr = np.abs(xK - xK_o).max() / prob.diag
+    gxerr = np.abs(gx0 - gx0_o).max() / np.abs(gx0_o).max()
+    say("unrolled", precision, st, "grad", ga, "oracle", ga_o, "rel", rel, "xK err/diag", xerr, "dx0 err", gxerr)
+    cg = gp.contacts()
+    rows_o, _ = path[-1][1].listing(prob)
+    np.testing.assert_array_equal(cg["rows"][:, :2], rows_o[:, :2])
+    if precision == 8:
+        assert xerr < 1e-10 and rel < 1e-8 and gxerr < 1e-8
+    else:
+        assert xerr < 1e-5 and rel < 2e-3
+
+
+def test_unrolled_adjoint_closed_form(G):
+    """All-chamber box from rest: the unrolled gradient of sum |x - x_f|^2 over
+    any K >= 1 iterations is the closed form."""
+    mesh = voxel_box(3, 2, 2, h=1.0, mode=mg.CH_ISO, chamber=0)
+    mesh["fixed"][5] = 1
+    gp = G.Problem(mesh["rest_xyz"], mesh["tets"], mesh["tet_mode"], mesh["tet_chamber"], mesh["fixed"], 1,
+                   precision=8, pcg_eta=1e-13, pcg_max=5000)
+    X = mesh["rest_xyz"]
+    xf = X[:, 5:6]
+    alpha = 1.8
+    xs = xf + alpha ** (1.0 / 3.0) * (X - xf)
+    ga, _, xK, st = gp.adjoint_unrolled([alpha], 4, 2.0 * (xs - xf))
+    exact = (2.0 / 3.0) * alpha ** (-1.0 / 3.0) * ((X - xf) ** 2).sum()
+    say("unrolled closed form", st, float(ga[0]), exact, "xK err", float((xK.cpu() - __import__("torch").tensor(xs)).abs().max()))
+    assert float(ga[0]) == pytest.approx(exact, rel=1e-9)
