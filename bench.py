@@ -191,7 +191,7 @@ def run_batched(G, mg, n_mesh, max_iter, sample):
     return out
 
 
-def run_adjoint(G, mg, wl, gp, x, alpha, t_solve_ms, reps=3):
+def run_adjoint(G, mg, wl, gp, x, alpha, t_solve_ms, n_iters, reps=3):
     """Adjoint of the converged solve left in gp (positions x)."""
     import torch
     verts, y = mg.finger_tip_targets(wl)
@@ -212,6 +212,13 @@ def run_adjoint(G, mg, wl, gp, x, alpha, t_solve_ms, reps=3):
     gp.profile(False)
     t = float(np.median(times))
     fd_ms = 2 * wl.n_chambers * t_solve_ms
+    # unrolled variant over the solve's own iteration budget, from rest
+    K = int(n_iters)
+    gp.reset_contacts()
+    gp.adjoint_unrolled(alpha, K, gt)                        # warm-up
+    gp.reset_contacts()
+    torch.cuda.synchronize()
+    ms_u, (ga_u, _, _, st_u) = timed_on(gp.stream, lambda: gp.adjoint_unrolled(alpha, K, gt))
     return {"value": round(1e3 / t, 3), "unit": "gradients/s", "ms_per_gradient": round(t, 3),
             "params": wl.n_chambers, "adjoint_iters": st["iters"], "pcg_iters": st["pcg_iters_total"],
             "residual": st["residual"], "status": st["status"], "anderson_memory": 16,
@@ -219,6 +226,9 @@ def run_adjoint(G, mg, wl, gp, x, alpha, t_solve_ms, reps=3):
             "forward_plus_adjoint_ms": round(t_solve_ms + t, 3),
             "fd_plain_ms": round(fd_ms, 3), "speedup_vs_fd": round(fd_ms / t, 2),
             "grad_norm": float(torch.linalg.norm(ga.double()).item()),
+            "unrolled": {"value": round(1e3 / ms_u, 3), "unit": "gradients/s", "ms_per_gradient": round(ms_u, 3),
+                         "K": K, "pcg_iters": st_u["pcg_iters_total"],
+                         "note": "K iterations from rest, checkpoints every ceil(sqrt(K)), forward + reverse sweep"},
             "kernels": {k: v for k, v in kernel_table(prof).items() if k.startswith("adj_")}}
 
 
@@ -326,7 +336,7 @@ def main():
     }
     if not a.no_adjoint:
         print("# adjoint", file=sys.stderr, flush=True)
-        out["adjoint"] = run_adjoint(G, mg, wl, gp, x, alpha, ms / a.steps)
+        out["adjoint"] = run_adjoint(G, mg, wl, gp, x, alpha, ms / a.steps, iters / a.steps)
     gp.close()
     if not a.no_batched:
         out["batched"] = run_batched(G, mg, a.batched_meshes, a.batched_max_iter, a.plain_sample)
