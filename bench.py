@@ -245,6 +245,7 @@ def main():
     ap.add_argument("--batched-max-iter", type=int, default=1000)
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default CG grid (counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 20 device-to-device copies of MIB MiB (reference traffic for HBM counters)")
     a = ap.parse_args()
@@ -274,7 +275,7 @@ def main():
     alpha = gp.tensor(wl.alpha)
     x = x0.clone()
     stream = gp.stream
-    grid, _ = gp.autotune(alpha, x, iters=20)
+    grid = gp.info["pcg_grid"] if a.no_autotune else gp.autotune(alpha, x, iters=20)[0]
 
     def step():
         x.copy_(x0)
