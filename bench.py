@@ -128,7 +128,7 @@ def timed_on(stream, fn):
     return e0.elapsed_time(e1), r
 
 
-def run_batched(G, mg, n_mesh, max_iter, sample):
+def run_batched(G, mg, n_mesh, max_iter, sample, autotune=True):
     import torch
     wls = mg.batched(n_mesh)
     Ts = np.array([w.n_tets for w in wls], dtype=np.int64)
@@ -137,7 +137,7 @@ def run_batched(G, mg, n_mesh, max_iter, sample):
     alpha = gb.tensor(np.concatenate([w.alpha for w in wls]))
     x0 = gb.tensor(gb._X)
     x = x0.clone()
-    grid, _ = gb.autotune(alpha, x, iters=8)
+    grid = gb.autotune(alpha, x, iters=8)[0] if autotune else gb.info["pcg_grid"]
 
     def solve():
         x.copy_(x0)
@@ -340,7 +340,8 @@ def main():
         out["adjoint"] = run_adjoint(G, mg, wl, gp, x, alpha, ms / a.steps, iters / a.steps)
     gp.close()
     if not a.no_batched:
-        out["batched"] = run_batched(G, mg, a.batched_meshes, a.batched_max_iter, a.plain_sample)
+        out["batched"] = run_batched(G, mg, a.batched_meshes, a.batched_max_iter, a.plain_sample,
+                                     autotune=not a.no_autotune)
     if not a.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = run_cpu_baseline(wl, a.cpu_budget)
