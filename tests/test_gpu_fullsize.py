@@ -1,0 +1,160 @@
+"""Parity at full size: the three-finger gripper (378,666 tets) and the
+256-mesh batch (5.56M tets), in the FP32 configuration the benchmark runs,
+on outputs the oracle can compute at that size:
+
+* gripper, after 30 GPU iterations from rest (a deformed state with self,
+  sphere and plane contacts):
+  - the local step on every tet against the oracle's;
+  - tet candidates, penetration and ray hits of a sample of query vertices
+    against the oracle's brute force restricted to that sample (bit-exact);
+  - one FP64 global step with the GPU's contact set against the oracle's
+    sparse direct solve;
+* batch: every sampled converged mesh is a fixed point of the oracle's
+  iteration with its own active set (one oracle step leaves the set
+  unchanged and moves it by less than 5e-6 of its diagonal).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2203_02054_amd import meshgen as mg
+import oracle
+from oracle import collision as oc
+from oracle import solver as osolver
+from oracle.collision import Contacts
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2203_02054_amd import geosim
+    geosim.lib()
+    return geosim
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_contacts(prob, cg, lo=0):
+    A = Contacts.empty(prob.query_verts.size, prob.n_slots)
+    ns = prob.spheres.shape[0]
+    for (v, typ, prim), t, nrm in zip(cg["rows"], cg["target"], cg["normal"]):
+        s = int(np.searchsorted(prob.query_verts, v - lo))
+        sl = 0 if typ == 0 else (1 + prim if typ == 1 else 1 + ns + prim)
+        A.active[s, sl] = True
+        A.target[s, sl], A.normal[s, sl], A.prim[s, sl] = t, nrm, prim
+    return A
+
+
+@pytest.fixture(scope="module")
+def gripper_state(G):
+    w = mg.gripper()
+    prob = oracle.Problem.from_workload(w)
+    gp = G.Problem.from_workload(w, precision=4, fixed_iters=30)
+    x, st = gp.solve(w.alpha)
+    say("gripper", w.n_tets, "tets: 30 iterations", st)
+    return w, prob, gp, x
+
+
+def test_gripper_local_step_full(G, gripper_state):
+    w, prob, gp, x = gripper_state
+    xs = x.cpu().numpy().astype(np.float64)
+    Tg = gp.local_step(x, w.alpha).cpu().numpy().astype(np.float64)       # [3, 4, T]
+    To = oracle.local_step(prob, xs, w.alpha)                              # [T, 3, 4]
+    err = np.abs(np.moveaxis(Tg, 2, 0) - To).max() / prob.diag
+    say("  local step on", prob.T, "tets: max error / diag", err)
+    assert err < 1e-5
+
+
+def test_gripper_collision_sampled(G, gripper_state):
+    w, prob, gp, x = gripper_state
+    x32 = x.cpu().numpy()
+    x64 = x32.astype(np.float64)
+    got = gp.collide(x)
+    # every 97th query vertex plus every vertex with a contact at this state
+    sample = np.union1d(prob.query_verts[::97], got["contacts"][:, 0]).astype(np.int64)
+    v, e, inside = oc.tet_candidates(prob, x64, sample)
+    exp = np.unique(np.stack([v, e], axis=1), axis=0)
+    gt = got["cand_tet"]
+    mine = gt[np.isin(gt[:, 0], sample)]
+    say("  sampled", sample.size, "query vertices: tet candidates", len(exp), "penetrating",
+        np.unique(v[inside]).size, "contacts", len(got["contacts"]))
+    np.testing.assert_array_equal(mine, exp)
+    # rays of the sampled penetrating vertices
+    pen = np.unique(v[inside])
+    if pen.size:
+        nrm, ok = oc.vertex_normals(prob, x64, pen)
+        hit, bf, bt, cand = oc.ray_cast(prob, x64, pen[ok], nrm[:, ok])
+        ctri = got["cand_tri"]
+        ctri = ctri[np.isin(ctri[:, 0], pen[ok])]
+        exp_tri = np.unique(np.stack(cand, axis=1), axis=0) if cand[0].size else np.zeros((0, 2), np.int64)
+        np.testing.assert_array_equal(ctri, exp_tri)
+        rows = got["contacts"]
+        for vv, h, f in zip(pen[ok], hit, bf):
+            r = rows[(rows[:, 0] == vv) & (rows[:, 1] == 0)]
+            if h:
+                assert len(r) == 1 and r[0, 2] == f
+
+
+def test_gripper_global_step_fp64(G, gripper_state):
+    """One FP64 iteration from the FP32 state with the GPU's contacts, against
+    the oracle's local step plus sparse direct global step with the contact
+    set the GPU found in that iteration."""
+    w, prob, _, x = gripper_state
+    gp = G.Problem.from_workload(w, precision=8, fixed_iters=1, pcg_eta=1e-13, pcg_max=20000)
+    x0 = x.double().contiguous()
+    x1, st = gp.solve(w.alpha, x0.clone())
+    # the solve holds fixed vertices at their rest positions (not at their
+    # FP32 roundings): the oracle starts from the same positions
+    xs = x0.cpu().numpy()
+    xs[:, prob.fixed] = prob.X0[:, prob.fixed]
+    cg = gp.contacts()
+    A = _oracle_contacts(prob, cg)
+    Tt = oracle.local_step(prob, xs, w.alpha)
+    xo = osolver.global_step(prob, Tt, A, xs)
+    xg = x1.cpu().numpy()
+    err = np.abs(xg - xo).max() / prob.diag
+    # the GPU's global step is a CG stopped at a 1e-13 relative residual; its
+    # residual in the oracle's system is the solver-independent check, the
+    # position error carries the condition number of M (long fingers)
+    M, _, bs = osolver.system(prob, A)
+    F, C = np.nonzero(prob.free)[0], np.nonzero(prob.fixed)[0]
+    b = (osolver.element_rhs(prob, Tt) + bs)[:, F].T - M[F][:, C] @ xs[:, C].T
+    res = np.linalg.norm(M[F][:, F] @ xg[:, F].T - b) / np.linalg.norm(b)
+    say("  one FP64 iteration:", st, "contacts", len(cg["rows"]), "relative residual", res,
+        "max error / diag", err)
+    assert res < 1e-11 and err < 1e-8
+
+
+def test_batch_sampled_meshes_are_oracle_fixed_points(G):
+    wls = mg.batched(256)
+    gb = G.Problem.batch(wls, precision=4, self_collision=1, max_iter=1000)
+    alpha = np.concatenate([w.alpha for w in wls])
+    xg, st = gb.solve(alpha)
+    its = gb.mesh_iters()
+    say("batch", sum(w.n_tets for w in wls), "tets:", st, "converged", int((its > 0).sum()))
+    lay = gb.layout()
+    cg = gb.contacts()
+    xg = xg.cpu().numpy().astype(np.float64)
+    conv = np.nonzero(its > 0)[0]
+    Ts = np.array([wls[m].n_tets for m in conv])
+    picks = [conv[np.argmin(Ts)], conv[np.argsort(Ts)[len(Ts) // 2]]]
+    for m in picks:
+        w = wls[m]
+        prob = oracle.Problem.from_workload(w, self_collision=True)
+        v0, v1 = lay["vert"][m], lay["vert"][m + 1]
+        sel = (cg["rows"][:, 0] >= v0) & (cg["rows"][:, 0] < v1)
+        sub = {k: cg[k][sel] for k in ("rows", "target", "normal")}
+        A = _oracle_contacts(prob, sub, lo=v0)
+        x = xg[:, v0:v1]
+        xn, A2, _, info = osolver.step(prob, x, w.alpha, A)
+        move = np.abs(xn - x).max() / prob.diag
+        say("  mesh", m, w.n_tets, "tets, converged at", its[m], ": oracle step moves", move,
+            "set changed", info["changed"])
+        assert not info["changed"] and move < 5e-6
