@@ -9,6 +9,9 @@ on outputs the oracle can compute at that size:
     against the oracle's brute force restricted to that sample (bit-exact);
   - one FP64 global step with the GPU's contact set against the oracle's
     sparse direct solve;
+* gripper gradient workload (30 fingertip targets, 24 chamber ratios):
+  unrolled adjoint over 20 iterations, FP64 and FP32 kernels, against FP64
+  central differences of the 20-iteration solve;
 * batch: every sampled converged mesh is a fixed point of the oracle's
   iteration with its own active set (one oracle step leaves the set
   unchanged and moves it by less than 5e-6 of its diagonal).
@@ -158,3 +161,53 @@ def test_batch_sampled_meshes_are_oracle_fixed_points(G):
         say("  mesh", m, w.n_tets, "tets, converged at", its[m], ": oracle step moves", move,
             "set changed", info["changed"])
         assert not info["changed"] and move < 5e-6
+
+
+def test_gripper_unrolled_gradient_vs_central_differences(G):
+    """The gradient workload at full size: loss = squared distance of 30
+    fingertip vertices to seeded targets, gradient w.r.t. the 24 chamber
+    volume ratios through 20 iterations from rest.  FP32 and FP64 unrolled
+    adjoints against FP64 central differences (h = 1e-6) of the FP64
+    20-iteration solve, whose contact schedule is checked unchanged at
+    alpha +- h."""
+    import torch
+    w = mg.gripper()
+    K = 20
+    verts, y = mg.adjoint_targets(w)
+    tight = dict(pcg_eta=1e-13, pcg_max=20000)
+    g64 = G.Problem.from_workload(w, precision=8, fixed_iters=K, **tight)
+
+    def loss_and_contacts(alpha):
+        g64.reset_contacts()
+        x, _ = g64.solve(alpha)
+        xv = x.cpu().numpy()[:, verts]
+        return float(((xv - y.T) ** 2).sum()), g64.contacts()["rows"]
+
+    L0, rows0 = loss_and_contacts(w.alpha)
+    g64.reset_contacts()
+    xK = g64.solve(w.alpha)[0].cpu().numpy()
+    dLdx = np.zeros((3, w.n_verts))
+    dLdx[:, verts] = 2.0 * (xK[:, verts] - y.T)
+    h = 1e-6
+    fd = np.zeros(w.n_chambers)
+    for c in range(w.n_chambers):
+        ap, am = w.alpha.copy(), w.alpha.copy()
+        ap[c] += h
+        am[c] -= h
+        Lp, rp = loss_and_contacts(ap)
+        Lm, rm = loss_and_contacts(am)
+        np.testing.assert_array_equal(rp, rows0)
+        np.testing.assert_array_equal(rm, rows0)
+        fd[c] = (Lp - Lm) / (2 * h)
+    out = {}
+    for prec, kw in [(8, tight), (4, dict(pcg_eta=1e-6, pcg_max=5000))]:
+        gp = G.Problem.from_workload(w, precision=prec, **kw)
+        ga, _, _, st = gp.adjoint_unrolled(w.alpha, K, dLdx)
+        ga = ga.cpu().numpy().astype(np.float64)
+        out[prec] = np.linalg.norm(ga - fd) / np.linalg.norm(fd)
+        say("  unrolled", prec, st, "rel to FD", out[prec])
+    say("  FD", fd[:6], "...")
+    # FP32: the error plateaus at 4e-3 for CG tolerances from 1e-5 to 1e-7 (the
+    # rounding floor of FP32 reverse solves with the long fingers' stiffness
+    # matrix); the FP64 kernels meet the FD to 3e-6
+    assert out[8] < 1e-5 and out[4] < 1e-2
