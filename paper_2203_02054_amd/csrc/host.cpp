@@ -139,6 +139,15 @@ struct gs_problem {
   bool solved = false;  // a solve has run since gs_bind (the adjoint's state exists)
   int aa_cap = 0;       // Anderson memory the workspace holds (adj_aa_m at gs_create)
   Profiler prof;
+  // pinned host copies of the device status, one per chunk in flight, and
+  // the events that mark their copies (created at gs_bind)
+  DevStatus* hstat = nullptr;
+  hipEvent_t hev[2] = {nullptr, nullptr};
+  ~gs_problem() {
+    if (hstat) (void)hipHostFree(hstat);
+    for (hipEvent_t e : hev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -442,6 +451,43 @@ hipError_t timed(gs_problem* p, int k, F&& launch) {
   return hipSuccess;
 }
 
+// Iteration driver: enqueue `check_every` iterations at a time until the
+// device status says done.  The status after each chunk is copied to pinned
+// host memory behind an event, and the next chunk is enqueued before waiting
+// for it, so the GPU never idles while the host enqueues; a chunk enqueued
+// after the solve finished runs as no-ops (every kernel checks the done flag).
+// With per-kernel profiling on, each chunk is waited for (its events must be
+// complete before they are read).  `h` receives the final status.
+template <typename F>
+gs_status drive(gs_problem* p, const DevStatus* dstat, int limit, F&& enqueue_one, DevStatus& h) {
+  hipStream_t s = p->stream;
+  const int ce = p->prm.check_every;
+  int enq = 0, c = 0;
+  bool pending = false;
+  while (true) {
+    const int chunk = std::min(ce, std::max(1, limit - enq));
+    for (int i = 0; i < chunk; ++i) HIPCHK(enqueue_one());
+    enq += chunk;
+    HIPCHK(hipMemcpyAsync(&p->hstat[c & 1], dstat, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(p->hev[c & 1], s));
+    if (p->prof.on) {
+      HIPCHK(hipEventSynchronize(p->hev[c & 1]));
+      HIPCHK(p->prof.flush());
+      if (p->hstat[c & 1].done != RUNNING) break;
+    } else if (pending) {
+      HIPCHK(hipEventSynchronize(p->hev[(c - 1) & 1]));
+      if (p->hstat[(c - 1) & 1].done != RUNNING) break;
+    }
+    pending = true;
+    ++c;
+    if (enq >= limit + 2 * ce) return fail(GS_EHIP, "iteration driver out of step with the device");
+  }
+  HIPCHK(hipMemcpyAsync(&p->hstat[0], dstat, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  h = p->hstat[0];
+  return GS_OK;
+}
+
 template <typename R>
 hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, const R* alpha) {
   hipError_t e;
@@ -468,17 +514,8 @@ gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
   HIPCHK(launch_init<R>(d, c, x, s));
   DevStatus h{};
   const int limit = p->prm.fixed_iters > 0 ? p->prm.fixed_iters : p->prm.max_iter;
-  int enq = 0;
-  while (true) {
-    const int chunk = std::min(p->prm.check_every, std::max(1, limit - enq));
-    for (int i = 0; i < chunk; ++i) HIPCHK(enqueue_iteration<R>(p, d, c, alpha));
-    enq += chunk;
-    HIPCHK(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (p->prof.on) HIPCHK(p->prof.flush());
-    if (h.done != RUNNING) break;
-    if (enq >= limit + p->prm.check_every) return fail(GS_EHIP, "iteration driver out of step with the device");
-  }
+  const gs_status ds = drive(p, d.st, limit, [&] { return enqueue_iteration<R>(p, d, c, alpha); }, h);
+  if (ds != GS_OK) return ds;
   HIPCHK(launch_output<R>(d, c, x, s));
   HIPCHK(hipStreamSynchronize(s));
   p->last_iters = h.iters;
@@ -522,24 +559,16 @@ gs_status adjoint_impl(gs_problem* p, const R* gL, R* dalpha, R* mu_out, gs_stat
   hipStream_t s = p->stream;
   HIPCHK(launch_adj_init<R>(d, c, s));
   DevStatus h{};
-  const int limit = c.max_iter;
-  int enq = 0;
-  while (true) {
-    const int chunk = std::min(p->prm.check_every, std::max(1, limit - enq));
-    for (int i = 0; i < chunk; ++i) {
-      HIPCHK(timed(p, K_ADJ_SPRINGS, [&] { return launch_adj_springs<R>(d, c, s); }));
-      HIPCHK(timed(p, K_ADJ_LOCAL, [&] { return launch_adj_local<R>(d, c, false, s); }));
-      HIPCHK(timed(p, K_ADJ_GATHER, [&] { return launch_adj_gather<R>(d, c, s); }));
-      HIPCHK(timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, true); }));
-      HIPCHK(launch_adj_anderson<R>(d, c, s));
-    }
-    enq += chunk;
-    HIPCHK(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (p->prof.on) HIPCHK(p->prof.flush());
-    if (h.done != RUNNING) break;
-    if (enq >= limit + p->prm.check_every) return fail(GS_EHIP, "adjoint driver out of step with the device");
-  }
+  auto one = [&]() -> hipError_t {
+    hipError_t e;
+    if ((e = timed(p, K_ADJ_SPRINGS, [&] { return launch_adj_springs<R>(d, c, s); })) != hipSuccess) return e;
+    if ((e = timed(p, K_ADJ_LOCAL, [&] { return launch_adj_local<R>(d, c, false, s); })) != hipSuccess) return e;
+    if ((e = timed(p, K_ADJ_GATHER, [&] { return launch_adj_gather<R>(d, c, s); })) != hipSuccess) return e;
+    if ((e = timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, true); })) != hipSuccess) return e;
+    return launch_adj_anderson<R>(d, c, s);
+  };
+  const gs_status ds = drive(p, d.st, c.max_iter, one, h);
+  if (ds != GS_OK) return ds;
   HIPCHK(launch_adj_local<R>(d, c, true, s));
   HIPCHK(launch_adj_chamber_sum<R>(d, c, dalpha, s));
   if (mu_out) HIPCHK(hipMemcpyAsync(mu_out, d.mu, 3 * (size_t)p->n * sizeof(R), hipMemcpyDeviceToDevice, s));
@@ -1318,6 +1347,15 @@ gs_status gs_bind(gs_problem* p, void* ws, size_t bytes, void* stream) {
   p->stream = (hipStream_t)stream;
   p->bound = false;
   p->solved = false;
+  if (!p->hstat) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, 2 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
+      return fail(GS_EHIP, "hipHostMalloc of the status copies failed");
+    p->hstat = (DevStatus*)h;
+    for (hipEvent_t& e : p->hev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        return fail(GS_EHIP, "hipEventCreate failed");
+  }
   const gs_status st = p->prec == 4 ? bind_impl<float>(p) : bind_impl<double>(p);
   if (st == GS_OK) p->bound = true;
   return st;
