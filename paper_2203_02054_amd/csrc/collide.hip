@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_hash_insert(Dev<R> d, Consts c) {
   e.x = d.xc[v];
   e.y = d.xc[(size_t)c.n + v];
   e.z = d.xc[2 * (size_t)c.n + v];
-  e.w = __longlong_as_double((long long)s);
+  e.w = __longlong_as_double((long long)(((unsigned long long)(unsigned)v << 32) | (unsigned)s));
   if (!(fabs(e.x * ic) < 1e9 && fabs(e.y * ic) < 1e9 && fabs(e.z * ic) < 1e9)) return;  // diverged iterate
   const int key = hash_cell(cell_of(e.x, ic), cell_of(e.y, ic), cell_of(e.z, ic), m, c.H);
   const int slot = atomicAdd(&d.hcount[key], 1);
@@ -50,13 +50,14 @@ __global__ __launch_bounds__(kBlock) void k_hash_insert(Dev<R> d, Consts c) {
 }
 
 template <typename R, bool DEBUG>
-__device__ __forceinline__ void test_point(const Dev<R>& d, const double4& en, int e, int m, const int (&vi)[4],
+__device__ __forceinline__ void test_point(const Dev<R>& d, const double4& en, int e, int vbeg, int vend, const int (&vi)[4],
                                           const double (&p)[4][3], const double (&lo)[3], const double (&hi)[3]) {
   const double q[3] = {en.x, en.y, en.z};
   if (!(lo[0] <= q[0] && q[0] <= hi[0] && lo[1] <= q[1] && q[1] <= hi[1] && lo[2] <= q[2] && q[2] <= hi[2])) return;
-  const int s = (int)__double_as_longlong(en.w);
-  const int v = d.qverts[s];
-  if (v == vi[0] || v == vi[1] || v == vi[2] || v == vi[3] || d.vmesh[v] != m) return;
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(en.w);
+  const int s = (int)(unsigned)(bits & 0xffffffffull);
+  const int v = (int)(unsigned)(bits >> 32);
+  if (v == vi[0] || v == vi[1] || v == vi[2] || v == vi[3] || v < vbeg || v >= vend) return;
   if (DEBUG) {
     const int k = atomicAdd(&d.st->cand_tet, 1);
     if (k < d.dbg_cap) {
@@ -70,7 +71,7 @@ __device__ __forceinline__ void test_point(const Dev<R>& d, const double4& en, i
   }
 }
 
-template <typename R, bool DEBUG>
+template <typename R, bool DEBUG, bool PREFETCH>
 __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
   if (is_done(d.st)) return;
   const int e = blockIdx.x * kBlock + threadIdx.x;
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
   const int m = d.tmesh[e];
   if (mesh_frozen(d, c.mask_done, m)) return;
   const double ic = d.mesh[m].inv_cell;
+  const int vbeg = d.mesh[m].vbeg, vend = d.mesh[m].vend;
   int vi[4];
   double p[4][3];
 #pragma unroll
@@ -113,8 +115,8 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
       en.x = d.xc[v];
       en.y = d.xc[(size_t)c.n + v];
       en.z = d.xc[2 * (size_t)c.n + v];
-      en.w = __longlong_as_double((long long)s);
-      test_point<R, DEBUG>(d, en, e, m, vi, p, lo, hi);
+      en.w = __longlong_as_double((long long)(((unsigned long long)(unsigned)v << 32) | (unsigned)s));
+      test_point<R, DEBUG>(d, en, e, vbeg, vend, vi, p, lo, hi);
     }
     return;
   }
@@ -131,29 +133,37 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) cnt[k] = (keys[k] >= 0) ? min(d.hcount[keys[k]], kHashCap) : 0;
-    double4 e0[8];
+    if (PREFETCH) {
+      // few tets (latency-bound): the first entries of all 8 cells in one round
+      double4 e0[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (cnt[k] > 0) e0[k] = slots[(size_t)keys[k] * kHashCap];
+      for (int k = 0; k < 8; ++k)
+        if (cnt[k] > 0) e0[k] = slots[(size_t)keys[k] * kHashCap];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (cnt[k] > 0) test_point<R, DEBUG>(d, e0[k], e, m, vi, p, lo, hi);
+      for (int k = 0; k < 8; ++k)
+        if (cnt[k] > 0) test_point<R, DEBUG>(d, e0[k], e, vbeg, vend, vi, p, lo, hi);
+    } else {
+      // many tets (throughput-bound): fewer registers, twice the occupancy
+#pragma unroll 1
+      for (int k = 0; k < 8; ++k)
+        if (cnt[k] > 0) test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap], e, vbeg, vend, vi, p, lo, hi);
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       for (int i = 1; i < cnt[k]; ++i)
-        test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, m, vi, p, lo, hi);
+        test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, vbeg, vend, vi, p, lo, hi);
   } else {
     for (int ix = clo[0]; ix <= chi[0]; ++ix)
       for (int iy = clo[1]; iy <= chi[1]; ++iy)
         for (int iz = clo[2]; iz <= chi[2]; ++iz) {
           const int key = hash_cell(ix, iy, iz, m, c.H);
           const int cn = min(d.hcount[key], kHashCap);
-          for (int i = 0; i < cn; ++i) test_point<R, DEBUG>(d, slots[(size_t)key * kHashCap + i], e, m, vi, p, lo, hi);
+          for (int i = 0; i < cn; ++i) test_point<R, DEBUG>(d, slots[(size_t)key * kHashCap + i], e, vbeg, vend, vi, p, lo, hi);
         }
   }
   const int nover = __hip_atomic_load(&d.st->n_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int i = 0; i < nover; ++i)
-    test_point<R, DEBUG>(d, reinterpret_cast<const double4*>(d.hover)[i], e, m, vi, p, lo, hi);
+    test_point<R, DEBUG>(d, reinterpret_cast<const double4*>(d.hover)[i], e, vbeg, vend, vi, p, lo, hi);
 }
 
 // One wavefront per penetrating vertex: vertex normal, then the first hit of
@@ -379,6 +389,10 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
   if (nact) atomicAdd(&d.st->n_contacts, nact);
 }
 
+// Tet count from which the tet query runs its lower-register variant (the
+// GPU then holds enough waves that occupancy beats prefetching).
+constexpr int kTetQueryWide = 1 << 18;
+
 template <typename R>
 hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s) {
   const int gs = cdiv(c.S, kBlock), gt = cdiv(c.T, kBlock);
@@ -388,9 +402,11 @@ hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, boo
       break;
     case STAGE_TET_QUERY:
       if (debug)
-        k_tet_query<R, true><<<gt, kBlock, 0, s>>>(d, c);
+        k_tet_query<R, true, true><<<gt, kBlock, 0, s>>>(d, c);
+      else if (c.T < kTetQueryWide)
+        k_tet_query<R, false, true><<<gt, kBlock, 0, s>>>(d, c);
       else
-        k_tet_query<R, false><<<gt, kBlock, 0, s>>>(d, c);
+        k_tet_query<R, false, false><<<gt, kBlock, 0, s>>>(d, c);
       break;
     case STAGE_RAY: {
       // one wavefront per penetrating vertex on the first pass (up to 8192)

@@ -395,6 +395,8 @@ std::vector<MeshConst> mesh_table(const gs_problem* p) {
     t[m].fend = p->fbeg[m + 1];
     t[m].sbeg = p->sbeg[m];
     t[m].send = p->sbeg[m + 1];
+    t[m].vbeg = p->vbeg[m];
+    t[m].vend = p->vbeg[m + 1];
   }
   return t;
 }

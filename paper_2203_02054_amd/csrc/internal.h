@@ -48,6 +48,7 @@ struct MeshConst {
   double inv_mean_vol;  // 1 / mean rest tet volume (omega_e = Vol(e) / mean Vol)
   int fbeg, fend;   // boundary faces of the mesh
   int sbeg, send;   // query vertices of the mesh
+  int vbeg, vend;   // vertices of the mesh
 };
 
 // Scalars of one problem (passed by value to kernels).
@@ -101,7 +102,7 @@ struct Dev {
   R* dsp;                  // [n] spring diagonal
   int32_t* pen;            // [S] penetration flag of each query vertex (this iteration)
   int32_t* hcount;         // [H] entries inserted per bucket (may exceed kHashCap)
-  double* hslot;           // [H][kHashCap][4] bucket entries (x, y, z, query index as bits)
+  double* hslot;           // [H][kHashCap][4] bucket entries (x, y, z, and as bits: query index | vertex << 32)
   double* hover;           // [S][4] entries of full buckets (scanned by every tet)
   int32_t* penlist;        // [S] penetrating query vertices (unordered)
   int32_t* fhit;           // [S] fresh self hit face or -1
