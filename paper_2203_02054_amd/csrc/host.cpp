@@ -49,9 +49,9 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   size_t X0, tets, tag, inc_start, inc_pos, ell_col, ell_val, ell_scaled, adiag, freem, faces, qverts, vq, qf_start, qf_list, kq,
       obst;
-  size_t u, xc, res4, cg, dl, p, dg, dsp, pen, hcount, hslot, hover, penlist, fhit, fc, fn, cact, ctgt, cnrm,
+  size_t u, xc, res4, cg, dl, dlp, p, dg, dsp, pen, hcount, hslot, hover, penlist, fhit, fc, fn, cact, ctgt, cnrm,
       cprim, part_a, part_b, part_c, part_d, part_e, part_f, st, trace, mesh, vmesh, tmesh, mres, mchanged, mdone;
-  size_t mu, acc3, ga, ch_start, ch_tets, mmax, mdone2, st2, alpha_last;
+  size_t mu, acc3, ga, ch_start, ch_tets, mmax, mdone2, st2, alpha_last, mgam;
   size_t aa_dx, aa_df, aa_xp, aa_fp, aa_h, aa_gamma, aa_part, aa_k;
   size_t lam, ga_acc, st3, st4;
   size_t total;
@@ -200,6 +200,7 @@ Layout make_layout(const gs_problem* p) {
   L.res4 = take(4 * T * 4 * W);
   L.cg = take(24 * n * W);
   L.dl = take(4 * n * W);
+  L.dlp = take(4 * n * W);
   L.p = take(4 * n * W);
   L.dg = take(n * W);
   L.dsp = take(n * W);
@@ -235,6 +236,7 @@ Layout make_layout(const gs_problem* p) {
   L.ch_start = take(((size_t)p->nch + 1) * 4);
   L.ch_tets = take(p->ch_tets.size() * 4);
   L.mmax = take((size_t)p->M * 8);
+  L.mgam = take((size_t)p->M * 16);
   L.mdone2 = take((size_t)p->M * 4);
   L.st2 = take(sizeof(DevStatus));
   L.alpha_last = take((size_t)p->nch * W);
@@ -282,6 +284,7 @@ Dev<R> make_dev(const gs_problem* p) {
   d.res4 = (R*)(b + L.res4);
   d.cg = (R*)(b + L.cg);
   d.dl = (R*)(b + L.dl);
+  d.dlp = (R*)(b + L.dlp);
   d.p = (R*)(b + L.p);
   d.dg = (R*)(b + L.dg);
   d.dsp = (R*)(b + L.dsp);
@@ -318,6 +321,7 @@ Dev<R> make_dev(const gs_problem* p) {
   d.ch_start = (const int32_t*)(b + L.ch_start);
   d.ch_tets = (const int32_t*)(b + L.ch_tets);
   d.mmax = (unsigned long long*)(b + L.mmax);
+  d.mgam = (double*)(b + L.mgam);
   d.alpha_last = (R*)(b + L.alpha_last);
   d.aa_dx = (R*)(b + L.aa_dx);
   d.aa_df = (R*)(b + L.aa_df);
@@ -855,7 +859,7 @@ void finalize(gs_problem* p) {
   int H = 1024;
   while (H < 2 * p->S) H <<= 1;
   p->H = H;
-  p->nparts = std::max({cdiv(p->T, kBlock), cdiv(n, kBlock), 2 * kMaxPcgGrid});
+  p->nparts = std::max({cdiv(p->T, kBlock), cdiv(n, kBlock), 8 * kMaxPcgGrid});
   p->slots = 1 + p->ns + p->np;
   // chamber -> tets, ascending tet id within a chamber
   p->ch_start.assign(p->nch + 1, 0);
@@ -986,15 +990,15 @@ void merge(gs_problem* p, const std::vector<gs_problem*>& parts) {
 // ---------------------------------------------------------------------------
 // Unrolled adjoint with checkpoints
 //
-// A record is the state before iteration k: displacement u_k, CG warm start,
-// and the contact set A_{k-1} (flags, targets, normals, prims).  Checkpoints
+// A record is the state before iteration k: displacement u_k, CG warm start
+// and the previous correction it is extrapolated from, and the contact set A_{k-1} (flags, targets, normals, prims).  Checkpoints
 // are kept every C = ceil(sqrt(K)) iterations; each segment is recomputed
 // from its checkpoint into C + 1 segment records before its reverse steps.
 
 namespace {
 
 struct RecordLayout {
-  size_t u, dl, cact, ctgt, cnrm, cprim, bytes;
+  size_t u, dl, dlp, cact, ctgt, cnrm, cprim, bytes;
 };
 
 RecordLayout record_layout(const gs_problem* p) {
@@ -1009,6 +1013,7 @@ RecordLayout record_layout(const gs_problem* p) {
   const size_t W = (size_t)p->prec, n = p->n, m = (size_t)p->S * p->slots;
   r.u = take(3 * n * W);
   r.dl = take(4 * n * W);
+  r.dlp = take(4 * n * W);
   r.cact = take(m);
   r.ctgt = take(3 * m * 8);
   r.cnrm = take(3 * m * 8);
@@ -1037,6 +1042,7 @@ hipError_t copy_record(gs_problem* p, char* rec, bool save, bool state, bool con
     size_t ws_off, rec_off, bytes;
     bool is_state;
   } items[] = {{L.u, R.u, 3 * n * W, true},       {L.dl, R.dl, 4 * n * W, true},
+               {L.dlp, R.dlp, 4 * n * W, true},
                {L.cact, R.cact, m, false},        {L.ctgt, R.ctgt, 3 * m * 8, false},
                {L.cnrm, R.cnrm, 3 * m * 8, false}, {L.cprim, R.cprim, m * 4, false}};
   for (const Item& it : items) {

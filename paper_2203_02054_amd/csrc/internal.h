@@ -97,6 +97,7 @@ struct Dev {
   R* cg;                   // [2][n][3][4] CG state per row, two buffers: r, w = A M^-1 r, s = A p
                            //   (each as x, y, z, pad); buffer 0 holds the right-hand side on entry
   R* dl;                   // [n][4] correction (kept across iterations: the warm start)
+  R* dlp;                  // [n][4] correction of the previous outer iteration
   R* p;                    // [n][4]
   R* dg;                   // [n] Jacobi diagonal
   R* dsp;                  // [n] spring diagonal
@@ -132,6 +133,7 @@ struct Dev {
   const int32_t* ch_start; // [nch+1] chamber -> tets
   const int32_t* ch_tets;  // chamber tets grouped by chamber, ascending
   unsigned long long* mmax;  // [M] max |mu| per mesh (double bits)
+  double* mgam;              // [M][2] warm-start weights per mesh of a batch
   R* alpha_last;           // [nch] volume ratios of the last solve
   // Anderson acceleration of the adjoint iteration (memory m = Consts::aa_m)
   R* aa_dx;                // [m][3][n] differences of successive iterates

@@ -45,6 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
       d.u[k * n + v] = uu;
       d.xc[k * n + v] = X + (double)uu;
       d.dl[4 * (size_t)v + k] = R(0);
+      d.dlp[4 * (size_t)v + k] = R(0);
     }
   }
   const int stride = gridDim.x * kBlock;
@@ -204,6 +205,34 @@ __device__ __forceinline__ W4<R> w4(R x, R y, R z) {
   return o;
 }
 
+// Weights (g1, g2) of the warm start g1 w1 + g2 w2 that minimise the A-norm
+// error of M d = b over span{w1, w2}: the 2x2 system H g = e with
+// H_ij = w_i' A w_j, e_i = w_i' b.  The start's residual is formed as
+// b - g1 A w1 - g2 A w2, so large weights of opposite sign (w1, w2 close to
+// parallel, as when the iteration contracts along one mode) would leave a
+// rounding error in it that the CG stopping test cannot see: the pair is
+// taken only when |g1| |w1|_A + |g2| |w2|_A stays within 16 |g1 w1 + g2 w2|_A
+// (about one decimal digit of cancellation), else the projection onto w1
+// alone; an empty w1 gives the zero start.
+__device__ __forceinline__ void galerkin_weights(double e1, double e2, double h11, double h12, double h22,
+                                                 double& g1, double& g2) {
+  g1 = 0.0;
+  g2 = 0.0;
+  if (!(h11 > 0.0) || isinf(h11)) return;
+  const double det = h11 * h22 - h12 * h12;
+  if (h22 > 0.0 && det > 0.0) {
+    const double a = (e1 * h22 - e2 * h12) / det, c = (e2 * h11 - e1 * h12) / det;
+    const double nn = a * a * h11 + 2.0 * a * c * h12 + c * c * h22;  // |g1 w1 + g2 w2|_A^2
+    const double sum = fabs(a) * sqrt(h11) + fabs(c) * sqrt(h22);
+    if (nn > 0.0 && sum * sum <= 256.0 * nn) {
+      g1 = a;
+      g2 = c;
+    }
+  }
+  if (g1 == 0.0 && g2 == 0.0) g1 = e1 / h11;
+  if (!(g1 == g1) || !(g2 == g2) || isinf(g1) || isinf(g2)) g1 = g2 = 0.0;
+}
+
 // Preconditioned conjugate gradient in the Chronopoulos-Gear arrangement:
 // both inner products of an iteration are taken after its single
 // matrix-vector product, so one grid-wide reduction (one barrier) per
@@ -241,7 +270,14 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
     int m = -1;
     if (v < c.n) {
       m = d.vmesh[v];
-      if (d.freem[v]) {
+      if (!ADJ && mesh_frozen(d, c.mask_done, m)) {
+        // a converged mesh of a batch: its positions stay as they are and its
+        // CG rows start (and so stay) at zero
+        W4<R>* dlw = reinterpret_cast<W4<R>*>(d.dl);
+        W4<R>* dlp = reinterpret_cast<W4<R>*>(d.dlp);
+        dlw[v] = w4<R>(R(0), R(0), R(0));
+        dlp[v] = w4<R>(R(0), R(0), R(0));
+      } else if (d.freem[v]) {
         const W4<R> dv = x[v];
         const R dd[3] = {dv.x, dv.y, dv.z};
         double uq = 0.0;
@@ -258,6 +294,7 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
             d.xc[k * n + v] = d.X0[k * n + v] + (double)uu;
           }
         }
+
         dm = sqrt(((double)dv.x * dv.x + (double)dv.y * dv.y) + (double)dv.z * dv.z);
         um = sqrt(uq);
       }
@@ -388,41 +425,163 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   const R* __restrict__ evl = d.ell_val;
   R* __restrict__ evs = d.ell_scaled;
 
-  // (A) r_0 = b - A x_0 with the warm start x_0 = previous correction;
-  //     p_{-1} = s_{-1} = 0; right-hand-side norm b' M^-1 b; a_vj / dg_j
+  // (A) r_0 = b - A x_0 from the warm start x_0; p_{-1} = s_{-1} = 0;
+  //     right-hand-side norm b' M^-1 b; a_vj / dg_j.  The adjoint solves start
+  //     from the previous correction.  The forward solve starts from the
+  //     A-norm-best combination x_0 = g1 w1 + g2 w2 of the previous correction
+  //     w1 = d_k and its change w2 = d_k - d_{k-1} (a 2x2 Galerkin projection
+  //     of M d = b onto their span: never a worse start, in the A-norm, than
+  //     d_k alone, and it follows a steady drift of the corrections).
   double acc_b = 0.0;
-  for (int v = tid0; v < c.n; v += stride) {
-    const R dv = dg[v], idg = R(1) / dv;
-    const W4<R> xv = x[v];
-    R ax0 = dv * xv.x, ax1 = dv * xv.y, ax2 = dv * xv.z;
+  if (ADJ) {
+    for (int v = tid0; v < c.n; v += stride) {
+      const R dv = dg[v], idg = R(1) / dv;
+      const W4<R> xv = x[v];
+      R ax0 = dv * xv.x, ax1 = dv * xv.y, ax2 = dv * xv.z;
 #pragma unroll 1
-    for (int k0 = 0; k0 < MW; k0 += CH) {
-      int jj[CH];
-      R aa[CH], dgn[CH];
-      W4<R> xn[CH];
+      for (int k0 = 0; k0 < MW; k0 += CH) {
+        int jj[CH];
+        R aa[CH], dgn[CH];
+        W4<R> xn[CH];
 #pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        jj[k] = ecol[(size_t)(k0 + k) * n + v];
-        aa[k] = evl[(size_t)(k0 + k) * n + v];
+        for (int k = 0; k < CH; ++k) {
+          jj[k] = ecol[(size_t)(k0 + k) * n + v];
+          aa[k] = evl[(size_t)(k0 + k) * n + v];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          xn[k] = x[jj[k]];
+          dgn[k] = dg[jj[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          ax0 += aa[k] * xn[k].x;
+          ax1 += aa[k] * xn[k].y;
+          ax2 += aa[k] * xn[k].z;
+          evs[(size_t)(k0 + k) * n + v] = aa[k] / dgn[k];
+        }
       }
+      const W4<R> b = cg0[3 * (size_t)v];
+      acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
+      cg0[3 * (size_t)v] = w4<R>(b.x - ax0, b.y - ax1, b.z - ax2);
+      cg0[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
+      p[v] = w4<R>(R(0), R(0), R(0));
+    }
+  } else {
+    W4<R>* __restrict__ xp = reinterpret_cast<W4<R>*>(d.dlp);
+    double e1 = 0.0, e2 = 0.0, h11 = 0.0, h12 = 0.0, h22 = 0.0;
+    for (int v = tid0; v < c.n; v += stride) {
+      const R dv = dg[v], idg = R(1) / dv;
+      const W4<R> w1 = x[v], wp = xp[v];
+      const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
+      R a10 = dv * w1.x, a11 = dv * w1.y, a12 = dv * w1.z;
+      R a20 = dv * w2.x, a21 = dv * w2.y, a22 = dv * w2.z;
+#pragma unroll 1
+      for (int k0 = 0; k0 < MW; k0 += CH) {
+        int jj[CH];
+        R aa[CH], dgn[CH];
+        W4<R> xn[CH], pn[CH];
 #pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        xn[k] = x[jj[k]];
-        dgn[k] = dg[jj[k]];
+        for (int k = 0; k < CH; ++k) {
+          jj[k] = ecol[(size_t)(k0 + k) * n + v];
+          aa[k] = evl[(size_t)(k0 + k) * n + v];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          xn[k] = x[jj[k]];
+          pn[k] = xp[jj[k]];
+          dgn[k] = dg[jj[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          a10 += aa[k] * xn[k].x;
+          a11 += aa[k] * xn[k].y;
+          a12 += aa[k] * xn[k].z;
+          a20 += aa[k] * (xn[k].x - pn[k].x);
+          a21 += aa[k] * (xn[k].y - pn[k].y);
+          a22 += aa[k] * (xn[k].z - pn[k].z);
+          evs[(size_t)(k0 + k) * n + v] = aa[k] / dgn[k];
+        }
       }
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        ax0 += aa[k] * xn[k].x;
-        ax1 += aa[k] * xn[k].y;
-        ax2 += aa[k] * xn[k].z;
-        evs[(size_t)(k0 + k) * n + v] = aa[k] / dgn[k];
+      const W4<R> b = cg0[3 * (size_t)v];
+      acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
+      const double t1 = ((double)w1.x * b.x + (double)w1.y * b.y) + (double)w1.z * b.z;
+      const double t2 = ((double)w2.x * b.x + (double)w2.y * b.y) + (double)w2.z * b.z;
+      const double t11 = ((double)w1.x * a10 + (double)w1.y * a11) + (double)w1.z * a12;
+      const double t12 = ((double)w1.x * a20 + (double)w1.y * a21) + (double)w1.z * a22;
+      const double t22 = ((double)w2.x * a20 + (double)w2.y * a21) + (double)w2.z * a22;
+      cg0[3 * (size_t)v + 1] = w4<R>(a10, a11, a12);  // A w1, A w2 until the second pass
+      cg0[3 * (size_t)v + 2] = w4<R>(a20, a21, a22);
+      if (c.M > 1) {
+        // per-row terms, summed per mesh below, in the half of the CG state
+        // the first iteration has yet to write
+        double* q = reinterpret_cast<double*>(cg0 + 3 * n);
+        q[v] = t1;
+        q[n + v] = t2;
+        q[2 * n + v] = t11;
+        q[3 * n + v] = t12;
+        q[4 * n + v] = t22;
+      } else {
+        e1 += t1;
+        e2 += t2;
+        h11 += t11;
+        h12 += t12;
+        h22 += t22;
       }
     }
-    const W4<R> b = cg0[3 * (size_t)v];
-    acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
-    cg0[3 * (size_t)v] = w4<R>(b.x - ax0, b.y - ax1, b.z - ax2);
-    cg0[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
-    p[v] = w4<R>(R(0), R(0), R(0));
+    double g1 = 0.0, g2 = 0.0;
+    if (c.M == 1) {
+      const double q[5] = {e1, e2, h11, h12, h22};
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        const double t = block_sum<kPcgBlock>(q[i], lds);
+        if (threadIdx.x == 0) d.part_c[(2 + i) * G + blockIdx.x] = t;
+      }
+      grid_barrier(bc, bg, G);
+      double E1, E2, H11, H12, H22, dummy;
+      grid_sum2(d.part_c + 2 * G, d.part_c + 3 * G, G, sh, E1, E2);
+      grid_sum2(d.part_c + 4 * G, d.part_c + 5 * G, G, sh, H11, H12);
+      grid_sum2(d.part_c + 6 * G, d.part_c + 6 * G, G, sh, H22, dummy);
+      galerkin_weights(E1, E2, H11, H12, H22, g1, g2);  // every block takes the same decision
+    } else {
+      // a batch: each mesh gets its own weights (the meshes' systems are
+      // independent), its sums taken by one block in a fixed order
+      grid_barrier(bc, bg, G);
+      const double* q = reinterpret_cast<const double*>(cg0 + 3 * n);
+      for (int m = blockIdx.x; m < c.M; m += G) {
+        const int v0 = d.mesh[m].vbeg, v1 = d.mesh[m].vend;
+        double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int v = v0 + (int)threadIdx.x; v < v1; v += kPcgBlock)
+#pragma unroll
+          for (int i = 0; i < 5; ++i) t[i] += q[i * n + v];
+        double S[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) S[i] = block_sum<kPcgBlock>(t[i], lds);
+        if (threadIdx.x == 0) {
+          double m1, m2;
+          galerkin_weights(S[0], S[1], S[2], S[3], S[4], m1, m2);
+          d.mgam[2 * m] = m1;
+          d.mgam[2 * m + 1] = m2;
+        }
+      }
+      grid_barrier(bc, bg, G);
+    }
+    for (int v = tid0; v < c.n; v += stride) {
+      R r1 = (R)g1, r2 = (R)g2;
+      if (c.M > 1) {
+        const int m = d.vmesh[v];
+        r1 = (R)d.mgam[2 * m];
+        r2 = (R)d.mgam[2 * m + 1];
+      }
+      const W4<R> w1 = x[v], wp = xp[v];
+      const W4<R> b = cg0[3 * (size_t)v], aw1 = cg0[3 * (size_t)v + 1], aw2 = cg0[3 * (size_t)v + 2];
+      x[v] = w4<R>(r1 * w1.x + r2 * (w1.x - wp.x), r1 * w1.y + r2 * (w1.y - wp.y), r1 * w1.z + r2 * (w1.z - wp.z));
+      xp[v] = w1;
+      cg0[3 * (size_t)v] = w4<R>(b.x - r1 * aw1.x - r2 * aw2.x, b.y - r1 * aw1.y - r2 * aw2.y,
+                                 b.z - r1 * aw1.z - r2 * aw2.z);
+      cg0[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
+      p[v] = w4<R>(R(0), R(0), R(0));
+    }
   }
   double bs = block_sum<kPcgBlock>(acc_b, lds);
   if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;

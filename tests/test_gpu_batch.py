@@ -33,9 +33,12 @@ def _batch_workloads():
 
 
 def _converging_workloads():
-    # meshes whose local/global iteration settles (some actuations keep toggling
-    # springs between two states and never converge, batched or alone)
-    return [mg.finger(4.0, 3, 2.0), mg.finger(4.0, 4, 2.0), mg.finger(4.0, 5, 2.0), mg.block()]
+    # meshes whose local/global iteration settles both batched and alone.  Some
+    # actuations end in a two-state cycle (a contact spring toggled every
+    # iteration); whether a mesh falls into one depends on its path, which the
+    # inexact global steps (CG tolerance, warm start, batch-wide CG scalars)
+    # shape: finger(4, 5, 2.0), for one, settles alone but cycles in this batch
+    return [mg.finger(4.0, 3, 2.0), mg.finger(4.0, 4, 2.0), mg.finger(3.5, 4, 2.0), mg.block()]
 
 
 def _split(x, lay, m):
