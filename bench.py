@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a 256 MiB copy);
 # see profiles/*_hbm_traffic.md.  Only valid for the kernel build the counters
 # were taken on: remove an entry when its kernel changes.
-PMC_TRAFFIC = {("finger", "pcg"): 22717133}
+PMC_TRAFFIC = {}
 
 
 def kernel_bytes(info, W, n_launch, pcg_iters):
@@ -50,9 +50,12 @@ def kernel_bytes(info, W, n_launch, pcg_iters):
       pcg        per CG iteration: per row the CG state (r, w, s: 3 vectors of
                  4 reals) read and written, p and the correction read and
                  written, the Jacobi diagonal; per off-diagonal entry its column
-                 and value.  Plus the two start-up passes and the end-of-iteration
-                 update (u read/written, correction read, collision positions
-                 written).
+                 and value.  Plus the start-up (the warm start: the last two
+                 corrections, right-hand side and diagonal read, their two
+                 products written, then combined into the start, residual,
+                 search vectors; the scaled ELL values written; w_0 = A u_0)
+                 and the end-of-iteration update (u read/written, correction
+                 read, collision positions written).
       local      per tet connectivity 16, tag 4, residual slot index 16, residual
                  columns written 4 x 4W; per vertex rest position 24 and
                  displacement 3W read once.
@@ -67,7 +70,7 @@ def kernel_bytes(info, W, n_launch, pcg_iters):
     out = {}
     m = pcg_iters / max(n_launch.get("pcg", 1), 1)
     per_it = n * (12 * W * 2 + 8 * W + 8 * W + W) + off * (4 + W)
-    startup = n * (17 * W) + off * (4 + 2 * W) + n * (9 * W) + off * (4 + W)
+    startup = n * (21 * W) + off * (4 + 2 * W) + n * (40 * W) + n * (9 * W) + off * (4 + W)
     finish = n * (3 * W + 4 * W + 24) + 4 * info["hash_buckets"]
     out["pcg"] = m * per_it + startup + finish
     out["local"] = T * (36 + 16 * W) + n * (24 + 3 * W)

@@ -256,7 +256,7 @@ gs_status gs_adjoint_unrolled(gs_problem* p, const void* dev_alpha, const void* 
 
 /* Choose the CG kernel's grid for this problem: times `iters` fixed
  * iterations from dev_x (with the stored contact set) for the default grid
- * (about one row per thread) and every power-of-two grid that can be
+ * (about 256 rows per block) and every power-of-two grid that can be
  * resident, keeps the fastest in params.pcg_blocks, and restores dev_x and
  * the stored contact set.  *chosen (may be NULL) receives the grid,
  * *ms_per_iter (may be NULL) its time per outer iteration.  Errors as

@@ -380,10 +380,12 @@ std::vector<R> cast_vec(const std::vector<double>& v) {
   return std::vector<R>(v.begin(), v.end());
 }
 
-// Workgroups of the cooperative CG kernel: about one row per thread, within
-// what can be resident and what the partial-sum arrays hold.
+// Workgroups of the cooperative CG kernel: about kPcgRowsPerBlock rows per
+// block (half a block's threads on a small mesh, so twice the compute units
+// share its neighbour gathers), within what can be resident and what the
+// partial-sum arrays hold.
 int pcg_grid_for(const gs_problem* p, int maxg) {
-  int g = p->prm.pcg_blocks > 0 ? p->prm.pcg_blocks : cdiv(p->n, kPcgThreads);
+  int g = p->prm.pcg_blocks > 0 ? p->prm.pcg_blocks : cdiv(p->n, kPcgRowsPerBlock);
   return std::max(1, std::min({g, maxg, kMaxPcgGrid, p->nparts / 2}));
 }
 
@@ -1435,8 +1437,8 @@ gs_status gs_autotune(gs_problem* p, const void* alpha, void* x, int32_t iters, 
   const gs_params saved = p->prm;
   const bool prof = p->prof.on;
   p->prof.on = false;
-  // candidates: the default (about one row per thread) and every power of two
-  std::vector<int> cand = {std::max(1, std::min({cdiv(p->n, kPcgThreads), maxg, kMaxPcgGrid, p->nparts / 2}))};
+  // candidates: the default (about 256 rows per block) and every power of two
+  std::vector<int> cand = {std::max(1, std::min({cdiv(p->n, kPcgRowsPerBlock), maxg, kMaxPcgGrid, p->nparts / 2}))};
   for (int g = 1; g <= std::min({maxg, kMaxPcgGrid, p->nparts / 2}); g *= 2)
     if (g != cand[0]) cand.push_back(g);
   hipEvent_t e0, e1;

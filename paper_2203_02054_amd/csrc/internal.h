@@ -13,6 +13,7 @@ constexpr int kCellCap = 64;         // hash cells a tet box may span before the
 constexpr int kHashCap = 8;          // entries stored in a hash bucket before the overflow list
 constexpr int kMaxSlots = 1 + 8 + 8; // self + spheres + planes
 constexpr int kPcgThreads = 512;     // threads per block of the cooperative CG kernel
+constexpr int kPcgRowsPerBlock = 256; // default rows per CG block (grid = n / 256, capped)
 constexpr int kMaxPcgGrid = 1024;     // workgroups of the cooperative CG kernel at most
 
 // Completion codes kept on the device (DevStatus::done).

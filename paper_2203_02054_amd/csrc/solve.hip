@@ -257,18 +257,19 @@ __device__ __forceinline__ void galerkin_weights(double e1, double e2, double h1
 // In the adjoint iteration (ADJ) the update is mu += d and a mesh is done once
 // max|d| <= tol max|mu| over its vertices.
 template <typename R, bool ADJ>
-__device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, int tid0, int stride, double* lds) {
+__device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, int row0, int row1, int tid0, int stride,
+                                            double* lds) {
   __shared__ int last;
   const size_t n = (size_t)c.n;
   const W4<R>* x = reinterpret_cast<const W4<R>*>(d.dl);
   double dmax = 0.0;
-  for (int v0 = tid0 - (int)(threadIdx.x & 63); v0 < c.n; v0 += stride) {
+  for (int v0 = row0 + (int)(threadIdx.x & ~63u); v0 < row1; v0 += kPcgBlock) {
     // one wavefront handles 64 consecutive rows: the per-mesh maximum of |d|
     // is reduced in the wavefront when all its rows share a mesh
     const int v = v0 + (int)(threadIdx.x & 63);
     double dm = 0.0, um = 0.0;
     int m = -1;
-    if (v < c.n) {
+    if (v < row1) {
       m = d.vmesh[v];
       if (!ADJ && mesh_frozen(d, c.mask_done, m)) {
         // a converged mesh of a batch: its positions stay as they are and its
@@ -415,6 +416,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   const int stride = G * kPcgBlock;
   const int tid0 = blockIdx.x * kPcgBlock + threadIdx.x;
   const size_t n = (size_t)c.n;
+  // each block owns one contiguous range of rows (a multiple of 64 long), so
+  // the rows spread over all G blocks however many rows a thread gets
+  const int chunk = ((c.n + G - 1) / G + 63) & ~63;
+  const int row0 = min(c.n, (int)blockIdx.x * chunk), row1 = min(c.n, row0 + chunk);
   unsigned* bc = &d.st->bar_count;
   unsigned* bg = &d.st->bar_gen;
   W4<R>* __restrict__ x = reinterpret_cast<W4<R>*>(d.dl);
@@ -434,7 +439,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   //     d_k alone, and it follows a steady drift of the corrections).
   double acc_b = 0.0;
   if (ADJ) {
-    for (int v = tid0; v < c.n; v += stride) {
+    for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       const R dv = dg[v], idg = R(1) / dv;
       const W4<R> xv = x[v];
       R ax0 = dv * xv.x, ax1 = dv * xv.y, ax2 = dv * xv.z;
@@ -470,7 +475,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   } else {
     W4<R>* __restrict__ xp = reinterpret_cast<W4<R>*>(d.dlp);
     double e1 = 0.0, e2 = 0.0, h11 = 0.0, h12 = 0.0, h22 = 0.0;
-    for (int v = tid0; v < c.n; v += stride) {
+    for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       const R dv = dg[v], idg = R(1) / dv;
       const W4<R> w1 = x[v], wp = xp[v];
       const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
@@ -566,7 +571,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       }
       grid_barrier(bc, bg, G);
     }
-    for (int v = tid0; v < c.n; v += stride) {
+    for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       R r1 = (R)g1, r2 = (R)g2;
       if (c.M > 1) {
         const int m = d.vmesh[v];
@@ -588,7 +593,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   grid_barrier(bc, bg, G);
   // (B) w_0 = A u_0, g_0 = (r_0, u_0), d_0 = (w_0, u_0)
   double acc_g = 0.0, acc_d = 0.0;
-  for (int v = tid0; v < c.n; v += stride) {
+  for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
     const R idg = R(1) / dg[v];
     const W4<R> rv = cg0[3 * (size_t)v];
     R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
@@ -640,7 +645,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     const R ra = (R)al, rb = (R)be;
     acc_g = 0.0;
     acc_d = 0.0;
-    for (int v = tid0; v < c.n; v += stride) {
+    for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       const R idg = R(1) / dg[v];
       const W4<R> rc = cs[3 * (size_t)v], wc = cs[3 * (size_t)v + 1], sc = cs[3 * (size_t)v + 2];
       const W4<R> pv0 = p[v];
@@ -714,7 +719,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     d.st->pcg_last = it;
     if (broke) __hip_atomic_store(&d.st->done, (int)BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (!broke) finish_tail<R, ADJ>(d, c, tid0, stride, lds);
+  if (!broke) finish_tail<R, ADJ>(d, c, row0, row1, tid0, stride, lds);
 }
 
 template <typename R>
