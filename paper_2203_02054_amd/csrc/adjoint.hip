@@ -317,7 +317,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(Dev<R> d, Consts c) {
     st->residual = INFINITY;
     st->energy = 0.0;
     st->bar_count = 0;
-    st->bar_gen = 0;
   }
 }
 
@@ -810,7 +809,6 @@ __global__ __launch_bounds__(kBlock) void k_unr_restore(Dev<R> d, Consts c, DevS
     st->ticket = 0;
     st->n_contacts = 0;
     st->bar_count = 0;
-    st->bar_gen = 0;
     run->done = RUNNING;
   }
 }
@@ -853,7 +851,6 @@ __global__ __launch_bounds__(kBlock) void k_unr_rhs(Dev<R> d, Consts c) {
     st->done = RUNNING;
     st->ticket = 0;
     st->bar_count = 0;
-    st->bar_gen = 0;
     st->pcg_last = 0;
   }
 }

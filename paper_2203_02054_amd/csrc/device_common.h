@@ -53,21 +53,21 @@ __device__ __forceinline__ double block_max(double v, double* lds) {
 }
 
 // ---- grid barrier (cooperative launch: every block is resident) -------------
-// Arrival counter + generation word.  Thread 0 of each block releases the
-// block's writes at agent scope, arrives, and spins on the generation; the
-// last arrival resets the counter and bumps the generation.
-__device__ __forceinline__ void grid_barrier(unsigned* count, unsigned* gen, unsigned nblocks) {
+// One arrival counter that only grows during a launch: barrier j of the launch
+// is complete once it reads (j + 1) * nblocks, so the last arrival has nothing
+// more to write and no generation word has to be reset and re-published.
+// Thread 0 of each block releases the block's writes at agent scope, arrives,
+// waits for the count (wrap-safe comparison) and acquires.  `target` is the
+// block's own count of arrivals expected so far.  The launch's last block
+// clears the counter once every block is past its last barrier.
+__device__ __forceinline__ void grid_barrier(unsigned* count, unsigned& target, unsigned nblocks) {
+  target += nblocks;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) __builtin_amdgcn_s_sleep(1);
-    }
+    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while ((int)(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0)
+      __builtin_amdgcn_s_sleep(1);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();

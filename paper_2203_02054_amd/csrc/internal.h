@@ -37,7 +37,8 @@ struct DevStatus {
   int n_active;         // meshes still iterating
   double residual;      // r_k of the last completed iteration
   double energy;        // Eq. 9 at x_k with the iteration's targets
-  unsigned bar_count, bar_gen, pad0, pad1;
+  unsigned bar_count;    // grid-barrier arrivals of the running CG launch (0 between launches)
+  unsigned pad0, pad1, pad2;
 };
 
 // Per-mesh constants of a problem made of one or several meshes.

@@ -77,7 +77,6 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
     st->residual = INFINITY;
     st->energy = 0.0;
     st->bar_count = 0;
-    st->bar_gen = 0;
   }
 }
 
@@ -179,6 +178,7 @@ constexpr int kPcgBlock = kPcgThreads;
 // trip: wave 0 reduces `a`, wave 1 reduces `b`; lane l first adds entries
 // l, l+64, l+128, ... in that order, then a fixed shuffle tree combines the
 // lanes (every block obtains the same bits).
+template <bool SYNC_AFTER = true>
 __device__ __forceinline__ void grid_sum2(const double* a, const double* b, int G, double* sh, double& ra,
                                           double& rb) {
   if (threadIdx.x < 128) {
@@ -192,7 +192,33 @@ __device__ __forceinline__ void grid_sum2(const double* a, const double* b, int 
   __syncthreads();
   ra = sh[0];
   rb = sh[1];
+  if (SYNC_AFTER) __syncthreads();
+}
+
+// Block sums of two values, stored by thread 0 to out_a and out_b (the
+// per-wave order and the fixed tree of block_sum).  No closing
+// __syncthreads: the caller's next step (a grid barrier) starts with one
+// before `lds` is written again.
+__device__ __forceinline__ void block_sum2_store(double a, double b, double (*lds)[kPcgBlock / 64], double* out_a,
+                                                 double* out_b) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    lds[0][w] = a;
+    lds[1][w] = b;
+  }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPcgBlock / 64; ++i) {
+      ta += lds[0][i];
+      tb += lds[1][i];
+    }
+    *out_a = ta;
+    *out_b = tb;
+  }
 }
 
 template <typename R>
@@ -396,6 +422,7 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   st->n_pen = 0;
   st->n_over = 0;
   st->ticket = 0;
+  st->bar_count = 0u;  // every block is past its last barrier
   __hip_atomic_store(&st->done, code, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -410,7 +437,8 @@ template <typename R, int MW, bool ADJ>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   constexpr int CH = Chunk<R>::n;
   __shared__ double lds[kPcgBlock / 64];
-  __shared__ double sh[2];
+  __shared__ double lds2[2][kPcgBlock / 64];
+  __shared__ double sh[4];
   if (is_done(d.st)) return;
   const int G = gridDim.x;
   const int stride = G * kPcgBlock;
@@ -421,7 +449,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   const int chunk = ((c.n + G - 1) / G + 63) & ~63;
   const int row0 = min(c.n, (int)blockIdx.x * chunk), row1 = min(c.n, row0 + chunk);
   unsigned* bc = &d.st->bar_count;
-  unsigned* bg = &d.st->bar_gen;
+  unsigned bar_target = 0;  // arrivals the next grid barrier waits for
   W4<R>* __restrict__ x = reinterpret_cast<W4<R>*>(d.dl);
   W4<R>* __restrict__ p = reinterpret_cast<W4<R>*>(d.p);
   W4<R>* const cg0 = reinterpret_cast<W4<R>*>(d.cg);
@@ -437,7 +465,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   //     w1 = d_k and its change w2 = d_k - d_{k-1} (a 2x2 Galerkin projection
   //     of M d = b onto their span: never a worse start, in the A-norm, than
   //     d_k alone, and it follows a steady drift of the corrections).
-  double acc_b = 0.0;
+  double acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
+  int cur = 0;  // half of the double-buffered CG state holding (r_0, w_0, s_0)
   if (ADJ) {
     for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       const R dv = dg[v], idg = R(1) / dv;
@@ -471,6 +500,38 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       cg0[3 * (size_t)v] = w4<R>(b.x - ax0, b.y - ax1, b.z - ax2);
       cg0[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
       p[v] = w4<R>(R(0), R(0), R(0));
+    }
+    const double bs = block_sum<kPcgBlock>(acc_b, lds);
+    if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
+    grid_barrier(bc, bar_target, G);
+    // (B) w_0 = A u_0, g_0 = (r_0, u_0), d_0 = (w_0, u_0)
+    for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
+      const R idg = R(1) / dg[v];
+      const W4<R> rv = cg0[3 * (size_t)v];
+      R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
+#pragma unroll 1
+      for (int k0 = 0; k0 < MW; k0 += CH) {
+        int jj[CH];
+        R aa[CH];
+        W4<R> rn[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          jj[k] = ecol[(size_t)(k0 + k) * n + v];
+          aa[k] = evs[(size_t)(k0 + k) * n + v];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) rn[k] = cg0[3 * (size_t)jj[k]];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          a0 += aa[k] * rn[k].x;
+          a1 += aa[k] * rn[k].y;
+          a2 += aa[k] * rn[k].z;
+        }
+      }
+      cg0[3 * (size_t)v + 1] = w4<R>(a0, a1, a2);
+      const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
+      acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
+      acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
     }
   } else {
     W4<R>* __restrict__ xp = reinterpret_cast<W4<R>*>(d.dlp);
@@ -534,6 +595,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         h22 += t22;
       }
     }
+    const double bs = block_sum<kPcgBlock>(acc_b, lds);
+    if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
     double g1 = 0.0, g2 = 0.0;
     if (c.M == 1) {
       const double q[5] = {e1, e2, h11, h12, h22};
@@ -542,7 +605,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         const double t = block_sum<kPcgBlock>(q[i], lds);
         if (threadIdx.x == 0) d.part_c[(2 + i) * G + blockIdx.x] = t;
       }
-      grid_barrier(bc, bg, G);
+      grid_barrier(bc, bar_target, G);
       double E1, E2, H11, H12, H22, dummy;
       grid_sum2(d.part_c + 2 * G, d.part_c + 3 * G, G, sh, E1, E2);
       grid_sum2(d.part_c + 4 * G, d.part_c + 5 * G, G, sh, H11, H12);
@@ -551,7 +614,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     } else {
       // a batch: each mesh gets its own weights (the meshes' systems are
       // independent), its sums taken by one block in a fixed order
-      grid_barrier(bc, bg, G);
+      grid_barrier(bc, bar_target, G);
       const double* q = reinterpret_cast<const double*>(cg0 + 3 * n);
       for (int m = blockIdx.x; m < c.M; m += G) {
         const int v0 = d.mesh[m].vbeg, v1 = d.mesh[m].vend;
@@ -569,8 +632,15 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           d.mgam[2 * m + 1] = m2;
         }
       }
-      grid_barrier(bc, bg, G);
+      grid_barrier(bc, bar_target, G);
     }
+    // x_0, r_0 = b - g1 A w1 - g2 A w2 and, in the same pass, w_0 = A u_0:
+    // the neighbours' r_0 are rebuilt from their (b, A w1, A w2) as the CG
+    // iterations rebuild r_{i+1}, so no barrier separates the two.  A row's
+    // neighbours belong to its mesh and share its weights.  The start goes to
+    // the other half of the CG state, whose (b, A w1, A w2) other blocks are
+    // still reading.
+    W4<R>* __restrict__ ns = cg0 + 3 * n;
     for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       R r1 = (R)g1, r2 = (R)g2;
       if (c.M > 1) {
@@ -578,54 +648,53 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         r1 = (R)d.mgam[2 * m];
         r2 = (R)d.mgam[2 * m + 1];
       }
+      const R idg = R(1) / dg[v];
       const W4<R> w1 = x[v], wp = xp[v];
       const W4<R> b = cg0[3 * (size_t)v], aw1 = cg0[3 * (size_t)v + 1], aw2 = cg0[3 * (size_t)v + 2];
+      const W4<R> rv = w4<R>(b.x - r1 * aw1.x - r2 * aw2.x, b.y - r1 * aw1.y - r2 * aw2.y,
+                             b.z - r1 * aw1.z - r2 * aw2.z);
+      R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
+#pragma unroll 1
+      for (int k0 = 0; k0 < MW; k0 += CH) {
+        int jj[CH];
+        R aa[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          jj[k] = ecol[(size_t)(k0 + k) * n + v];
+          aa[k] = evs[(size_t)(k0 + k) * n + v];
+        }
+        W4<R> nb[CH], n1[CH], n2[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const size_t b3 = 3 * (size_t)jj[k];
+          nb[k] = cg0[b3];
+          n1[k] = cg0[b3 + 1];
+          n2[k] = cg0[b3 + 2];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          a0 += aa[k] * (nb[k].x - r1 * n1[k].x - r2 * n2[k].x);
+          a1 += aa[k] * (nb[k].y - r1 * n1[k].y - r2 * n2[k].y);
+          a2 += aa[k] * (nb[k].z - r1 * n1[k].z - r2 * n2[k].z);
+        }
+      }
       x[v] = w4<R>(r1 * w1.x + r2 * (w1.x - wp.x), r1 * w1.y + r2 * (w1.y - wp.y), r1 * w1.z + r2 * (w1.z - wp.z));
       xp[v] = w1;
-      cg0[3 * (size_t)v] = w4<R>(b.x - r1 * aw1.x - r2 * aw2.x, b.y - r1 * aw1.y - r2 * aw2.y,
-                                 b.z - r1 * aw1.z - r2 * aw2.z);
-      cg0[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
       p[v] = w4<R>(R(0), R(0), R(0));
+      ns[3 * (size_t)v] = rv;
+      ns[3 * (size_t)v + 1] = w4<R>(a0, a1, a2);
+      ns[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
+      const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
+      acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
+      acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
     }
+    cur = 1;
   }
-  double bs = block_sum<kPcgBlock>(acc_b, lds);
-  if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
-  grid_barrier(bc, bg, G);
-  // (B) w_0 = A u_0, g_0 = (r_0, u_0), d_0 = (w_0, u_0)
-  double acc_g = 0.0, acc_d = 0.0;
-  for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
-    const R idg = R(1) / dg[v];
-    const W4<R> rv = cg0[3 * (size_t)v];
-    R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
-#pragma unroll 1
-    for (int k0 = 0; k0 < MW; k0 += CH) {
-      int jj[CH];
-      R aa[CH];
-      W4<R> rn[CH];
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        jj[k] = ecol[(size_t)(k0 + k) * n + v];
-        aa[k] = evs[(size_t)(k0 + k) * n + v];
-      }
-#pragma unroll
-      for (int k = 0; k < CH; ++k) rn[k] = cg0[3 * (size_t)jj[k]];
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        a0 += aa[k] * rn[k].x;
-        a1 += aa[k] * rn[k].y;
-        a2 += aa[k] * rn[k].z;
-      }
-    }
-    cg0[3 * (size_t)v + 1] = w4<R>(a0, a1, a2);
-    const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
-    acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
-    acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
-  }
-  bs = block_sum<kPcgBlock>(acc_g, lds);
+  double bs = block_sum<kPcgBlock>(acc_g, lds);
   if (threadIdx.x == 0) d.part_c[blockIdx.x] = bs;
   bs = block_sum<kPcgBlock>(acc_d, lds);
   if (threadIdx.x == 0) d.part_e[blockIdx.x] = bs;
-  grid_barrier(bc, bg, G);
+  grid_barrier(bc, bar_target, G);
   double gam, del, rhs, dummy;
   grid_sum2(d.part_c, d.part_e, G, sh, gam, del);
   grid_sum2(d.part_d, d.part_d, G, sh, rhs, dummy);
@@ -638,7 +707,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     run = false;
   }
   double al = run ? gam / del : 0.0, be = 0.0;
-  int cur = 0;
   while (run && it < c.pcg_max) {
     const W4<R>* cs = cg0 + cur * 3 * n;
     W4<R>* ns = cg0 + (cur ^ 1) * 3 * n;
@@ -690,13 +758,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     // partial sums alternate halves so a slow block still reading the previous
     // iteration's sums is never overwritten
     const int half = (it & 1) ? 0 : G;
-    bs = block_sum<kPcgBlock>(acc_g, lds);
-    if (threadIdx.x == 0) d.part_c[half + blockIdx.x] = bs;
-    bs = block_sum<kPcgBlock>(acc_d, lds);
-    if (threadIdx.x == 0) d.part_e[half + blockIdx.x] = bs;
-    grid_barrier(bc, bg, G);
+    block_sum2_store(acc_g, acc_d, lds2, d.part_c + half + blockIdx.x, d.part_e + half + blockIdx.x);
+    grid_barrier(bc, bar_target, G);
     double gn, dn;
-    grid_sum2(d.part_c + half, d.part_e + half, G, sh, gn, dn);
+    grid_sum2<false>(d.part_c + half, d.part_e + half, G, sh + 2 * (it & 1), gn, dn);
     ++it;
     cur ^= 1;
     if (!(gn >= 0.0) || isinf(gn) || !(dn == dn) || isinf(dn)) {
@@ -719,7 +784,17 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     d.st->pcg_last = it;
     if (broke) __hip_atomic_store(&d.st->done, (int)BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (!broke) finish_tail<R, ADJ>(d, c, row0, row1, tid0, stride, lds);
+  if (!broke) {
+    finish_tail<R, ADJ>(d, c, row0, row1, tid0, stride, lds);
+  } else if (threadIdx.x == 0) {
+    // every block leaves after the same barrier; the last one out clears the
+    // barrier counter for the next launch
+    const int t = __hip_atomic_fetch_add(&d.st->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == G - 1) {
+      d.st->ticket = 0;
+      d.st->bar_count = 0u;
+    }
+  }
 }
 
 template <typename R>
