@@ -71,10 +71,48 @@ __device__ __forceinline__ void test_point(const Dev<R>& d, const double4& en, i
   }
 }
 
+// Tests the entries of up to 8 buckets (key < 0: none).  PREFETCH (few
+// tets, latency-bound): the first entries of all non-empty buckets are loaded
+// in one round; otherwise one by one, with fewer registers.  Entries past the
+// first follow one by one.
+template <typename R, bool DEBUG, bool PREFETCH>
+__device__ __forceinline__ void test_buckets(const Dev<R>& d, const double4* slots, const int (&keys)[8], int e,
+                                             int vbeg, int vend, const int (&vi)[4], const double (&p)[4][3],
+                                             const double (&lo)[3], const double (&hi)[3]) {
+  int cnt[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) cnt[k] = (keys[k] >= 0) ? min(d.hcount[keys[k]], kHashCap) : 0;
+  if (PREFETCH) {
+    double4 e0[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (cnt[k] > 0) e0[k] = slots[(size_t)keys[k] * kHashCap];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (cnt[k] > 0) test_point<R, DEBUG>(d, e0[k], e, vbeg, vend, vi, p, lo, hi);
+  } else {
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k)
+      if (cnt[k] > 0) test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap], e, vbeg, vend, vi, p, lo, hi);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    for (int i = 1; i < cnt[k]; ++i)
+      test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, vbeg, vend, vi, p, lo, hi);
+}
+
+// Lanes per tet of the tet query: with few tets (latency-bound) a tet's cell
+// groups are shared by 4 consecutive lanes, so the longest chain of
+// dependent bucket reads is about one group; with many tets one lane each.
+template <bool PREFETCH>
+struct TetQueryLanes { static constexpr int n = PREFETCH ? 4 : 1; };
+
 template <typename R, bool DEBUG, bool PREFETCH>
 __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
+  constexpr int L = TetQueryLanes<PREFETCH>::n;
   if (is_done(d.st)) return;
-  const int e = blockIdx.x * kBlock + threadIdx.x;
+  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int e = gid / L, sub = gid % L;
   if (e >= c.T) return;
   const int m = d.tmesh[e];
   if (mesh_frozen(d, c.mask_done, m)) return;
@@ -109,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
   const double4* slots = reinterpret_cast<const double4*>(d.hslot);
   if (ncell > kCellCap) {
     // a tet stretched over many cells: test every query vertex of its mesh (still exact)
-    for (int s = d.mesh[m].sbeg; s < d.mesh[m].send; ++s) {
+    for (int s = d.mesh[m].sbeg + sub; s < d.mesh[m].send; s += L) {
       const int v = d.qverts[s];
       double4 en;
       en.x = d.xc[v];
@@ -120,49 +158,23 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
     }
     return;
   }
-  const bool small = (chi[0] - clo[0] <= 1) && (chi[1] - clo[1] <= 1) && (chi[2] - clo[2] <= 1);
-  if (small) {
-    // common case (at most 2 cells per axis): bucket counts and first entries
-    // of all cells are fetched in one round trip
-    int keys[8], cnt[8];
+  // the covered cells in groups of 8 (x fastest), group j taken by lane
+  // j mod L: one round trip fetches a group's bucket counts, the next the
+  // first entries of its non-empty buckets (the common tet covers at most 2
+  // cells per axis: one group)
+  const int nx = chi[0] - clo[0] + 1, ny = chi[1] - clo[1] + 1;
+  const int nc = (int)ncell;
+  for (int c0 = 8 * sub; c0 < nc; c0 += 8 * L) {
+    int keys[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int ix = clo[0] + (k & 1), iy = clo[1] + ((k >> 1) & 1), iz = clo[2] + ((k >> 2) & 1);
-      const bool ok = ix <= chi[0] && iy <= chi[1] && iz <= chi[2];
-      keys[k] = ok ? hash_cell(ix, iy, iz, m, c.H) : -1;
+      const int i = c0 + k;
+      keys[k] = i < nc ? hash_cell(clo[0] + i % nx, clo[1] + (i / nx) % ny, clo[2] + i / (nx * ny), m, c.H) : -1;
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) cnt[k] = (keys[k] >= 0) ? min(d.hcount[keys[k]], kHashCap) : 0;
-    if (PREFETCH) {
-      // few tets (latency-bound): the first entries of all 8 cells in one round
-      double4 e0[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (cnt[k] > 0) e0[k] = slots[(size_t)keys[k] * kHashCap];
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (cnt[k] > 0) test_point<R, DEBUG>(d, e0[k], e, vbeg, vend, vi, p, lo, hi);
-    } else {
-      // many tets (throughput-bound): fewer registers, twice the occupancy
-#pragma unroll 1
-      for (int k = 0; k < 8; ++k)
-        if (cnt[k] > 0) test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap], e, vbeg, vend, vi, p, lo, hi);
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      for (int i = 1; i < cnt[k]; ++i)
-        test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, vbeg, vend, vi, p, lo, hi);
-  } else {
-    for (int ix = clo[0]; ix <= chi[0]; ++ix)
-      for (int iy = clo[1]; iy <= chi[1]; ++iy)
-        for (int iz = clo[2]; iz <= chi[2]; ++iz) {
-          const int key = hash_cell(ix, iy, iz, m, c.H);
-          const int cn = min(d.hcount[key], kHashCap);
-          for (int i = 0; i < cn; ++i) test_point<R, DEBUG>(d, slots[(size_t)key * kHashCap + i], e, vbeg, vend, vi, p, lo, hi);
-        }
+    test_buckets<R, DEBUG, PREFETCH>(d, slots, keys, e, vbeg, vend, vi, p, lo, hi);
   }
   const int nover = __hip_atomic_load(&d.st->n_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int i = 0; i < nover; ++i)
+  for (int i = sub; i < nover; i += L)
     test_point<R, DEBUG>(d, reinterpret_cast<const double4*>(d.hover)[i], e, vbeg, vend, vi, p, lo, hi);
 }
 
@@ -389,22 +401,24 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
   if (nact) atomicAdd(&d.st->n_contacts, nact);
 }
 
-// Tet count from which the tet query runs its lower-register variant (the
-// GPU then holds enough waves that occupancy beats prefetching).
+// Tet count from which the tet query runs its one-lane-per-tet,
+// lower-register variant (the GPU then holds enough waves that occupancy
+// beats prefetching and lane sharing).
 constexpr int kTetQueryWide = 1 << 18;
 
 template <typename R>
 hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s) {
   const int gs = cdiv(c.S, kBlock), gt = cdiv(c.T, kBlock);
+  const int gt4 = cdiv(c.T * TetQueryLanes<true>::n, kBlock);
   switch (stage) {
     case STAGE_HASH_INSERT:
       k_hash_insert<R><<<gs, kBlock, 0, s>>>(d, c);
       break;
     case STAGE_TET_QUERY:
       if (debug)
-        k_tet_query<R, true, true><<<gt, kBlock, 0, s>>>(d, c);
+        k_tet_query<R, true, true><<<gt4, kBlock, 0, s>>>(d, c);
       else if (c.T < kTetQueryWide)
-        k_tet_query<R, false, true><<<gt, kBlock, 0, s>>>(d, c);
+        k_tet_query<R, false, true><<<gt4, kBlock, 0, s>>>(d, c);
       else
         k_tet_query<R, false, false><<<gt, kBlock, 0, s>>>(d, c);
       break;
