@@ -9,6 +9,12 @@
 
 namespace gs {
 
+// Three reals padded to 16 (float) or 32 (double) bytes: one vector load.
+template <typename R>
+struct alignas(4 * sizeof(R)) W4 {
+  R x, y, z, w;
+};
+
 // ---- reductions (64-wide wavefronts) ---------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -496,19 +496,34 @@ gs_status drive(gs_problem* p, const DevStatus* dstat, int limit, F&& enqueue_on
   return GS_OK;
 }
 
+// One outer iteration.  Below kTetQueryWide tets the local step rides in the
+// tet-query launch (both read only the iteration's positions), and with any
+// collision the contact update rides in the gather launch: 5 launches per
+// iteration with self-collision instead of 7.
 template <typename R>
 hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, const R* alpha) {
   hipError_t e;
   hipStream_t s = p->stream;
+  const bool fused_local = c.self_col && c.T < kTetQueryWide;
   if (c.self_col) {
-    for (int st = 0; st < N_COLLIDE_STAGES; ++st)
-      if ((e = timed(p, st, [&] { return launch_collide_stage<R>(d, c, st, false, s); })) != hipSuccess) return e;
+    if ((e = timed(p, STAGE_HASH_INSERT,
+                   [&] { return launch_collide_stage<R>(d, c, STAGE_HASH_INSERT, false, s); })) != hipSuccess)
+      return e;
+    if (fused_local)
+      e = timed(p, STAGE_TET_QUERY, [&] { return launch_query_local<R>(d, c, alpha, s); });
+    else
+      e = timed(p, STAGE_TET_QUERY, [&] { return launch_collide_stage<R>(d, c, STAGE_TET_QUERY, false, s); });
+    if (e != hipSuccess) return e;
+    if ((e = timed(p, STAGE_RAY, [&] { return launch_collide_stage<R>(d, c, STAGE_RAY, false, s); })) != hipSuccess)
+      return e;
   }
-  if (c.self_col || c.obst_col) {
-    if ((e = timed(p, K_CONTACTS, [&] { return launch_contacts<R>(d, c, s); })) != hipSuccess) return e;
-  }
-  if ((e = timed(p, K_LOCAL, [&] { return launch_local<R>(d, c, alpha, s); })) != hipSuccess) return e;
-  if ((e = timed(p, K_GATHER, [&] { return launch_gather<R>(d, c, s); })) != hipSuccess) return e;
+  if (!fused_local)
+    if ((e = timed(p, K_LOCAL, [&] { return launch_local<R>(d, c, alpha, s); })) != hipSuccess) return e;
+  if (c.self_col || c.obst_col)
+    e = timed(p, K_CONTACTS, [&] { return launch_contacts_gather<R>(d, c, s); });
+  else
+    e = timed(p, K_GATHER, [&] { return launch_gather<R>(d, c, s); });
+  if (e != hipSuccess) return e;
   return timed(p, K_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s); });
 }
 

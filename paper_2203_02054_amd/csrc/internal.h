@@ -14,6 +14,10 @@ constexpr int kHashCap = 8;          // entries stored in a hash bucket before t
 constexpr int kMaxSlots = 1 + 8 + 8; // self + spheres + planes
 constexpr int kPcgThreads = 512;     // threads per block of the cooperative CG kernel
 constexpr int kPcgRowsPerBlock = 256; // default rows per CG block (grid = n / 256, capped)
+// Tet count from which the tet query runs its one-lane-per-tet,
+// lower-register variant (the GPU then holds enough waves that occupancy
+// beats prefetching and lane sharing) and is not fused with the local step.
+constexpr int kTetQueryWide = 1 << 18;
 constexpr int kMaxPcgGrid = 1024;     // workgroups of the cooperative CG kernel at most
 
 // Completion codes kept on the device (DevStatus::done).
@@ -164,7 +168,9 @@ enum { STAGE_HASH_INSERT = 0, STAGE_TET_QUERY, STAGE_RAY, N_COLLIDE_STAGES };
 template <typename R>
 hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s);
 template <typename R> hipError_t launch_contacts(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R> hipError_t launch_contacts_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_local(const Dev<R>& d, const Consts& c, const R* alpha, hipStream_t s);
+template <typename R> hipError_t launch_query_local(const Dev<R>& d, const Consts& c, const R* alpha, hipStream_t s);
 template <typename R> hipError_t launch_local_debug(const Dev<R>& d, const Consts& c, const R* alpha, const R* x,
                                                     R* targets, hipStream_t s);
 template <typename R> hipError_t launch_gather(const Dev<R>& d, const Consts& c, hipStream_t s);

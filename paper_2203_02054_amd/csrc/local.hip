@@ -10,50 +10,71 @@
 // M V with columns sorted by norm (the structure of McAdams et al. 2011, here
 // with exact Jacobi angles and a fixed sweep count).
 #include "tet_math.h"
+#include "tet_query.h"
 
 namespace gs {
+
+// Local step of tet e: its residual columns, scattered to the incidence
+// slots; returns its term of the elastic part of Eq. (9).
+template <typename R>
+__device__ __forceinline__ double local_one(const Dev<R>& d, const Consts& c, const R* __restrict__ alpha, int e) {
+  const int m = d.tmesh[e];
+  V4<R>* res = reinterpret_cast<V4<R>*>(d.res4);
+  double eloc = 0.0;
+  if (mesh_frozen(d, c.mask_done, m)) {
+    // a converged mesh of a batch: no residual, so its correction stays zero
+    V4<R> z;
+    z.x = z.y = z.z = z.w = R(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) res[d.inc_pos[j * c.T + e]] = z;
+  } else {
+    int vi[4];
+    R P[3][4], D[3][4], Dminv[3][3];
+    double vol;
+    load_tet<R, false>(d, c, e, nullptr, vi, P, D, Dminv, vol);
+    const int tag = d.tag[e];
+    const int mode = tag & 7, ch = tag >> 3;
+    const R a = (mode != GS_BODY) ? alpha[ch] : R(1);
+    R Tt[3][4];
+    tet_target<R>(mode, a, P, D, Dminv, (R)vol, c, Tt);
+    const R om = (R)(vol * d.mesh[m].inv_mean_vol);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const R r0 = Tt[0][j] - D[0][j], r1 = Tt[1][j] - D[1][j], r2 = Tt[2][j] - D[2][j];
+      V4<R> v;
+      v.x = om * r0;
+      v.y = om * r1;
+      v.z = om * r2;
+      v.w = R(0);
+      res[d.inc_pos[j * c.T + e]] = v;
+      eloc += (double)om * ((double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2);
+    }
+  }
+  return eloc;
+}
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_local(Dev<R> d, Consts c, const R* __restrict__ alpha) {
   __shared__ double lds[kBlock / 64];
   if (is_done(d.st)) return;
   const int e = blockIdx.x * kBlock + threadIdx.x;
-  double eloc = 0.0;
-  if (e < c.T) {
-    const int m = d.tmesh[e];
-    V4<R>* res = reinterpret_cast<V4<R>*>(d.res4);
-    if (mesh_frozen(d, c.mask_done, m)) {
-      // a converged mesh of a batch: no residual, so its correction stays zero
-      V4<R> z;
-      z.x = z.y = z.z = z.w = R(0);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) res[d.inc_pos[j * c.T + e]] = z;
-    } else {
-      int vi[4];
-      R P[3][4], D[3][4], Dminv[3][3];
-      double vol;
-      load_tet<R, false>(d, c, e, nullptr, vi, P, D, Dminv, vol);
-      const int tag = d.tag[e];
-      const int mode = tag & 7, ch = tag >> 3;
-      const R a = (mode != GS_BODY) ? alpha[ch] : R(1);
-      R Tt[3][4];
-      tet_target<R>(mode, a, P, D, Dminv, (R)vol, c, Tt);
-      const R om = (R)(vol * d.mesh[m].inv_mean_vol);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const R r0 = Tt[0][j] - D[0][j], r1 = Tt[1][j] - D[1][j], r2 = Tt[2][j] - D[2][j];
-        V4<R> v;
-        v.x = om * r0;
-        v.y = om * r1;
-        v.z = om * r2;
-        v.w = R(0);
-        res[d.inc_pos[j * c.T + e]] = v;
-        eloc += (double)om * ((double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2);
-      }
-    }
-  }
+  const double eloc = e < c.T ? local_one(d, c, alpha, e) : 0.0;
   const double bs = block_sum<kBlock>(eloc, lds);
   if (threadIdx.x == 0) d.part_a[blockIdx.x] = bs;
+}
+
+// Local step and tet query in one launch for meshes below kTetQueryWide tets
+// (both read only the positions of the iteration): thread g runs the local
+// step of tet g, then lane g of the four-lanes-per-tet query.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_query_local(Dev<R> d, Consts c, const R* __restrict__ alpha) {
+  __shared__ double lds[kBlock / 64];
+  if (is_done(d.st)) return;
+  const int g = blockIdx.x * kBlock + threadIdx.x;
+  const double eloc = g < c.T ? local_one(d, c, alpha, g) : 0.0;
+  const double bs = block_sum<kBlock>(eloc, lds);
+  if (threadIdx.x == 0 && (int)blockIdx.x < cdiv(c.T, kBlock)) d.part_a[blockIdx.x] = bs;
+  tet_query_lane<R, false, true>(d, c, g);
 }
 
 template <typename R>
@@ -83,6 +104,12 @@ hipError_t launch_local(const Dev<R>& d, const Consts& c, const R* alpha, hipStr
 }
 
 template <typename R>
+hipError_t launch_query_local(const Dev<R>& d, const Consts& c, const R* alpha, hipStream_t s) {
+  k_query_local<R><<<cdiv(c.T * TetQueryLanes<true>::n, kBlock), kBlock, 0, s>>>(d, c, alpha);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_local_debug(const Dev<R>& d, const Consts& c, const R* alpha, const R* x, R* targets,
                               hipStream_t s) {
   k_local_debug<R><<<cdiv(c.T, kBlock), kBlock, 0, s>>>(d, c, alpha, x, targets);
@@ -91,6 +118,8 @@ hipError_t launch_local_debug(const Dev<R>& d, const Consts& c, const R* alpha, 
 
 template hipError_t launch_local<float>(const Dev<float>&, const Consts&, const float*, hipStream_t);
 template hipError_t launch_local<double>(const Dev<double>&, const Consts&, const double*, hipStream_t);
+template hipError_t launch_query_local<float>(const Dev<float>&, const Consts&, const float*, hipStream_t);
+template hipError_t launch_query_local<double>(const Dev<double>&, const Consts&, const double*, hipStream_t);
 template hipError_t launch_local_debug<float>(const Dev<float>&, const Consts&, const float*, const float*, float*,
                                               hipStream_t);
 template hipError_t launch_local_debug<double>(const Dev<double>&, const Consts&, const double*, const double*,

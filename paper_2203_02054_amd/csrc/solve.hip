@@ -21,14 +21,9 @@
 // block, so all blocks take identical decisions.
 #include <algorithm>
 
-#include "device_common.h"
+#include "gather.h"
 
 namespace gs {
-
-template <typename R>
-struct alignas(4 * sizeof(R)) W4 {
-  R x, y, z, w;
-};
 
 // Start of a solve: u from the warm start (fixed vertices reset), collision
 // positions, cleared hash counters and status.
@@ -118,56 +113,14 @@ __global__ __launch_bounds__(kBlock) void k_output(Dev<R> d, Consts c, R* __rest
   for (int k = 0; k < 3; ++k) xout[k * n + v] = (R)(d.X0[k * n + v] + (double)d.u[k * n + v]);
 }
 
-// Right-hand side of the correction system per vertex: the element residual
-// columns (deterministic gather in incidence order) plus spring pulls; the
-// Jacobi diagonal; the spring part of Eq. (9).
+// Right-hand side of the correction system per vertex (gather_row), and the
+// block partials of the spring energy.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_gather(Dev<R> d, Consts c) {
   __shared__ double lds[kBlock / 64];
   if (is_done(d.st)) return;
   const int v = blockIdx.x * kBlock + threadIdx.x;
-  const size_t n = (size_t)c.n;
-  double esp = 0.0;
-  if (v < c.n) {
-    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-    const W4<R>* res = reinterpret_cast<const W4<R>*>(d.res4);
-    const int i1 = d.inc_start[v + 1];
-    for (int i = d.inc_start[v]; i < i1; ++i) {
-      const W4<R> t = res[i];
-      r0 += (double)t.x;
-      r1 += (double)t.y;
-      r2 += (double)t.z;
-    }
-    double ds = 0.0;
-    const bool frozen = mesh_frozen(d, c.mask_done, d.vmesh[v]);
-    if (!d.freem[v] || frozen) {
-      r0 = r1 = r2 = 0.0;
-    } else {
-      const int s = d.vq[v];
-      if (s >= 0) {
-        const double x0 = d.xc[v], x1 = d.xc[n + v], x2 = d.xc[2 * n + v];
-        const double k = d.kq[s];
-        for (int sl = 0; sl < c.slots; ++sl) {
-          const int b = s * c.slots + sl;
-          if (!d.cact[b]) continue;
-          const double e0 = d.ctgt[3 * b] - x0, e1 = d.ctgt[3 * b + 1] - x1, e2 = d.ctgt[3 * b + 2] - x2;
-          ds += k;
-          r0 += k * e0;
-          r1 += k * e1;
-          r2 += k * e2;
-          esp += k * (e0 * e0 + e1 * e1 + e2 * e2);
-        }
-      }
-    }
-    W4<R> rb;
-    rb.x = (R)r0;
-    rb.y = (R)r1;
-    rb.z = (R)r2;
-    rb.w = R(0);
-    reinterpret_cast<W4<R>*>(d.cg)[3 * (size_t)v] = rb;
-    d.dsp[v] = (R)ds;
-    d.dg[v] = d.freem[v] ? (R)((double)d.adiag[v] + ds) : R(1);
-  }
+  const double esp = v < c.n ? gather_row(d, c, v) : 0.0;
   const double bs = block_sum<kBlock>(esp, lds);
   if (threadIdx.x == 0) d.part_b[blockIdx.x] = bs;
 }

@@ -132,9 +132,7 @@ __device__ __forceinline__ R det3(const R (&A)[3][3]) {
 }
 
 template <typename R>
-struct alignas(4 * sizeof(R)) V4 {
-  R x, y, z, w;
-};
+using V4 = W4<R>;
 
 // Target shape of one tet.  P: centred rest shape, D: centred current shape,
 // Dminv: inverse rest edge matrix, vol: rest volume.
