@@ -20,6 +20,7 @@
 // accumulated in double; block partials are summed in block order by every
 // block, so all blocks take identical decisions.
 #include <algorithm>
+#include <type_traits>
 
 #include "gather.h"
 
@@ -386,8 +387,9 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
 template <typename R> struct Chunk { static constexpr int n = 16; };
 template <> struct Chunk<double> { static constexpr int n = 4; };
 
-template <typename R, int MW, bool ADJ>
+template <typename R, int MW, bool ADJ, bool PAIR>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
+  static_assert(!PAIR || (std::is_same<R, float>::value && MW == 16), "paired lanes: FP32, ELL width 16");
   constexpr int CH = Chunk<R>::n;
   __shared__ double lds[kPcgBlock / 64];
   __shared__ double lds2[2][kPcgBlock / 64];
@@ -401,6 +403,13 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // the rows spread over all G blocks however many rows a thread gets
   const int chunk = ((c.n + G - 1) / G + 63) & ~63;
   const int row0 = min(c.n, (int)blockIdx.x * chunk), row1 = min(c.n, row0 + chunk);
+  if (PAIR && 2 * chunk > kPcgBlock) {
+    // launched for a grid with more rows per block than lane pairs (the host
+    // chooses the variant from the same formula): refuse, uniformly
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      __hip_atomic_store(&d.st->done, (int)BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
   unsigned* bc = &d.st->bar_count;
   unsigned bar_target = 0;  // arrivals the next grid barrier waits for
   W4<R>* __restrict__ x = reinterpret_cast<W4<R>*>(d.dl);
@@ -660,6 +669,111 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     run = false;
   }
   double al = run ? gam / del : 0.0, be = 0.0;
+  // End of an iteration after its row work: block partials, the grid
+  // barrier, the grid sums and the next step lengths; false ends the solve.
+  auto next_step = [&](double ag, double ad) -> bool {
+    // partial sums alternate halves so a slow block still reading the previous
+    // iteration's sums is never overwritten
+    const int half = (it & 1) ? 0 : G;
+    block_sum2_store(ag, ad, lds2, d.part_c + half + blockIdx.x, d.part_e + half + blockIdx.x);
+    grid_barrier(bc, bar_target, G);
+    double gn, dn;
+    grid_sum2<false>(d.part_c + half, d.part_e + half, G, sh + 2 * (it & 1), gn, dn);
+    ++it;
+    cur ^= 1;
+    if (!(gn >= 0.0) || isinf(gn) || !(dn == dn) || isinf(dn)) {
+      broke = true;
+      return false;
+    }
+    if (gn <= stop) return false;
+    const double bn = gn / gam;
+    const double den = dn - bn * gn / al;
+    if (!(den > 0.0)) {
+      broke = true;
+      return false;
+    }
+    al = gn / den;
+    be = bn;
+    gam = gn;
+    return true;
+  };
+  // PAIR (FP32, ELL width 16, at most kPcgBlock / 2 rows per block):
+  // lanes 2i and 2i+1 share row row0 + i, each gathering 8 of its 16
+  // neighbour slots, and the row's own state (r, w, s, p, x, 1/dg) and its
+  // lane's ELL columns and scaled values stay in registers through the
+  // iterations.  An iteration then has one level of dependent memory reads
+  // (the neighbours' r, w, s) instead of two.
+  if constexpr (PAIR) {
+    {
+      const int pv_row = row0 + (int)(threadIdx.x >> 1), pv_half = (int)(threadIdx.x & 1);
+      const bool pv_has = pv_row < row1;
+      int pj[8];
+      R pa[8];
+      W4<R> prc, pwc, psc, ppv, pxv;
+      R pidg = R(0);
+      if (pv_has) {
+        const W4<R>* cs = cg0 + cur * 3 * n;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          pj[k] = ecol[(size_t)(8 * pv_half + k) * n + pv_row];
+          pa[k] = evs[(size_t)(8 * pv_half + k) * n + pv_row];
+        }
+        prc = cs[3 * (size_t)pv_row];
+        pwc = cs[3 * (size_t)pv_row + 1];
+        psc = cs[3 * (size_t)pv_row + 2];
+        ppv = p[pv_row];
+        pxv = x[pv_row];
+        pidg = R(1) / dg[pv_row];
+      }
+      while (run && it < c.pcg_max) {
+        const W4<R>* cs = cg0 + cur * 3 * n;
+        W4<R>* ns = cg0 + (cur ^ 1) * 3 * n;
+        const R ra = (R)al, rb = (R)be;
+        acc_g = 0.0;
+        acc_d = 0.0;
+        if (pv_has) {
+          const W4<R> pv = w4<R>(prc.x * pidg + rb * ppv.x, prc.y * pidg + rb * ppv.y, prc.z * pidg + rb * ppv.z);
+          const W4<R> sv = w4<R>(pwc.x + rb * psc.x, pwc.y + rb * psc.y, pwc.z + rb * psc.z);
+          const W4<R> rv = w4<R>(prc.x - ra * sv.x, prc.y - ra * sv.y, prc.z - ra * sv.z);
+          ppv = pv;
+          pxv = w4<R>(pxv.x + ra * pv.x, pxv.y + ra * pv.y, pxv.z + ra * pv.z);
+          W4<R> nr[8], nw[8], nsv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const size_t b3 = 3 * (size_t)pj[k];
+            nr[k] = cs[b3];
+            nw[k] = cs[b3 + 1];
+            nsv[k] = cs[b3 + 2];
+          }
+          R a0 = R(0), a1 = R(0), a2 = R(0);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            a0 += pa[k] * (nr[k].x - ra * (nw[k].x + rb * nsv[k].x));
+            a1 += pa[k] * (nr[k].y - ra * (nw[k].y + rb * nsv[k].y));
+            a2 += pa[k] * (nr[k].z - ra * (nw[k].z + rb * nsv[k].z));
+          }
+          // both lanes form (own term) + (slots 0-7) + (slots 8-15) in that order
+          const R b0 = __shfl_xor(a0, 1, 64), b1 = __shfl_xor(a1, 1, 64), b2 = __shfl_xor(a2, 1, 64);
+          const W4<R> wn = pv_half == 0 ? w4<R>(rv.x + a0 + b0, rv.y + a1 + b1, rv.z + a2 + b2)
+                                        : w4<R>(rv.x + b0 + a0, rv.y + b1 + a1, rv.z + b2 + a2);
+          if (pv_half == 0) {
+            ns[3 * (size_t)pv_row] = rv;
+            ns[3 * (size_t)pv_row + 1] = wn;
+            ns[3 * (size_t)pv_row + 2] = sv;
+            const R u0 = rv.x * pidg, u1 = rv.y * pidg, u2 = rv.z * pidg;
+            acc_g = ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
+            acc_d = ((double)wn.x * u0 + (double)wn.y * u1) + (double)wn.z * u2;
+          }
+          prc = rv;
+          pwc = wn;
+          psc = sv;
+        }
+        if (!next_step(acc_g, acc_d)) break;
+      }
+      if (pv_has && pv_half == 0) x[pv_row] = pxv;
+    }
+  }
+  if constexpr (!PAIR)
   while (run && it < c.pcg_max) {
     const W4<R>* cs = cg0 + cur * 3 * n;
     W4<R>* ns = cg0 + (cur ^ 1) * 3 * n;
@@ -708,29 +822,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
       acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
     }
-    // partial sums alternate halves so a slow block still reading the previous
-    // iteration's sums is never overwritten
-    const int half = (it & 1) ? 0 : G;
-    block_sum2_store(acc_g, acc_d, lds2, d.part_c + half + blockIdx.x, d.part_e + half + blockIdx.x);
-    grid_barrier(bc, bar_target, G);
-    double gn, dn;
-    grid_sum2<false>(d.part_c + half, d.part_e + half, G, sh + 2 * (it & 1), gn, dn);
-    ++it;
-    cur ^= 1;
-    if (!(gn >= 0.0) || isinf(gn) || !(dn == dn) || isinf(dn)) {
-      broke = true;
-      break;
-    }
-    if (gn <= stop) break;
-    const double bn = gn / gam;
-    const double den = dn - bn * gn / al;
-    if (!(den > 0.0)) {
-      broke = true;
-      break;
-    }
-    al = gn / den;
-    be = bn;
-    gam = gn;
+    if (!next_step(acc_g, acc_d)) break;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.st->pcg_total += it;
@@ -774,36 +866,48 @@ hipError_t launch_gather(const Dev<R>& d, const Consts& c, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Rows per block of the CG kernel for n rows on a grid of G blocks (a
+// multiple of 64; the kernel derives the same value).
+inline int pcg_chunk(int n, int G) { return (cdiv(n, G) + 63) & ~63; }
+
+// The CG kernel for a matrix of ELL width ell_w; pair selects the
+// paired-lane variant (FP32, width 16 only).
+template <typename R>
+const void* pcg_kernel(int ell_w, bool adjoint, bool pair) {
+  if constexpr (std::is_same<R, float>::value) {
+    if (pair && ell_w <= 16) return adjoint ? (const void*)k_pcg<R, 16, true, true> : (const void*)k_pcg<R, 16, false, true>;
+  }
+  if (adjoint)
+    return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false>
+                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false> : (const void*)k_pcg<R, 64, true, false>;
+  return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false>
+                     : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false> : (const void*)k_pcg<R, 64, false, false>;
+}
+
 template <typename R>
 hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint) {
   void* args[] = {(void*)&d, (void*)&c};
-  const void* f;
-  if (adjoint)
-    f = c.ell_w <= 16 ? (const void*)k_pcg<R, 16, true>
-                      : c.ell_w <= 32 ? (const void*)k_pcg<R, 32, true> : (const void*)k_pcg<R, 64, true>;
-  else
-    f = c.ell_w <= 16 ? (const void*)k_pcg<R, 16, false>
-                      : c.ell_w <= 32 ? (const void*)k_pcg<R, 32, false> : (const void*)k_pcg<R, 64, false>;
-  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
+  const bool pair = std::is_same<R, float>::value && c.ell_w <= 16 && 2 * pcg_chunk(c.n, grid) <= kPcgBlock;
+  return hipLaunchCooperativeKernel(pcg_kernel<R>(c.ell_w, adjoint, pair), dim3(grid), dim3(kPcgBlock), args, 0, s);
 }
 
 
 // Workgroups of the CG kernel that can be resident at once for a matrix of
-// ELL width ell_w: the smaller occupancy of its forward and adjoint variants
-// times the compute units (0 on a runtime error).
+// ELL width ell_w: the smallest occupancy of its variants times the compute
+// units (0 on a runtime error).
 template <typename R>
 int pcg_max_grid(int ell_w) {
-  const void* f = ell_w <= 16 ? (const void*)k_pcg<R, 16, false>
-                              : ell_w <= 32 ? (const void*)k_pcg<R, 32, false> : (const void*)k_pcg<R, 64, false>;
-  const void* a = ell_w <= 16 ? (const void*)k_pcg<R, 16, true>
-                              : ell_w <= 32 ? (const void*)k_pcg<R, 32, true> : (const void*)k_pcg<R, 64, true>;
-  int of = 0, oa = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&of, f, kPcgBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&oa, a, kPcgBlock, 0) != hipSuccess)
-    return 0;
+  int occ = 1 << 30, dev = 0, cus = 0;
+  for (int v = 0; v < 4; ++v) {
+    int o = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, pcg_kernel<R>(ell_w, v & 1, v >> 1), kPcgBlock, 0) !=
+        hipSuccess)
+      return 0;
+    occ = std::min(occ, o);
+  }
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  return std::min(of, oa) * cus;
+  return occ * cus;
 }
 
 #define INST(R)                                                                                  \
