@@ -134,6 +134,7 @@ struct gs_problem {
   bool bound = false;
   Layout lay{};
   int pcg_grid = 1;
+  int pcg_maxg = 0;  // CG workgroups that can be resident at once
   int trace_len = 0;
   int last_iters = 0;
   bool solved = false;  // a solve has run since gs_bind (the adjoint's state exists)
@@ -445,9 +446,17 @@ gs_status bind_impl(gs_problem* p) {
   HIPCHK(hipStreamSynchronize(s));
   const int maxg = pcg_max_grid<R>(p->ell_w);
   if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
+  p->pcg_maxg = maxg;
   p->pcg_grid = pcg_grid_for(p, maxg);
   return GS_OK;
 }
+
+// The CG kernel's grid barrier needs every workgroup resident at once.  A
+// grid of at most half of what can be resident gets an ordinary launch (on
+// an otherwise idle device every workgroup is placed at once, and work of
+// other streams only delays some of them, it cannot hold them off for
+// good); a larger one the cooperative launch, which guarantees it.
+bool pcg_cooperative(const gs_problem* p) { return 2 * p->pcg_grid > p->pcg_maxg; }
 
 // Launch one kernel, bracketed by timing events when profiling is on.
 template <typename F>
@@ -524,7 +533,7 @@ hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, co
   else
     e = timed(p, K_GATHER, [&] { return launch_gather<R>(d, c, s); });
   if (e != hipSuccess) return e;
-  return timed(p, K_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s); });
+  return timed(p, K_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, false, pcg_cooperative(p)); });
 }
 
 template <typename R>
@@ -587,7 +596,7 @@ gs_status adjoint_impl(gs_problem* p, const R* gL, R* dalpha, R* mu_out, gs_stat
     if ((e = timed(p, K_ADJ_SPRINGS, [&] { return launch_adj_springs<R>(d, c, s); })) != hipSuccess) return e;
     if ((e = timed(p, K_ADJ_LOCAL, [&] { return launch_adj_local<R>(d, c, false, s); })) != hipSuccess) return e;
     if ((e = timed(p, K_ADJ_GATHER, [&] { return launch_adj_gather<R>(d, c, s); })) != hipSuccess) return e;
-    if ((e = timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, true); })) != hipSuccess) return e;
+    if ((e = timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, true, pcg_cooperative(p)); })) != hipSuccess) return e;
     return launch_adj_anderson<R>(d, c, s);
   };
   const gs_status ds = drive(p, d.st, c.max_iter, one, h);
@@ -1141,7 +1150,7 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
       HIPCHK(copy_record(p, seg + (size_t)(k + 1 - k0) * RL.bytes, false, false, true));
       HIPCHK(launch_unr_restore<R>(d, cf, run, s));
       HIPCHK(launch_unr_rhs<R>(dc, cc, s));
-      HIPCHK(timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(dc, cc, p->pcg_grid, s, true); }));
+      HIPCHK(timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(dc, cc, p->pcg_grid, s, true, pcg_cooperative(p)); }));
       HIPCHK(timed(p, K_ADJ_SPRINGS, [&] { return launch_adj_springs<R>(dv, cv, s); }));
       HIPCHK(timed(p, K_ADJ_LOCAL, [&] { return launch_adj_local_mode<R>(dv, cv, ADJ_JT, s); }));
       HIPCHK(timed(p, K_ADJ_GATHER, [&] { return launch_adj_gather<R>(dv, cv, s); }));
@@ -1405,6 +1414,8 @@ gs_status gs_set_params(gs_problem* p, const gs_params* prm) {
   }
   if (p->bound) {
     const int maxg = p->prec == 4 ? pcg_max_grid<float>(p->ell_w) : pcg_max_grid<double>(p->ell_w);
+    if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
+    p->pcg_maxg = maxg;
     p->pcg_grid = pcg_grid_for(p, maxg);
     HIPCHK(hipStreamSynchronize(p->stream));
   }
@@ -1449,6 +1460,7 @@ gs_status gs_autotune(gs_problem* p, const void* alpha, void* x, int32_t iters, 
   };
   const int maxg = p->prec == 4 ? pcg_max_grid<float>(p->ell_w) : pcg_max_grid<double>(p->ell_w);
   if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
+  p->pcg_maxg = maxg;
   const gs_params saved = p->prm;
   const bool prof = p->prof.on;
   p->prof.on = false;

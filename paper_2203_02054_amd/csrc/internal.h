@@ -175,7 +175,7 @@ template <typename R> hipError_t launch_local_debug(const Dev<R>& d, const Const
                                                     R* targets, hipStream_t s);
 template <typename R> hipError_t launch_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R>
-hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint = false);
+hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint, bool cooperative);
 // implicit adjoint
 template <typename R> hipError_t launch_adj_init(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_adj_springs(const Dev<R>& d, const Consts& c, hipStream_t s);

@@ -885,10 +885,12 @@ const void* pcg_kernel(int ell_w, bool adjoint, bool pair) {
 }
 
 template <typename R>
-hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint) {
+hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint, bool cooperative) {
   void* args[] = {(void*)&d, (void*)&c};
   const bool pair = std::is_same<R, float>::value && c.ell_w <= 16 && 2 * pcg_chunk(c.n, grid) <= kPcgBlock;
-  return hipLaunchCooperativeKernel(pcg_kernel<R>(c.ell_w, adjoint, pair), dim3(grid), dim3(kPcgBlock), args, 0, s);
+  const void* f = pcg_kernel<R>(c.ell_w, adjoint, pair);
+  if (cooperative) return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
+  return hipLaunchKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
 }
 
 
@@ -915,7 +917,7 @@ int pcg_max_grid(int ell_w) {
   template hipError_t launch_set_positions<R>(const Dev<R>&, const Consts&, const R*, hipStream_t); \
   template hipError_t launch_output<R>(const Dev<R>&, const Consts&, R*, hipStream_t);          \
   template hipError_t launch_gather<R>(const Dev<R>&, const Consts&, hipStream_t);              \
-  template hipError_t launch_pcg<R>(const Dev<R>&, const Consts&, int, hipStream_t, bool);      \
+  template hipError_t launch_pcg<R>(const Dev<R>&, const Consts&, int, hipStream_t, bool, bool); \
   template int pcg_max_grid<R>(int);
 INST(float)
 INST(double)
