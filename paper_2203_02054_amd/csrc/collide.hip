@@ -56,18 +56,20 @@ __global__ __launch_bounds__(kBlock) void k_tet_query(Dev<R> d, Consts c) {
   tet_query_lane<R, DEBUG, PREFETCH>(d, c, blockIdx.x * kBlock + threadIdx.x);
 }
 
-// One wavefront per penetrating vertex: vertex normal, then the first hit of
-// [x_v, x_v - L_ray n_v] on a boundary face not containing v.
+// One workgroup per penetrating vertex: vertex normal, then the first hit of
+// [x_v, x_v - L_ray n_v] on a boundary face of its mesh not containing v, the
+// faces split over the workgroup's lanes and the first hit (smallest t, ties
+// to the lowest face id) reduced through the wavefronts and LDS.
 template <typename R, bool DEBUG>
 __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
+  __shared__ double sh_t[kBlock / 64];
+  __shared__ int sh_f[kBlock / 64];
   if (is_done(d.st)) return;
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * kBlock) >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int npen = __hip_atomic_load(&d.st->n_pen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const size_t n = (size_t)c.n;
   const int F = c.F;
-  for (int i = wave; i < npen; i += nwaves) {
+  for (int i = blockIdx.x; i < npen; i += gridDim.x) {
     const int s = d.penlist[i];
     const int v = d.qverts[s];
     const MeshConst mc = d.mesh[d.vmesh[v]];
@@ -92,8 +94,8 @@ __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
     {
       len = sqrt((acc[0] * acc[0] + acc[1] * acc[1]) + acc[2] * acc[2]);
     }
-    if (!(len > 0.0)) {
-      if (lane == 0) d.fhit[s] = -1;
+    if (!(len > 0.0)) {  // the same for every thread of the block
+      if (threadIdx.x == 0) d.fhit[s] = -1;
       continue;
     }
     double o[3], dir[3], end[3], slo[3], shi[3];
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
     }
     double best_t = INFINITY;
     int best_f = INT_MAX;
-    for (int f = mc.fbeg + lane; f < mc.fend; f += 64) {
+    for (int f = mc.fbeg + (int)threadIdx.x; f < mc.fend; f += kBlock) {
       const int i0 = d.faces[f], i1 = d.faces[F + f], i2 = d.faces[2 * F + f];
       if (i0 == v || i1 == v || i2 == v) continue;
       double a0[3], a1[3], a2[3];
@@ -148,6 +150,16 @@ __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
       }
     }
     if (lane == 0) {
+      sh_t[wv] = best_t;
+      sh_f[wv] = best_f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < kBlock / 64; ++w)
+        if (sh_t[w] < best_t || (sh_t[w] == best_t && sh_f[w] < best_f)) {
+          best_t = sh_t[w];
+          best_f = sh_f[w];
+        }
       if (best_f == INT_MAX) {
         d.fhit[s] = -1;
       } else {
@@ -167,6 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
         for (int k = 0; k < 3; ++k) d.fn[3 * s + k] = cr[k] / ln;
       }
     }
+    __syncthreads();  // sh_t / sh_f are reused by the next vertex
   }
 }
 
@@ -318,8 +331,8 @@ hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, boo
         k_tet_query<R, false, false><<<gt, kBlock, 0, s>>>(d, c);
       break;
     case STAGE_RAY: {
-      // one wavefront per penetrating vertex on the first pass (up to 8192)
-      const int gr = max(1, min(cdiv(c.S, kBlock / 64), 2048));
+      // one workgroup per penetrating vertex on the first pass (up to 2048)
+      const int gr = max(1, min(c.S, 2048));
       if (debug)
         k_ray<R, true><<<gr, kBlock, 0, s>>>(d, c);
       else
