@@ -175,6 +175,50 @@ __device__ __forceinline__ void block_sum2_store(double a, double b, double (*ld
   }
 }
 
+// Block sums of K values in one LDS round, stored by thread 0 to out[i]
+// (the per-wave order and fixed tree of block_sum; no closing __syncthreads,
+// the caller's grid barrier starts with one).
+template <int K>
+__device__ __forceinline__ void block_sums_store(const double (&v)[K], double (*lds)[kPcgBlock / 64],
+                                                 double* const (&out)[K]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const double t = wave_sum(v[i]);
+    if (lane == 0) lds[i][w] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+    if ((int)threadIdx.x == i) {  // static indices: no private-memory array
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < kPcgBlock / 64; ++j) t += lds[i][j];
+      *out[i] = t;
+    }
+}
+
+// Sums of the G block partials of K <= kPcgBlock / 64 arrays in one round:
+// wavefront i reduces array i in grid_sum2's order; every block obtains the
+// same bits.
+template <int K>
+__device__ __forceinline__ void grid_sums(const double* const (&src)[K], int G, double* sh, double (&out)[K]) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (w < K) {
+    const double* a = src[0];
+#pragma unroll
+    for (int i = 1; i < K; ++i)
+      if (w == i) a = src[i];  // static indices: no private-memory array
+    double t = (l < G) ? a[l] : 0.0;
+    for (int k = l + 64; k < G; k += 64) t += a[k];
+    t = wave_sum(t);
+    if (l == 0) sh[w] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < K; ++i) out[i] = sh[i];
+}
+
 template <typename R>
 __device__ __forceinline__ W4<R> w4(R x, R y, R z) {
   W4<R> o;
@@ -339,11 +383,29 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
     d.mres[mi] = 0ull;
     if (!ADJ) d.mchanged[mi] = 0;
   }
-  const double E = block_sum<kPcgBlock>(eloc, lds);
-  const double res = block_max<kPcgBlock>(rloc, lds);
-  const double n_act = block_sum<kPcgBlock>(active, lds);
-  const double nbad = block_sum<kPcgBlock>(bad, lds);
+  // the four block reductions in one LDS round (per-wave order and fixed tree
+  // of block_sum / block_max)
+  __shared__ double lds4[4][kPcgBlock / 64];
+  {
+    const double a = wave_sum(eloc), b = wave_max(rloc), e = wave_sum(active), f = wave_sum(bad);
+    if ((threadIdx.x & 63) == 0) {
+      const int w = threadIdx.x >> 6;
+      lds4[0][w] = a;
+      lds4[1][w] = b;
+      lds4[2][w] = e;
+      lds4[3][w] = f;
+    }
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  double E = 0.0, res = 0.0, n_act = 0.0, nbad = 0.0;
+#pragma unroll
+  for (int i = 0; i < kPcgBlock / 64; ++i) {
+    E += lds4[0][i];
+    res = fmax(res, lds4[1][i]);
+    n_act += lds4[2][i];
+    nbad += lds4[3][i];
+  }
   st->residual = res;
   st->energy = E;
   st->iters = it;
@@ -392,8 +454,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   static_assert(!PAIR || (std::is_same<R, float>::value && MW == 16), "paired lanes: FP32, ELL width 16");
   constexpr int CH = Chunk<R>::n;
   __shared__ double lds[kPcgBlock / 64];
-  __shared__ double lds2[2][kPcgBlock / 64];
-  __shared__ double sh[4];
+  __shared__ double lds2[6][kPcgBlock / 64];
+  __shared__ double sh[8];
   if (is_done(d.st)) return;
   const int G = gridDim.x;
   const int stride = G * kPcgBlock;
@@ -557,23 +619,22 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         h22 += t22;
       }
     }
-    const double bs = block_sum<kPcgBlock>(acc_b, lds);
-    if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
     double g1 = 0.0, g2 = 0.0;
     if (c.M == 1) {
-      const double q[5] = {e1, e2, h11, h12, h22};
-#pragma unroll
-      for (int i = 0; i < 5; ++i) {
-        const double t = block_sum<kPcgBlock>(q[i], lds);
-        if (threadIdx.x == 0) d.part_c[(2 + i) * G + blockIdx.x] = t;
-      }
+      const double q[6] = {e1, e2, h11, h12, h22, acc_b};
+      double* const dst[6] = {d.part_c + 2 * G + blockIdx.x, d.part_c + 3 * G + blockIdx.x,
+                              d.part_c + 4 * G + blockIdx.x, d.part_c + 5 * G + blockIdx.x,
+                              d.part_c + 6 * G + blockIdx.x, d.part_d + blockIdx.x};
+      block_sums_store<6>(q, lds2, dst);
       grid_barrier(bc, bar_target, G);
-      double E1, E2, H11, H12, H22, dummy;
-      grid_sum2(d.part_c + 2 * G, d.part_c + 3 * G, G, sh, E1, E2);
-      grid_sum2(d.part_c + 4 * G, d.part_c + 5 * G, G, sh, H11, H12);
-      grid_sum2(d.part_c + 6 * G, d.part_c + 6 * G, G, sh, H22, dummy);
-      galerkin_weights(E1, E2, H11, H12, H22, g1, g2);  // every block takes the same decision
+      const double* const src[5] = {d.part_c + 2 * G, d.part_c + 3 * G, d.part_c + 4 * G, d.part_c + 5 * G,
+                                    d.part_c + 6 * G};
+      double S[5];
+      grid_sums<5>(src, G, sh, S);
+      galerkin_weights(S[0], S[1], S[2], S[3], S[4], g1, g2);  // every block takes the same decision
     } else {
+      const double bs = block_sum<kPcgBlock>(acc_b, lds);
+      if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
       // a batch: each mesh gets its own weights (the meshes' systems are
       // independent), its sums taken by one block in a fixed order
       grid_barrier(bc, bar_target, G);
@@ -652,14 +713,17 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     }
     cur = 1;
   }
-  double bs = block_sum<kPcgBlock>(acc_g, lds);
-  if (threadIdx.x == 0) d.part_c[blockIdx.x] = bs;
-  bs = block_sum<kPcgBlock>(acc_d, lds);
-  if (threadIdx.x == 0) d.part_e[blockIdx.x] = bs;
+  block_sum2_store(acc_g, acc_d, lds2, d.part_c + blockIdx.x, d.part_e + blockIdx.x);
   grid_barrier(bc, bar_target, G);
-  double gam, del, rhs, dummy;
-  grid_sum2(d.part_c, d.part_e, G, sh, gam, del);
-  grid_sum2(d.part_d, d.part_d, G, sh, rhs, dummy);
+  double gam, del, rhs;
+  {
+    const double* const src[3] = {d.part_c, d.part_e, d.part_d};
+    double S[3];
+    grid_sums<3>(src, G, sh, S);
+    gam = S[0];
+    del = S[1];
+    rhs = S[2];
+  }
   const double stop = c.pcg_eta * c.pcg_eta * rhs;
   int it = 0;
   bool broke = !(rhs >= 0.0) || isinf(rhs) || !(gam >= 0.0) || isinf(gam);
