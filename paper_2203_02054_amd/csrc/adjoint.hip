@@ -512,14 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_gather(Dev<R> d, Consts c) {
   if (v >= c.n) return;
   const size_t n = (size_t)c.n;
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-  const V4<R>* res = reinterpret_cast<const V4<R>*>(d.res4);
-  const int i1 = d.inc_start[v + 1];
-  for (int i = d.inc_start[v]; i < i1; ++i) {
-    const V4<R> t = res[i];
-    r0 += (double)t.x;
-    r1 += (double)t.y;
-    r2 += (double)t.z;
-  }
+  sum_columns(reinterpret_cast<const W4<R>*>(d.res4), d.inc_start[v], d.inc_start[v + 1], r0, r1, r2);
   r0 += d.acc3[v];
   r1 += d.acc3[n + v];
   r2 += d.acc3[2 * n + v];
@@ -799,6 +792,9 @@ __global__ __launch_bounds__(kBlock) void k_unr_restore(Dev<R> d, Consts c, DevS
 #pragma unroll
     for (int k = 0; k < 3; ++k) d.xc[k * n + v] = d.X0[k * n + v] + (double)d.u[k * n + v];
   }
+  // the spatial hash held other positions: cleared, refilled before the next
+  // iteration's tet query
+  for (int i = v; i < c.H; i += gridDim.x * kBlock) d.hcount[i] = 0;
   if (v == 0) {
     DevStatus* st = d.st;
     st->done = RUNNING;
@@ -883,7 +879,7 @@ hipError_t launch_adj_init(const Dev<R>& d, const Consts& c, hipStream_t s) {
 template <typename R>
 hipError_t launch_adj_springs(const Dev<R>& d, const Consts& c, hipStream_t s) {
   if (!c.self_col || c.S == 0) return hipSuccess;
-  k_adj_springs<R><<<cdiv(c.S, kBlock), kBlock, 0, s>>>(d, c);
+  k_adj_springs<R><<<max(1, cdiv(c.S, kBlock)), kBlock, 0, s>>>(d, c);
   return hipGetLastError();
 }
 template <typename R>
@@ -904,7 +900,7 @@ hipError_t launch_adj_gather(const Dev<R>& d, const Consts& c, hipStream_t s) {
 template <typename R>
 hipError_t launch_adj_chamber_sum(const Dev<R>& d, const Consts& c, R* out, hipStream_t s) {
   if (c.nch == 0) return hipSuccess;
-  k_adj_chamber_sum<R><<<c.nch, kBlock, 0, s>>>(d, c, out);
+  k_adj_chamber_sum<R><<<max(1, c.nch), kBlock, 0, s>>>(d, c, out);
   return hipGetLastError();
 }
 
@@ -921,7 +917,7 @@ hipError_t launch_unr_rhs(const Dev<R>& d, const Consts& c, hipStream_t s) {
 template <typename R>
 hipError_t launch_unr_accumulate(const Dev<R>& d, const Consts& c, hipStream_t s) {
   if (c.nch == 0) return hipSuccess;
-  k_unr_accumulate<R><<<c.nch, kBlock, 0, s>>>(d, c);
+  k_unr_accumulate<R><<<max(1, c.nch), kBlock, 0, s>>>(d, c);
   return hipGetLastError();
 }
 template <typename R>

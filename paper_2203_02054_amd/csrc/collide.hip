@@ -21,10 +21,10 @@
 
 namespace gs {
 
-// Insert every query vertex into the bucket of its cell.  A bucket keeps its
-// first kHashCap entries; further entries go to an overflow list that every
-// tet scans, so no candidate is ever lost.  Entries carry the position, so a
-// candidate costs one 32-byte read.
+// Insert every query vertex into the bucket of its cell (the first iteration
+// after positions were set; later iterations insert in the CG kernel's final
+// update).  A bucket keeps its first kHashCap entries; further entries go to
+// an overflow list that every tet scans, so no candidate is ever lost.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_hash_insert(Dev<R> d, Consts c) {
   if (is_done(d.st)) return;
@@ -33,21 +33,7 @@ __global__ __launch_bounds__(kBlock) void k_hash_insert(Dev<R> d, Consts c) {
   const int v = d.qverts[s];
   const int m = d.vmesh[v];
   if (mesh_frozen(d, c.mask_done, m)) return;
-  const double ic = d.mesh[m].inv_cell;
-  double4 e;
-  e.x = d.xc[v];
-  e.y = d.xc[(size_t)c.n + v];
-  e.z = d.xc[2 * (size_t)c.n + v];
-  e.w = __longlong_as_double((long long)(((unsigned long long)(unsigned)v << 32) | (unsigned)s));
-  if (!(fabs(e.x * ic) < 1e9 && fabs(e.y * ic) < 1e9 && fabs(e.z * ic) < 1e9)) return;  // diverged iterate
-  const int key = hash_cell(cell_of(e.x, ic), cell_of(e.y, ic), cell_of(e.z, ic), m, c.H);
-  const int slot = atomicAdd(&d.hcount[key], 1);
-  if (slot < kHashCap) {
-    reinterpret_cast<double4*>(d.hslot)[(size_t)key * kHashCap + slot] = e;
-  } else {
-    const int o = atomicAdd(&d.st->n_over, 1);
-    reinterpret_cast<double4*>(d.hover)[o] = e;
-  }
+  hash_insert_entry(d, c, s, v, m, d.xc[v], d.xc[(size_t)c.n + v], d.xc[2 * (size_t)c.n + v]);
 }
 
 template <typename R, bool DEBUG, bool PREFETCH>
@@ -298,12 +284,19 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
 
 // Contact update and right-hand-side gather in one pass over the vertices:
 // a query vertex's thread first updates its own contact slots, then gathers
-// its row, which reads only those slots.
+// its row, which reads only those slots.  With self-collision it also clears
+// the spatial hash, which the CG kernel refills with the new positions.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_contacts_gather(Dev<R> d, Consts c) {
   __shared__ double lds[kBlock / 64];
   if (is_done(d.st)) return;
   const int v = blockIdx.x * kBlock + threadIdx.x;
+  if (c.self_col) {
+    // the iteration's tet query is done: clear the hash for the insertions of
+    // the CG kernel's final update
+    for (int i = v; i < c.H; i += gridDim.x * kBlock) d.hcount[i] = 0;
+    if (v == 0) d.st->n_over = 0;
+  }
   double esp = 0.0;
   if (v < c.n) {
     const int s = d.vq[v];
@@ -316,7 +309,8 @@ __global__ __launch_bounds__(kBlock) void k_contacts_gather(Dev<R> d, Consts c) 
 
 template <typename R>
 hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s) {
-  const int gs = cdiv(c.S, kBlock), gt = cdiv(c.T, kBlock);
+  // grids of at least one block: a mesh may have no query vertex (all fixed)
+  const int gs = max(1, cdiv(c.S, kBlock)), gt = cdiv(c.T, kBlock);
   const int gt4 = cdiv(c.T * TetQueryLanes<true>::n, kBlock);
   switch (stage) {
     case STAGE_HASH_INSERT:
@@ -347,7 +341,7 @@ hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, boo
 
 template <typename R>
 hipError_t launch_contacts(const Dev<R>& d, const Consts& c, hipStream_t s) {
-  k_contacts<R><<<cdiv(c.S, kBlock), kBlock, 0, s>>>(d, c);
+  k_contacts<R><<<max(1, cdiv(c.S, kBlock)), kBlock, 0, s>>>(d, c);
   return hipGetLastError();
 }
 

@@ -15,6 +15,31 @@ struct alignas(4 * sizeof(R)) W4 {
   R x, y, z, w;
 };
 
+// Sum of the incidence columns res[i0, i1) into double accumulators, in index
+// order; the loads are issued 8 at a time so their latencies overlap.
+template <typename R>
+__device__ __forceinline__ void sum_columns(const W4<R>* __restrict__ res, int i0, int i1, double& r0, double& r1,
+                                            double& r2) {
+  int i = i0;
+  for (; i + 8 <= i1; i += 8) {
+    W4<R> t[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = res[i + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      r0 += (double)t[k].x;
+      r1 += (double)t[k].y;
+      r2 += (double)t[k].z;
+    }
+  }
+  for (; i < i1; ++i) {
+    const W4<R> t = res[i];
+    r0 += (double)t.x;
+    r1 += (double)t.y;
+    r2 += (double)t.z;
+  }
+}
+
 // ---- reductions (64-wide wavefronts) ---------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -145,6 +170,31 @@ __device__ __forceinline__ int hash_cell(int ix, int iy, int iz, int m, int H) {
   const uint32_t h = ((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u) ^
                      ((uint32_t)m * 2654435761u);
   return (int)(h & (uint32_t)(H - 1));
+}
+
+// Inserts query vertex s (vertex v of mesh m, collision position x) into the
+// bucket of its cell; a full bucket's entry goes to the overflow list, which
+// holds S entries (one insertion per query vertex between clears).  Entries
+// carry the position, so a candidate costs one 32-byte read.  A diverged
+// position is not inserted.
+template <typename DevT>
+__device__ __forceinline__ void hash_insert_entry(const DevT& d, const Consts& c, int s, int v, int m, double x0,
+                                                  double x1, double x2) {
+  const double ic = d.mesh[m].inv_cell;
+  if (!(fabs(x0 * ic) < 1e9 && fabs(x1 * ic) < 1e9 && fabs(x2 * ic) < 1e9)) return;
+  double4 e;
+  e.x = x0;
+  e.y = x1;
+  e.z = x2;
+  e.w = __longlong_as_double((long long)(((unsigned long long)(unsigned)v << 32) | (unsigned)s));
+  const int key = hash_cell(cell_of(x0, ic), cell_of(x1, ic), cell_of(x2, ic), m, c.H);
+  const int slot = atomicAdd(&d.hcount[key], 1);
+  if (slot < kHashCap) {
+    reinterpret_cast<double4*>(d.hslot)[(size_t)key * kHashCap + slot] = e;
+  } else {
+    const int o = atomicAdd(&d.st->n_over, 1);
+    if (o < c.S) reinterpret_cast<double4*>(d.hover)[o] = e;
+  }
 }
 
 // Mesh of a vertex / tet is frozen once it has converged (batched solves).

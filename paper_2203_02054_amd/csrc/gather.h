@@ -14,14 +14,7 @@ __device__ __forceinline__ double gather_row(const Dev<R>& d, const Consts& c, i
   const size_t n = (size_t)c.n;
   double esp = 0.0;
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-  const W4<R>* res = reinterpret_cast<const W4<R>*>(d.res4);
-  const int i1 = d.inc_start[v + 1];
-  for (int i = d.inc_start[v]; i < i1; ++i) {
-    const W4<R> t = res[i];
-    r0 += (double)t.x;
-    r1 += (double)t.y;
-    r2 += (double)t.z;
-  }
+  sum_columns(reinterpret_cast<const W4<R>*>(d.res4), d.inc_start[v], d.inc_start[v + 1], r0, r1, r2);
   double ds = 0.0;
   const bool frozen = mesh_frozen(d, c.mask_done, d.vmesh[v]);
   if (!d.freem[v] || frozen) {

@@ -49,7 +49,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   size_t X0, tets, tag, inc_start, inc_pos, ell_col, ell_val, ell_scaled, adiag, freem, faces, qverts, vq, qf_start, qf_list, kq,
       obst;
-  size_t u, xc, res4, cg, dl, dlp, p, dg, dsp, pen, hcount, hslot, hover, penlist, fhit, fc, fn, cact, ctgt, cnrm,
+  size_t u, xc, res4, cg, dl, dlp, dlpp, p, dg, dsp, pen, hcount, hslot, hover, penlist, fhit, fc, fn, cact, ctgt, cnrm,
       cprim, part_a, part_b, part_c, part_d, part_e, part_f, st, trace, mesh, vmesh, tmesh, mres, mchanged, mdone;
   size_t mu, acc3, ga, ch_start, ch_tets, mmax, mdone2, st2, alpha_last, mgam;
   size_t aa_dx, aa_df, aa_xp, aa_fp, aa_h, aa_gamma, aa_part, aa_k;
@@ -135,6 +135,7 @@ struct gs_problem {
   Layout lay{};
   int pcg_grid = 1;
   int pcg_maxg = 0;  // CG workgroups that can be resident at once
+  bool hash_ready = false;  // the device hash holds the current collision positions
   int trace_len = 0;
   int last_iters = 0;
   bool solved = false;  // a solve has run since gs_bind (the adjoint's state exists)
@@ -202,6 +203,7 @@ Layout make_layout(const gs_problem* p) {
   L.cg = take(24 * n * W);
   L.dl = take(4 * n * W);
   L.dlp = take(4 * n * W);
+  L.dlpp = take(4 * n * W);
   L.p = take(4 * n * W);
   L.dg = take(n * W);
   L.dsp = take(n * W);
@@ -286,6 +288,7 @@ Dev<R> make_dev(const gs_problem* p) {
   d.cg = (R*)(b + L.cg);
   d.dl = (R*)(b + L.dl);
   d.dlp = (R*)(b + L.dlp);
+  d.dlpp = (R*)(b + L.dlpp);
   d.p = (R*)(b + L.p);
   d.dg = (R*)(b + L.dg);
   d.dsp = (R*)(b + L.dsp);
@@ -506,18 +509,24 @@ gs_status drive(gs_problem* p, const DevStatus* dstat, int limit, F&& enqueue_on
 }
 
 // One outer iteration.  Below kTetQueryWide tets the local step rides in the
-// tet-query launch (both read only the iteration's positions), and with any
-// collision the contact update rides in the gather launch: 5 launches per
-// iteration with self-collision instead of 7.
+// tet-query launch (both read only the iteration's positions); with any
+// collision the contact update rides in the gather launch; the spatial hash
+// is refilled by the CG kernel: 4 launches per iteration with self-collision
+// instead of 7.
 template <typename R>
 hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, const R* alpha) {
   hipError_t e;
   hipStream_t s = p->stream;
   const bool fused_local = c.self_col && c.T < kTetQueryWide;
   if (c.self_col) {
-    if ((e = timed(p, STAGE_HASH_INSERT,
-                   [&] { return launch_collide_stage<R>(d, c, STAGE_HASH_INSERT, false, s); })) != hipSuccess)
-      return e;
+    // after positions were set the hash is built here; afterwards the CG
+    // kernel's final update refills it (the contact/gather pass clears it)
+    if (!p->hash_ready) {
+      if ((e = timed(p, STAGE_HASH_INSERT,
+                     [&] { return launch_collide_stage<R>(d, c, STAGE_HASH_INSERT, false, s); })) != hipSuccess)
+        return e;
+      p->hash_ready = true;
+    }
     if (fused_local)
       e = timed(p, STAGE_TET_QUERY, [&] { return launch_query_local<R>(d, c, alpha, s); });
     else
@@ -544,6 +553,7 @@ gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
   if (p->nch > 0)
     HIPCHK(hipMemcpyAsync(d.alpha_last, alpha, (size_t)p->nch * sizeof(R), hipMemcpyDeviceToDevice, s));
   HIPCHK(launch_init<R>(d, c, x, s));
+  p->hash_ready = false;
   DevStatus h{};
   const int limit = p->prm.fixed_iters > 0 ? p->prm.fixed_iters : p->prm.max_iter;
   const gs_status ds = drive(p, d.st, limit, [&] { return enqueue_iteration<R>(p, d, c, alpha); }, h);
@@ -885,7 +895,7 @@ void finalize(gs_problem* p) {
   int H = 1024;
   while (H < 2 * p->S) H <<= 1;
   p->H = H;
-  p->nparts = std::max({cdiv(p->T, kBlock), cdiv(n, kBlock), 8 * kMaxPcgGrid});
+  p->nparts = std::max({cdiv(p->T, kBlock), cdiv(n, kBlock), 12 * kMaxPcgGrid});
   p->slots = 1 + p->ns + p->np;
   // chamber -> tets, ascending tet id within a chamber
   p->ch_start.assign(p->nch + 1, 0);
@@ -1024,7 +1034,7 @@ void merge(gs_problem* p, const std::vector<gs_problem*>& parts) {
 namespace {
 
 struct RecordLayout {
-  size_t u, dl, dlp, cact, ctgt, cnrm, cprim, bytes;
+  size_t u, dl, dlp, dlpp, cact, ctgt, cnrm, cprim, bytes;
 };
 
 RecordLayout record_layout(const gs_problem* p) {
@@ -1040,6 +1050,7 @@ RecordLayout record_layout(const gs_problem* p) {
   r.u = take(3 * n * W);
   r.dl = take(4 * n * W);
   r.dlp = take(4 * n * W);
+  r.dlpp = take(4 * n * W);
   r.cact = take(m);
   r.ctgt = take(3 * m * 8);
   r.cnrm = take(3 * m * 8);
@@ -1068,7 +1079,7 @@ hipError_t copy_record(gs_problem* p, char* rec, bool save, bool state, bool con
     size_t ws_off, rec_off, bytes;
     bool is_state;
   } items[] = {{L.u, R.u, 3 * n * W, true},       {L.dl, R.dl, 4 * n * W, true},
-               {L.dlp, R.dlp, 4 * n * W, true},
+               {L.dlp, R.dlp, 4 * n * W, true},         {L.dlpp, R.dlpp, 4 * n * W, true},
                {L.cact, R.cact, m, false},        {L.ctgt, R.ctgt, 3 * m * 8, false},
                {L.cnrm, R.cnrm, 3 * m * 8, false}, {L.cprim, R.cprim, m * 4, false}};
   for (const Item& it : items) {
@@ -1100,6 +1111,7 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
     HIPCHK(hipMemcpyAsync(d.alpha_last, alpha, (size_t)p->nch * sizeof(R), hipMemcpyDeviceToDevice, s));
   // forward sweep with checkpoints
   HIPCHK(launch_init<R>(d, cf, x0, s));
+  p->hash_ready = false;
   for (int k = 0; k < K; ++k) {
     if (k % C == 0) HIPCHK(copy_record(p, ck + (size_t)(k / C) * RL.bytes, true, true, true));
     HIPCHK(enqueue_iteration<R>(p, d, cf, alpha));
@@ -1139,6 +1151,7 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
     // recompute the segment from its checkpoint
     HIPCHK(copy_record(p, ck + (size_t)sg * RL.bytes, false, true, true));
     HIPCHK(launch_unr_restore<R>(d, cf, run, s));
+    p->hash_ready = false;
     for (int k = k0; k < k1; ++k) {
       HIPCHK(copy_record(p, seg + (size_t)(k - k0) * RL.bytes, true, true, true));
       HIPCHK(enqueue_iteration<R>(p, d, cf, alpha));
@@ -1149,6 +1162,7 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
       HIPCHK(copy_record(p, seg + (size_t)(k - k0) * RL.bytes, false, true, false));
       HIPCHK(copy_record(p, seg + (size_t)(k + 1 - k0) * RL.bytes, false, false, true));
       HIPCHK(launch_unr_restore<R>(d, cf, run, s));
+      p->hash_ready = false;
       HIPCHK(launch_unr_rhs<R>(dc, cc, s));
       HIPCHK(timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(dc, cc, p->pcg_grid, s, true, pcg_cooperative(p)); }));
       HIPCHK(timed(p, K_ADJ_SPRINGS, [&] { return launch_adj_springs<R>(dv, cv, s); }));
@@ -1685,6 +1699,7 @@ gs_status gs_collide_debug(gs_problem* p, const void* x, int32_t cap, void* scra
     d.dbg_tet = (int32_t*)scratch;
     d.dbg_tri = (int32_t*)scratch + 2 * (size_t)cap;
     HIPCHK(launch_set_positions<R>(d, c, (const R*)x, s));
+    p->hash_ready = false;
     if (c.self_col)
       for (int stg = 0; stg < N_COLLIDE_STAGES; ++stg) HIPCHK(launch_collide_stage<R>(d, c, stg, true, s));
     if (c.self_col || c.obst_col) HIPCHK(launch_contacts<R>(d, c, s));

@@ -104,6 +104,7 @@ struct Dev {
                            //   (each as x, y, z, pad); buffer 0 holds the right-hand side on entry
   R* dl;                   // [n][4] correction (kept across iterations: the warm start)
   R* dlp;                  // [n][4] correction of the previous outer iteration
+  R* dlpp;                 // [n][4] correction two outer iterations back
   R* p;                    // [n][4]
   R* dg;                   // [n] Jacobi diagonal
   R* dsp;                  // [n] spring diagonal

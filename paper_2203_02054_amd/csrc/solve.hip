@@ -42,6 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
       d.xc[k * n + v] = X + (double)uu;
       d.dl[4 * (size_t)v + k] = R(0);
       d.dlp[4 * (size_t)v + k] = R(0);
+      d.dlpp[4 * (size_t)v + k] = R(0);
     }
   }
   const int stride = gridDim.x * kBlock;
@@ -175,12 +176,12 @@ __device__ __forceinline__ void block_sum2_store(double a, double b, double (*ld
   }
 }
 
-// Block sums of K values in one LDS round, stored by thread 0 to out[i]
-// (the per-wave order and fixed tree of block_sum; no closing __syncthreads,
-// the caller's grid barrier starts with one).
+// Block sums of K values in one LDS round; thread i stores sum i to
+// base[i * stride] (the per-wave order and fixed tree of block_sum; no
+// closing __syncthreads, the caller's grid barrier starts with one).
 template <int K>
-__device__ __forceinline__ void block_sums_store(const double (&v)[K], double (*lds)[kPcgBlock / 64],
-                                                 double* const (&out)[K]) {
+__device__ __forceinline__ void block_sums_store(const double (&v)[K], double (*lds)[kPcgBlock / 64], double* base,
+                                                 int stride) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
@@ -188,27 +189,22 @@ __device__ __forceinline__ void block_sums_store(const double (&v)[K], double (*
     if (lane == 0) lds[i][w] = t;
   }
   __syncthreads();
+  if ((int)threadIdx.x < K) {
+    double t = 0.0;
 #pragma unroll
-  for (int i = 0; i < K; ++i)
-    if ((int)threadIdx.x == i) {  // static indices: no private-memory array
-      double t = 0.0;
-#pragma unroll
-      for (int j = 0; j < kPcgBlock / 64; ++j) t += lds[i][j];
-      *out[i] = t;
-    }
+    for (int j = 0; j < kPcgBlock / 64; ++j) t += lds[threadIdx.x][j];
+    base[(size_t)threadIdx.x * stride] = t;
+  }
 }
 
-// Sums of the G block partials of K <= kPcgBlock / 64 arrays in one round:
-// wavefront i reduces array i in grid_sum2's order; every block obtains the
-// same bits.
+// Sums of the G block partials of K <= kPcgBlock / 64 arrays base + i *
+// stride in one round: wavefront i reduces array i in grid_sum2's order;
+// every block obtains the same bits.
 template <int K>
-__device__ __forceinline__ void grid_sums(const double* const (&src)[K], int G, double* sh, double (&out)[K]) {
+__device__ __forceinline__ void grid_sums(const double* base, int stride, int G, double* sh, double (&out)[K]) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (w < K) {
-    const double* a = src[0];
-#pragma unroll
-    for (int i = 1; i < K; ++i)
-      if (w == i) a = src[i];  // static indices: no private-memory array
+    const double* a = base + (size_t)w * stride;
     double t = (l < G) ? a[l] : 0.0;
     for (int k = l + 64; k < G; k += 64) t += a[k];
     t = wave_sum(t);
@@ -217,6 +213,27 @@ __device__ __forceinline__ void grid_sums(const double* const (&src)[K], int G, 
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < K; ++i) out[i] = sh[i];
+}
+
+// A double every lane of the wavefront holds equally, moved to scalar
+// registers (the CG scalars: they then take no vector registers in the loop).
+__device__ __forceinline__ double uniform_d(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The x, y, z lanes of a padded vector (the padding lane is not loaded: a
+// 12-byte load, three registers instead of four).
+template <typename R>
+__device__ __forceinline__ W4<R> ld3(const W4<R>* p) {
+  W4<R> o;
+  o.x = p->x;
+  o.y = p->y;
+  o.z = p->z;
+  o.w = R(0);
+  return o;
 }
 
 template <typename R>
@@ -257,6 +274,39 @@ __device__ __forceinline__ void galerkin_weights(double e1, double e2, double h1
   if (!(g1 == g1) || !(g2 == g2) || isinf(g1) || isinf(g2)) g1 = g2 = 0.0;
 }
 
+// Three-vector version: the 3x3 system over span{w1, w2, w3} by Cholesky,
+// accepted under the same cancellation bound (sum of |g_i| |w_i|_A within 16
+// |x_0|_A), else the two-vector weights of (w1, w2).
+__device__ __forceinline__ void galerkin_weights3(double e1, double e2, double e3, double h11, double h12,
+                                                  double h13, double h22, double h23, double h33, double& g1,
+                                                  double& g2, double& g3) {
+  g3 = 0.0;
+  if (h11 > 0.0 && h22 > 0.0 && h33 > 0.0 && !isinf(h11) && !isinf(h22) && !isinf(h33)) {
+    const double l11 = sqrt(h11), l21 = h12 / l11, l31 = h13 / l11;
+    const double p2 = h22 - l21 * l21;
+    if (p2 > 1e-12 * h22) {
+      const double l22 = sqrt(p2), l32 = (h23 - l31 * l21) / l22;
+      const double p3 = h33 - l31 * l31 - l32 * l32;
+      if (p3 > 1e-12 * h33) {
+        const double l33 = sqrt(p3);
+        const double y1 = e1 / l11, y2 = (e2 - l21 * y1) / l22, y3 = (e3 - l31 * y1 - l32 * y2) / l33;
+        const double c = y3 / l33, b = (y2 - l32 * c) / l22, a = (y1 - l21 * b - l31 * c) / l11;
+        const double nn = a * (a * h11 + b * h12 + c * h13) + b * (a * h12 + b * h22 + c * h23) +
+                          c * (a * h13 + b * h23 + c * h33);  // |g1 w1 + g2 w2 + g3 w3|_A^2
+        const double sum = fabs(a) * sqrt(h11) + fabs(b) * sqrt(h22) + fabs(c) * sqrt(h33);
+        if (nn > 0.0 && sum * sum <= 256.0 * nn && !isinf(a) && !isinf(b) && !isinf(c) && a == a && b == b &&
+            c == c) {
+          g1 = a;
+          g2 = b;
+          g3 = c;
+          return;
+        }
+      }
+    }
+  }
+  galerkin_weights(e1, e2, h11, h12, h22, g1, g2);
+}
+
 // Preconditioned conjugate gradient in the Chronopoulos-Gear arrangement:
 // both inner products of an iteration are taken after its single
 // matrix-vector product, so one grid-wide reduction (one barrier) per
@@ -275,14 +325,15 @@ __device__ __forceinline__ void galerkin_weights(double e1, double e2, double h1
 // fixed-width ELL array (padded with the row itself and value 0) so every
 // neighbour load of a row is issued at once.
 // End of an outer iteration, run by the CG kernel after its last reduction:
-// u += d on the rows each block owns, collision positions refreshed, hash
-// buckets cleared for the next iteration; r_k = max|d| / diag and the
-// convergence decision are taken by the last block to arrive (ticket).
+// u += d on the rows each block owns, collision positions refreshed and, with
+// self-collision, the query vertices inserted into the spatial hash (cleared
+// by the contact/gather pass) for the next iteration's tet query;
+// r_k = max|d| / diag and the convergence decision are taken by the last
+// block to arrive (ticket).
 // In the adjoint iteration (ADJ) the update is mu += d and a mesh is done once
 // max|d| <= tol max|mu| over its vertices.
 template <typename R, bool ADJ>
-__device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, int row0, int row1, int tid0, int stride,
-                                            double* lds) {
+__device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, int row0, int row1, double* lds) {
   __shared__ int last;
   const size_t n = (size_t)c.n;
   const W4<R>* x = reinterpret_cast<const W4<R>*>(d.dl);
@@ -302,10 +353,11 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
         W4<R>* dlp = reinterpret_cast<W4<R>*>(d.dlp);
         dlw[v] = w4<R>(R(0), R(0), R(0));
         dlp[v] = w4<R>(R(0), R(0), R(0));
+        reinterpret_cast<W4<R>*>(d.dlpp)[v] = w4<R>(R(0), R(0), R(0));
       } else if (d.freem[v]) {
         const W4<R> dv = x[v];
         const R dd[3] = {dv.x, dv.y, dv.z};
-        double uq = 0.0;
+        double uq = 0.0, xn[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           if (ADJ) {
@@ -316,10 +368,11 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
           } else {
             const R uu = d.u[k * n + v] + dd[k];
             d.u[k * n + v] = uu;
-            d.xc[k * n + v] = d.X0[k * n + v] + (double)uu;
+            xn[k] = d.X0[k * n + v] + (double)uu;
+            d.xc[k * n + v] = xn[k];
           }
         }
-
+        if (!ADJ && c.self_col && d.vq[v] >= 0) hash_insert_entry(d, c, d.vq[v], v, m, xn[0], xn[1], xn[2]);
         dm = sqrt(((double)dv.x * dv.x + (double)dv.y * dv.y) + (double)dv.z * dv.z);
         um = sqrt(uq);
       }
@@ -341,8 +394,6 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
       if (ADJ && um > 0.0) atomicMax(&d.mmax[m], (unsigned long long)__double_as_longlong(um));
     }
   }
-  if (!ADJ)
-    for (int i = tid0; i < c.H; i += stride) d.hcount[i] = 0;
   const double bm = block_max<kPcgBlock>(dmax, lds);
   if (threadIdx.x == 0) {
     d.part_f[blockIdx.x] = bm;
@@ -436,7 +487,6 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   st->n_contacts_last = st->n_contacts;
   st->n_contacts = 0;
   st->n_pen = 0;
-  st->n_over = 0;
   st->ticket = 0;
   st->bar_count = 0u;  // every block is past its last barrier
   __hip_atomic_store(&st->done, code, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -454,8 +504,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   static_assert(!PAIR || (std::is_same<R, float>::value && MW == 16), "paired lanes: FP32, ELL width 16");
   constexpr int CH = Chunk<R>::n;
   __shared__ double lds[kPcgBlock / 64];
-  __shared__ double lds2[6][kPcgBlock / 64];
-  __shared__ double sh[8];
+  __shared__ double lds2[10][kPcgBlock / 64];
+  __shared__ double sh[16];
   if (is_done(d.st)) return;
   const int G = gridDim.x;
   const int stride = G * kPcgBlock;
@@ -558,80 +608,96 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
     }
   } else {
+    // history: w1 = d_k, w2 = d_k - d_{k-1}, w3 = d_k - 2 d_{k-1} + d_{k-2}
+    // (the last correction, its change and the change's change)
     W4<R>* __restrict__ xp = reinterpret_cast<W4<R>*>(d.dlp);
-    double e1 = 0.0, e2 = 0.0, h11 = 0.0, h12 = 0.0, h22 = 0.0;
+    W4<R>* __restrict__ xpp = reinterpret_cast<W4<R>*>(d.dlpp);
+    double tq[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // e1 e2 e3 h11 h12 h13 h22 h23 h33
+    // neighbour slots per gather round: all 16 at once for the latency-bound
+    // paired variant, 8 in the unpaired kernel, whose registers the CG loop sets
+    constexpr int CH1 = PAIR ? CH : (CH < 8 ? CH : 8);
     for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       const R dv = dg[v], idg = R(1) / dv;
-      const W4<R> w1 = x[v], wp = xp[v];
+      const W4<R> w1 = x[v], wp = xp[v], wpp = xpp[v];
       const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
+      const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
       R a10 = dv * w1.x, a11 = dv * w1.y, a12 = dv * w1.z;
       R a20 = dv * w2.x, a21 = dv * w2.y, a22 = dv * w2.z;
+      R a30 = dv * w3.x, a31 = dv * w3.y, a32 = dv * w3.z;
 #pragma unroll 1
-      for (int k0 = 0; k0 < MW; k0 += CH) {
-        int jj[CH];
-        R aa[CH], dgn[CH];
-        W4<R> xn[CH], pn[CH];
+      for (int k0 = 0; k0 < MW; k0 += CH1) {
+        int jj[CH1];
+        R aa[CH1], dgn[CH1];
+        W4<R> xn[CH1], pn[CH1], qn[CH1];
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
+        for (int k = 0; k < CH1; ++k) {
           jj[k] = ecol[(size_t)(k0 + k) * n + v];
           aa[k] = evl[(size_t)(k0 + k) * n + v];
         }
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
+        for (int k = 0; k < CH1; ++k) {
           xn[k] = x[jj[k]];
           pn[k] = xp[jj[k]];
+          qn[k] = xpp[jj[k]];
           dgn[k] = dg[jj[k]];
         }
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
+        for (int k = 0; k < CH1; ++k) {
+          const R d0 = xn[k].x - pn[k].x, d1 = xn[k].y - pn[k].y, d2 = xn[k].z - pn[k].z;
           a10 += aa[k] * xn[k].x;
           a11 += aa[k] * xn[k].y;
           a12 += aa[k] * xn[k].z;
-          a20 += aa[k] * (xn[k].x - pn[k].x);
-          a21 += aa[k] * (xn[k].y - pn[k].y);
-          a22 += aa[k] * (xn[k].z - pn[k].z);
+          a20 += aa[k] * d0;
+          a21 += aa[k] * d1;
+          a22 += aa[k] * d2;
+          a30 += aa[k] * (d0 - (pn[k].x - qn[k].x));
+          a31 += aa[k] * (d1 - (pn[k].y - qn[k].y));
+          a32 += aa[k] * (d2 - (pn[k].z - qn[k].z));
           evs[(size_t)(k0 + k) * n + v] = aa[k] / dgn[k];
         }
       }
       const W4<R> b = cg0[3 * (size_t)v];
       acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
-      const double t1 = ((double)w1.x * b.x + (double)w1.y * b.y) + (double)w1.z * b.z;
-      const double t2 = ((double)w2.x * b.x + (double)w2.y * b.y) + (double)w2.z * b.z;
-      const double t11 = ((double)w1.x * a10 + (double)w1.y * a11) + (double)w1.z * a12;
-      const double t12 = ((double)w1.x * a20 + (double)w1.y * a21) + (double)w1.z * a22;
-      const double t22 = ((double)w2.x * a20 + (double)w2.y * a21) + (double)w2.z * a22;
-      cg0[3 * (size_t)v + 1] = w4<R>(a10, a11, a12);  // A w1, A w2 until the second pass
+      const double t[9] = {((double)w1.x * b.x + (double)w1.y * b.y) + (double)w1.z * b.z,
+                           ((double)w2.x * b.x + (double)w2.y * b.y) + (double)w2.z * b.z,
+                           ((double)w3.x * b.x + (double)w3.y * b.y) + (double)w3.z * b.z,
+                           ((double)w1.x * a10 + (double)w1.y * a11) + (double)w1.z * a12,
+                           ((double)w1.x * a20 + (double)w1.y * a21) + (double)w1.z * a22,
+                           ((double)w1.x * a30 + (double)w1.y * a31) + (double)w1.z * a32,
+                           ((double)w2.x * a20 + (double)w2.y * a21) + (double)w2.z * a22,
+                           ((double)w2.x * a30 + (double)w2.y * a31) + (double)w2.z * a32,
+                           ((double)w3.x * a30 + (double)w3.y * a31) + (double)w3.z * a32};
+      // A w1, A w2, A w3 until the second pass (p is free until the first CG
+      // iteration, which takes p_{-1} = 0 without reading it)
+      cg0[3 * (size_t)v + 1] = w4<R>(a10, a11, a12);
       cg0[3 * (size_t)v + 2] = w4<R>(a20, a21, a22);
+      p[v] = w4<R>(a30, a31, a32);
       if (c.M > 1) {
-        // per-row terms, summed per mesh below, in the half of the CG state
-        // the first iteration has yet to write
+        // a batch projects on (w1, w2): per-row terms, summed per mesh below,
+        // in the half of the CG state the first iteration has yet to write
         double* q = reinterpret_cast<double*>(cg0 + 3 * n);
-        q[v] = t1;
-        q[n + v] = t2;
-        q[2 * n + v] = t11;
-        q[3 * n + v] = t12;
-        q[4 * n + v] = t22;
+        q[v] = t[0];
+        q[n + v] = t[1];
+        q[2 * n + v] = t[3];
+        q[3 * n + v] = t[4];
+        q[4 * n + v] = t[6];
       } else {
-        e1 += t1;
-        e2 += t2;
-        h11 += t11;
-        h12 += t12;
-        h22 += t22;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) tq[i] += t[i];
       }
     }
-    double g1 = 0.0, g2 = 0.0;
+    double g1 = 0.0, g2 = 0.0, g3 = 0.0;
     if (c.M == 1) {
-      const double q[6] = {e1, e2, h11, h12, h22, acc_b};
-      double* const dst[6] = {d.part_c + 2 * G + blockIdx.x, d.part_c + 3 * G + blockIdx.x,
-                              d.part_c + 4 * G + blockIdx.x, d.part_c + 5 * G + blockIdx.x,
-                              d.part_c + 6 * G + blockIdx.x, d.part_d + blockIdx.x};
-      block_sums_store<6>(q, lds2, dst);
+      // partials at part_c[(2 + i) G + block] for the nine terms, part_d for b' M^-1 b
+      const double q[10] = {tq[0], tq[1], tq[2], tq[3], tq[4], tq[5], tq[6], tq[7], tq[8], acc_b};
+      block_sums_store<10>(q, lds2, d.part_c + 2 * G + blockIdx.x, G);
+      if (threadIdx.x == 9) d.part_d[blockIdx.x] = d.part_c[11 * G + blockIdx.x];
       grid_barrier(bc, bar_target, G);
-      const double* const src[5] = {d.part_c + 2 * G, d.part_c + 3 * G, d.part_c + 4 * G, d.part_c + 5 * G,
-                                    d.part_c + 6 * G};
-      double S[5];
-      grid_sums<5>(src, G, sh, S);
-      galerkin_weights(S[0], S[1], S[2], S[3], S[4], g1, g2);  // every block takes the same decision
+      double S1[5], S2[4];
+      grid_sums<5>(d.part_c + 2 * G, G, G, sh, S1);
+      grid_sums<4>(d.part_c + 7 * G, G, G, sh + 8, S2);
+      // every block takes the same decision from the same sums
+      galerkin_weights3(S1[0], S1[1], S1[2], S1[3], S1[4], S2[0], S2[1], S2[2], S2[3], g1, g2, g3);
     } else {
       const double bs = block_sum<kPcgBlock>(acc_b, lds);
       if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
@@ -657,53 +723,59 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       }
       grid_barrier(bc, bar_target, G);
     }
-    // x_0, r_0 = b - g1 A w1 - g2 A w2 and, in the same pass, w_0 = A u_0:
-    // the neighbours' r_0 are rebuilt from their (b, A w1, A w2) as the CG
-    // iterations rebuild r_{i+1}, so no barrier separates the two.  A row's
-    // neighbours belong to its mesh and share its weights.  The start goes to
-    // the other half of the CG state, whose (b, A w1, A w2) other blocks are
-    // still reading.
+    // x_0, r_0 = b - g1 A w1 - g2 A w2 - g3 A w3 and, in the same pass,
+    // w_0 = A u_0: the neighbours' r_0 are rebuilt from their
+    // (b, A w1, A w2, A w3) as the CG iterations rebuild r_{i+1}, so no barrier
+    // separates the two.  A row's neighbours belong to its mesh and share its
+    // weights.  The start goes to the other half of the CG state, whose
+    // (b, A w1, A w2) other blocks are still reading; the history moves on.
+    constexpr int CH2 = PAIR ? (CH < 8 ? CH : 8) : (CH < 4 ? CH : 4);
     W4<R>* __restrict__ ns = cg0 + 3 * n;
     for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
-      R r1 = (R)g1, r2 = (R)g2;
+      R r1 = (R)g1, r2 = (R)g2, r3 = (R)g3;
       if (c.M > 1) {
         const int m = d.vmesh[v];
         r1 = (R)d.mgam[2 * m];
         r2 = (R)d.mgam[2 * m + 1];
+        r3 = R(0);
       }
       const R idg = R(1) / dg[v];
-      const W4<R> w1 = x[v], wp = xp[v];
-      const W4<R> b = cg0[3 * (size_t)v], aw1 = cg0[3 * (size_t)v + 1], aw2 = cg0[3 * (size_t)v + 2];
-      const W4<R> rv = w4<R>(b.x - r1 * aw1.x - r2 * aw2.x, b.y - r1 * aw1.y - r2 * aw2.y,
-                             b.z - r1 * aw1.z - r2 * aw2.z);
+      const W4<R> w1 = x[v], wp = xp[v], wpp = xpp[v];
+      const W4<R> b = cg0[3 * (size_t)v], aw1 = cg0[3 * (size_t)v + 1], aw2 = cg0[3 * (size_t)v + 2], aw3 = p[v];
+      const W4<R> rv = w4<R>(b.x - r1 * aw1.x - r2 * aw2.x - r3 * aw3.x, b.y - r1 * aw1.y - r2 * aw2.y - r3 * aw3.y,
+                             b.z - r1 * aw1.z - r2 * aw2.z - r3 * aw3.z);
       R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
 #pragma unroll 1
-      for (int k0 = 0; k0 < MW; k0 += CH) {
-        int jj[CH];
-        R aa[CH];
+      for (int k0 = 0; k0 < MW; k0 += CH2) {
+        int jj[CH2];
+        R aa[CH2];
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
+        for (int k = 0; k < CH2; ++k) {
           jj[k] = ecol[(size_t)(k0 + k) * n + v];
           aa[k] = evs[(size_t)(k0 + k) * n + v];
         }
-        W4<R> nb[CH], n1[CH], n2[CH];
+        W4<R> nb[CH2], n1[CH2], n2[CH2], n3[CH2];
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
+        for (int k = 0; k < CH2; ++k) {
           const size_t b3 = 3 * (size_t)jj[k];
           nb[k] = cg0[b3];
           n1[k] = cg0[b3 + 1];
           n2[k] = cg0[b3 + 2];
+          n3[k] = p[jj[k]];
         }
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          a0 += aa[k] * (nb[k].x - r1 * n1[k].x - r2 * n2[k].x);
-          a1 += aa[k] * (nb[k].y - r1 * n1[k].y - r2 * n2[k].y);
-          a2 += aa[k] * (nb[k].z - r1 * n1[k].z - r2 * n2[k].z);
+        for (int k = 0; k < CH2; ++k) {
+          a0 += aa[k] * (nb[k].x - r1 * n1[k].x - r2 * n2[k].x - r3 * n3[k].x);
+          a1 += aa[k] * (nb[k].y - r1 * n1[k].y - r2 * n2[k].y - r3 * n3[k].y);
+          a2 += aa[k] * (nb[k].z - r1 * n1[k].z - r2 * n2[k].z - r3 * n3[k].z);
         }
       }
-      x[v] = w4<R>(r1 * w1.x + r2 * (w1.x - wp.x), r1 * w1.y + r2 * (w1.y - wp.y), r1 * w1.z + r2 * (w1.z - wp.z));
+      const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
+      const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
+      x[v] = w4<R>(r1 * w1.x + r2 * w2.x + r3 * w3.x, r1 * w1.y + r2 * w2.y + r3 * w3.y,
+                   r1 * w1.z + r2 * w2.z + r3 * w3.z);
+      xpp[v] = wp;
       xp[v] = w1;
-      p[v] = w4<R>(R(0), R(0), R(0));
       ns[3 * (size_t)v] = rv;
       ns[3 * (size_t)v + 1] = w4<R>(a0, a1, a2);
       ns[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
@@ -715,16 +787,13 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   }
   block_sum2_store(acc_g, acc_d, lds2, d.part_c + blockIdx.x, d.part_e + blockIdx.x);
   grid_barrier(bc, bar_target, G);
-  double gam, del, rhs;
-  {
-    const double* const src[3] = {d.part_c, d.part_e, d.part_d};
-    double S[3];
-    grid_sums<3>(src, G, sh, S);
-    gam = S[0];
-    del = S[1];
-    rhs = S[2];
-  }
-  const double stop = c.pcg_eta * c.pcg_eta * rhs;
+  double gam, del, rhs, dummy;
+  grid_sum2(d.part_c, d.part_e, G, sh, gam, del);
+  grid_sum2(d.part_d, d.part_d, G, sh, rhs, dummy);
+  gam = uniform_d(gam);
+  del = uniform_d(del);
+  rhs = uniform_d(rhs);
+  const double stop = uniform_d(c.pcg_eta * c.pcg_eta * rhs);
   int it = 0;
   bool broke = !(rhs >= 0.0) || isinf(rhs) || !(gam >= 0.0) || isinf(gam);
   bool run = !broke && gam > stop;
@@ -743,6 +812,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     grid_barrier(bc, bar_target, G);
     double gn, dn;
     grid_sum2<false>(d.part_c + half, d.part_e + half, G, sh + 2 * (it & 1), gn, dn);
+    gn = uniform_d(gn);
+    dn = uniform_d(dn);
     ++it;
     cur ^= 1;
     if (!(gn >= 0.0) || isinf(gn) || !(dn == dn) || isinf(dn)) {
@@ -756,8 +827,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       broke = true;
       return false;
     }
-    al = gn / den;
-    be = bn;
+    al = uniform_d(gn / den);
+    be = uniform_d(bn);
     gam = gn;
     return true;
   };
@@ -785,7 +856,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         prc = cs[3 * (size_t)pv_row];
         pwc = cs[3 * (size_t)pv_row + 1];
         psc = cs[3 * (size_t)pv_row + 2];
-        ppv = p[pv_row];
+        ppv = w4<R>(R(0), R(0), R(0));  // p_{-1} = 0
         pxv = x[pv_row];
         pidg = R(1) / dg[pv_row];
       }
@@ -847,7 +918,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       const R idg = R(1) / dg[v];
       const W4<R> rc = cs[3 * (size_t)v], wc = cs[3 * (size_t)v + 1], sc = cs[3 * (size_t)v + 2];
-      const W4<R> pv0 = p[v];
+      const W4<R> pv0 = p[v];  // at i = 0 b_0 = 0: p_{-1} enters as 0 * (finite start-up data)
       const W4<R> xv = x[v];
       const W4<R> pv = w4<R>(rc.x * idg + rb * pv0.x, rc.y * idg + rb * pv0.y, rc.z * idg + rb * pv0.z);
       const W4<R> sv = w4<R>(wc.x + rb * sc.x, wc.y + rb * sc.y, wc.z + rb * sc.z);
@@ -868,9 +939,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
           const size_t b3 = 3 * (size_t)jj[k];
-          nr[k] = cs[b3];
-          nw[k] = cs[b3 + 1];
-          nsv[k] = cs[b3 + 2];
+          nr[k] = ld3(cs + b3);
+          nw[k] = ld3(cs + b3 + 1);
+          nsv[k] = ld3(cs + b3 + 2);
         }
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
@@ -894,7 +965,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     if (broke) __hip_atomic_store(&d.st->done, (int)BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (!broke) {
-    finish_tail<R, ADJ>(d, c, row0, row1, tid0, stride, lds);
+    finish_tail<R, ADJ>(d, c, row0, row1, lds);
   } else if (threadIdx.x == 0) {
     // every block leaves after the same barrier; the last one out clears the
     // barrier counter for the next launch

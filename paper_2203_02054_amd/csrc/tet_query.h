@@ -133,7 +133,7 @@ __device__ __forceinline__ void tet_query_lane(const Dev<R>& d, const Consts& c,
     }
     test_buckets<R, DEBUG, PREFETCH>(d, slots, keys, e, vbeg, vend, vi, p, lo, hi);
   }
-  const int nover = __hip_atomic_load(&d.st->n_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int nover = min(__hip_atomic_load(&d.st->n_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), c.S);
   for (int i = sub; i < nover; i += L)
     test_point<R, DEBUG>(d, reinterpret_cast<const double4*>(d.hover)[i], e, vbeg, vend, vi, p, lo, hi);
 }
