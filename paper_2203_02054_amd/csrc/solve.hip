@@ -804,12 +804,18 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   double al = run ? gam / del : 0.0, be = 0.0;
   // End of an iteration after its row work: block partials, the grid
   // barrier, the grid sums and the next step lengths; false ends the solve.
-  auto next_step = [&](double ag, double ad) -> bool {
-    // partial sums alternate halves so a slow block still reading the previous
-    // iteration's sums is never overwritten
+  // publish: the iteration's block partials, then the grid barrier (partial
+  // sums alternate halves so a slow block still reading the previous
+  // iteration's sums is never overwritten)
+  auto publish = [&](double ag, double ad) {
     const int half = (it & 1) ? 0 : G;
     block_sum2_store(ag, ad, lds2, d.part_c + half + blockIdx.x, d.part_e + half + blockIdx.x);
     grid_barrier(bc, bar_target, G);
+  };
+  // advance: the grid sums of the published partials and the next step
+  // lengths; false ends the solve
+  auto advance = [&]() -> bool {
+    const int half = (it & 1) ? 0 : G;
     double gn, dn;
     grid_sum2<false>(d.part_c + half, d.part_e + half, G, sh + 2 * (it & 1), gn, dn);
     gn = uniform_d(gn);
@@ -831,6 +837,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     be = uniform_d(bn);
     gam = gn;
     return true;
+  };
+  auto next_step = [&](double ag, double ad) -> bool {
+    publish(ag, ad);
+    return advance();
   };
   // PAIR (FP32, ELL width 16, at most kPcgBlock / 2 rows per block):
   // lanes 2i and 2i+1 share row row0 + i, each gathering 8 of its 16
@@ -860,8 +870,22 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         pxv = x[pv_row];
         pidg = R(1) / dg[pv_row];
       }
+      // the neighbours' (r, w, s) of the coming iteration, loaded right after
+      // the barrier that publishes them, while the partial sums are read
+      W4<R> nr[8], nw[8], nsv[8];
+      auto gather = [&](const W4<R>* cs) {
+        if (pv_has) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const size_t b3 = 3 * (size_t)pj[k];
+            nr[k] = ld3(cs + b3);
+            nw[k] = ld3(cs + b3 + 1);
+            nsv[k] = ld3(cs + b3 + 2);
+          }
+        }
+      };
+      gather(cg0 + cur * 3 * n);
       while (run && it < c.pcg_max) {
-        const W4<R>* cs = cg0 + cur * 3 * n;
         W4<R>* ns = cg0 + (cur ^ 1) * 3 * n;
         const R ra = (R)al, rb = (R)be;
         acc_g = 0.0;
@@ -872,14 +896,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           const W4<R> rv = w4<R>(prc.x - ra * sv.x, prc.y - ra * sv.y, prc.z - ra * sv.z);
           ppv = pv;
           pxv = w4<R>(pxv.x + ra * pv.x, pxv.y + ra * pv.y, pxv.z + ra * pv.z);
-          W4<R> nr[8], nw[8], nsv[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const size_t b3 = 3 * (size_t)pj[k];
-            nr[k] = cs[b3];
-            nw[k] = cs[b3 + 1];
-            nsv[k] = cs[b3 + 2];
-          }
           R a0 = R(0), a1 = R(0), a2 = R(0);
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
@@ -903,7 +919,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           pwc = wn;
           psc = sv;
         }
-        if (!next_step(acc_g, acc_d)) break;
+        publish(acc_g, acc_d);
+        gather(ns);
+        if (!advance()) break;
       }
       if (pv_has && pv_half == 0) x[pv_row] = pxv;
     }
