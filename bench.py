@@ -50,12 +50,13 @@ def kernel_bytes(info, W, n_launch, pcg_iters):
       pcg        per CG iteration: per row the CG state (r, w, s: 3 vectors of
                  4 reals) read and written, p and the correction read and
                  written, the Jacobi diagonal; per off-diagonal entry its column
-                 and value.  Plus the start-up (the warm start: the last two
-                 corrections, right-hand side and diagonal read, their two
-                 products written, then combined into the start, residual,
-                 search vectors; the scaled ELL values written; w_0 = A u_0)
-                 and the end-of-iteration update (u read/written, correction
-                 read, collision positions written).
+                 and value.  Plus the start-up (the warm start: the last three
+                 corrections, right-hand side and diagonal read, their three
+                 products written; the scaled ELL values written; then the
+                 start, its residual and w_0 = A u_0 formed, the history moved
+                 on) and the end-of-iteration update (u read/written,
+                 correction read, collision positions written, each query
+                 vertex's 32-byte hash entry and bucket count).
       local      per tet connectivity 16, tag 4, residual slot index 16, residual
                  columns written 4 x 4W; per vertex rest position 24 and
                  displacement 3W read once.
@@ -70,8 +71,8 @@ def kernel_bytes(info, W, n_launch, pcg_iters):
     out = {}
     m = pcg_iters / max(n_launch.get("pcg", 1), 1)
     per_it = n * (12 * W * 2 + 8 * W + 8 * W + W) + off * (4 + W)
-    startup = n * (21 * W) + off * (4 + 2 * W) + n * (40 * W) + n * (9 * W) + off * (4 + W)
-    finish = n * (3 * W + 4 * W + 24) + 4 * info["hash_buckets"]
+    startup = n * (29 * W) + off * (4 + 2 * W) + n * (52 * W) + off * (4 + W)
+    finish = n * (3 * W + 4 * W + 24) + S * 36
     out["pcg"] = m * per_it + startup + finish
     out["local"] = T * (36 + 16 * W) + n * (24 + 3 * W)
     out["gather"] = 4 * T * 4 * W + n * (4 + 6 * W)

@@ -361,6 +361,9 @@ Consts make_consts(const gs_problem* p) {
   c.fixed_iters = p->prm.fixed_iters;
   c.pcg_max = p->prm.pcg_max;
   c.nparts = p->nparts;
+  // the local step runs in the tet-query launch (four lanes per tet) below
+  // kTetQueryWide tets with self-collision, else on its own (one per tet)
+  c.a_parts = (p->prm.self_collision && p->T < kTetQueryWide) ? cdiv(4L * p->T, kBlock) : cdiv(p->T, kBlock);
   c.ell_w = p->ell_w;
   c.trace_len = p->trace_len;
   c.c1 = p->prm.c1;

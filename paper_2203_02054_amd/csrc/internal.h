@@ -69,6 +69,7 @@ struct Consts {
   int trace_len;        // rows of the per-iteration trace
   int aa_m;             // adjoint: Anderson memory (0: plain fixed-point iteration)
   int adj_jt;           // adjoint gather writes (db/dx)^T mu alone to `lam` (unrolled reverse sweep)
+  int a_parts;          // energy partials the local step writes per iteration (part_a)
   double c1, c2, kappa, tol, pcg_eta;
 };
 

@@ -64,17 +64,28 @@ __global__ __launch_bounds__(kBlock) void k_local(Dev<R> d, Consts c, const R* _
 }
 
 // Local step and tet query in one launch for meshes below kTetQueryWide tets
-// (both read only the positions of the iteration): thread g runs the local
-// step of tet g, then lane g of the four-lanes-per-tet query.
+// (both read only the iteration's positions).  A workgroup takes 64 tets;
+// wavefronts 0-2 share their queries (wavefront w: cell groups j = w mod 3),
+// wavefront 3 runs their local steps, so the two kinds of work run side by
+// side on the compute unit instead of one after the other in every lane.
+// The energy partials are per workgroup.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_query_local(Dev<R> d, Consts c, const R* __restrict__ alpha) {
+  static_assert(kBlock == 256, "four wavefronts per workgroup");
   __shared__ double lds[kBlock / 64];
   if (is_done(d.st)) return;
-  const int g = blockIdx.x * kBlock + threadIdx.x;
-  const double eloc = g < c.T ? local_one(d, c, alpha, g) : 0.0;
+  const int wv = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + (int)(threadIdx.x & 63);
+  double eloc = 0.0;
+  if (wv == 3) {
+    if (e < c.T) eloc = local_one(d, c, alpha, e);
+  } else {
+    tet_query_part<R, false, true>(d, c, e, wv, 3);
+  }
+  // the energy reduction after both kinds of work (a barrier before the
+  // query would hold it behind the local steps)
   const double bs = block_sum<kBlock>(eloc, lds);
-  if (threadIdx.x == 0 && (int)blockIdx.x < cdiv(c.T, kBlock)) d.part_a[blockIdx.x] = bs;
-  tet_query_lane<R, false, true>(d, c, g);
+  if (threadIdx.x == 0) d.part_a[blockIdx.x] = bs;
 }
 
 template <typename R>

@@ -410,7 +410,7 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   const int it = st->iters + 1;
   double eloc = 0.0, rloc = 0.0, active = 0.0, bad = 0.0;
   if (!ADJ) {
-    const int gl = cdiv(c.T, kBlock), gg = cdiv(c.n, kBlock);
+    const int gl = c.a_parts, gg = cdiv(c.n, kBlock);
     for (int b = threadIdx.x; b < gl; b += kPcgBlock) eloc += d.part_a[b];
     for (int b = threadIdx.x; b < gg; b += kPcgBlock) eloc += d.part_b[b];
   }
@@ -787,6 +787,45 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   }
   block_sum2_store(acc_g, acc_d, lds2, d.part_c + blockIdx.x, d.part_e + blockIdx.x);
   grid_barrier(bc, bar_target, G);
+  // PAIR: the lane pair's persistent state and its first neighbour gather,
+  // issued before the grid sums so the round trips overlap
+  const int pv_row = row0 + (int)(threadIdx.x >> 1), pv_half = (int)(threadIdx.x & 1);
+  const bool pv_has = PAIR && pv_row < row1;
+  int pj[8];
+  R pa[8];
+  W4<R> prc, pwc, psc, ppv, pxv;
+  R pidg = R(0);
+  // the neighbours' (r, w, s) of the coming iteration, loaded right after the
+  // barrier that publishes them, while the partial sums are read
+  W4<R> nr[8], nw[8], nsv[8];
+  auto gather = [&](const W4<R>* cs) {
+    if (pv_has) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const size_t b3 = 3 * (size_t)pj[k];
+        nr[k] = ld3(cs + b3);
+        nw[k] = ld3(cs + b3 + 1);
+        nsv[k] = ld3(cs + b3 + 2);
+      }
+    }
+  };
+  if constexpr (PAIR) {
+    if (pv_has) {
+      const W4<R>* cs = cg0 + cur * 3 * n;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        pj[k] = ecol[(size_t)(8 * pv_half + k) * n + pv_row];
+        pa[k] = evs[(size_t)(8 * pv_half + k) * n + pv_row];
+      }
+      prc = cs[3 * (size_t)pv_row];
+      pwc = cs[3 * (size_t)pv_row + 1];
+      psc = cs[3 * (size_t)pv_row + 2];
+      ppv = w4<R>(R(0), R(0), R(0));  // p_{-1} = 0
+      pxv = x[pv_row];
+      pidg = R(1) / dg[pv_row];
+    }
+    gather(cg0 + cur * 3 * n);
+  }
   double gam, del, rhs, dummy;
   grid_sum2(d.part_c, d.part_e, G, sh, gam, del);
   grid_sum2(d.part_d, d.part_d, G, sh, rhs, dummy);
@@ -850,41 +889,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // (the neighbours' r, w, s) instead of two.
   if constexpr (PAIR) {
     {
-      const int pv_row = row0 + (int)(threadIdx.x >> 1), pv_half = (int)(threadIdx.x & 1);
-      const bool pv_has = pv_row < row1;
-      int pj[8];
-      R pa[8];
-      W4<R> prc, pwc, psc, ppv, pxv;
-      R pidg = R(0);
-      if (pv_has) {
-        const W4<R>* cs = cg0 + cur * 3 * n;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          pj[k] = ecol[(size_t)(8 * pv_half + k) * n + pv_row];
-          pa[k] = evs[(size_t)(8 * pv_half + k) * n + pv_row];
-        }
-        prc = cs[3 * (size_t)pv_row];
-        pwc = cs[3 * (size_t)pv_row + 1];
-        psc = cs[3 * (size_t)pv_row + 2];
-        ppv = w4<R>(R(0), R(0), R(0));  // p_{-1} = 0
-        pxv = x[pv_row];
-        pidg = R(1) / dg[pv_row];
-      }
-      // the neighbours' (r, w, s) of the coming iteration, loaded right after
-      // the barrier that publishes them, while the partial sums are read
-      W4<R> nr[8], nw[8], nsv[8];
-      auto gather = [&](const W4<R>* cs) {
-        if (pv_has) {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const size_t b3 = 3 * (size_t)pj[k];
-            nr[k] = ld3(cs + b3);
-            nw[k] = ld3(cs + b3 + 1);
-            nsv[k] = ld3(cs + b3 + 2);
-          }
-        }
-      };
-      gather(cg0 + cur * 3 * n);
       while (run && it < c.pcg_max) {
         W4<R>* ns = cg0 + (cur ^ 1) * 3 * n;
         const R ra = (R)al, rb = (R)be;
@@ -924,6 +928,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         if (!advance()) break;
       }
       if (pv_has && pv_half == 0) x[pv_row] = pxv;
+      // the final update reads x with one row per thread, other wavefronts
+      // than the lane pairs that wrote it
+      __syncthreads();
     }
   }
   if constexpr (!PAIR)

@@ -68,11 +68,10 @@ __device__ __forceinline__ void test_buckets(const Dev<R>& d, const double4* slo
       test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, vbeg, vend, vi, p, lo, hi);
 }
 
-// One lane of the tet query: tet gid / L, cell groups gid mod L, gid mod L + L, ...
+// Part sub of nsub of the query of tet e: cell groups sub, sub + nsub, ...
+// (and the same share of the brute-force and overflow scans).
 template <typename R, bool DEBUG, bool PREFETCH>
-__device__ __forceinline__ void tet_query_lane(const Dev<R>& d, const Consts& c, int gid) {
-  constexpr int L = TetQueryLanes<PREFETCH>::n;
-  const int e = gid / L, sub = gid % L;
+__device__ __forceinline__ void tet_query_part(const Dev<R>& d, const Consts& c, int e, int sub, int nsub) {
   if (e >= c.T) return;
   const int m = d.tmesh[e];
   if (mesh_frozen(d, c.mask_done, m)) return;
@@ -107,7 +106,7 @@ __device__ __forceinline__ void tet_query_lane(const Dev<R>& d, const Consts& c,
   const double4* slots = reinterpret_cast<const double4*>(d.hslot);
   if (ncell > kCellCap) {
     // a tet stretched over many cells: test every query vertex of its mesh (still exact)
-    for (int s = d.mesh[m].sbeg + sub; s < d.mesh[m].send; s += L) {
+    for (int s = d.mesh[m].sbeg + sub; s < d.mesh[m].send; s += nsub) {
       const int v = d.qverts[s];
       double4 en;
       en.x = d.xc[v];
@@ -118,13 +117,13 @@ __device__ __forceinline__ void tet_query_lane(const Dev<R>& d, const Consts& c,
     }
     return;
   }
-  // the covered cells in groups of 8 (x fastest), group j taken by lane
-  // j mod L: one round trip fetches a group's bucket counts, the next the
+  // the covered cells in groups of 8 (x fastest), group j taken by part
+  // j mod nsub: one round trip fetches a group's bucket counts, the next the
   // first entries of its non-empty buckets (the common tet covers at most 2
   // cells per axis: one group)
   const int nx = chi[0] - clo[0] + 1, ny = chi[1] - clo[1] + 1;
   const int nc = (int)ncell;
-  for (int c0 = 8 * sub; c0 < nc; c0 += 8 * L) {
+  for (int c0 = 8 * sub; c0 < nc; c0 += 8 * nsub) {
     int keys[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -134,8 +133,15 @@ __device__ __forceinline__ void tet_query_lane(const Dev<R>& d, const Consts& c,
     test_buckets<R, DEBUG, PREFETCH>(d, slots, keys, e, vbeg, vend, vi, p, lo, hi);
   }
   const int nover = min(__hip_atomic_load(&d.st->n_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), c.S);
-  for (int i = sub; i < nover; i += L)
+  for (int i = sub; i < nover; i += nsub)
     test_point<R, DEBUG>(d, reinterpret_cast<const double4*>(d.hover)[i], e, vbeg, vend, vi, p, lo, hi);
+}
+
+// One lane of the stand-alone tet query: tet gid / L, part gid mod L of L.
+template <typename R, bool DEBUG, bool PREFETCH>
+__device__ __forceinline__ void tet_query_lane(const Dev<R>& d, const Consts& c, int gid) {
+  constexpr int L = TetQueryLanes<PREFETCH>::n;
+  tet_query_part<R, DEBUG, PREFETCH>(d, c, gid / L, gid % L, L);
 }
 
 }  // namespace gs
