@@ -333,10 +333,12 @@ gs_status gs_trace(gs_problem* p, int32_t cap, double* rows, int32_t* count);
  * duration in milliseconds and the number of launches; gs_kernel_name(k)
  * names the kernel ("pcg", "local", ...); the CG kernel also applies the
  * correction and takes the convergence decision.  Fused launches are counted
- * under one name: with self-collision on a mesh below 2^18 tets, "tet_query"
- * includes the local step ("local" then counts no launches); with any
- * collision, "contacts" includes the right-hand-side gather ("gather" counts
- * none).  gs_profile(p, 0) stops. */
+ * under one name: "pcg" also updates the contact set and gathers the
+ * right-hand side ("contacts" and "gather" count no launches in a solve);
+ * with self-collision on a mesh below 2^18 tets, "tet_query" includes the
+ * local step ("local" then counts none); "hash_insert" runs only on a solve's
+ * first iteration (the CG kernel refills the hash).  gs_profile(p, 0)
+ * stops. */
 #define GS_N_KERNELS 11
 gs_status gs_profile(gs_problem* p, int32_t enable);
 gs_status gs_profile_read(const gs_problem* p, double* ms, int64_t* launches);

@@ -16,7 +16,7 @@
 // identical inputs give identical sets on any conforming implementation.
 #include <climits>
 
-#include "gather.h"
+#include "contacts.h"
 #include "tet_query.h"
 
 namespace gs {
@@ -169,112 +169,6 @@ __global__ __launch_bounds__(kBlock) void k_ray(Dev<R> d, Consts c) {
   }
 }
 
-__device__ __forceinline__ bool released(const double* x, const double* tc, const double* nc, double eps) {
-  const double g = (nc[0] * (x[0] - tc[0]) + nc[1] * (x[1] - tc[1])) + nc[2] * (x[2] - tc[2]);
-  return fabs(g) > eps;
-}
-
-// Active set A_k from A_{k-1} (stored in place), per query vertex.
-template <typename R>
-__device__ __forceinline__ void contacts_one(const Dev<R>& d, const Consts& c, int s) {
-  const int v = d.qverts[s];
-  const int m = d.vmesh[v];
-  if (mesh_frozen(d, c.mask_done, m)) return;
-  const double eps = d.mesh[m].eps;
-  double x[3];
-  load3(d.xc, (size_t)c.n, v, x);
-  const int base = s * c.slots;
-  bool changed = false;
-  int nact = 0;
-  if (c.self_col) {
-    const bool old = d.cact[base] != 0;
-    const bool pen = d.pen[s] != 0;
-    const int hit = pen ? d.fhit[s] : -1;
-    bool now = false;
-    if (pen && hit >= 0) {
-      now = true;
-      for (int k = 0; k < 3; ++k) {
-        d.ctgt[3 * base + k] = d.fc[3 * s + k];
-        d.cnrm[3 * base + k] = d.fn[3 * s + k];
-      }
-      d.cprim[base] = hit;
-    } else if (old) {
-      now = pen ? true : !released(x, d.ctgt + 3 * base, d.cnrm + 3 * base, eps);
-    }
-    if (pen && hit < 0) atomicAdd(&d.st->ray_miss, 1);
-    d.cact[base] = now ? ((pen && hit >= 0) ? 2 : 1) : 0;
-    changed |= (now != old);
-    nact += now;
-    d.pen[s] = 0;
-  }
-  if (c.obst_col) {
-    for (int j = 0; j < c.ns; ++j) {
-      const double* sp = d.obst + 4 * j;
-      const int slot = base + 1 + j;
-      const bool old = d.cact[slot] != 0;
-      const double dx = x[0] - sp[0], dy = x[1] - sp[1], dz = x[2] - sp[2];
-      const double q = (dx * dx + dy * dy) + dz * dz;
-      const bool inside = q < sp[3] * sp[3];
-      bool now = false;
-      if (inside || old) {
-        const double dist = sqrt(q);
-        double nc[3];
-        if (dist > 0.0) {
-          nc[0] = dx / dist;
-          nc[1] = dy / dist;
-          nc[2] = dz / dist;
-        } else {
-          nc[0] = 0.0;
-          nc[1] = 0.0;
-          nc[2] = 1.0;
-        }
-        const double rr = sp[3] + eps;
-        const double tc[3] = {sp[0] + rr * nc[0], sp[1] + rr * nc[1], sp[2] + rr * nc[2]};
-        now = inside || !released(x, tc, nc, eps);
-        if (now) {
-          for (int k = 0; k < 3; ++k) {
-            d.ctgt[3 * slot + k] = tc[k];
-            d.cnrm[3 * slot + k] = nc[k];
-          }
-          d.cprim[slot] = j;
-        }
-      }
-      d.cact[slot] = now ? 1 : 0;
-      changed |= (now != old);
-      nact += now;
-    }
-    for (int j = 0; j < c.np; ++j) {
-      const double* pl = d.obst + 4 * c.ns + 6 * j;
-      const int slot = base + 1 + c.ns + j;
-      const bool old = d.cact[slot] != 0;
-      const double sd = (pl[3] * (x[0] - pl[0]) + pl[4] * (x[1] - pl[1])) + pl[5] * (x[2] - pl[2]);
-      const bool inside = sd < 0.0;
-      bool now = false;
-      if (inside || old) {
-        const double se = sd - eps;
-        const double nc[3] = {pl[3], pl[4], pl[5]};
-        const double tc[3] = {x[0] - se * nc[0], x[1] - se * nc[1], x[2] - se * nc[2]};
-        now = inside || !released(x, tc, nc, eps);
-        if (now) {
-          for (int k = 0; k < 3; ++k) {
-            d.ctgt[3 * slot + k] = tc[k];
-            d.cnrm[3 * slot + k] = nc[k];
-          }
-          d.cprim[slot] = j;
-        }
-      }
-      d.cact[slot] = now ? 1 : 0;
-      changed |= (now != old);
-      nact += now;
-    }
-  }
-  if (changed) {
-    atomicOr(&d.st->changed, 1);
-    d.mchanged[m] = 1;
-  }
-  if (nact) atomicAdd(&d.st->n_contacts, nact);
-}
-
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
   if (is_done(d.st)) return;
@@ -282,30 +176,6 @@ __global__ __launch_bounds__(kBlock) void k_contacts(Dev<R> d, Consts c) {
   if (s < c.S) contacts_one(d, c, s);
 }
 
-// Contact update and right-hand-side gather in one pass over the vertices:
-// a query vertex's thread first updates its own contact slots, then gathers
-// its row, which reads only those slots.  With self-collision it also clears
-// the spatial hash, which the CG kernel refills with the new positions.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_contacts_gather(Dev<R> d, Consts c) {
-  __shared__ double lds[kBlock / 64];
-  if (is_done(d.st)) return;
-  const int v = blockIdx.x * kBlock + threadIdx.x;
-  if (c.self_col) {
-    // the iteration's tet query is done: clear the hash for the insertions of
-    // the CG kernel's final update
-    for (int i = v; i < c.H; i += gridDim.x * kBlock) d.hcount[i] = 0;
-    if (v == 0) d.st->n_over = 0;
-  }
-  double esp = 0.0;
-  if (v < c.n) {
-    const int s = d.vq[v];
-    if (s >= 0) contacts_one(d, c, s);
-    esp = gather_row(d, c, v);
-  }
-  const double bs = block_sum<kBlock>(esp, lds);
-  if (threadIdx.x == 0) d.part_b[blockIdx.x] = bs;
-}
 
 template <typename R>
 hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s) {
@@ -345,17 +215,10 @@ hipError_t launch_contacts(const Dev<R>& d, const Consts& c, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_contacts_gather(const Dev<R>& d, const Consts& c, hipStream_t s) {
-  k_contacts_gather<R><<<cdiv(c.n, kBlock), kBlock, 0, s>>>(d, c);
-  return hipGetLastError();
-}
 
 template hipError_t launch_collide_stage<float>(const Dev<float>&, const Consts&, int, bool, hipStream_t);
 template hipError_t launch_collide_stage<double>(const Dev<double>&, const Consts&, int, bool, hipStream_t);
 template hipError_t launch_contacts<float>(const Dev<float>&, const Consts&, hipStream_t);
 template hipError_t launch_contacts<double>(const Dev<double>&, const Consts&, hipStream_t);
-template hipError_t launch_contacts_gather<float>(const Dev<float>&, const Consts&, hipStream_t);
-template hipError_t launch_contacts_gather<double>(const Dev<double>&, const Consts&, hipStream_t);
 
 }  // namespace gs

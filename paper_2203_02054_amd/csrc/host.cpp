@@ -512,10 +512,10 @@ gs_status drive(gs_problem* p, const DevStatus* dstat, int limit, F&& enqueue_on
 }
 
 // One outer iteration.  Below kTetQueryWide tets the local step rides in the
-// tet-query launch (both read only the iteration's positions); with any
-// collision the contact update rides in the gather launch; the spatial hash
-// is refilled by the CG kernel: 4 launches per iteration with self-collision
-// instead of 7.
+// tet-query launch (both read only the iteration's positions); the CG kernel
+// updates the contacts, gathers the right-hand side, clears the spatial hash
+// and refills it with the new positions: 3 launches per iteration with
+// self-collision (tet query + local step, ray cast, CG) instead of 7.
 template <typename R>
 hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, const R* alpha) {
   hipError_t e;
@@ -540,11 +540,7 @@ hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, co
   }
   if (!fused_local)
     if ((e = timed(p, K_LOCAL, [&] { return launch_local<R>(d, c, alpha, s); })) != hipSuccess) return e;
-  if (c.self_col || c.obst_col)
-    e = timed(p, K_CONTACTS, [&] { return launch_contacts_gather<R>(d, c, s); });
-  else
-    e = timed(p, K_GATHER, [&] { return launch_gather<R>(d, c, s); });
-  if (e != hipSuccess) return e;
+  // the CG kernel first updates the contacts and gathers the right-hand side
   return timed(p, K_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, false, pcg_cooperative(p)); });
 }
 

@@ -170,12 +170,10 @@ enum { STAGE_HASH_INSERT = 0, STAGE_TET_QUERY, STAGE_RAY, N_COLLIDE_STAGES };
 template <typename R>
 hipError_t launch_collide_stage(const Dev<R>& d, const Consts& c, int stage, bool debug, hipStream_t s);
 template <typename R> hipError_t launch_contacts(const Dev<R>& d, const Consts& c, hipStream_t s);
-template <typename R> hipError_t launch_contacts_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_local(const Dev<R>& d, const Consts& c, const R* alpha, hipStream_t s);
 template <typename R> hipError_t launch_query_local(const Dev<R>& d, const Consts& c, const R* alpha, hipStream_t s);
 template <typename R> hipError_t launch_local_debug(const Dev<R>& d, const Consts& c, const R* alpha, const R* x,
                                                     R* targets, hipStream_t s);
-template <typename R> hipError_t launch_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R>
 hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint, bool cooperative);
 // implicit adjoint

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "contacts.h"
 #include "gather.h"
 
 namespace gs {
@@ -115,17 +116,6 @@ __global__ __launch_bounds__(kBlock) void k_output(Dev<R> d, Consts c, R* __rest
   for (int k = 0; k < 3; ++k) xout[k * n + v] = (R)(d.X0[k * n + v] + (double)d.u[k * n + v]);
 }
 
-// Right-hand side of the correction system per vertex (gather_row), and the
-// block partials of the spring energy.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_gather(Dev<R> d, Consts c) {
-  __shared__ double lds[kBlock / 64];
-  if (is_done(d.st)) return;
-  const int v = blockIdx.x * kBlock + threadIdx.x;
-  const double esp = v < c.n ? gather_row(d, c, v) : 0.0;
-  const double bs = block_sum<kBlock>(esp, lds);
-  if (threadIdx.x == 0) d.part_b[blockIdx.x] = bs;
-}
 
 constexpr int kPcgBlock = kPcgThreads;
 
@@ -410,7 +400,7 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   const int it = st->iters + 1;
   double eloc = 0.0, rloc = 0.0, active = 0.0, bad = 0.0;
   if (!ADJ) {
-    const int gl = c.a_parts, gg = cdiv(c.n, kBlock);
+    const int gl = c.a_parts, gg = gridDim.x;  // spring-energy partials: one per CG block
     for (int b = threadIdx.x; b < gl; b += kPcgBlock) eloc += d.part_a[b];
     for (int b = threadIdx.x; b < gg; b += kPcgBlock) eloc += d.part_b[b];
   }
@@ -534,11 +524,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
 
   // (A) r_0 = b - A x_0 from the warm start x_0; p_{-1} = s_{-1} = 0;
   //     right-hand-side norm b' M^-1 b; a_vj / dg_j.  The adjoint solves start
-  //     from the previous correction.  The forward solve starts from the
-  //     A-norm-best combination x_0 = g1 w1 + g2 w2 of the previous correction
-  //     w1 = d_k and its change w2 = d_k - d_{k-1} (a 2x2 Galerkin projection
-  //     of M d = b onto their span: never a worse start, in the A-norm, than
-  //     d_k alone, and it follows a steady drift of the corrections).
+  //     from the previous correction.  The forward solve first forms its
+  //     right-hand side (phase 0), then starts from the A-norm-best
+  //     combination of the previous correction and its first and second
+  //     differences (a Galerkin projection of M d = b onto their span: never
+  //     a worse start, in the A-norm, than the previous correction alone).
   double acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
   int cur = 0;  // half of the double-buffered CG state holding (r_0, w_0, s_0)
   if (ADJ) {
@@ -608,6 +598,27 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
     }
   } else {
+    // (0) the outer iteration's contact update and right-hand side for the
+    //     block's rows, each by the thread that then runs the row's first
+    //     warm-start pass (which reads only the row's own b and diagonal);
+    //     with self-collision the spatial hash is cleared for the final
+    //     update's insertions (the iteration's tet query has run)
+    {
+      double esp = 0.0;
+      for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
+        if (c.self_col || c.obst_col) {
+          const int s = d.vq[v];
+          if (s >= 0) contacts_one(d, c, s);
+        }
+        esp += gather_row(d, c, v);
+      }
+      if (c.self_col) {
+        for (int i = tid0; i < c.H; i += stride) d.hcount[i] = 0;
+        if (tid0 == 0) d.st->n_over = 0;
+      }
+      const double bs = block_sum<kPcgBlock>(esp, lds);
+      if (threadIdx.x == 0) d.part_b[blockIdx.x] = bs;
+    }
     // history: w1 = d_k, w2 = d_k - d_{k-1}, w3 = d_k - 2 d_{k-1} + d_{k-2}
     // (the last correction, its change and the change's change)
     W4<R>* __restrict__ xp = reinterpret_cast<W4<R>*>(d.dlp);
@@ -627,7 +638,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
 #pragma unroll 1
       for (int k0 = 0; k0 < MW; k0 += CH1) {
         int jj[CH1];
-        R aa[CH1], dgn[CH1];
+        R aa[CH1];
         W4<R> xn[CH1], pn[CH1], qn[CH1];
 #pragma unroll
         for (int k = 0; k < CH1; ++k) {
@@ -636,10 +647,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         }
 #pragma unroll
         for (int k = 0; k < CH1; ++k) {
-          xn[k] = x[jj[k]];
-          pn[k] = xp[jj[k]];
-          qn[k] = xpp[jj[k]];
-          dgn[k] = dg[jj[k]];
+          xn[k] = ld3(x + jj[k]);
+          pn[k] = ld3(xp + jj[k]);
+          qn[k] = ld3(xpp + jj[k]);
         }
 #pragma unroll
         for (int k = 0; k < CH1; ++k) {
@@ -653,7 +663,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           a30 += aa[k] * (d0 - (pn[k].x - qn[k].x));
           a31 += aa[k] * (d1 - (pn[k].y - qn[k].y));
           a32 += aa[k] * (d2 - (pn[k].z - qn[k].z));
-          evs[(size_t)(k0 + k) * n + v] = aa[k] / dgn[k];
         }
       }
       const W4<R> b = cg0[3 * (size_t)v];
@@ -748,20 +757,28 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
 #pragma unroll 1
       for (int k0 = 0; k0 < MW; k0 += CH2) {
         int jj[CH2];
-        R aa[CH2];
+        R aa[CH2], dgn[CH2];
 #pragma unroll
         for (int k = 0; k < CH2; ++k) {
           jj[k] = ecol[(size_t)(k0 + k) * n + v];
-          aa[k] = evs[(size_t)(k0 + k) * n + v];
+          aa[k] = evl[(size_t)(k0 + k) * n + v];
         }
         W4<R> nb[CH2], n1[CH2], n2[CH2], n3[CH2];
 #pragma unroll
         for (int k = 0; k < CH2; ++k) {
           const size_t b3 = 3 * (size_t)jj[k];
-          nb[k] = cg0[b3];
-          n1[k] = cg0[b3 + 1];
-          n2[k] = cg0[b3 + 2];
-          n3[k] = p[jj[k]];
+          nb[k] = ld3(cg0 + b3);
+          n1[k] = ld3(cg0 + b3 + 1);
+          n2[k] = ld3(cg0 + b3 + 2);
+          n3[k] = ld3(p + jj[k]);
+          dgn[k] = dg[jj[k]];
+        }
+        // a_vj / dg_j for the CG iterations (the neighbours' diagonals of
+        // this outer iteration are visible past the barrier above)
+#pragma unroll
+        for (int k = 0; k < CH2; ++k) {
+          aa[k] = aa[k] / dgn[k];
+          evs[(size_t)(k0 + k) * n + v] = aa[k];
         }
 #pragma unroll
         for (int k = 0; k < CH2; ++k) {
@@ -1020,11 +1037,6 @@ hipError_t launch_output(const Dev<R>& d, const Consts& c, R* xout, hipStream_t 
   return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_gather(const Dev<R>& d, const Consts& c, hipStream_t s) {
-  k_gather<R><<<cdiv(c.n, kBlock), kBlock, 0, s>>>(d, c);
-  return hipGetLastError();
-}
 
 // Rows per block of the CG kernel for n rows on a grid of G blocks (a
 // multiple of 64; the kernel derives the same value).
@@ -1076,7 +1088,6 @@ int pcg_max_grid(int ell_w) {
   template hipError_t launch_init<R>(const Dev<R>&, const Consts&, const R*, hipStream_t);      \
   template hipError_t launch_set_positions<R>(const Dev<R>&, const Consts&, const R*, hipStream_t); \
   template hipError_t launch_output<R>(const Dev<R>&, const Consts&, R*, hipStream_t);          \
-  template hipError_t launch_gather<R>(const Dev<R>&, const Consts&, hipStream_t);              \
   template hipError_t launch_pcg<R>(const Dev<R>&, const Consts&, int, hipStream_t, bool, bool); \
   template int pcg_max_grid<R>(int);
 INST(float)
