@@ -394,16 +394,13 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   }
   __syncthreads();
   if (!last) return;
-  // the last block: energy (fixed order per thread, then a fixed tree), and the
-  // per-mesh convergence decisions (r = max|d| / diag, active set unchanged)
+  // the last block: the per-mesh convergence decisions (r = max|d| / diag,
+  // active set unchanged), then, when the iteration is the last or traced,
+  // the energy (fixed order per thread, then a fixed tree); the energy is
+  // reported only, so the other iterations skip its partial sums
   DevStatus* st = d.st;
   const int it = st->iters + 1;
-  double eloc = 0.0, rloc = 0.0, active = 0.0, bad = 0.0;
-  if (!ADJ) {
-    const int gl = c.a_parts, gg = gridDim.x;  // spring-energy partials: one per CG block
-    for (int b = threadIdx.x; b < gl; b += kPcgBlock) eloc += d.part_a[b];
-    for (int b = threadIdx.x; b < gg; b += kPcgBlock) eloc += d.part_b[b];
-  }
+  double rloc = 0.0, active = 0.0, bad = 0.0;
   for (int mi = threadIdx.x; mi < c.M; mi += kPcgBlock) {
     const double dmx = __longlong_as_double((long long)d.mres[mi]);
     double r;
@@ -424,36 +421,28 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
     d.mres[mi] = 0ull;
     if (!ADJ) d.mchanged[mi] = 0;
   }
-  // the four block reductions in one LDS round (per-wave order and fixed tree
-  // of block_sum / block_max)
+  // the three block reductions in one LDS round (per-wave order and fixed
+  // tree of block_sum / block_max); every thread reads the results
   __shared__ double lds4[4][kPcgBlock / 64];
   {
-    const double a = wave_sum(eloc), b = wave_max(rloc), e = wave_sum(active), f = wave_sum(bad);
+    const double b0 = wave_max(rloc), e0 = wave_sum(active), f0 = wave_sum(bad);
     if ((threadIdx.x & 63) == 0) {
       const int w = threadIdx.x >> 6;
-      lds4[0][w] = a;
-      lds4[1][w] = b;
-      lds4[2][w] = e;
-      lds4[3][w] = f;
+      lds4[1][w] = b0;
+      lds4[2][w] = e0;
+      lds4[3][w] = f0;
     }
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  double E = 0.0, res = 0.0, n_act = 0.0, nbad = 0.0;
+  double res = 0.0, n_act = 0.0, nbad = 0.0;
 #pragma unroll
   for (int i = 0; i < kPcgBlock / 64; ++i) {
-    E += lds4[0][i];
     res = fmax(res, lds4[1][i]);
     n_act += lds4[2][i];
     nbad += lds4[3][i];
   }
-  st->residual = res;
-  st->energy = E;
-  st->iters = it;
-  st->n_active = (int)n_act;
-  const int changed = st->changed;
   int code = RUNNING;
-  if (nbad > 0.0 || !(E == E))
+  if (nbad > 0.0)
     code = BREAKDOWN;
   else if (c.fixed_iters > 0)
     code = (it >= c.fixed_iters) ? FIXED_DONE : RUNNING;
@@ -461,6 +450,26 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
     code = CONVERGED;
   else if (it >= c.max_iter)
     code = MAXITER;
+  double E = st->energy;
+  if (!ADJ && (code != RUNNING || it <= c.trace_len)) {  // the same for every thread
+    double eloc = 0.0;
+    const int gl = c.a_parts, gg = gridDim.x;  // spring-energy partials: one per CG block
+    for (int b = threadIdx.x; b < gl; b += kPcgBlock) eloc += d.part_a[b];
+    for (int b = threadIdx.x; b < gg; b += kPcgBlock) eloc += d.part_b[b];
+    const double a0 = wave_sum(eloc);
+    if ((threadIdx.x & 63) == 0) lds4[0][threadIdx.x >> 6] = a0;
+    __syncthreads();
+    E = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPcgBlock / 64; ++i) E += lds4[0][i];
+    if (!(E == E)) code = BREAKDOWN;
+  }
+  if (threadIdx.x != 0) return;
+  st->residual = res;
+  st->energy = E;
+  st->iters = it;
+  st->n_active = (int)n_act;
+  const int changed = st->changed;
   if (it <= c.trace_len) {
     double* row = d.trace + 6 * (size_t)(it - 1);
     row[0] = res;
