@@ -286,7 +286,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(Dev<R> d, Consts c) {
     for (int k = 0; k < 3; ++k) {
       d.mu[k * n + v] = R(0);
       d.acc3[k * n + v] = 0.0;
-      d.dl[4 * (size_t)v + k] = R(0);
+      d.dl[4 * (size_t)v + k] = R(0);  // the CG start and its history: none yet
+      d.dlp[4 * (size_t)v + k] = R(0);
+      d.dlpp[4 * (size_t)v + k] = R(0);
     }
   }
   const int stride = gridDim.x * kBlock;
@@ -833,7 +835,11 @@ __global__ __launch_bounds__(kBlock) void k_unr_rhs(Dev<R> d, Consts c) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       d.mu[k * n + v] = R(0);
+      // each reverse solve starts from zero, with no history (its system
+      // differs from the previous one's)
       d.dl[4 * (size_t)v + k] = R(0);
+      d.dlp[4 * (size_t)v + k] = R(0);
+      d.dlpp[4 * (size_t)v + k] = R(0);
     }
   }
   for (int i = v; i < c.M; i += gridDim.x * kBlock) {

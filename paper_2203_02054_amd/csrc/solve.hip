@@ -532,87 +532,21 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   R* __restrict__ evs = d.ell_scaled;
 
   // (A) r_0 = b - A x_0 from the warm start x_0; p_{-1} = s_{-1} = 0;
-  //     right-hand-side norm b' M^-1 b; a_vj / dg_j.  The adjoint solves start
-  //     from the previous correction.  The forward solve first forms its
-  //     right-hand side (phase 0), then starts from the A-norm-best
-  //     combination of the previous correction and its first and second
-  //     differences (a Galerkin projection of M d = b onto their span: never
-  //     a worse start, in the A-norm, than the previous correction alone).
+  //     right-hand-side norm b' M^-1 b; a_vj / dg_j.  Every solve starts from
+  //     the A-norm-best combination of the previous correction and its first
+  //     and second differences (a Galerkin projection of M d = b onto their
+  //     span: never a worse start, in the A-norm, than the previous correction
+  //     alone).  The forward solve first forms its right-hand side (phase 0);
+  //     the adjoint kernels have formed theirs before the launch.
   double acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
   int cur = 0;  // half of the double-buffered CG state holding (r_0, w_0, s_0)
-  if (ADJ) {
-    for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
-      const R dv = dg[v], idg = R(1) / dv;
-      const W4<R> xv = x[v];
-      R ax0 = dv * xv.x, ax1 = dv * xv.y, ax2 = dv * xv.z;
-#pragma unroll 1
-      for (int k0 = 0; k0 < MW; k0 += CH) {
-        int jj[CH];
-        R aa[CH], dgn[CH];
-        W4<R> xn[CH];
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          jj[k] = ecol[(size_t)(k0 + k) * n + v];
-          aa[k] = evl[(size_t)(k0 + k) * n + v];
-        }
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          xn[k] = x[jj[k]];
-          dgn[k] = dg[jj[k]];
-        }
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          ax0 += aa[k] * xn[k].x;
-          ax1 += aa[k] * xn[k].y;
-          ax2 += aa[k] * xn[k].z;
-          evs[(size_t)(k0 + k) * n + v] = aa[k] / dgn[k];
-        }
-      }
-      const W4<R> b = cg0[3 * (size_t)v];
-      acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
-      cg0[3 * (size_t)v] = w4<R>(b.x - ax0, b.y - ax1, b.z - ax2);
-      cg0[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
-      p[v] = w4<R>(R(0), R(0), R(0));
-    }
-    const double bs = block_sum<kPcgBlock>(acc_b, lds);
-    if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
-    grid_barrier(bc, bar_target, G);
-    // (B) w_0 = A u_0, g_0 = (r_0, u_0), d_0 = (w_0, u_0)
-    for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
-      const R idg = R(1) / dg[v];
-      const W4<R> rv = cg0[3 * (size_t)v];
-      R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
-#pragma unroll 1
-      for (int k0 = 0; k0 < MW; k0 += CH) {
-        int jj[CH];
-        R aa[CH];
-        W4<R> rn[CH];
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          jj[k] = ecol[(size_t)(k0 + k) * n + v];
-          aa[k] = evs[(size_t)(k0 + k) * n + v];
-        }
-#pragma unroll
-        for (int k = 0; k < CH; ++k) rn[k] = cg0[3 * (size_t)jj[k]];
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          a0 += aa[k] * rn[k].x;
-          a1 += aa[k] * rn[k].y;
-          a2 += aa[k] * rn[k].z;
-        }
-      }
-      cg0[3 * (size_t)v + 1] = w4<R>(a0, a1, a2);
-      const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
-      acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
-      acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
-    }
-  } else {
+  {
     // (0) the outer iteration's contact update and right-hand side for the
     //     block's rows, each by the thread that then runs the row's first
     //     warm-start pass (which reads only the row's own b and diagonal);
     //     with self-collision the spatial hash is cleared for the final
     //     update's insertions (the iteration's tet query has run)
-    {
+    if constexpr (!ADJ) {
       double esp = 0.0;
       for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
         if (c.self_col || c.obst_col) {
