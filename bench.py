@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a 256 MiB copy);
 # see profiles/*_hbm_traffic.md.  Only valid for the kernel build the counters
 # were taken on: remove an entry when its kernel changes.
-PMC_TRAFFIC = {}
+PMC_TRAFFIC = {("finger", "pcg"): 16645355}
 
 
 def kernel_bytes(info, W, n_launch, pcg_iters):
@@ -47,10 +47,12 @@ def kernel_bytes(info, W, n_launch, pcg_iters):
     move, each array element counted once per launch (W = 4 or 8 bytes per
     real, int32 indices, collision positions in double).
 
-      pcg        per CG iteration: per row the CG state (r, w, s: 3 vectors of
-                 4 reals) read and written, p and the correction read and
-                 written, the Jacobi diagonal; per off-diagonal entry its column
-                 and value.  Plus the start-up (the warm start: the last three
+      pcg        phase 0, the right-hand-side gather (as `gather` below; the
+                 contact update of the few active contact slots is not
+                 counted).  Per CG iteration: per row the CG state (r, w, s: 3
+                 vectors of 4 reals) read and written, p and the correction read
+                 and written, the Jacobi diagonal; per off-diagonal entry its
+                 column and value.  Plus the start-up (the warm start: the last three
                  corrections, right-hand side and diagonal read, their three
                  products written; the scaled ELL values written; then the
                  start, its residual and w_0 = A u_0 formed, the history moved
@@ -61,7 +63,8 @@ def kernel_bytes(info, W, n_launch, pcg_iters):
                  columns written 4 x 4W; per vertex rest position 24 and
                  displacement 3W read once.
       gather     per incidence one residual column 4W; per vertex the
-                 incidence range 4, right-hand side 4W and two diagonals 2W.
+                 incidence range 4, right-hand side 4W and two diagonals 2W
+                 (the CG kernel's phase 0; the adjoint's own gather kernel).
       tet_query  per tet connectivity 16; per vertex its collision position 24.
       hash_insert per query vertex its id 4, position 24, entry written 32.
     """
@@ -73,9 +76,9 @@ def kernel_bytes(info, W, n_launch, pcg_iters):
     per_it = n * (12 * W * 2 + 8 * W + 8 * W + W) + off * (4 + W)
     startup = n * (29 * W) + off * (4 + 2 * W) + n * (52 * W) + off * (4 + W)
     finish = n * (3 * W + 4 * W + 24) + S * 36
-    out["pcg"] = m * per_it + startup + finish
-    out["local"] = T * (36 + 16 * W) + n * (24 + 3 * W)
     out["gather"] = 4 * T * 4 * W + n * (4 + 6 * W)
+    out["pcg"] = out["gather"] + m * per_it + startup + finish
+    out["local"] = T * (36 + 16 * W) + n * (24 + 3 * W)
     out["tet_query"] = 16 * T + 24 * n
     out["hash_insert"] = S * 60
     return out

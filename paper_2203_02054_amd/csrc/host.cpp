@@ -84,6 +84,21 @@ struct Profiler {
     if (!start) fam.push_back(f);
     return hipEventRecord(pool[i], s);
   }
+  // an event pair for a launch that records the kernel's own start and end
+  hipError_t pair(int f, hipEvent_t& a, hipEvent_t& b) {
+    const size_t i = 2 * fam.size();
+    while (pool.size() <= i + 1) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      pool.push_back(e);
+    }
+    fam.push_back(f);
+    a = pool[i];
+    b = pool[i + 1];
+    return hipSuccess;
+  }
+  void drop_last() { fam.pop_back(); }
   hipError_t flush() {
     for (size_t k = 0; k < fam.size(); ++k) {
       float t = 0.f;
@@ -474,6 +489,21 @@ hipError_t timed(gs_problem* p, int k, F&& launch) {
   return hipSuccess;
 }
 
+// The CG launch, profiled: an ordinary launch carries the events itself, so
+// they bracket the kernel alone (events recorded on the stream around it would
+// add the dispatch gap); a cooperative launch is bracketed as the others.
+template <typename R>
+hipError_t timed_pcg(gs_problem* p, int k, const Dev<R>& d, const Consts& c, bool adjoint) {
+  const bool coop = pcg_cooperative(p);
+  if (!p->prof.on || coop)
+    return timed(p, k, [&] { return launch_pcg<R>(d, c, p->pcg_grid, p->stream, adjoint, coop); });
+  hipEvent_t a, b;
+  hipError_t e = p->prof.pair(k, a, b);
+  if (e != hipSuccess) return e;
+  if ((e = launch_pcg<R>(d, c, p->pcg_grid, p->stream, adjoint, false, a, b)) != hipSuccess) p->prof.drop_last();
+  return e;
+}
+
 // Iteration driver: enqueue `check_every` iterations at a time until the
 // device status says done.  The status after each chunk is copied to pinned
 // host memory behind an event, and the next chunk is enqueued before waiting
@@ -541,7 +571,7 @@ hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, co
   if (!fused_local)
     if ((e = timed(p, K_LOCAL, [&] { return launch_local<R>(d, c, alpha, s); })) != hipSuccess) return e;
   // the CG kernel first updates the contacts and gathers the right-hand side
-  return timed(p, K_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, false, pcg_cooperative(p)); });
+  return timed_pcg<R>(p, K_PCG, d, c, false);
 }
 
 template <typename R>
@@ -605,7 +635,7 @@ gs_status adjoint_impl(gs_problem* p, const R* gL, R* dalpha, R* mu_out, gs_stat
     if ((e = timed(p, K_ADJ_SPRINGS, [&] { return launch_adj_springs<R>(d, c, s); })) != hipSuccess) return e;
     if ((e = timed(p, K_ADJ_LOCAL, [&] { return launch_adj_local<R>(d, c, false, s); })) != hipSuccess) return e;
     if ((e = timed(p, K_ADJ_GATHER, [&] { return launch_adj_gather<R>(d, c, s); })) != hipSuccess) return e;
-    if ((e = timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(d, c, p->pcg_grid, s, true, pcg_cooperative(p)); })) != hipSuccess) return e;
+    if ((e = timed_pcg<R>(p, K_ADJ_PCG, d, c, true)) != hipSuccess) return e;
     return launch_adj_anderson<R>(d, c, s);
   };
   const gs_status ds = drive(p, d.st, c.max_iter, one, h);
@@ -1163,7 +1193,7 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
       HIPCHK(launch_unr_restore<R>(d, cf, run, s));
       p->hash_ready = false;
       HIPCHK(launch_unr_rhs<R>(dc, cc, s));
-      HIPCHK(timed(p, K_ADJ_PCG, [&] { return launch_pcg<R>(dc, cc, p->pcg_grid, s, true, pcg_cooperative(p)); }));
+      HIPCHK(timed_pcg<R>(p, K_ADJ_PCG, dc, cc, true));
       HIPCHK(timed(p, K_ADJ_SPRINGS, [&] { return launch_adj_springs<R>(dv, cv, s); }));
       HIPCHK(timed(p, K_ADJ_LOCAL, [&] { return launch_adj_local_mode<R>(dv, cv, ADJ_JT, s); }));
       HIPCHK(timed(p, K_ADJ_GATHER, [&] { return launch_adj_gather<R>(dv, cv, s); }));

@@ -175,7 +175,8 @@ template <typename R> hipError_t launch_query_local(const Dev<R>& d, const Const
 template <typename R> hipError_t launch_local_debug(const Dev<R>& d, const Consts& c, const R* alpha, const R* x,
                                                     R* targets, hipStream_t s);
 template <typename R>
-hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint, bool cooperative);
+hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint, bool cooperative,
+                      hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // implicit adjoint
 template <typename R> hipError_t launch_adj_init(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_adj_springs(const Dev<R>& d, const Consts& c, hipStream_t s);

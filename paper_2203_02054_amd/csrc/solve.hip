@@ -4,8 +4,9 @@
 // With targets fixed, Eq. (9) is minimised by M x = b, M = A_el + diag(k)
 // (springs), fixed vertices held at X0.  The iterate is the displacement
 // u = x - X0; each outer iteration solves M d = b - M x_k for the correction d
-// with a Jacobi-preconditioned conjugate gradient warm-started at the previous
-// correction d_{k-1} and stopped once sqrt(r'z) <= eta sqrt(b'D^-1 b), b the
+// with a Jacobi-preconditioned conjugate gradient warm-started from the
+// previous corrections (the Galerkin projection onto d_{k-1} and its first and
+// second differences) and stopped once sqrt(r'z) <= eta sqrt(b'D^-1 b), b the
 // right-hand side (relative to b, not to the warm-started residual).  The
 // slow modes of the local/global map are smooth bending modes, where both the
 // outer iteration and Jacobi-CG converge slowly; the warm start carries the
@@ -14,11 +15,14 @@
 // pulls k (c - x): it vanishes exactly at the fixed point, so an inexact inner
 // solve changes the path, not the answer.
 //
-// The CG runs as one cooperative kernel on a small grid (every block
-// resident): the per-barrier cost on this GPU grows with the number of
+// The CG runs as one persistent kernel on a small grid (every block resident:
+// an ordinary launch when the grid is at most half the resident capacity, a
+// cooperative launch otherwise): the per-barrier cost on this GPU grows with the number of
 // participating blocks, so the solve uses few, wide blocks.  Dot products are
 // accumulated in double; block partials are summed in block order by every
 // block, so all blocks take identical decisions.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <type_traits>
 
@@ -1000,11 +1004,14 @@ const void* pcg_kernel(int ell_w, bool adjoint, bool pair) {
 }
 
 template <typename R>
-hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint, bool cooperative) {
+hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint, bool cooperative,
+                      hipEvent_t ev_start, hipEvent_t ev_stop) {
   void* args[] = {(void*)&d, (void*)&c};
   const bool pair = std::is_same<R, float>::value && c.ell_w <= 16 && 2 * pcg_chunk(c.n, grid) <= kPcgBlock;
   const void* f = pcg_kernel<R>(c.ell_w, adjoint, pair);
   if (cooperative) return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
+  if (ev_start || ev_stop)  // the events take the kernel's own start and end times
+    return hipExtLaunchKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s, ev_start, ev_stop, 0);
   return hipLaunchKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
 }
 
@@ -1031,7 +1038,7 @@ int pcg_max_grid(int ell_w) {
   template hipError_t launch_init<R>(const Dev<R>&, const Consts&, const R*, hipStream_t);      \
   template hipError_t launch_set_positions<R>(const Dev<R>&, const Consts&, const R*, hipStream_t); \
   template hipError_t launch_output<R>(const Dev<R>&, const Consts&, R*, hipStream_t);          \
-  template hipError_t launch_pcg<R>(const Dev<R>&, const Consts&, int, hipStream_t, bool, bool); \
+  template hipError_t launch_pcg<R>(const Dev<R>&, const Consts&, int, hipStream_t, bool, bool, hipEvent_t, hipEvent_t); \
   template int pcg_max_grid<R>(int);
 INST(float)
 INST(double)
