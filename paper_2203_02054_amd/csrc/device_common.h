@@ -15,6 +15,36 @@ struct alignas(4 * sizeof(R)) W4 {
   R x, y, z, w;
 };
 
+// Store of a W4 with the sc1 cache policy: written through to the device's
+// coherence point instead of left dirty in the XCD's L2.  The grid barrier's
+// agent-scope release writes back every dirty L2 line, which costs time in
+// proportion to what is dirty; state that other workgroups read after a
+// barrier is stored this way, so that write-back finds little to do.  The
+// release and acquire fences stay as they are.  `base` must be the same for
+// the whole wavefront (it forms the buffer descriptor) and `i` is an element
+// index from it with i * sizeof(W4) < 2^31.
+template <typename R>
+__device__ __forceinline__ void st_wt(W4<R>* base, unsigned i, const W4<R>& v) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  constexpr int kSc1 = 16;                  // cache-policy operand of the buffer store: sc1
+  constexpr int kRawDword3 = 0x00020000;    // raw buffer descriptor word 3 (32-bit data format)
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, 0x7fffffff, kRawDword3);
+  if constexpr (sizeof(R) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, i * 16u, 0, kSc1);
+  } else {
+    struct Half {
+      R a, b;
+    };
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, Half{v.x, v.y}), r, i * 32u, 0, kSc1);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, Half{v.z, v.w}), r, i * 32u + 16u, 0, kSc1);
+  }
+}
+
+// A double partial sum stored the same way (an agent-scope relaxed store).
+__device__ __forceinline__ void st_wt(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Sum of the incidence columns res[i0, i1) into double accumulators, in index
 // order; the loads are issued 8 at a time so their latencies overlap.
 template <typename R>

@@ -165,8 +165,8 @@ __device__ __forceinline__ void block_sum2_store(double a, double b, double (*ld
       ta += lds[0][i];
       tb += lds[1][i];
     }
-    *out_a = ta;
-    *out_b = tb;
+    st_wt(out_a, ta);
+    st_wt(out_b, tb);
   }
 }
 
@@ -187,7 +187,7 @@ __device__ __forceinline__ void block_sums_store(const double (&v)[K], double (*
     double t = 0.0;
 #pragma unroll
     for (int j = 0; j < kPcgBlock / 64; ++j) t += lds[threadIdx.x][j];
-    base[(size_t)threadIdx.x * stride] = t;
+    st_wt(base + (size_t)threadIdx.x * stride, t);
   }
 }
 
@@ -625,9 +625,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
                            ((double)w3.x * a30 + (double)w3.y * a31) + (double)w3.z * a32};
       // A w1, A w2, A w3 until the second pass (p is free until the first CG
       // iteration, which takes p_{-1} = 0 without reading it)
-      cg0[3 * (size_t)v + 1] = w4<R>(a10, a11, a12);
-      cg0[3 * (size_t)v + 2] = w4<R>(a20, a21, a22);
-      p[v] = w4<R>(a30, a31, a32);
+      // read by neighbouring rows of other blocks after the barrier
+      st_wt(cg0 + 3 * (size_t)row0, 3u * (v - row0) + 1u, w4<R>(a10, a11, a12));
+      st_wt(cg0 + 3 * (size_t)row0, 3u * (v - row0) + 2u, w4<R>(a20, a21, a22));
+      st_wt(p + row0, (unsigned)(v - row0), w4<R>(a30, a31, a32));
       if (c.M > 1) {
         // a batch projects on (w1, w2): per-row terms, summed per mesh below,
         // in the half of the CG state the first iteration has yet to write
@@ -736,13 +737,15 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       }
       const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
       const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
-      x[v] = w4<R>(r1 * w1.x + r2 * w2.x + r3 * w3.x, r1 * w1.y + r2 * w2.y + r3 * w3.y,
-                   r1 * w1.z + r2 * w2.z + r3 * w3.z);
-      xpp[v] = wp;
-      xp[v] = w1;
-      ns[3 * (size_t)v] = rv;
-      ns[3 * (size_t)v + 1] = w4<R>(a0, a1, a2);
-      ns[3 * (size_t)v + 2] = w4<R>(R(0), R(0), R(0));
+      const unsigned vi = (unsigned)(v - row0);
+      st_wt(x + row0, vi,
+            w4<R>(r1 * w1.x + r2 * w2.x + r3 * w3.x, r1 * w1.y + r2 * w2.y + r3 * w3.y,
+                  r1 * w1.z + r2 * w2.z + r3 * w3.z));
+      st_wt(xpp + row0, vi, wp);
+      st_wt(xp + row0, vi, w1);
+      st_wt(ns + 3 * (size_t)row0, 3u * vi, rv);
+      st_wt(ns + 3 * (size_t)row0, 3u * vi + 1u, w4<R>(a0, a1, a2));
+      st_wt(ns + 3 * (size_t)row0, 3u * vi + 2u, w4<R>(R(0), R(0), R(0)));
       const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
       acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
       acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
@@ -876,9 +879,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           const W4<R> wn = pv_half == 0 ? w4<R>(rv.x + a0 + b0, rv.y + a1 + b1, rv.z + a2 + b2)
                                         : w4<R>(rv.x + b0 + a0, rv.y + b1 + a1, rv.z + b2 + a2);
           if (pv_half == 0) {
-            ns[3 * (size_t)pv_row] = rv;
-            ns[3 * (size_t)pv_row + 1] = wn;
-            ns[3 * (size_t)pv_row + 2] = sv;
+            const unsigned vi = 3u * (unsigned)(pv_row - row0);
+            st_wt(ns + 3 * (size_t)row0, vi, rv);
+            st_wt(ns + 3 * (size_t)row0, vi + 1u, wn);
+            st_wt(ns + 3 * (size_t)row0, vi + 2u, sv);
             const R u0 = rv.x * pidg, u1 = rv.y * pidg, u2 = rv.z * pidg;
             acc_g = ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
             acc_d = ((double)wn.x * u0 + (double)wn.y * u1) + (double)wn.z * u2;
@@ -912,8 +916,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       const W4<R> pv = w4<R>(rc.x * idg + rb * pv0.x, rc.y * idg + rb * pv0.y, rc.z * idg + rb * pv0.z);
       const W4<R> sv = w4<R>(wc.x + rb * sc.x, wc.y + rb * sc.y, wc.z + rb * sc.z);
       const W4<R> rv = w4<R>(rc.x - ra * sv.x, rc.y - ra * sv.y, rc.z - ra * sv.z);
-      p[v] = pv;
-      x[v] = w4<R>(xv.x + ra * pv.x, xv.y + ra * pv.y, xv.z + ra * pv.z);
+      const unsigned vi = (unsigned)(v - row0);
+      st_wt(p + row0, vi, pv);
+      st_wt(x + row0, vi, w4<R>(xv.x + ra * pv.x, xv.y + ra * pv.y, xv.z + ra * pv.z));
       R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
 #pragma unroll 1
       for (int k0 = 0; k0 < MW; k0 += CH) {
@@ -939,9 +944,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           a2 += aa[k] * (nr[k].z - ra * (nw[k].z + rb * nsv[k].z));
         }
       }
-      ns[3 * (size_t)v] = rv;
-      ns[3 * (size_t)v + 1] = w4<R>(a0, a1, a2);
-      ns[3 * (size_t)v + 2] = sv;
+      st_wt(ns + 3 * (size_t)row0, 3u * vi, rv);
+      st_wt(ns + 3 * (size_t)row0, 3u * vi + 1u, w4<R>(a0, a1, a2));
+      st_wt(ns + 3 * (size_t)row0, 3u * vi + 2u, sv);
       const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
       acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
       acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
