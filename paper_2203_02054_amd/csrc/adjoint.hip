@@ -580,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_gather(Dev<R> d, Consts c) {
   rb.y = (R)r1;
   rb.z = (R)r2;
   rb.w = R(0);
-  reinterpret_cast<A4<R>*>(d.cg)[3 * (size_t)v] = rb;
+  reinterpret_cast<A4<R>*>(d.cg)[c.cg_soa ? (size_t)v : 3 * (size_t)v] = rb;
   d.dg[v] = d.freem[v] ? (R)((double)d.adiag[v] + ds) : R(1);
 }
 
@@ -830,7 +830,7 @@ __global__ __launch_bounds__(kBlock) void k_unr_rhs(Dev<R> d, Consts c) {
     rb.y = fr ? d.lam[n + v] : R(0);
     rb.z = fr ? d.lam[2 * n + v] : R(0);
     rb.w = R(0);
-    reinterpret_cast<A4<R>*>(d.cg)[3 * (size_t)v] = rb;
+    reinterpret_cast<A4<R>*>(d.cg)[c.cg_soa ? (size_t)v : 3 * (size_t)v] = rb;
     d.dg[v] = fr ? (R)((double)d.adiag[v] + ds) : R(1);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {

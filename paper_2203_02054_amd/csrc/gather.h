@@ -9,7 +9,8 @@
 
 namespace gs {
 
-template <typename R>
+// SOA: the CG state's layout (three arrays of rows, else rows of three vectors).
+template <bool SOA, typename R>
 __device__ __forceinline__ double gather_row(const Dev<R>& d, const Consts& c, int v) {
   const size_t n = (size_t)c.n;
   double esp = 0.0;
@@ -41,7 +42,7 @@ __device__ __forceinline__ double gather_row(const Dev<R>& d, const Consts& c, i
   rb.y = (R)r1;
   rb.z = (R)r2;
   rb.w = R(0);
-  reinterpret_cast<W4<R>*>(d.cg)[3 * (size_t)v] = rb;
+  reinterpret_cast<W4<R>*>(d.cg)[SOA ? (size_t)v : 3 * (size_t)v] = rb;
   d.dsp[v] = (R)ds;
   d.dg[v] = d.freem[v] ? (R)((double)d.adiag[v] + ds) : R(1);
   return esp;

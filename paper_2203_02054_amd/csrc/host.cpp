@@ -380,6 +380,7 @@ Consts make_consts(const gs_problem* p) {
   // kTetQueryWide tets with self-collision, else on its own (one per tet)
   c.a_parts = (p->prm.self_collision && p->T < kTetQueryWide) ? cdiv(4L * p->T, kBlock) : cdiv(p->T, kBlock);
   c.ell_w = p->ell_w;
+  c.cg_soa = pcg_paired(p->prec, p->ell_w, p->n, p->pcg_grid) ? 1 : 0;
   c.trace_len = p->trace_len;
   c.c1 = p->prm.c1;
   c.c2 = p->prm.c2;

@@ -70,6 +70,7 @@ struct Consts {
   int aa_m;             // adjoint: Anderson memory (0: plain fixed-point iteration)
   int adj_jt;           // adjoint gather writes (db/dx)^T mu alone to `lam` (unrolled reverse sweep)
   int a_parts;          // energy partials the local step writes per iteration (part_a)
+  int cg_soa;           // CG state layout for the current grid: 1 = [3][n] (paired variant), 0 = [n][3]
   double c1, c2, kappa, tol, pcg_eta;
 };
 
@@ -101,7 +102,7 @@ struct Dev {
   R* u;                    // [3][n] displacement from X0
   double* xc;              // [3][n] X0 + u in double (collision positions)
   R* res4;                 // [4T][4] element residual columns in incidence order
-  R* cg;                   // [2][n][3][4] CG state per row, two buffers: r, w = A M^-1 r, s = A p
+  R* cg;                   // [2][3n][4] CG state, two buffers of r, w = A M^-1 r, s = A p: [3][n] or [n][3] (cg_soa)
                            //   (each as x, y, z, pad); buffer 0 holds the right-hand side on entry
   R* dl;                   // [n][4] correction (kept across iterations: the warm start)
   R* dlp;                  // [n][4] correction of the previous outer iteration
@@ -198,5 +199,16 @@ template <typename R> hipError_t launch_set_positions(const Dev<R>& d, const Con
 template <typename R> int pcg_max_grid(int ell_w);
 
 __host__ __device__ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Rows per block of the CG kernel for n rows on a grid of G blocks (a
+// multiple of 64; the kernel derives the same value).
+__host__ __device__ inline int pcg_chunk(int n, int G) { return (cdiv(n, G) + 63) & ~63; }
+
+// Whether a CG launch on G blocks runs the paired-lane variant (FP32, ELL
+// width 16, at most one lane pair per row).  That variant keeps the CG state
+// as three arrays of rows, the others as rows of three vectors (Consts::cg_soa).
+__host__ __device__ inline bool pcg_paired(int real_bytes, int ell_w, int n, int G) {
+  return real_bytes == 4 && ell_w <= 16 && 2 * pcg_chunk(n, G) <= kPcgThreads;
+}
 
 }  // namespace gs

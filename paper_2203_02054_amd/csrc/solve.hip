@@ -306,8 +306,9 @@ __device__ __forceinline__ void galerkin_weights3(double e1, double e2, double e
 // matrix-vector product, so one grid-wide reduction (one barrier) per
 // iteration suffices.  The product w_{i+1} = A M^-1 r_{i+1} needs r_{i+1} at
 // neighbouring rows; each block rebuilds those values from the neighbours'
-// previous state (r_i, w_i, s_{i-1}: three 16-byte vectors per row, in the
-// other half of a double buffer) instead of waiting for a second barrier.
+// previous state (r_i, w_i, s_{i-1}: one 16-byte vector per row in each of
+// three arrays, in the other half of a double buffer) instead of waiting for
+// a second barrier.
 //
 //   p_i = u_i + b_i p_{i-1}        s_i = w_i + b_i s_{i-1}      (s_i = A p_i)
 //   x_{i+1} = x_i + a_i p_i        r_{i+1} = r_i - a_i s_i      u = M^-1 r
@@ -514,6 +515,13 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   const int stride = G * kPcgBlock;
   const int tid0 = blockIdx.x * kPcgBlock + threadIdx.x;
   const size_t n = (size_t)c.n;
+  // CG state layout: element q (r, w, s) of row v at q * qs + v * vs in each
+  // half.  The paired variant keeps three arrays of rows, so a wavefront's
+  // (write-through) store covers whole cache lines; the others keep rows of
+  // three vectors, one neighbour's state in one 48- or 96-byte record, which
+  // suits their bandwidth-bound gathers.
+  constexpr bool SOA = PAIR;
+  const size_t qs = SOA ? n : 1, vs = SOA ? 1 : 3;
   // each block owns one contiguous range of rows (a multiple of 64 long), so
   // the rows spread over all G blocks however many rows a thread gets
   const int chunk = ((c.n + G - 1) / G + 63) & ~63;
@@ -557,7 +565,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           const int s = d.vq[v];
           if (s >= 0) contacts_one(d, c, s);
         }
-        esp += gather_row(d, c, v);
+        esp += gather_row<SOA>(d, c, v);
       }
       if (c.self_col) {
         for (int i = tid0; i < c.H; i += stride) d.hcount[i] = 0;
@@ -612,7 +620,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           a32 += aa[k] * (d2 - (pn[k].z - qn[k].z));
         }
       }
-      const W4<R> b = cg0[3 * (size_t)v];
+      const W4<R> b = cg0[v * vs];
       acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
       const double t[9] = {((double)w1.x * b.x + (double)w1.y * b.y) + (double)w1.z * b.z,
                            ((double)w2.x * b.x + (double)w2.y * b.y) + (double)w2.z * b.z,
@@ -626,8 +634,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       // A w1, A w2, A w3 until the second pass (p is free until the first CG
       // iteration, which takes p_{-1} = 0 without reading it)
       // read by neighbouring rows of other blocks after the barrier
-      st_wt(cg0 + 3 * (size_t)row0, 3u * (v - row0) + 1u, w4<R>(a10, a11, a12));
-      st_wt(cg0 + 3 * (size_t)row0, 3u * (v - row0) + 2u, w4<R>(a20, a21, a22));
+      st_wt(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a10, a11, a12));
+      st_wt(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a20, a21, a22));
       st_wt(p + row0, (unsigned)(v - row0), w4<R>(a30, a31, a32));
       if (c.M > 1) {
         // a batch projects on (w1, w2): per-row terms, summed per mesh below,
@@ -698,7 +706,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       }
       const R idg = R(1) / dg[v];
       const W4<R> w1 = x[v], wp = xp[v], wpp = xpp[v];
-      const W4<R> b = cg0[3 * (size_t)v], aw1 = cg0[3 * (size_t)v + 1], aw2 = cg0[3 * (size_t)v + 2], aw3 = p[v];
+      const W4<R> b = cg0[v * vs], aw1 = cg0[qs + v * vs], aw2 = cg0[2 * qs + v * vs], aw3 = p[v];
       const W4<R> rv = w4<R>(b.x - r1 * aw1.x - r2 * aw2.x - r3 * aw3.x, b.y - r1 * aw1.y - r2 * aw2.y - r3 * aw3.y,
                              b.z - r1 * aw1.z - r2 * aw2.z - r3 * aw3.z);
       R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
@@ -714,10 +722,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         W4<R> nb[CH2], n1[CH2], n2[CH2], n3[CH2];
 #pragma unroll
         for (int k = 0; k < CH2; ++k) {
-          const size_t b3 = 3 * (size_t)jj[k];
-          nb[k] = ld3(cg0 + b3);
-          n1[k] = ld3(cg0 + b3 + 1);
-          n2[k] = ld3(cg0 + b3 + 2);
+          nb[k] = ld3(cg0 + jj[k] * vs);
+          n1[k] = ld3(cg0 + qs + jj[k] * vs);
+          n2[k] = ld3(cg0 + 2 * qs + jj[k] * vs);
           n3[k] = ld3(p + jj[k]);
           dgn[k] = dg[jj[k]];
         }
@@ -743,9 +750,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
                   r1 * w1.z + r2 * w2.z + r3 * w3.z));
       st_wt(xpp + row0, vi, wp);
       st_wt(xp + row0, vi, w1);
-      st_wt(ns + 3 * (size_t)row0, 3u * vi, rv);
-      st_wt(ns + 3 * (size_t)row0, 3u * vi + 1u, w4<R>(a0, a1, a2));
-      st_wt(ns + 3 * (size_t)row0, 3u * vi + 2u, w4<R>(R(0), R(0), R(0)));
+      st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
+      st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
+      st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), w4<R>(R(0), R(0), R(0)));
       const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
       acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
       acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
@@ -769,10 +776,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     if (pv_has) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const size_t b3 = 3 * (size_t)pj[k];
-        nr[k] = ld3(cs + b3);
-        nw[k] = ld3(cs + b3 + 1);
-        nsv[k] = ld3(cs + b3 + 2);
+        nr[k] = ld3(cs + pj[k] * vs);
+        nw[k] = ld3(cs + qs + pj[k] * vs);
+        nsv[k] = ld3(cs + 2 * qs + pj[k] * vs);
       }
     }
   };
@@ -784,9 +790,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         pj[k] = ecol[(size_t)(8 * pv_half + k) * n + pv_row];
         pa[k] = evs[(size_t)(8 * pv_half + k) * n + pv_row];
       }
-      prc = cs[3 * (size_t)pv_row];
-      pwc = cs[3 * (size_t)pv_row + 1];
-      psc = cs[3 * (size_t)pv_row + 2];
+      prc = cs[pv_row * vs];
+      pwc = cs[qs + pv_row * vs];
+      psc = cs[2 * qs + pv_row * vs];
       ppv = w4<R>(R(0), R(0), R(0));  // p_{-1} = 0
       pxv = x[pv_row];
       pidg = R(1) / dg[pv_row];
@@ -879,10 +885,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           const W4<R> wn = pv_half == 0 ? w4<R>(rv.x + a0 + b0, rv.y + a1 + b1, rv.z + a2 + b2)
                                         : w4<R>(rv.x + b0 + a0, rv.y + b1 + a1, rv.z + b2 + a2);
           if (pv_half == 0) {
-            const unsigned vi = 3u * (unsigned)(pv_row - row0);
-            st_wt(ns + 3 * (size_t)row0, vi, rv);
-            st_wt(ns + 3 * (size_t)row0, vi + 1u, wn);
-            st_wt(ns + 3 * (size_t)row0, vi + 2u, sv);
+            const unsigned vi = (unsigned)(pv_row - row0);
+            st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
+            st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), wn);
+            st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), sv);
             const R u0 = rv.x * pidg, u1 = rv.y * pidg, u2 = rv.z * pidg;
             acc_g = ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
             acc_d = ((double)wn.x * u0 + (double)wn.y * u1) + (double)wn.z * u2;
@@ -910,7 +916,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     acc_d = 0.0;
     for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       const R idg = R(1) / dg[v];
-      const W4<R> rc = cs[3 * (size_t)v], wc = cs[3 * (size_t)v + 1], sc = cs[3 * (size_t)v + 2];
+      const W4<R> rc = cs[v * vs], wc = cs[qs + v * vs], sc = cs[2 * qs + v * vs];
       const W4<R> pv0 = p[v];  // at i = 0 b_0 = 0: p_{-1} enters as 0 * (finite start-up data)
       const W4<R> xv = x[v];
       const W4<R> pv = w4<R>(rc.x * idg + rb * pv0.x, rc.y * idg + rb * pv0.y, rc.z * idg + rb * pv0.z);
@@ -932,10 +938,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         W4<R> nr[CH], nw[CH], nsv[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-          const size_t b3 = 3 * (size_t)jj[k];
-          nr[k] = ld3(cs + b3);
-          nw[k] = ld3(cs + b3 + 1);
-          nsv[k] = ld3(cs + b3 + 2);
+          nr[k] = ld3(cs + jj[k] * vs);
+          nw[k] = ld3(cs + qs + jj[k] * vs);
+          nsv[k] = ld3(cs + 2 * qs + jj[k] * vs);
         }
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
@@ -944,9 +949,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           a2 += aa[k] * (nr[k].z - ra * (nw[k].z + rb * nsv[k].z));
         }
       }
-      st_wt(ns + 3 * (size_t)row0, 3u * vi, rv);
-      st_wt(ns + 3 * (size_t)row0, 3u * vi + 1u, w4<R>(a0, a1, a2));
-      st_wt(ns + 3 * (size_t)row0, 3u * vi + 2u, sv);
+      st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
+      st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
+      st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), sv);
       const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
       acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
       acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
@@ -990,9 +995,6 @@ hipError_t launch_output(const Dev<R>& d, const Consts& c, R* xout, hipStream_t 
 }
 
 
-// Rows per block of the CG kernel for n rows on a grid of G blocks (a
-// multiple of 64; the kernel derives the same value).
-inline int pcg_chunk(int n, int G) { return (cdiv(n, G) + 63) & ~63; }
 
 // The CG kernel for a matrix of ELL width ell_w; pair selects the
 // paired-lane variant (FP32, width 16 only).
@@ -1012,7 +1014,10 @@ template <typename R>
 hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint, bool cooperative,
                       hipEvent_t ev_start, hipEvent_t ev_stop) {
   void* args[] = {(void*)&d, (void*)&c};
-  const bool pair = std::is_same<R, float>::value && c.ell_w <= 16 && 2 * pcg_chunk(c.n, grid) <= kPcgBlock;
+  const bool pair = pcg_paired((int)sizeof(R), c.ell_w, c.n, grid);
+  // the adjoint kernels wrote the right-hand side in the layout of the grid
+  // the constants were made for
+  if (adjoint && c.cg_soa != (pair ? 1 : 0)) return hipErrorInvalidValue;
   const void* f = pcg_kernel<R>(c.ell_w, adjoint, pair);
   if (cooperative) return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
   if (ev_start || ev_stop)  // the events take the kernel's own start and end times
