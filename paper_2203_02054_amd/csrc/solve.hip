@@ -552,6 +552,23 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   //     the adjoint kernels have formed theirs before the launch.
   double acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
   int cur = 0;  // half of the double-buffered CG state holding (r_0, w_0, s_0)
+  // PAIR: lanes 2i and 2i+1 share row row0 + i from the start-up on, each
+  // taking 8 of the row's 16 neighbour slots; the row's state passes from
+  // phase to phase in registers
+  const int pv_row = row0 + (int)(threadIdx.x >> 1), pv_half = (int)(threadIdx.x & 1);
+  const bool pv_has = PAIR && pv_row < row1;
+  int pj[8];
+  R pa[8];
+  W4<R> prc, pwc, psc, ppv, pxv;
+  R pidg = R(0);
+  W4<R> pb, pw1, pwp, pwpp, paw1, paw2, paw3;  // b, the history and its products
+  R pdv = R(0);
+  // sum of a row's own term and its two lanes' partial neighbour sums, in the
+  // same order on both lanes: own, slots 0-7, slots 8-15
+  auto pair_sum = [&](R own, R part) {
+    const R o = __shfl_xor(part, 1, 64);
+    return pv_half == 0 ? (own + part) + o : (own + o) + part;
+  };
   {
     // (0) the outer iteration's contact update and right-hand side for the
     //     block's rows, each by the thread that then runs the row's first
@@ -560,12 +577,22 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     //     update's insertions (the iteration's tet query has run)
     if constexpr (!ADJ) {
       double esp = 0.0;
-      for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
-        if (c.self_col || c.obst_col) {
-          const int s = d.vq[v];
-          if (s >= 0) contacts_one(d, c, s);
+      if constexpr (PAIR) {
+        if (pv_has) {
+          if (pv_half == 0 && (c.self_col || c.obst_col)) {
+            const int s = d.vq[pv_row];
+            if (s >= 0) contacts_one(d, c, s);
+          }
+          esp = gather_row_pair<SOA>(d, c, pv_row, pv_half, pb, pdv);
         }
-        esp += gather_row<SOA>(d, c, v);
+      } else {
+        for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
+          if (c.self_col || c.obst_col) {
+            const int s = d.vq[v];
+            if (s >= 0) contacts_one(d, c, s);
+          }
+          esp += gather_row<SOA>(d, c, v);
+        }
       }
       if (c.self_col) {
         for (int i = tid0; i < c.H; i += stride) d.hcount[i] = 0;
@@ -579,76 +606,153 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     W4<R>* __restrict__ xp = reinterpret_cast<W4<R>*>(d.dlp);
     W4<R>* __restrict__ xpp = reinterpret_cast<W4<R>*>(d.dlpp);
     double tq[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // e1 e2 e3 h11 h12 h13 h22 h23 h33
-    // neighbour slots per gather round: all 16 at once for the latency-bound
-    // paired variant, 8 in the unpaired kernel, whose registers the CG loop sets
-    constexpr int CH1 = PAIR ? CH : (CH < 8 ? CH : 8);
-    for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
-      const R dv = dg[v], idg = R(1) / dv;
-      const W4<R> w1 = x[v], wp = xp[v], wpp = xpp[v];
-      const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
-      const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
-      R a10 = dv * w1.x, a11 = dv * w1.y, a12 = dv * w1.z;
-      R a20 = dv * w2.x, a21 = dv * w2.y, a22 = dv * w2.z;
-      R a30 = dv * w3.x, a31 = dv * w3.y, a32 = dv * w3.z;
-#pragma unroll 1
-      for (int k0 = 0; k0 < MW; k0 += CH1) {
-        int jj[CH1];
-        R aa[CH1];
-        W4<R> xn[CH1], pn[CH1], qn[CH1];
+    // unpaired kernels: 8 neighbour slots per gather round (the CG loop sets
+    // their registers); the paired kernel's lanes take 8 slots each
+    constexpr int CH1 = CH < 8 ? CH : 8;
+    if constexpr (PAIR) {
+      if (pv_has) {
+        const int v = pv_row;
+        if constexpr (ADJ) {  // the adjoint kernels formed b and the diagonal
+          pb = cg0[v * vs];
+          pdv = dg[v];
+        }
+        const R dv = pdv, idg = R(1) / dv;
+        pw1 = x[v];
+        pwp = xp[v];
+        pwpp = xpp[v];
+        const W4<R> w1 = pw1, wp = pwp, wpp = pwpp;
+        const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
+        const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
+        R s10 = R(0), s11 = R(0), s12 = R(0), s20 = R(0), s21 = R(0), s22 = R(0), s30 = R(0), s31 = R(0), s32 = R(0);
+        W4<R> xn[8], pn[8], qn[8];
 #pragma unroll
-        for (int k = 0; k < CH1; ++k) {
-          jj[k] = ecol[(size_t)(k0 + k) * n + v];
-          aa[k] = evl[(size_t)(k0 + k) * n + v];
+        for (int k = 0; k < 8; ++k) {
+          pj[k] = ecol[(size_t)(8 * pv_half + k) * n + v];
+          pa[k] = evl[(size_t)(8 * pv_half + k) * n + v];
         }
 #pragma unroll
-        for (int k = 0; k < CH1; ++k) {
-          xn[k] = ld3(x + jj[k]);
-          pn[k] = ld3(xp + jj[k]);
-          qn[k] = ld3(xpp + jj[k]);
+        for (int k = 0; k < 8; ++k) {
+          xn[k] = ld3(x + pj[k]);
+          pn[k] = ld3(xp + pj[k]);
+          qn[k] = ld3(xpp + pj[k]);
         }
 #pragma unroll
-        for (int k = 0; k < CH1; ++k) {
+        for (int k = 0; k < 8; ++k) {
           const R d0 = xn[k].x - pn[k].x, d1 = xn[k].y - pn[k].y, d2 = xn[k].z - pn[k].z;
-          a10 += aa[k] * xn[k].x;
-          a11 += aa[k] * xn[k].y;
-          a12 += aa[k] * xn[k].z;
-          a20 += aa[k] * d0;
-          a21 += aa[k] * d1;
-          a22 += aa[k] * d2;
-          a30 += aa[k] * (d0 - (pn[k].x - qn[k].x));
-          a31 += aa[k] * (d1 - (pn[k].y - qn[k].y));
-          a32 += aa[k] * (d2 - (pn[k].z - qn[k].z));
+          s10 += pa[k] * xn[k].x;
+          s11 += pa[k] * xn[k].y;
+          s12 += pa[k] * xn[k].z;
+          s20 += pa[k] * d0;
+          s21 += pa[k] * d1;
+          s22 += pa[k] * d2;
+          s30 += pa[k] * (d0 - (pn[k].x - qn[k].x));
+          s31 += pa[k] * (d1 - (pn[k].y - qn[k].y));
+          s32 += pa[k] * (d2 - (pn[k].z - qn[k].z));
+        }
+        const R a10 = pair_sum(dv * w1.x, s10), a11 = pair_sum(dv * w1.y, s11), a12 = pair_sum(dv * w1.z, s12);
+        const R a20 = pair_sum(dv * w2.x, s20), a21 = pair_sum(dv * w2.y, s21), a22 = pair_sum(dv * w2.z, s22);
+        const R a30 = pair_sum(dv * w3.x, s30), a31 = pair_sum(dv * w3.y, s31), a32 = pair_sum(dv * w3.z, s32);
+        paw1 = w4<R>(a10, a11, a12);
+        paw2 = w4<R>(a20, a21, a22);
+        paw3 = w4<R>(a30, a31, a32);
+        if (pv_half == 0) {
+          const W4<R> b = pb;
+          acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
+          const double t[9] = {((double)w1.x * b.x + (double)w1.y * b.y) + (double)w1.z * b.z,
+                               ((double)w2.x * b.x + (double)w2.y * b.y) + (double)w2.z * b.z,
+                               ((double)w3.x * b.x + (double)w3.y * b.y) + (double)w3.z * b.z,
+                               ((double)w1.x * a10 + (double)w1.y * a11) + (double)w1.z * a12,
+                               ((double)w1.x * a20 + (double)w1.y * a21) + (double)w1.z * a22,
+                               ((double)w1.x * a30 + (double)w1.y * a31) + (double)w1.z * a32,
+                               ((double)w2.x * a20 + (double)w2.y * a21) + (double)w2.z * a22,
+                               ((double)w2.x * a30 + (double)w2.y * a31) + (double)w2.z * a32,
+                               ((double)w3.x * a30 + (double)w3.y * a31) + (double)w3.z * a32};
+          // A w1, A w2, A w3 for the neighbours' second pass
+          st_wt(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), paw1);
+          st_wt(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), paw2);
+          st_wt(p + row0, (unsigned)(v - row0), paw3);
+          if (c.M > 1) {
+            double* q = reinterpret_cast<double*>(cg0 + 3 * n);
+            q[v] = t[0];
+            q[n + v] = t[1];
+            q[2 * n + v] = t[3];
+            q[3 * n + v] = t[4];
+            q[4 * n + v] = t[6];
+          } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) tq[i] += t[i];
+          }
         }
       }
-      const W4<R> b = cg0[v * vs];
-      acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
-      const double t[9] = {((double)w1.x * b.x + (double)w1.y * b.y) + (double)w1.z * b.z,
-                           ((double)w2.x * b.x + (double)w2.y * b.y) + (double)w2.z * b.z,
-                           ((double)w3.x * b.x + (double)w3.y * b.y) + (double)w3.z * b.z,
-                           ((double)w1.x * a10 + (double)w1.y * a11) + (double)w1.z * a12,
-                           ((double)w1.x * a20 + (double)w1.y * a21) + (double)w1.z * a22,
-                           ((double)w1.x * a30 + (double)w1.y * a31) + (double)w1.z * a32,
-                           ((double)w2.x * a20 + (double)w2.y * a21) + (double)w2.z * a22,
-                           ((double)w2.x * a30 + (double)w2.y * a31) + (double)w2.z * a32,
-                           ((double)w3.x * a30 + (double)w3.y * a31) + (double)w3.z * a32};
-      // A w1, A w2, A w3 until the second pass (p is free until the first CG
-      // iteration, which takes p_{-1} = 0 without reading it)
-      // read by neighbouring rows of other blocks after the barrier
-      st_wt(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a10, a11, a12));
-      st_wt(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a20, a21, a22));
-      st_wt(p + row0, (unsigned)(v - row0), w4<R>(a30, a31, a32));
-      if (c.M > 1) {
-        // a batch projects on (w1, w2): per-row terms, summed per mesh below,
-        // in the half of the CG state the first iteration has yet to write
-        double* q = reinterpret_cast<double*>(cg0 + 3 * n);
-        q[v] = t[0];
-        q[n + v] = t[1];
-        q[2 * n + v] = t[3];
-        q[3 * n + v] = t[4];
-        q[4 * n + v] = t[6];
-      } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) tq[i] += t[i];
+    } else {
+      for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
+        const R dv = dg[v], idg = R(1) / dv;
+        const W4<R> w1 = x[v], wp = xp[v], wpp = xpp[v];
+        const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
+        const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
+        R a10 = dv * w1.x, a11 = dv * w1.y, a12 = dv * w1.z;
+        R a20 = dv * w2.x, a21 = dv * w2.y, a22 = dv * w2.z;
+        R a30 = dv * w3.x, a31 = dv * w3.y, a32 = dv * w3.z;
+  #pragma unroll 1
+        for (int k0 = 0; k0 < MW; k0 += CH1) {
+          int jj[CH1];
+          R aa[CH1];
+          W4<R> xn[CH1], pn[CH1], qn[CH1];
+  #pragma unroll
+          for (int k = 0; k < CH1; ++k) {
+            jj[k] = ecol[(size_t)(k0 + k) * n + v];
+            aa[k] = evl[(size_t)(k0 + k) * n + v];
+          }
+  #pragma unroll
+          for (int k = 0; k < CH1; ++k) {
+            xn[k] = ld3(x + jj[k]);
+            pn[k] = ld3(xp + jj[k]);
+            qn[k] = ld3(xpp + jj[k]);
+          }
+  #pragma unroll
+          for (int k = 0; k < CH1; ++k) {
+            const R d0 = xn[k].x - pn[k].x, d1 = xn[k].y - pn[k].y, d2 = xn[k].z - pn[k].z;
+            a10 += aa[k] * xn[k].x;
+            a11 += aa[k] * xn[k].y;
+            a12 += aa[k] * xn[k].z;
+            a20 += aa[k] * d0;
+            a21 += aa[k] * d1;
+            a22 += aa[k] * d2;
+            a30 += aa[k] * (d0 - (pn[k].x - qn[k].x));
+            a31 += aa[k] * (d1 - (pn[k].y - qn[k].y));
+            a32 += aa[k] * (d2 - (pn[k].z - qn[k].z));
+          }
+        }
+        const W4<R> b = cg0[v * vs];
+        acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
+        const double t[9] = {((double)w1.x * b.x + (double)w1.y * b.y) + (double)w1.z * b.z,
+                             ((double)w2.x * b.x + (double)w2.y * b.y) + (double)w2.z * b.z,
+                             ((double)w3.x * b.x + (double)w3.y * b.y) + (double)w3.z * b.z,
+                             ((double)w1.x * a10 + (double)w1.y * a11) + (double)w1.z * a12,
+                             ((double)w1.x * a20 + (double)w1.y * a21) + (double)w1.z * a22,
+                             ((double)w1.x * a30 + (double)w1.y * a31) + (double)w1.z * a32,
+                             ((double)w2.x * a20 + (double)w2.y * a21) + (double)w2.z * a22,
+                             ((double)w2.x * a30 + (double)w2.y * a31) + (double)w2.z * a32,
+                             ((double)w3.x * a30 + (double)w3.y * a31) + (double)w3.z * a32};
+        // A w1, A w2, A w3 until the second pass (p is free until the first CG
+        // iteration, which takes p_{-1} = 0 without reading it)
+        // read by neighbouring rows of other blocks after the barrier
+        st_wt(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a10, a11, a12));
+        st_wt(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a20, a21, a22));
+        st_wt(p + row0, (unsigned)(v - row0), w4<R>(a30, a31, a32));
+        if (c.M > 1) {
+          // a batch projects on (w1, w2): per-row terms, summed per mesh below,
+          // in the half of the CG state the first iteration has yet to write
+          double* q = reinterpret_cast<double*>(cg0 + 3 * n);
+          q[v] = t[0];
+          q[n + v] = t[1];
+          q[2 * n + v] = t[3];
+          q[3 * n + v] = t[4];
+          q[4 * n + v] = t[6];
+        } else {
+  #pragma unroll
+          for (int i = 0; i < 9; ++i) tq[i] += t[i];
+        }
       }
     }
     double g1 = 0.0, g2 = 0.0, g3 = 0.0;
@@ -694,81 +798,137 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     // separates the two.  A row's neighbours belong to its mesh and share its
     // weights.  The start goes to the other half of the CG state, whose
     // (b, A w1, A w2) other blocks are still reading; the history moves on.
-    constexpr int CH2 = PAIR ? (CH < 8 ? CH : 8) : (CH < 4 ? CH : 4);
+    constexpr int CH2 = CH < 4 ? CH : 4;
     W4<R>* __restrict__ ns = cg0 + 3 * n;
-    for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
-      R r1 = (R)g1, r2 = (R)g2, r3 = (R)g3;
-      if (c.M > 1) {
-        const int m = d.vmesh[v];
-        r1 = (R)d.mgam[2 * m];
-        r2 = (R)d.mgam[2 * m + 1];
-        r3 = R(0);
+    if constexpr (PAIR) {
+      if (pv_has) {
+        const int v = pv_row;
+        R r1 = (R)g1, r2 = (R)g2, r3 = (R)g3;
+        if (c.M > 1) {
+          const int m = d.vmesh[v];
+          r1 = (R)d.mgam[2 * m];
+          r2 = (R)d.mgam[2 * m + 1];
+          r3 = R(0);
+        }
+        const R idg = R(1) / pdv;
+        const W4<R> b = pb, aw1 = paw1, aw2 = paw2, aw3 = paw3;
+        const W4<R> rv = w4<R>(b.x - r1 * aw1.x - r2 * aw2.x - r3 * aw3.x, b.y - r1 * aw1.y - r2 * aw2.y - r3 * aw3.y,
+                               b.z - r1 * aw1.z - r2 * aw2.z - r3 * aw3.z);
+        W4<R> nb[8], n1[8], n2[8], n3[8];
+        R dgn[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          nb[k] = ld3(cg0 + pj[k] * vs);
+          n1[k] = ld3(cg0 + qs + pj[k] * vs);
+          n2[k] = ld3(cg0 + 2 * qs + pj[k] * vs);
+          n3[k] = ld3(p + pj[k]);
+          dgn[k] = dg[pj[k]];
+        }
+        R s0 = R(0), s1 = R(0), s2 = R(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          // a_vj / dg_j, kept for the CG iterations
+          pa[k] = pa[k] / dgn[k];
+          evs[(size_t)(8 * pv_half + k) * n + v] = pa[k];
+          s0 += pa[k] * (nb[k].x - r1 * n1[k].x - r2 * n2[k].x - r3 * n3[k].x);
+          s1 += pa[k] * (nb[k].y - r1 * n1[k].y - r2 * n2[k].y - r3 * n3[k].y);
+          s2 += pa[k] * (nb[k].z - r1 * n1[k].z - r2 * n2[k].z - r3 * n3[k].z);
+        }
+        const R a0 = pair_sum(rv.x, s0), a1 = pair_sum(rv.y, s1), a2 = pair_sum(rv.z, s2);
+        const W4<R> w1 = pw1, wp = pwp, wpp = pwpp;
+        const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
+        const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
+        const W4<R> x0 = w4<R>(r1 * w1.x + r2 * w2.x + r3 * w3.x, r1 * w1.y + r2 * w2.y + r3 * w3.y,
+                               r1 * w1.z + r2 * w2.z + r3 * w3.z);
+        if (pv_half == 0) {
+          const unsigned vi = (unsigned)(v - row0);
+          st_wt(x + row0, vi, x0);
+          st_wt(xpp + row0, vi, wp);
+          st_wt(xp + row0, vi, w1);
+          st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
+          st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
+          st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), w4<R>(R(0), R(0), R(0)));
+          const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
+          acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
+          acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
+        }
+        // the row's state for the CG iterations
+        prc = rv;
+        pwc = w4<R>(a0, a1, a2);
+        psc = w4<R>(R(0), R(0), R(0));
+        ppv = w4<R>(R(0), R(0), R(0));  // p_{-1} = 0
+        pxv = x0;
+        pidg = idg;
       }
-      const R idg = R(1) / dg[v];
-      const W4<R> w1 = x[v], wp = xp[v], wpp = xpp[v];
-      const W4<R> b = cg0[v * vs], aw1 = cg0[qs + v * vs], aw2 = cg0[2 * qs + v * vs], aw3 = p[v];
-      const W4<R> rv = w4<R>(b.x - r1 * aw1.x - r2 * aw2.x - r3 * aw3.x, b.y - r1 * aw1.y - r2 * aw2.y - r3 * aw3.y,
-                             b.z - r1 * aw1.z - r2 * aw2.z - r3 * aw3.z);
-      R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
-#pragma unroll 1
-      for (int k0 = 0; k0 < MW; k0 += CH2) {
-        int jj[CH2];
-        R aa[CH2], dgn[CH2];
-#pragma unroll
-        for (int k = 0; k < CH2; ++k) {
-          jj[k] = ecol[(size_t)(k0 + k) * n + v];
-          aa[k] = evl[(size_t)(k0 + k) * n + v];
+    } else {
+      for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
+        R r1 = (R)g1, r2 = (R)g2, r3 = (R)g3;
+        if (c.M > 1) {
+          const int m = d.vmesh[v];
+          r1 = (R)d.mgam[2 * m];
+          r2 = (R)d.mgam[2 * m + 1];
+          r3 = R(0);
         }
-        W4<R> nb[CH2], n1[CH2], n2[CH2], n3[CH2];
-#pragma unroll
-        for (int k = 0; k < CH2; ++k) {
-          nb[k] = ld3(cg0 + jj[k] * vs);
-          n1[k] = ld3(cg0 + qs + jj[k] * vs);
-          n2[k] = ld3(cg0 + 2 * qs + jj[k] * vs);
-          n3[k] = ld3(p + jj[k]);
-          dgn[k] = dg[jj[k]];
+        const R idg = R(1) / dg[v];
+        const W4<R> w1 = x[v], wp = xp[v], wpp = xpp[v];
+        const W4<R> b = cg0[v * vs], aw1 = cg0[qs + v * vs], aw2 = cg0[2 * qs + v * vs], aw3 = p[v];
+        const W4<R> rv = w4<R>(b.x - r1 * aw1.x - r2 * aw2.x - r3 * aw3.x, b.y - r1 * aw1.y - r2 * aw2.y - r3 * aw3.y,
+                               b.z - r1 * aw1.z - r2 * aw2.z - r3 * aw3.z);
+        R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
+  #pragma unroll 1
+        for (int k0 = 0; k0 < MW; k0 += CH2) {
+          int jj[CH2];
+          R aa[CH2], dgn[CH2];
+  #pragma unroll
+          for (int k = 0; k < CH2; ++k) {
+            jj[k] = ecol[(size_t)(k0 + k) * n + v];
+            aa[k] = evl[(size_t)(k0 + k) * n + v];
+          }
+          W4<R> nb[CH2], n1[CH2], n2[CH2], n3[CH2];
+  #pragma unroll
+          for (int k = 0; k < CH2; ++k) {
+            nb[k] = ld3(cg0 + jj[k] * vs);
+            n1[k] = ld3(cg0 + qs + jj[k] * vs);
+            n2[k] = ld3(cg0 + 2 * qs + jj[k] * vs);
+            n3[k] = ld3(p + jj[k]);
+            dgn[k] = dg[jj[k]];
+          }
+          // a_vj / dg_j for the CG iterations (the neighbours' diagonals of
+          // this outer iteration are visible past the barrier above)
+  #pragma unroll
+          for (int k = 0; k < CH2; ++k) {
+            aa[k] = aa[k] / dgn[k];
+            evs[(size_t)(k0 + k) * n + v] = aa[k];
+          }
+  #pragma unroll
+          for (int k = 0; k < CH2; ++k) {
+            a0 += aa[k] * (nb[k].x - r1 * n1[k].x - r2 * n2[k].x - r3 * n3[k].x);
+            a1 += aa[k] * (nb[k].y - r1 * n1[k].y - r2 * n2[k].y - r3 * n3[k].y);
+            a2 += aa[k] * (nb[k].z - r1 * n1[k].z - r2 * n2[k].z - r3 * n3[k].z);
+          }
         }
-        // a_vj / dg_j for the CG iterations (the neighbours' diagonals of
-        // this outer iteration are visible past the barrier above)
-#pragma unroll
-        for (int k = 0; k < CH2; ++k) {
-          aa[k] = aa[k] / dgn[k];
-          evs[(size_t)(k0 + k) * n + v] = aa[k];
-        }
-#pragma unroll
-        for (int k = 0; k < CH2; ++k) {
-          a0 += aa[k] * (nb[k].x - r1 * n1[k].x - r2 * n2[k].x - r3 * n3[k].x);
-          a1 += aa[k] * (nb[k].y - r1 * n1[k].y - r2 * n2[k].y - r3 * n3[k].y);
-          a2 += aa[k] * (nb[k].z - r1 * n1[k].z - r2 * n2[k].z - r3 * n3[k].z);
-        }
+        const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
+        const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
+        const unsigned vi = (unsigned)(v - row0);
+        st_wt(x + row0, vi,
+              w4<R>(r1 * w1.x + r2 * w2.x + r3 * w3.x, r1 * w1.y + r2 * w2.y + r3 * w3.y,
+                    r1 * w1.z + r2 * w2.z + r3 * w3.z));
+        st_wt(xpp + row0, vi, wp);
+        st_wt(xp + row0, vi, w1);
+        st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
+        st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
+        st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), w4<R>(R(0), R(0), R(0)));
+        const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
+        acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
+        acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
       }
-      const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
-      const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
-      const unsigned vi = (unsigned)(v - row0);
-      st_wt(x + row0, vi,
-            w4<R>(r1 * w1.x + r2 * w2.x + r3 * w3.x, r1 * w1.y + r2 * w2.y + r3 * w3.y,
-                  r1 * w1.z + r2 * w2.z + r3 * w3.z));
-      st_wt(xpp + row0, vi, wp);
-      st_wt(xp + row0, vi, w1);
-      st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
-      st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
-      st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), w4<R>(R(0), R(0), R(0)));
-      const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
-      acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
-      acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
     }
     cur = 1;
   }
   block_sum2_store(acc_g, acc_d, lds2, d.part_c + blockIdx.x, d.part_e + blockIdx.x);
   grid_barrier(bc, bar_target, G);
-  // PAIR: the lane pair's persistent state and its first neighbour gather,
-  // issued before the grid sums so the round trips overlap
-  const int pv_row = row0 + (int)(threadIdx.x >> 1), pv_half = (int)(threadIdx.x & 1);
-  const bool pv_has = PAIR && pv_row < row1;
-  int pj[8];
-  R pa[8];
-  W4<R> prc, pwc, psc, ppv, pxv;
-  R pidg = R(0);
+  // PAIR: the lane pair's first neighbour gather, issued before the grid
+  // sums so the round trips overlap
   // the neighbours' (r, w, s) of the coming iteration, loaded right after the
   // barrier that publishes them, while the partial sums are read
   W4<R> nr[8], nw[8], nsv[8];
@@ -783,20 +943,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     }
   };
   if constexpr (PAIR) {
-    if (pv_has) {
-      const W4<R>* cs = cg0 + cur * 3 * n;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        pj[k] = ecol[(size_t)(8 * pv_half + k) * n + pv_row];
-        pa[k] = evs[(size_t)(8 * pv_half + k) * n + pv_row];
-      }
-      prc = cs[pv_row * vs];
-      pwc = cs[qs + pv_row * vs];
-      psc = cs[2 * qs + pv_row * vs];
-      ppv = w4<R>(R(0), R(0), R(0));  // p_{-1} = 0
-      pxv = x[pv_row];
-      pidg = R(1) / dg[pv_row];
-    }
     gather(cg0 + cur * 3 * n);
   }
   double gam, del, rhs, dummy;
