@@ -522,6 +522,16 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // suits their bandwidth-bound gathers.
   constexpr bool SOA = PAIR;
   const size_t qs = SOA ? n : 1, vs = SOA ? 1 : 3;
+  // state that other blocks read after a barrier: written through (sc1) in
+  // the paired variant, whose wavefront stores cover whole cache lines; the
+  // others' 16-byte stores at a 48-byte stride would write partial lines
+  // through to HBM, so their lines are assembled in L2 and written back
+  auto st_state = [&](W4<R>* base, unsigned i, const W4<R>& v) {
+    if constexpr (SOA)
+      st_wt(base, i, v);
+    else
+      base[i] = v;
+  };
   // each block owns one contiguous range of rows (a multiple of 64 long), so
   // the rows spread over all G blocks however many rows a thread gets
   const int chunk = ((c.n + G - 1) / G + 63) & ~63;
@@ -668,9 +678,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
                                ((double)w2.x * a30 + (double)w2.y * a31) + (double)w2.z * a32,
                                ((double)w3.x * a30 + (double)w3.y * a31) + (double)w3.z * a32};
           // A w1, A w2, A w3 for the neighbours' second pass
-          st_wt(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), paw1);
-          st_wt(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), paw2);
-          st_wt(p + row0, (unsigned)(v - row0), paw3);
+          st_state(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), paw1);
+          st_state(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), paw2);
+          st_state(p + row0, (unsigned)(v - row0), paw3);
           if (c.M > 1) {
             double* q = reinterpret_cast<double*>(cg0 + 3 * n);
             q[v] = t[0];
@@ -737,9 +747,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         // A w1, A w2, A w3 until the second pass (p is free until the first CG
         // iteration, which takes p_{-1} = 0 without reading it)
         // read by neighbouring rows of other blocks after the barrier
-        st_wt(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a10, a11, a12));
-        st_wt(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a20, a21, a22));
-        st_wt(p + row0, (unsigned)(v - row0), w4<R>(a30, a31, a32));
+        st_state(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a10, a11, a12));
+        st_state(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a20, a21, a22));
+        st_state(p + row0, (unsigned)(v - row0), w4<R>(a30, a31, a32));
         if (c.M > 1) {
           // a batch projects on (w1, w2): per-row terms, summed per mesh below,
           // in the half of the CG state the first iteration has yet to write
@@ -842,12 +852,12 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
                                r1 * w1.z + r2 * w2.z + r3 * w3.z);
         if (pv_half == 0) {
           const unsigned vi = (unsigned)(v - row0);
-          st_wt(x + row0, vi, x0);
-          st_wt(xpp + row0, vi, wp);
-          st_wt(xp + row0, vi, w1);
-          st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
-          st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
-          st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), w4<R>(R(0), R(0), R(0)));
+          st_state(x + row0, vi, x0);
+          st_state(xpp + row0, vi, wp);
+          st_state(xp + row0, vi, w1);
+          st_state(ns + row0 * vs, (unsigned)(vi * vs), rv);
+          st_state(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
+          st_state(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), w4<R>(R(0), R(0), R(0)));
           const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
           acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
           acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
@@ -910,14 +920,14 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         const W4<R> w2 = w4<R>(w1.x - wp.x, w1.y - wp.y, w1.z - wp.z);
         const W4<R> w3 = w4<R>(w2.x - (wp.x - wpp.x), w2.y - (wp.y - wpp.y), w2.z - (wp.z - wpp.z));
         const unsigned vi = (unsigned)(v - row0);
-        st_wt(x + row0, vi,
+        st_state(x + row0, vi,
               w4<R>(r1 * w1.x + r2 * w2.x + r3 * w3.x, r1 * w1.y + r2 * w2.y + r3 * w3.y,
                     r1 * w1.z + r2 * w2.z + r3 * w3.z));
-        st_wt(xpp + row0, vi, wp);
-        st_wt(xp + row0, vi, w1);
-        st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
-        st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
-        st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), w4<R>(R(0), R(0), R(0)));
+        st_state(xpp + row0, vi, wp);
+        st_state(xp + row0, vi, w1);
+        st_state(ns + row0 * vs, (unsigned)(vi * vs), rv);
+        st_state(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
+        st_state(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), w4<R>(R(0), R(0), R(0)));
         const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
         acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
         acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
@@ -1032,9 +1042,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
                                         : w4<R>(rv.x + b0 + a0, rv.y + b1 + a1, rv.z + b2 + a2);
           if (pv_half == 0) {
             const unsigned vi = (unsigned)(pv_row - row0);
-            st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
-            st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), wn);
-            st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), sv);
+            st_state(ns + row0 * vs, (unsigned)(vi * vs), rv);
+            st_state(ns + qs + row0 * vs, (unsigned)(vi * vs), wn);
+            st_state(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), sv);
             const R u0 = rv.x * pidg, u1 = rv.y * pidg, u2 = rv.z * pidg;
             acc_g = ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
             acc_d = ((double)wn.x * u0 + (double)wn.y * u1) + (double)wn.z * u2;
@@ -1069,8 +1079,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       const W4<R> sv = w4<R>(wc.x + rb * sc.x, wc.y + rb * sc.y, wc.z + rb * sc.z);
       const W4<R> rv = w4<R>(rc.x - ra * sv.x, rc.y - ra * sv.y, rc.z - ra * sv.z);
       const unsigned vi = (unsigned)(v - row0);
-      st_wt(p + row0, vi, pv);
-      st_wt(x + row0, vi, w4<R>(xv.x + ra * pv.x, xv.y + ra * pv.y, xv.z + ra * pv.z));
+      st_state(p + row0, vi, pv);
+      st_state(x + row0, vi, w4<R>(xv.x + ra * pv.x, xv.y + ra * pv.y, xv.z + ra * pv.z));
       R a0 = rv.x, a1 = rv.y, a2 = rv.z;  // dg_v * (r_v / dg_v)
 #pragma unroll 1
       for (int k0 = 0; k0 < MW; k0 += CH) {
@@ -1095,9 +1105,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           a2 += aa[k] * (nr[k].z - ra * (nw[k].z + rb * nsv[k].z));
         }
       }
-      st_wt(ns + row0 * vs, (unsigned)(vi * vs), rv);
-      st_wt(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
-      st_wt(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), sv);
+      st_state(ns + row0 * vs, (unsigned)(vi * vs), rv);
+      st_state(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
+      st_state(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), sv);
       const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
       acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
       acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
