@@ -17,7 +17,10 @@ oracle or a closed form:
   free rows: the solve returns the rest shape at once, and the gradient
   with respect to its chamber is zero;
 * a mesh without chambers: the solve and the adjoint run with an empty
-  actuation vector.
+  actuation vector;
+* the FP32 implicit and unrolled adjoints in both CG state layouts. One
+  block runs the unpaired kernel (rows of three vectors); the default grid
+  runs the paired kernel (three arrays of rows). The gradients agree.
 """
 import dataclasses
 import sys
@@ -135,3 +138,34 @@ def test_mesh_without_chambers_solves_and_differentiates(G):
     np.testing.assert_allclose(xg.cpu().numpy(), m["rest_xyz"], atol=1e-12)
     ga, ast = gp.adjoint(np.ones((3, gp.n)))
     assert ast["status"] == G.OK and ga.numel() == 0
+
+
+def test_fp32_adjoints_agree_in_both_cg_layouts(G, finger_oracle_150):
+    """The adjoint kernels write the CG right-hand side in the layout of the
+    grid they are given (three arrays of rows for the paired kernel, rows of
+    three vectors otherwise). The same forward path (pcg_eta 1e-7, the contact
+    rows of the oracle) differentiated on one block and on the default grid
+    gives the same gradients to FP32 accuracy."""
+    wl, prob, xo, orows = finger_oracle_150
+    rng = np.random.default_rng(7)
+    g = rng.standard_normal((3, prob.n))
+    g[:, prob.fixed] = 0.0
+    out = {}
+    for blocks in (1, 0):
+        gp = G.Problem.from_workload(wl, precision=4, pcg_eta=1e-7, pcg_max=3000, fixed_iters=150,
+                                     pcg_blocks=blocks, adj_tol=1e-7, adj_aa_m=16)
+        grid = gp.info["pcg_grid"]
+        rows_per_block = ((gp.n + grid - 1) // grid + 63) // 64 * 64
+        _, st = gp.solve(wl.alpha)
+        np.testing.assert_array_equal(gp.contacts()["rows"], orows)
+        ga, ast = gp.adjoint(g)
+        gu, _, _, ust = gp.adjoint_unrolled(wl.alpha, 20, g)
+        say("pcg_blocks", blocks, "grid", grid, "rows per block", rows_per_block, "adjoint", ast, "unrolled", ust)
+        assert ast["status"] == G.OK
+        out[blocks] = (ga.cpu().numpy().astype(np.float64), gu.cpu().numpy().astype(np.float64), rows_per_block)
+    assert out[1][2] > 256 and out[0][2] <= 256  # unpaired, then paired
+    for i, name in ((0, "implicit"), (1, "unrolled")):
+        a, b = out[1][i], out[0][i]
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        say(name, "one block", a, "default grid", b, "rel", rel)
+        assert rel < 1e-3
