@@ -191,18 +191,32 @@ __device__ __forceinline__ void block_sums_store(const double (&v)[K], double (*
   }
 }
 
-// Sums of the G block partials of K <= kPcgBlock / 64 arrays base + i *
-// stride in one round: wavefront i reduces array i in grid_sum2's order;
-// every block obtains the same bits.
+// Sums of the G block partials of K arrays base + i * stride in one round:
+// wavefront w reduces arrays w, w + 8, ... in grid_sum2's order, all of its
+// loads issued before the first reduction; every block obtains the same bits.
 template <int K>
 __device__ __forceinline__ void grid_sums(const double* base, int stride, int G, double* sh, double (&out)[K]) {
+  constexpr int NW = kPcgBlock / 64;
+  constexpr int PER = (K + NW - 1) / NW;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  if (w < K) {
-    const double* a = base + (size_t)w * stride;
-    double t = (l < G) ? a[l] : 0.0;
-    for (int k = l + 64; k < G; k += 64) t += a[k];
-    t = wave_sum(t);
-    if (l == 0) sh[w] = t;
+  double t[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = w + j * NW;
+    t[j] = 0.0;
+    if (i < K) {
+      const double* a = base + (size_t)i * stride;
+      t[j] = (l < G) ? a[l] : 0.0;
+      for (int k = l + 64; k < G; k += 64) t[j] += a[k];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = w + j * NW;
+    if (i < K) {
+      const double r = wave_sum(t[j]);
+      if (l == 0) sh[i] = r;
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -561,6 +575,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   //     alone).  The forward solve first forms its right-hand side (phase 0);
   //     the adjoint kernels have formed theirs before the launch.
   double acc_b = 0.0, acc_g = 0.0, acc_d = 0.0;
+  double rhs1 = 0.0;  // paired kernel, one mesh: b' M^-1 b, summed after the first barrier
   int cur = 0;  // half of the double-buffered CG state holding (r_0, w_0, s_0)
   // PAIR: lanes 2i and 2i+1 share row row0 + i from the start-up on, each
   // taking 8 of the row's 16 neighbour slots; the row's state passes from
@@ -767,16 +782,30 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     }
     double g1 = 0.0, g2 = 0.0, g3 = 0.0;
     if (c.M == 1) {
-      // partials at part_c[(2 + i) G + block] for the nine terms, part_d for b' M^-1 b
+      // partials at part_c[(2 + i) G + block]: the nine terms, then b' M^-1 b
+      // (also in part_d).  The paired kernel reads the ten grid sums in one
+      // round after the barrier; the unpaired kernels, whose registers the CG
+      // loop fills, read the nine terms in two and b' M^-1 b after the next
+      // barrier.
       const double q[10] = {tq[0], tq[1], tq[2], tq[3], tq[4], tq[5], tq[6], tq[7], tq[8], acc_b};
       block_sums_store<10>(q, lds2, d.part_c + 2 * G + blockIdx.x, G);
-      if (threadIdx.x == 9) d.part_d[blockIdx.x] = d.part_c[11 * G + blockIdx.x];
+      if (!PAIR && threadIdx.x == 9) d.part_d[blockIdx.x] = d.part_c[11 * G + blockIdx.x];
       grid_barrier(bc, bar_target, G);
-      double S1[5], S2[4];
-      grid_sums<5>(d.part_c + 2 * G, G, G, sh, S1);
-      grid_sums<4>(d.part_c + 7 * G, G, G, sh + 8, S2);
+      double S[10];
+      if constexpr (PAIR) {
+        grid_sums<10>(d.part_c + 2 * G, G, G, sh, S);
+        rhs1 = S[9];
+      } else {
+        double S1[5], S2[4];
+        grid_sums<5>(d.part_c + 2 * G, G, G, sh, S1);
+        grid_sums<4>(d.part_c + 7 * G, G, G, sh + 8, S2);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) S[i] = S1[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S[5 + i] = S2[i];
+      }
       // every block takes the same decision from the same sums
-      galerkin_weights3(S1[0], S1[1], S1[2], S1[3], S1[4], S2[0], S2[1], S2[2], S2[3], g1, g2, g3);
+      galerkin_weights3(S[0], S[1], S[2], S[3], S[4], S[5], S[6], S[7], S[8], g1, g2, g3);
     } else {
       const double bs = block_sum<kPcgBlock>(acc_b, lds);
       if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
@@ -955,9 +984,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   if constexpr (PAIR) {
     gather(cg0 + cur * 3 * n);
   }
-  double gam, del, rhs, dummy;
+  double gam, del, rhs = rhs1, dummy;
   grid_sum2(d.part_c, d.part_e, G, sh, gam, del);
-  grid_sum2(d.part_d, d.part_d, G, sh, rhs, dummy);
+  if (!PAIR || c.M > 1) grid_sum2(d.part_d, d.part_d, G, sh, rhs, dummy);
   gam = uniform_d(gam);
   del = uniform_d(del);
   rhs = uniform_d(rhs);
