@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_local(Dev<R> d, Consts c, const R* _
 
 // Local step and tet query in one launch for meshes below kTetQueryWide tets
 // (both read only the iteration's positions).  A workgroup takes 64 tets;
-// wavefronts 0-2 share their queries (wavefront w: cell groups j = w mod 3),
+// wavefronts 0-2 share their queries (wavefront w: the cells i = w mod 3),
 // wavefront 3 runs their local steps, so the two kinds of work run side by
 // side on the compute unit instead of one after the other in every lane.
 // The energy partials are per workgroup.

@@ -10,9 +10,9 @@
 
 namespace gs {
 
-// Lanes per tet of the tet query: with few tets (latency-bound) a tet's cell
-// groups are shared by 4 consecutive lanes, so the longest chain of
-// dependent bucket reads is about one group; with many tets one lane each.
+// Lanes per tet of the tet query: with few tets (latency-bound) a tet's cells
+// are shared by 4 consecutive lanes, so each lane's chain of dependent bucket
+// reads covers a few cells; with many tets one lane each.
 template <bool PREFETCH>
 struct TetQueryLanes { static constexpr int n = PREFETCH ? 4 : 1; };
 
@@ -39,9 +39,9 @@ __device__ __forceinline__ void test_point(const Dev<R>& d, const double4& en, i
 }
 
 // Tests the entries of up to 8 buckets (key < 0: none).  PREFETCH (few
-// tets, latency-bound): the first entries of all non-empty buckets are loaded
-// in one round; otherwise one by one, with fewer registers.  Entries past the
-// first follow one by one.
+// tets, latency-bound): the entries are loaded in rounds, round i taking the
+// i-th entry of every bucket that has one, so a round costs one memory round
+// trip; otherwise one by one, with fewer registers.
 template <typename R, bool DEBUG, bool PREFETCH>
 __device__ __forceinline__ void test_buckets(const Dev<R>& d, const double4* slots, const int (&keys)[8], int e,
                                              int vbeg, int vend, const int (&vi)[4], const double (&p)[4][3],
@@ -62,14 +62,29 @@ __device__ __forceinline__ void test_buckets(const Dev<R>& d, const double4* slo
     for (int k = 0; k < 8; ++k)
       if (cnt[k] > 0) test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap], e, vbeg, vend, vi, p, lo, hi);
   }
+  if (PREFETCH) {
+    int cmax = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k)
-    for (int i = 1; i < cnt[k]; ++i)
-      test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, vbeg, vend, vi, p, lo, hi);
+    for (int k = 0; k < 8; ++k) cmax = max(cmax, cnt[k]);
+    for (int i = 1; i < cmax; ++i) {
+      double4 ei[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (cnt[k] > i) ei[k] = slots[(size_t)keys[k] * kHashCap + i];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (cnt[k] > i) test_point<R, DEBUG>(d, ei[k], e, vbeg, vend, vi, p, lo, hi);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      for (int i = 1; i < cnt[k]; ++i)
+        test_point<R, DEBUG>(d, slots[(size_t)keys[k] * kHashCap + i], e, vbeg, vend, vi, p, lo, hi);
+  }
 }
 
-// Part sub of nsub of the query of tet e: cell groups sub, sub + nsub, ...
-// (and the same share of the brute-force and overflow scans).
+// Part sub of nsub of the query of tet e: cells sub, sub + nsub, ... (and the
+// same share of the brute-force and overflow scans).
 template <typename R, bool DEBUG, bool PREFETCH>
 __device__ __forceinline__ void tet_query_part(const Dev<R>& d, const Consts& c, int e, int sub, int nsub) {
   if (e >= c.T) return;
@@ -117,17 +132,17 @@ __device__ __forceinline__ void tet_query_part(const Dev<R>& d, const Consts& c,
     }
     return;
   }
-  // the covered cells in groups of 8 (x fastest), group j taken by part
-  // j mod nsub: one round trip fetches a group's bucket counts, the next the
-  // first entries of its non-empty buckets (the common tet covers at most 2
-  // cells per axis: one group)
+  // the covered cells (x fastest), cell i taken by part i mod nsub, each part
+  // taking its cells in groups of 8: one round trip fetches a group's bucket
+  // counts, the next the first entries of its non-empty buckets (the common
+  // tet covers at most 2 cells per axis, 8 cells: shared by the parts)
   const int nx = chi[0] - clo[0] + 1, ny = chi[1] - clo[1] + 1;
   const int nc = (int)ncell;
-  for (int c0 = 8 * sub; c0 < nc; c0 += 8 * nsub) {
+  for (int c0 = sub; c0 < nc; c0 += 8 * nsub) {
     int keys[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int i = c0 + k;
+      const int i = c0 + k * nsub;
       keys[k] = i < nc ? hash_cell(clo[0] + i % nx, clo[1] + (i / nx) % ny, clo[2] + i / (nx * ny), m, c.H) : -1;
     }
     test_buckets<R, DEBUG, PREFETCH>(d, slots, keys, e, vbeg, vend, vi, p, lo, hi);
