@@ -19,7 +19,8 @@
  *                released by Eq. (8);
  *   global step  with targets fixed, Eq. (9) is a linear least-squares
  *                problem in the vertex positions, solved here by a
- *                Jacobi-preconditioned conjugate gradient on a CSR matrix.
+ *                Jacobi-preconditioned conjugate gradient on the sparse
+ *                matrix in ELL form (16, 32 or 64 entries per row).
  *
  * Conventions
  * -----------
@@ -146,7 +147,7 @@ void gs_default_params(gs_params* params);
  * rest shapes and weights omega_e = Vol(e)/mean Vol (Eq. 9), boundary faces
  * (faces of exactly one tet, outward), query vertices (non-fixed boundary
  * vertices), A_el = sum_e omega_e S_e^T N S_e with N = I - 11^T/4 (below
- * Eq. 1) as CSR with fixed rows/columns removed, h_ref (mean rest edge
+ * Eq. 1) with fixed rows/columns removed (kept in ELL form), h_ref (mean rest edge
  * length), eps = eps_rel h_ref, L_ray = ray_rel h_ref and the spatial-hash
  * geometry.  Errors: GS_EINVAL, GS_EDEGENERATE.  *out is owned by the caller
  * and released with gs_destroy. */
