@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a 256 MiB copy);
 # see profiles/*_hbm_traffic.md.  Only valid for the kernel build the counters
 # were taken on: remove an entry when its kernel changes.
-PMC_TRAFFIC = {("finger", "pcg"): 20769319}
+PMC_TRAFFIC = {("finger", "pcg"): 20769319, ("batched", "pcg"): 29054596115}
 
 
 def kernel_bytes(info, W, n_launch, pcg_iters):
@@ -165,7 +165,7 @@ def run_batched(G, mg, n_mesh, max_iter, sample, autotune=True):
     _, st_p = gb.solve(alpha, x)
     prof = gb.profile_read()
     gb.profile(False)
-    roof = roofline_of(prof, gb.info, 4, st_p["pcg_iters_total"])
+    roof = roofline_of(prof, gb.info, 4, st_p["pcg_iters_total"], "batched")
     # plain path on a sample of the meshes (every n_mesh/sample-th), one by one
     idx = list(range(0, n_mesh, max(1, n_mesh // sample)))[:sample]
     t_plain, work_plain = 0.0, 0
