@@ -103,7 +103,7 @@ typedef struct {
                              correction                                           */
   int32_t pcg_max;        /* inner CG iteration cap per outer iteration           */
   int32_t check_every;    /* outer iterations between host convergence polls     */
-  int32_t pcg_blocks;     /* workgroups of the cooperative CG kernel (0: auto)    */
+  int32_t pcg_blocks;     /* workgroups of the persistent CG kernel (0: auto)     */
   int32_t trace_len;      /* iterations recorded by gs_trace (workspace grows)    */
   double adj_tol;         /* adjoint stop: max|d mu| <= adj_tol max|mu| per mesh  */
   int32_t adj_max_iter;   /* adjoint iteration cap                                */

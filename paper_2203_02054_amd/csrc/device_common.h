@@ -1,4 +1,4 @@
-// Device helpers: wavefront/block reductions, a grid barrier for cooperative
+// Device helpers: wavefront/block reductions, a grid barrier for persistent
 // launches, and the exact (FP64, fixed order, no contraction) predicates.
 #pragma once
 
@@ -113,12 +113,15 @@ __device__ __forceinline__ double block_max(double v, double* lds) {
   return t;
 }
 
-// ---- grid barrier (cooperative launch: every block is resident) -------------
+// ---- grid barrier (every block resident: an ordinary launch of a grid that
+// fits in half the resident capacity, or a cooperative launch) ---------------
 // One arrival counter that only grows during a launch: barrier j of the launch
 // is complete once it reads (j + 1) * nblocks, so the last arrival has nothing
 // more to write and no generation word has to be reset and re-published.
 // Thread 0 of each block releases the block's writes at agent scope, arrives,
-// waits for the count (wrap-safe comparison) and acquires.  `target` is the
+// waits for the count (wrap-safe comparison) and acquires.  The release writes
+// back the XCD's dirty L2 lines, so state that other blocks read afterwards
+// is stored write-through (st_wt) to leave it little to do.  `target` is the
 // block's own count of arrivals expected so far.  The launch's last block
 // clears the counter once every block is past its last barrier.
 __device__ __forceinline__ void grid_barrier(unsigned* count, unsigned& target, unsigned nblocks) {

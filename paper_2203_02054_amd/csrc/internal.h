@@ -12,13 +12,13 @@ constexpr int kBlock = 256;          // threads per block of the streaming kerne
 constexpr int kCellCap = 64;         // hash cells a tet box may span before the brute-force path
 constexpr int kHashCap = 8;          // entries stored in a hash bucket before the overflow list
 constexpr int kMaxSlots = 1 + 8 + 8; // self + spheres + planes
-constexpr int kPcgThreads = 512;     // threads per block of the cooperative CG kernel
+constexpr int kPcgThreads = 512;     // threads per block of the persistent CG kernel
 constexpr int kPcgRowsPerBlock = 256; // default rows per CG block (grid = n / 256, capped)
 // Tet count from which the tet query runs its one-lane-per-tet,
 // lower-register variant (the GPU then holds enough waves that occupancy
 // beats prefetching and lane sharing) and is not fused with the local step.
 constexpr int kTetQueryWide = 1 << 18;
-constexpr int kMaxPcgGrid = 1024;     // workgroups of the cooperative CG kernel at most
+constexpr int kMaxPcgGrid = 1024;     // workgroups of the persistent CG kernel at most
 
 // Completion codes kept on the device (DevStatus::done).
 enum { RUNNING = 0, CONVERGED = 1, MAXITER = 2, BREAKDOWN = 3, FIXED_DONE = 4 };
