@@ -257,8 +257,8 @@ def main():
                     help="only run 20 device-to-device copies of MIB MiB (reference traffic for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding plan is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(N > 1 is not supported).", file=sys.stderr)
         sys.exit(2)
 
     import torch
