@@ -197,3 +197,30 @@ def test_ray_candidates_match_double_loop():
                 expect.append((int(v), f))
     assert sorted(zip(cv.tolist(), cf.tolist())) == expect
     assert len(expect) > 0
+
+
+def test_vertex_normals_are_area_weighted_on_an_anisotropic_voxel():
+    """One voxel stretched to 1 x 2 x 3 (Kuhn split: every face diagonal starts
+    at the lower corner of its face).  Each boundary triangle adds its cross
+    product, twice its area along its outward normal, so the corner (0,0,0),
+    met by two triangles on each of its three faces, has the normal
+    -(b c, a c, a b) / |.| = -(6, 3, 2) / 7, and the corner (a,0,0), met by two
+    triangles on the face x = a and one on each of the others, has
+    (2 b c, -a c, -a b) / |.| = (12, -3, -2) / sqrt(157).  An unweighted sum
+    of unit face normals would give (1, 1, 1) / sqrt(3) and (2, -1, -1) /
+    sqrt(6) instead."""
+    mesh = voxel_box(1, 1, 1, h=1.0)
+    mesh["rest_xyz"] = mesh["rest_xyz"] * np.array([[1.0], [2.0], [3.0]])
+    prob = _prob(mesh)
+    corner0 = int(np.nonzero(np.all(prob.X0.T == [0.0, 0.0, 0.0], axis=1))[0][0])
+    corner1 = int(np.nonzero(np.all(prob.X0.T == [1.0, 0.0, 0.0], axis=1))[0][0])
+    n, ok = oc.vertex_normals(prob, prob.X0, np.array([corner0, corner1]))
+    assert ok.all()
+    exp0 = -np.array([6.0, 3.0, 2.0]) / 7.0
+    exp1 = np.array([12.0, -3.0, -2.0]) / np.sqrt(157.0)
+    np.testing.assert_allclose(n[:, 0], exp0, atol=1e-15)
+    np.testing.assert_allclose(n[:, 1], exp1, atol=1e-15)
+    # the mistake this pins: unit face normals summed without their areas
+    assert np.abs(n[:, 0] + np.ones(3) / np.sqrt(3)).max() > 0.1
+    assert np.abs(n[:, 1] - np.array([2.0, -1.0, -1.0]) / np.sqrt(6)).max() > 0.1
+
