@@ -123,13 +123,55 @@ def vertex_normals(prob, x: np.ndarray, verts: np.ndarray):
     return n, ok
 
 
-def tet_candidates(prob, x: np.ndarray, qverts: np.ndarray, chunk: int = 0):
-    """C_tet as (v, e) arrays sorted by (v, e), and the penetration flag per pair."""
+def _box_pairs_kdtree(x, lo, hi, qverts):
+    """(query index, tet) pairs whose inclusive box test passes, found through
+    a k-d tree of the query vertices: each tet's box lies inside the ball
+    around its centre with the half diagonal as radius (widened by a relative
+    1e-9 for rounding), so the ball query returns every vertex of the box and
+    the box test below, the same comparisons as the brute force, decides."""
+    from scipy.spatial import cKDTree
+    ctr = 0.5 * (lo + hi)
+    rad = 0.5 * np.sqrt(((hi - lo) ** 2).sum(axis=0))
+    rad = rad * (1.0 + 1e-9) + 1e-12 * (np.abs(ctr).max() + 1.0)
+    tree = cKDTree(np.ascontiguousarray(x[:, qverts].T))
+    lists = tree.query_ball_point(np.ascontiguousarray(ctr.T), rad, workers=-1)
+    lens = np.fromiter((len(l) for l in lists), dtype=np.int64, count=len(lists))
+    ei = np.repeat(np.arange(lo.shape[1], dtype=np.int64), lens)
+    si = np.fromiter((i for l in lists for i in l), dtype=np.int64, count=int(lens.sum()))
+    p = x[:, qverts[si]]
+    m = np.ones(si.size, dtype=bool)
+    for ax in range(3):
+        m &= p[ax] >= lo[ax, ei]
+        m &= p[ax] <= hi[ax, ei]
+    si, ei = si[m], ei[m]
+    order = np.lexsort((ei, si))
+    return si[order], ei[order]
+
+
+def tet_candidates(prob, x: np.ndarray, qverts: np.ndarray, chunk: int = 0, broadphase: str = "brute"):
+    """C_tet as (v, e) arrays sorted by (v, e), and the penetration flag per pair.
+
+    broadphase "brute" tests every (vertex, tet) pair (the definition);
+    "kdtree" finds the same pairs through a k-d tree of the query vertices
+    (for full-size meshes; checked equal to the brute force in the tests)."""
     tets = prob.tets
     T = tets.shape[1]
     xe = x[:, tets]                                     # [3, 4, T]
     lo = xe.min(axis=1)
     hi = xe.max(axis=1)
+    if broadphase == "kdtree":
+        qv = np.asarray(qverts, dtype=np.int64)
+        si, ei = _box_pairs_kdtree(x, lo, hi, qv)
+        v = qv[si]
+        inc = (tets[:, ei] == v[None, :]).any(axis=0)
+        v, e = v[~inc], ei[~inc]
+        a, b, c, d = (x[:, tets[k, e]] for k in range(4))
+        pv = x[:, v]
+        inside = ((orient(pv, b, c, d) > 0) & (orient(a, pv, c, d) > 0)
+                  & (orient(a, b, pv, d) > 0) & (orient(a, b, c, pv) > 0))
+        return v.astype(np.int64), e.astype(np.int64), inside
+    if broadphase != "brute":
+        raise ValueError("broadphase must be 'brute' or 'kdtree'")
     chunk = chunk or max(1, min(4096, int(2e7 // max(T, 1))))
     vs, es = [], []
     for s0 in range(0, qverts.size, chunk):
@@ -259,8 +301,10 @@ def _released(x, c, n, eps) -> bool:
     return abs(g) > eps
 
 
-def collide(prob, x: np.ndarray, prev: Contacts | None = None, want_candidates: bool = False):
+def collide(prob, x: np.ndarray, prev: Contacts | None = None, want_candidates: bool = False,
+            broadphase: str = "brute"):
     """Active set A_k at positions x given A_{k-1} = prev (Algorithm 1, CollisionCheck).
+    ``broadphase`` is passed to ``tet_candidates``.
 
     Returns (Contacts, info) with info = dict(pen_self, self_fresh, ray_miss,
     cand_tet, cand_tri); self_fresh marks the self contacts given a new target
@@ -278,7 +322,7 @@ def collide(prob, x: np.ndarray, prev: Contacts | None = None, want_candidates: 
                 cand_tri=None)
 
     if p.self_collision:
-        v, e, inside = tet_candidates(prob, x, qv)
+        v, e, inside = tet_candidates(prob, x, qv, broadphase=broadphase)
         pen_v = np.unique(v[inside])
         pen = np.isin(qv, pen_v)
         info["pen_self"] = pen

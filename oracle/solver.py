@@ -18,7 +18,10 @@ a warm start) and A_{-1} = {} (or an imported set), for k = 0, 1, ...:
 collision at x_k with A_{k-1} gives A_k; the local step at x_k gives T_k; the
 global step gives x_{k+1}; r_k = max_v |x_{k+1,v} - x_{k,v}| / diag.  Stop
 when r_k <= tol and A_k == A_{k-1}, else at max_iter (not converged); with
-fixed_iters > 0 run exactly that many iterations.
+fixed_iters > 0 run exactly that many iterations.  The paper points to
+Anderson acceleration for this fixed-point iteration (end of Section III-B);
+``solve(..., anderson=m)`` adds it with an energy safeguard, keeping the
+plain iteration's fixed points and stopping rule.
 """
 from __future__ import annotations
 
@@ -135,12 +138,54 @@ def step(prob, x, alpha, prev: Contacts | None, factor=None):
     return xn, A, Tt, info
 
 
+def anderson_update(g, f, dX, dF):
+    """One Anderson (type II) update of a fixed-point iteration x -> G(x)
+    (Walker & Ni 2011): with the current residual f = G(x) - x, the image
+    g = G(x) and the last differences dX_j = x_{j+1} - x_j, dF_j = f_{j+1} - f_j
+    as the columns of dX and dF,
+
+        gamma = argmin_gamma |f - dF gamma|_2,   x_new = g - (dX + dF) gamma
+
+    (dX + dF holds the differences of G).  With no columns it is the plain step
+    x_new = g.  The least-squares problem is solved by numpy's lstsq."""
+    if dF.shape[1] == 0:
+        return g.copy(), np.zeros(0)
+    gam, *_ = np.linalg.lstsq(dF, f, rcond=None)
+    return g - (dX + dF) @ gam, gam
+
+
 def solve(prob, alpha, x0=None, contacts0: Contacts | None = None, max_iter=None,
-          fixed_iters=None, tol=None, history: bool = False, callback=None):
+          fixed_iters=None, tol=None, history: bool = False, callback=None, anderson: int = 0,
+          aa_guard: str = "residual", aa_slack: float = 0.5, aa_keep_set: bool = True):
     """Local/global iteration to convergence (or a fixed iteration count).
 
-    Returns (x, contacts, stats) with stats = dict(iters, residual, converged,
-    n_contacts, ray_miss, energy, history).
+    With ``anderson`` = m > 0 the iteration is Anderson-accelerated (memory m)
+    with a safeguard, after Peng et al. (2018) for local/global solvers; the
+    fixed points, and the stopping rule, are those of the plain iteration.
+    Every iteration evaluates the plain map at the current point x_k
+    (collision, local step, exact global step: G(x_k)), its residual and its
+    energy E_k (Eq. 9 at x_k with the targets and contact set found there):
+
+    * r_k = max_v |G(x_k)_v - x_k,v| / diag; converged (result G(x_k)) when
+      r_k <= tol and the active set is unchanged, as in the plain iteration;
+    * x_k was an accelerated point and fails the guard: with
+      aa_guard = "residual", r_k > (1 + aa_slack) r_acc; with "energy",
+      E_k > E_acc + aa_slack |E_acc| (r_acc, E_acc: those of the last
+      accepted point); "none" has no value test; with aa_keep_set an
+      accelerated x_k whose active set differs from the last accepted
+      point's is rejected too.  A rejected x_k is replaced by the plain step
+      G(x_acc) from the last accepted point, evaluated with that point's
+      active set as the previous one (the plain iteration's state), and the
+      history is cleared;
+    * otherwise x_k is accepted (E_acc = E_k): the history gains
+      (x_k - x_prev, f_k - f_prev) with f = G(x) - x (after being cleared
+      when the active set changed), keeps its last m columns, and the next
+      point is ``anderson_update`` of G(x_k).
+
+    The last iteration (fixed_iters or max_iter reached) ends on the plain
+    step G(x_k), as a converged one does.  Fixed vertices stay at their rest
+    positions (their differences are zero).  Returns (x, contacts, stats) with stats = dict(iters, residual,
+    converged, n_contacts, ray_miss, energy, history, rejected).
     """
     p = prob.params
     max_iter = p.max_iter if max_iter is None else max_iter
@@ -155,23 +200,77 @@ def solve(prob, alpha, x0=None, contacts0: Contacts | None = None, max_iter=None
     n_it = fixed_iters if fixed_iters > 0 else max_iter
     converged = False
     info = dict(r=np.inf, E=np.nan, ray_miss=0, n_contacts=0)
+    m = int(anderson)
+    if aa_guard not in ("residual", "energy", "none"):
+        raise ValueError("aa_guard must be 'residual', 'energy' or 'none'")
+    cand = False                   # x is an accelerated point (not yet accepted)
+    e_acc = np.inf                 # energy of the last accepted point
+    r_acc = np.inf                 # residual of the last accepted point
+    x_fb = None                    # plain step from the last accepted point
+    x_prev = f_prev = None         # last accepted point and its residual
+    A_acc = None                   # active set found at the last accepted point
+    dX, dF = [], []
+    rejected = 0
     k = 0
     for k in range(n_it):
         xn, A, Tt, info = step(prob, x, alpha, prev, factor)
         if history:
             hist.append(dict(k=k, E=info["E"], E_sur=info["E_sur"], r=info["r"],
-                             n_contacts=info["n_contacts"], changed=info["changed"]))
+                             n_contacts=info["n_contacts"], changed=info["changed"], cand=cand))
         if callback is not None:
             callback(k, x, xn, A, info)
-        x = xn
         done = info["r"] <= tol and not info["changed"]
         prev = A
-        if fixed_iters <= 0 and done:
-            converged = True
+        if history:
+            hist[-1]["accepted"] = True
+        stop = fixed_iters <= 0 and done
+        if m <= 0 or stop:
+            x = xn
+            if stop:
+                converged = True
+                break
+            continue
+        reject = cand and ((aa_guard == "residual" and not info["r"] <= (1.0 + aa_slack) * r_acc) or
+                           (aa_guard == "energy" and not info["E"] <= e_acc + aa_slack * abs(e_acc)) or
+                           (aa_keep_set and info["changed"]))
+        if reject:
+            rejected += 1
+            if history:
+                hist[-1]["accepted"] = False
+        if k == n_it - 1:
+            x = xn                 # the last iteration ends on the plain step
             break
+        if reject:
+            x = x_fb
+            prev = A_acc.copy()
+            cand = False
+            x_prev = f_prev = None
+            dX, dF = [], []
+            continue
+        e_acc, r_acc = info["E"], info["r"]
+        A_acc = A.copy()
+        f = xn - x
+        if info["changed"]:
+            x_prev = f_prev = None
+            dX, dF = [], []
+        if x_prev is not None:
+            dX.append((x - x_prev).reshape(-1))
+            dF.append((f - f_prev).reshape(-1))
+            if len(dX) > m:
+                dX.pop(0)
+                dF.pop(0)
+        x_prev, f_prev = x.copy(), f.copy()
+        x_fb = xn
+        if dX:
+            xa, _ = anderson_update(xn.reshape(-1), f.reshape(-1), np.stack(dX, axis=1), np.stack(dF, axis=1))
+            x = xa.reshape(3, -1)
+            cand = True
+        else:
+            x = xn
+            cand = False
     if fixed_iters > 0:
         converged = info["r"] <= tol and not info["changed"]
     stats = dict(iters=(k + 1) if n_it > 0 else 0, residual=info["r"], converged=converged,
                  n_contacts=prev.count, ray_miss=info["ray_miss"], energy=info["E"],
-                 history=hist)
+                 history=hist, rejected=rejected)
     return x, prev, stats

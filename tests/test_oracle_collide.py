@@ -224,3 +224,26 @@ def test_vertex_normals_are_area_weighted_on_an_anisotropic_voxel():
     assert np.abs(n[:, 0] + np.ones(3) / np.sqrt(3)).max() > 0.1
     assert np.abs(n[:, 1] - np.array([2.0, -1.0, -1.0]) / np.sqrt(6)).max() > 0.1
 
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_kdtree_broadphase_finds_the_brute_force_pairs(seed):
+    """The k-d tree broadphase returns exactly the brute-force candidate pairs
+    and penetration flags (deformed slit with jitter, and a pressed finger
+    state with contacts), and the collision response built on it is the same."""
+    prob, x = _deformed_slit(seed=seed)
+    a = oc.tet_candidates(prob, x, prob.query_verts)
+    b = oc.tet_candidates(prob, x, prob.query_verts, broadphase="kdtree")
+    for u, w in zip(a, b):
+        np.testing.assert_array_equal(u, w)
+    assert a[2].any()
+    from tests.meshes import pressed_finger
+    w = pressed_finger()
+    pf = oracle.Problem.from_workload(w)
+    xs, A, _ = oracle.solve(pf, w.alpha, fixed_iters=20 + seed)
+    a = oc.tet_candidates(pf, xs, pf.query_verts)
+    b = oc.tet_candidates(pf, xs, pf.query_verts, broadphase="kdtree")
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+    A1, _ = oracle.collide(pf, xs, A)
+    A2, _ = oracle.collide(pf, xs, A, broadphase="kdtree")
+    assert A1.same_set(A2) and np.array_equal(A1.target, A2.target) and np.array_equal(A1.prim, A2.prim)
