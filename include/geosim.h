@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define GEOSIM_VERSION 100
+#define GEOSIM_VERSION 200
 
 typedef int32_t gs_status;
 
@@ -110,7 +110,42 @@ typedef struct {
   int32_t adj_aa_m;       /* Anderson memory of the adjoint iteration, 0..16 (0:
                              plain fixed-point iteration); the workspace holds
                              the value given at gs_create                         */
+  int32_t aa_m;           /* Anderson memory of the local/global iteration, 0..16
+                             (0: the plain iteration; end of Section III-B); the
+                             workspace holds max(aa_m, adj_aa_m) given at
+                             gs_create, a later larger value is clamped to it     */
+  int32_t aa_guard;       /* tests an accelerated point must pass (GS_AA_GUARD_*) */
+  double aa_slack;        /* relative slack of that test                          */
+  double barrier_timeout_ms; /* bound on one wait of the CG kernel's grid barrier;
+                             a workgroup that waits longer gives up and the call
+                             returns GS_EHIP (0: give up at the first wait)      */
+  double pcg_eta_min;     /* 0: the inner CG stops at pcg_eta; else iteration k's
+                             solve stops at clamp(r_{k-1}, pcg_eta_min, pcg_eta)
+                             (loose far from the fixed point, tighter near it;
+                             the accelerated iteration needs accurate steps
+                             where the map contracts slowly)                     */
 } gs_params;
+
+/* Safeguards of the accelerated iteration.  Every iteration evaluates the
+ * plain map at the current point x_k: collision, local step and global step
+ * give G(x_k), the active set A_k, the residual r_k = max_v |G(x_k)_v -
+ * x_k,v| / diag and the energy E_k of Eq. (9).  An accelerated point that
+ * fails the test is rejected: the next point is the plain step from the last
+ * accepted point, taken with that point's active set (so a rejection leaves
+ * exactly the plain iteration's state behind), and the Anderson history is
+ * cleared.  aa_guard is one of
+ *   RESIDUAL  reject when r_k > (1 + aa_slack) r_acc (r_acc: residual at the
+ *             last accepted point);
+ *   ENERGY    reject when E_k > E_acc + aa_slack |E_acc| (one mesh only; Eq. 9
+ *             decreases along plain steps only with as-rigid-as-possible
+ *             body targets, hyperelastic = 0);
+ *   NONE      no value test;
+ * optionally or-ed with
+ *   SET       also reject when A_k differs from the last accepted point's
+ *             set (an accelerated step may not create or release contacts:
+ *             the active set evolves along plain steps only).
+ * An accepted point whose set changed clears the history (the map changed). */
+enum { GS_AA_GUARD_NONE = 0, GS_AA_GUARD_RESIDUAL = 1, GS_AA_GUARD_ENERGY = 2, GS_AA_GUARD_SET = 4 };
 
 typedef struct {
   int32_t iters;           /* outer iterations run                                */
@@ -119,6 +154,8 @@ typedef struct {
   int32_t ray_miss;        /* penetrating vertices whose ray found no boundary    */
   double residual;         /* r_k of the last iteration                           */
   double energy;           /* Eq. (9) at x_k with the last targets                */
+  int32_t aa_rejected;     /* accelerated points rejected by the safeguard        */
+  int32_t pad;
 } gs_stats;
 
 /* Sizes derived by gs_create (set-up step). */
@@ -139,7 +176,9 @@ const char* gs_last_error(void);
 /* Defaults: Ecoflex 00-30 (c1 = 0.0418, c2 = 0.0106 MPa), hyperelastic on,
  * kappa_col 1, eps_rel 0.05, ray_rel 4, no collision, tol 1e-6,
  * max_iter 20000, fixed_iters 0, pcg_eta 1e-3, pcg_max 200, check_every 16,
- * pcg_blocks 0, trace_len 0, adj_tol 1e-6, adj_max_iter 20000, adj_aa_m 16. */
+ * pcg_blocks 0, trace_len 0, adj_tol 1e-6, adj_max_iter 20000, adj_aa_m 16,
+ * aa_m 8, aa_guard GS_AA_GUARD_RESIDUAL | GS_AA_GUARD_SET, aa_slack 0.5,
+ * barrier_timeout_ms 2000, pcg_eta_min 0. */
 void gs_default_params(gs_params* params);
 
 /* Host set-up for one mesh (done once per mesh; not per iteration): orient
@@ -196,14 +235,24 @@ gs_status gs_bind(gs_problem* p, void* dev_workspace, size_t bytes, void* hip_st
  * iteration limits).  Obstacles and mesh stay.  GS_EINVAL on bad values. */
 gs_status gs_set_params(gs_problem* p, const gs_params* params);
 
-/* Solve: iterate from dev_x (warm start; fixed vertices are reset to X0) and
- * the stored active contact set (empty after gs_bind, or the set left by the
- * previous solve / gs_set_contacts), for the per-chamber volume ratios
- * dev_alpha[n_chambers], until r_k <= tol with the active set unchanged, or
- * exactly fixed_iters iterations.  dev_x [3][n] receives the result.
- * Returns GS_OK, GS_NOT_CONVERGED (last iterate written), GS_EBREAKDOWN,
- * GS_ESTATE (not bound), GS_EINVAL (null pointers), GS_EHIP.  stats may be
- * NULL. */
+/* Solve (Section III-B, inner loop of Algorithm 1): iterate from dev_x (warm
+ * start; fixed vertices are reset to X0) and the stored active contact set
+ * (empty after gs_bind, or the set left by the previous solve /
+ * gs_set_contacts), for the per-chamber volume ratios dev_alpha[n_chambers],
+ * until r_k <= tol with the active set unchanged, or exactly fixed_iters
+ * iterations.  Each iteration evaluates the plain local/global map G at the
+ * current point x_k (collision check and response, local step, global step),
+ * r_k = max_v |G(x_k)_v - x_k,v| / bbox diagonal.  With aa_m = 0 the next
+ * point is G(x_k); with aa_m > 0 it is the Anderson point (Walker & Ni 2011)
+ * built from the last aa_m accepted points and residuals, or, when the
+ * guard (aa_guard) rejects x_k, the plain step from the last accepted point;
+ * the history is cleared whenever the active set changes.  Either way the
+ * result is G(x_k) of the last iteration, and the stopping rule is the plain
+ * iteration's.  In a batch each mesh has its own history and decisions.
+ * dev_x [3][n] receives the result.  Returns GS_OK, GS_NOT_CONVERGED (last
+ * iterate written), GS_EBREAKDOWN, GS_ESTATE (not bound), GS_EINVAL (null
+ * pointers), GS_EHIP (also when a grid barrier gave up, see
+ * barrier_timeout_ms).  stats may be NULL. */
 gs_status gs_solve(gs_problem* p, const void* dev_alpha, void* dev_x, gs_stats* stats);
 
 /* Forget the stored active contact set (the next solve starts from none). */
@@ -338,9 +387,11 @@ gs_status gs_trace(gs_problem* p, int32_t cap, double* rows, int32_t* count);
  * right-hand side ("contacts" and "gather" count no launches in a solve);
  * with self-collision on a mesh below 2^18 tets, "tet_query" includes the
  * local step ("local" then counts none); "hash_insert" runs only on a solve's
- * first iteration (the CG kernel refills the hash).  gs_profile(p, 0)
- * stops. */
-#define GS_N_KERNELS 11
+ * first iteration (the CG kernel refills the hash, or, with aa_m > 0, the
+ * accelerated iteration's position update); "anderson" is that update with
+ * its dot products and least-squares solve (three launches counted as one).
+ * gs_profile(p, 0) stops. */
+#define GS_N_KERNELS 12
 gs_status gs_profile(gs_problem* p, int32_t enable);
 gs_status gs_profile_read(const gs_problem* p, double* ms, int64_t* launches);
 const char* gs_kernel_name(int32_t k);

@@ -27,6 +27,7 @@
 //                 face (per contact, scattered with double atomics: the few
 //                 such contacts touch the vertex, its boundary-face ring and
 //                 the hit face's vertices); kept self contacts are constant.
+#include "anderson.h"
 #include "tet_math.h"
 
 namespace gs {
@@ -609,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_chamber_sum(Dev<R> d, Consts c, 
 // (dF^T dF + ridge) gamma = dF^T f are solved in double by one thread; the
 // dot products are block partials summed in a fixed order.
 
-constexpr int kAaMax = 16;
+constexpr int kAaMax = kAaMaxMem;
 constexpr int kAaBlock = 256;
 
 // New difference column (k >= 1), previous iterate / residual, and the
@@ -662,18 +663,15 @@ __global__ __launch_bounds__(kAaBlock) void k_aa_diff_dots(Dev<R> d, Consts c) {
 }
 
 // Sum the partials (one wavefront per value), update the Gram matrix, and
-// solve for gamma: right-looking Cholesky with a relative ridge, one LDS
-// entry per thread, then the two triangular solves by wavefront 0 (one
-// shuffle-reduced dot product per row).  A non-positive pivot gives
-// gamma = 0 (a plain step).  Counts the iteration.
-constexpr int kAaSolveBlock = kAaMax * kAaMax;
+// solve for gamma (gram_solve: Cholesky with a relative ridge; a
+// non-positive pivot gives gamma = 0, a plain step).  Counts the iteration.
+constexpr int kAaSolveBlock = kAaSolveThreads;
 
 template <typename R>
 __global__ __launch_bounds__(kAaSolveBlock) void k_aa_solve(Dev<R> d, Consts c, int G) {
   __shared__ double val[2 * kAaMax];
   __shared__ double A[kAaMax][kAaMax];
   __shared__ double y[kAaMax];
-  __shared__ int ok;
   if (is_done(d.st)) return;
   const int k = d.aa_k[0];
   const int m = c.aa_m;
@@ -689,8 +687,7 @@ __global__ __launch_bounds__(kAaSolveBlock) void k_aa_solve(Dev<R> d, Consts c, 
   }
   __syncthreads();
   const int i = mk > 0 ? tid / mk : 0, j = mk > 0 ? tid % mk : 0;
-  const bool mine = tid < mk * mk;
-  if (mine) {
+  if (tid < mk * mk) {
     // Gram matrix: the new column from the partial sums, the rest as stored
     double h;
     if (i == col) h = val[2 * j];
@@ -699,49 +696,11 @@ __global__ __launch_bounds__(kAaSolveBlock) void k_aa_solve(Dev<R> d, Consts c, 
     d.aa_h[i * m + j] = h;
     A[i][j] = h;
   }
-  if (tid == 0) ok = mk > 0 ? 1 : 0;
+  if (tid < mk) y[tid] = val[2 * tid + 1];
   __syncthreads();
-  if (mk > 0) {
-    if (tid == 0) {
-      double dmax = 0.0;
-      for (int q = 0; q < mk; ++q) dmax = fmax(dmax, A[q][q]);
-      if (!(dmax > 0.0)) ok = 0;
-      val[0] = 1e-10 * dmax;  // the partials are no longer needed
-    }
-    __syncthreads();
-    if (mine && i == j) A[i][i] += val[0];
-    __syncthreads();
-    for (int kk = 0; kk < mk; ++kk) {
-      if (tid == 0) {
-        if (ok && A[kk][kk] > 0.0) A[kk][kk] = sqrt(A[kk][kk]);
-        else ok = 0;
-      }
-      __syncthreads();
-      if (!ok) break;
-      if (tid > kk && tid < mk) A[tid][kk] /= A[kk][kk];
-      __syncthreads();
-      if (mine && i > kk && j > kk && j <= i) A[i][j] -= A[i][kk] * A[j][kk];
-      __syncthreads();
-    }
-    if (wave == 0) {
-      // L y = v, then L^T gamma = y (lower triangle of A holds L); lane r
-      // keeps y_r and gamma_r, the row dot products are shuffle-reduced
-      double yl = 0.0, gl = 0.0;
-      for (int r = 0; r < mk; ++r) {
-        double t = (lane < r) ? A[r][lane] * yl : 0.0;
-        t = wave_sum(t);
-        const double yr = (val[2 * r + 1] - t) / A[r][r];
-        if (lane == r) yl = yr;
-      }
-      for (int r = mk - 1; r >= 0; --r) {
-        double t = (lane > r && lane < mk) ? A[lane][r] * gl : 0.0;
-        t = wave_sum(t);
-        const double gr = (__shfl(yl, r, 64) - t) / A[r][r];
-        if (lane == r) gl = gr;
-      }
-      if (lane < mk) d.aa_gamma[lane] = ok ? gl : 0.0;
-    }
-  }
+  double gj;
+  gram_solve(A, y, mk, &gj);
+  if (wave == 0 && lane < mk) d.aa_gamma[lane] = gj;
   if (tid == 0) d.aa_k[0] = k + 1;
 }
 

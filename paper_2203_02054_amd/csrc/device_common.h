@@ -124,17 +124,42 @@ __device__ __forceinline__ double block_max(double v, double* lds) {
 // is stored write-through (st_wt) to leave it little to do.  `target` is the
 // block's own count of arrivals expected so far.  The launch's last block
 // clears the counter once every block is past its last barrier.
-__device__ __forceinline__ void grid_barrier(unsigned* count, unsigned& target, unsigned nblocks) {
+//
+// The wait is bounded: a block that has waited `timeout` ticks of the
+// constant-rate wall clock (a workgroup that never arrives: the grid was not
+// co-resident), or that finds the status word `done` already set to STALLED
+// by another block, stores STALLED there (only over RUNNING) and returns
+// false without the acquire; every caller then leaves the kernel at once,
+// so all blocks end normally and the host reads the code instead of the GPU
+// spinning.  A block launched after the others gave up finds the word set
+// at its start and returns.  timeout = 0 gives up at the first unfinished
+// poll (the host's way to exercise this path).
+__device__ __forceinline__ bool grid_barrier(unsigned* count, unsigned& target, unsigned nblocks, int* done,
+                                             unsigned long long timeout) {
+  __shared__ int ok_sh;
   target += nblocks;
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while ((int)(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0)
+    int ok = 1;
+    const unsigned long long t0 = wall_clock64();
+    while ((int)(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == STALLED ||
+          wall_clock64() - t0 >= timeout) {
+        int expect = RUNNING;
+        __hip_atomic_compare_exchange_strong(done, &expect, (int)STALLED, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
       __builtin_amdgcn_s_sleep(1);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok_sh = ok;
   }
   __syncthreads();
+  return ok_sh != 0;
 }
 
 // ---- exact predicates -------------------------------------------------------

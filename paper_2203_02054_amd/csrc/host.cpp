@@ -54,15 +54,16 @@ struct Layout {
   size_t mu, acc3, ga, ch_start, ch_tets, mmax, mdone2, st2, alpha_last, mgam;
   size_t aa_dx, aa_df, aa_xp, aa_fp, aa_h, aa_gamma, aa_part, aa_k;
   size_t lam, ga_acc, st3, st4;
+  size_t faa, faa_h, faa_gam, faa_blk, faa_mblk, cact_s, ctgt_s, cnrm_s, cprim_s;
   size_t total;
 };
 
-constexpr int kNKernels = 11;
+constexpr int kNKernels = 12;
 const char* const kKernelNames[kNKernels] = {"hash_insert", "tet_query", "ray_cast",  "contacts",
                                              "local",       "gather",    "pcg",       "adj_springs",
-                                             "adj_local",   "adj_gather", "adj_pcg"};
+                                             "adj_local",   "adj_gather", "adj_pcg",  "anderson"};
 enum { K_CONTACTS = 3, K_LOCAL = 4, K_GATHER = 5, K_PCG = 6, K_ADJ_SPRINGS = 7, K_ADJ_LOCAL = 8, K_ADJ_GATHER = 9,
-       K_ADJ_PCG = 10 };
+       K_ADJ_PCG = 10, K_ANDERSON = 11 };
 
 // Optional per-kernel timing: each launch is bracketed by two events on the
 // bound stream; elapsed times are collected whenever the driver synchronises.
@@ -142,6 +143,8 @@ struct gs_problem {
   std::vector<int32_t> vbeg, tbeg, chbeg, fbeg, sbeg;  // [M+1] offsets
   std::vector<int32_t> vmesh, tmesh;
   std::vector<int32_t> ch_start, ch_tets;  // chamber -> tets (ascending)
+  std::vector<AaBlock> faa_blk;            // blocks of the acceleration's dot-product kernel
+  std::vector<int32_t> faa_mblk;           // [M+1] first block of each mesh
   // device binding
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -154,7 +157,8 @@ struct gs_problem {
   int trace_len = 0;
   int last_iters = 0;
   bool solved = false;  // a solve has run since gs_bind (the adjoint's state exists)
-  int aa_cap = 0;       // Anderson memory the workspace holds (adj_aa_m at gs_create)
+  int aa_cap = 0;       // Anderson memory the workspace holds (max(aa_m, adj_aa_m) at gs_create)
+  int wclk_khz = 0;     // rate of the device's constant wall clock (grid-barrier time limit)
   Profiler prof;
   // pinned host copies of the device status, one per chunk in flight, and
   // the events that mark their copies (created at gs_bind)
@@ -169,6 +173,15 @@ struct gs_problem {
 
 namespace {
 
+gs_status check_params(const gs_params* p);
+
+// The energy guard compares one mesh's energy: not for a batch.
+gs_status check_batch_params(const gs_params* p, int M) {
+  if (M > 1 && p->aa_m > 0 && (p->aa_guard & 3) == GS_AA_GUARD_ENERGY)
+    return fail(GS_EINVAL, "the energy guard of the accelerated iteration needs a single mesh");
+  return GS_OK;
+}
+
 gs_status check_params(const gs_params* p) {
   if (!p) return fail(GS_EINVAL, "null params");
   if (!(p->c1 > 0) || !(p->c2 >= 0) || !std::isfinite(p->c1) || !std::isfinite(p->c2))
@@ -180,7 +193,13 @@ gs_status check_params(const gs_params* p) {
   if (p->check_every < 1) return fail(GS_EINVAL, "check_every must be >= 1");
   if (p->trace_len < 0) return fail(GS_EINVAL, "trace_len must be >= 0");
   if (!(p->adj_tol >= 0) || p->adj_max_iter < 1) return fail(GS_EINVAL, "bad adj_tol/adj_max_iter");
-  if (p->adj_aa_m < 0 || p->adj_aa_m > 16) return fail(GS_EINVAL, "adj_aa_m must be in [0, 16]");
+  if (p->adj_aa_m < 0 || p->adj_aa_m > kAaMaxMem) return fail(GS_EINVAL, "adj_aa_m must be in [0, 16]");
+  if (p->aa_m < 0 || p->aa_m > kAaMaxMem) return fail(GS_EINVAL, "aa_m must be in [0, 16]");
+  if ((p->aa_guard & ~7) != 0 || (p->aa_guard & 3) == 3) return fail(GS_EINVAL, "bad aa_guard");
+  if (!(p->aa_slack >= 0) || !std::isfinite(p->aa_slack)) return fail(GS_EINVAL, "aa_slack must be >= 0");
+  if (!(p->barrier_timeout_ms >= 0) || !std::isfinite(p->barrier_timeout_ms))
+    return fail(GS_EINVAL, "barrier_timeout_ms must be >= 0");
+  if (!(p->pcg_eta_min >= 0 && p->pcg_eta_min <= p->pcg_eta)) return fail(GS_EINVAL, "need 0 <= pcg_eta_min <= pcg_eta");
   return GS_OK;
 }
 
@@ -271,6 +290,15 @@ Layout make_layout(const gs_problem* p) {
   L.ga_acc = take((size_t)p->nch * 8);
   L.st3 = take(sizeof(DevStatus));
   L.st4 = take(sizeof(DevStatus));
+  L.faa = take((size_t)p->M * sizeof(AaMesh));
+  L.faa_h = take((size_t)p->M * kAaMaxMem * kAaMaxMem * 8);
+  L.faa_gam = take((size_t)p->M * kAaMaxMem * 8);
+  L.faa_blk = take(p->faa_blk.size() * sizeof(AaBlock));
+  L.faa_mblk = take(p->faa_mblk.size() * 4);
+  L.cact_s = take(S * sl);
+  L.ctgt_s = take(3 * S * sl * 8);
+  L.cnrm_s = take(3 * S * sl * 8);
+  L.cprim_s = take(S * sl * 4);
   L.total = align256(off);
   return L;
 }
@@ -352,6 +380,15 @@ Dev<R> make_dev(const gs_problem* p) {
   d.aa_k = (int32_t*)(b + L.aa_k);
   d.lam = (R*)(b + L.lam);
   d.ga_acc = (double*)(b + L.ga_acc);
+  d.faa = (AaMesh*)(b + L.faa);
+  d.faa_h = (double*)(b + L.faa_h);
+  d.faa_gam = (double*)(b + L.faa_gam);
+  d.faa_blk = (const AaBlock*)(b + L.faa_blk);
+  d.faa_mblk = (const int32_t*)(b + L.faa_mblk);
+  d.cact_s = (uint8_t*)(b + L.cact_s);
+  d.ctgt_s = (double*)(b + L.ctgt_s);
+  d.cnrm_s = (double*)(b + L.cnrm_s);
+  d.cprim_s = (int32_t*)(b + L.cprim_s);
   d.dbg_tet = nullptr;
   d.dbg_tri = nullptr;
   d.dbg_cap = 0;
@@ -387,8 +424,14 @@ Consts make_consts(const gs_problem* p) {
   c.kappa = p->prm.kappa_col;
   c.tol = p->prm.tol;
   c.pcg_eta = p->prm.pcg_eta;
+  c.pcg_eta_min = p->prm.pcg_eta_min;
   c.M = p->M;
   c.mask_done = p->prm.fixed_iters > 0 ? 0 : 1;
+  c.faa_m = std::min(p->prm.aa_m, p->aa_cap);
+  c.faa_guard = p->prm.aa_guard;
+  c.faa_slack = p->prm.aa_slack;
+  c.faa_nblk = (int)p->faa_blk.size();
+  c.bar_timeout = (unsigned long long)(p->prm.barrier_timeout_ms * (double)p->wclk_khz);
   return c;
 }
 
@@ -458,6 +501,8 @@ gs_status bind_impl(gs_problem* p) {
   HIPCHK(upload(b, L.tmesh, p->tmesh, s));
   HIPCHK(upload(b, L.ch_start, p->ch_start, s));
   HIPCHK(upload(b, L.ch_tets, p->ch_tets, s));
+  HIPCHK(upload(b, L.faa_blk, p->faa_blk, s));
+  HIPCHK(upload(b, L.faa_mblk, p->faa_mblk, s));
   HIPCHK(hipMemsetAsync(b + L.mres, 0, (size_t)p->M * 8, s));
   HIPCHK(hipMemsetAsync(b + L.mchanged, 0, (size_t)p->M * 4, s));
   HIPCHK(hipMemsetAsync(b + L.mdone, 0, (size_t)p->M * 4, s));
@@ -470,6 +515,10 @@ gs_status bind_impl(gs_problem* p) {
   if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
   p->pcg_maxg = maxg;
   p->pcg_grid = pcg_grid_for(p, maxg);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&p->wclk_khz, hipDeviceAttributeWallClockRate, dev));
+  if (p->wclk_khz <= 0) return fail(GS_EHIP, "device reports no wall-clock rate");
   return GS_OK;
 }
 
@@ -572,8 +621,23 @@ hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, co
   if (!fused_local)
     if ((e = timed(p, K_LOCAL, [&] { return launch_local<R>(d, c, alpha, s); })) != hipSuccess) return e;
   // the CG kernel first updates the contacts and gathers the right-hand side
-  return timed_pcg<R>(p, K_PCG, d, c, false);
+  if ((e = timed_pcg<R>(p, K_PCG, d, c, false)) != hipSuccess) return e;
+  if (c.faa_m > 0) return timed(p, K_ANDERSON, [&] { return launch_fwd_anderson<R>(d, c, s); });
+  return hipSuccess;
 }
+
+// Accelerated points rejected in the last solve (summed over the meshes).
+gs_status aa_rejections(gs_problem* p, int& total) {
+  total = 0;
+  std::vector<AaMesh> a(p->M);
+  HIPCHK(hipMemcpyAsync(a.data(), p->ws + p->lay.faa, a.size() * sizeof(AaMesh), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  for (const AaMesh& q : a) total += q.rejected;
+  return GS_OK;
+}
+
+const char* kStalledMsg =
+    "a grid barrier of the CG kernel gave up waiting (workgroups not co-resident, or barrier_timeout_ms too short)";
 
 template <typename R>
 gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
@@ -591,7 +655,12 @@ gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
   HIPCHK(launch_output<R>(d, c, x, s));
   HIPCHK(hipStreamSynchronize(s));
   p->last_iters = h.iters;
-  p->solved = true;
+  p->solved = h.done != STALLED;
+  int rej = 0;
+  if (c.faa_m > 0) {
+    const gs_status r = aa_rejections(p, rej);
+    if (r != GS_OK) return r;
+  }
   if (stats) {
     stats->iters = h.iters;
     stats->pcg_iters_total = h.pcg_total;
@@ -599,7 +668,10 @@ gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
     stats->ray_miss = h.ray_miss_last;
     stats->residual = h.residual;
     stats->energy = h.energy;
+    stats->aa_rejected = rej;
+    stats->pad = 0;
   }
+  if (h.done == STALLED) return fail(GS_EHIP, kStalledMsg);
   if (h.done == BREAKDOWN) return fail(GS_EBREAKDOWN, "non-finite value or CG curvature p'Ap <= 0");
   if (h.done == MAXITER) {
     g_err = "max_iter reached";
@@ -627,6 +699,7 @@ gs_status adjoint_impl(gs_problem* p, const R* gL, R* dalpha, R* mu_out, gs_stat
   c.max_iter = p->prm.adj_max_iter;
   c.trace_len = 0;
   c.aa_m = std::min(p->prm.adj_aa_m, p->aa_cap);
+  c.faa_m = 0;  // the forward acceleration's kernels are not part of the adjoint iteration
   if (c.aa_m > 0) c.mask_done = 0;  // the accelerated update mixes meshes: converge all at once
   hipStream_t s = p->stream;
   HIPCHK(launch_adj_init<R>(d, c, s));
@@ -652,7 +725,10 @@ gs_status adjoint_impl(gs_problem* p, const R* gL, R* dalpha, R* mu_out, gs_stat
     stats->ray_miss = 0;
     stats->residual = h.residual;
     stats->energy = 0.0;
+    stats->aa_rejected = 0;
+    stats->pad = 0;
   }
+  if (h.done == STALLED) return fail(GS_EHIP, kStalledMsg);
   if (h.done == BREAKDOWN) return fail(GS_EBREAKDOWN, "non-finite value or CG curvature p'Ap <= 0 in the adjoint");
   if (h.done == MAXITER) {
     g_err = "adj_max_iter reached";
@@ -936,6 +1012,16 @@ void finalize(gs_problem* p) {
   std::vector<int32_t> cur(p->ch_start.begin(), p->ch_start.end() - 1);
   for (int e = 0; e < p->T; ++e)
     if ((p->tag[e] & 7) != GS_BODY) p->ch_tets[cur[p->tag[e] >> 3]++] = e;
+  // blocks of the acceleration's dot products: kFaaRows rows each, never
+  // straddling meshes (a mesh's sums are taken over its own blocks)
+  p->faa_blk.clear();
+  p->faa_mblk.assign(1, 0);
+  for (int m = 0; m < p->M; ++m) {
+    for (int v0 = p->vbeg[m]; v0 < p->vbeg[m + 1]; v0 += kFaaRows)
+      p->faa_blk.push_back({m, v0, std::min(v0 + kFaaRows, p->vbeg[m + 1]), 0});
+    p->faa_mblk.push_back((int32_t)p->faa_blk.size());
+  }
+  if ((int)p->faa_blk.size() > p->nparts) throw std::runtime_error("too many blocks for the partial-sum arrays");
 }
 
 // Concatenate single-mesh set-ups into one problem: vertex, tet, chamber,
@@ -1137,6 +1223,7 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
   Consts cf = make_consts(p);                          // forward iterations: never stop early
   cf.fixed_iters = 1 << 30;
   cf.mask_done = 0;
+  cf.faa_m = 0;                                        // the plain map is what the sweep differentiates
   if (p->nch > 0)
     HIPCHK(hipMemcpyAsync(d.alpha_last, alpha, (size_t)p->nch * sizeof(R), hipMemcpyDeviceToDevice, s));
   // forward sweep with checkpoints
@@ -1149,6 +1236,7 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
   DevStatus h{};
   HIPCHK(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (h.done == STALLED) return fail(GS_EHIP, kStalledMsg);
   if (h.done == BREAKDOWN) return fail(GS_EBREAKDOWN, "non-finite value or CG curvature p'Ap <= 0");
   if (xK) HIPCHK(launch_output<R>(d, cf, xK, s));
   HIPCHK(copy_record(p, fin, true, false, true));
@@ -1165,7 +1253,9 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
   cv.mask_done = 0;
   cv.adj_jt = 1;
   cv.aa_m = 0;
+  cv.faa_m = 0;
   Consts cc = make_consts(p);
+  cc.faa_m = 0;
   cc.mask_done = 0;
   cc.fixed_iters = 0;
   cc.max_iter = 1;
@@ -1205,6 +1295,7 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
     HIPCHK(hipMemcpyAsync(&hc, dc.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (p->prof.on) HIPCHK(p->prof.flush());
+    if (hc.done == STALLED) return fail(GS_EHIP, kStalledMsg);
     if (hc.done == BREAKDOWN) return fail(GS_EBREAKDOWN, "breakdown in a reverse CG solve");
     rev_pcg += hc.pcg_total;
   }
@@ -1220,6 +1311,8 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
     stats->ray_miss = h.ray_miss_last;
     stats->residual = h.residual;
     stats->energy = h.energy;
+    stats->aa_rejected = 0;
+    stats->pad = 0;
   }
   return GS_OK;
 }
@@ -1257,6 +1350,11 @@ void gs_default_params(gs_params* p) {
   p->adj_tol = 1e-6;
   p->adj_max_iter = 20000;
   p->adj_aa_m = 16;
+  p->aa_m = 8;
+  p->aa_guard = GS_AA_GUARD_RESIDUAL | GS_AA_GUARD_SET;
+  p->aa_slack = 0.5;
+  p->barrier_timeout_ms = 2000.0;
+  p->pcg_eta_min = 0.0;
 }
 
 gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** out) {
@@ -1273,7 +1371,7 @@ gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** ou
   if (!p) return fail(GS_EINVAL, "out of host memory");
   p->prm = *prm;
   p->trace_len = prm->trace_len;
-  p->aa_cap = prm->adj_aa_m;
+  p->aa_cap = std::max(prm->adj_aa_m, prm->aa_m);
   try {
     st = setup(p, m);
     if (st == GS_OK) finalize(p);
@@ -1294,6 +1392,7 @@ gs_status gs_create_batch(int32_t n_mesh, const gs_mesh_desc* meshes, const gs_p
   if (n_mesh < 1 || !meshes) return fail(GS_EINVAL, "need at least one mesh");
   gs_status st = check_params(prm);
   if (st != GS_OK) return st;
+  if ((st = check_batch_params(prm, n_mesh)) != GS_OK) return st;
   long nt = 0, nv = 0;
   for (int m = 0; m < n_mesh; ++m) {
     const gs_mesh_desc* d = &meshes[m];
@@ -1322,7 +1421,7 @@ gs_status gs_create_batch(int32_t n_mesh, const gs_mesh_desc* meshes, const gs_p
       p->prm = *prm;
       p->prec = meshes[0].precision;
       p->trace_len = prm->trace_len;
-      p->aa_cap = prm->adj_aa_m;
+      p->aa_cap = std::max(prm->adj_aa_m, prm->aa_m);
       merge(p, parts);
       finalize(p);
     }
@@ -1441,8 +1540,9 @@ gs_status gs_bind(gs_problem* p, void* ws, size_t bytes, void* stream) {
 
 gs_status gs_set_params(gs_problem* p, const gs_params* prm) {
   if (!p) return fail(GS_EINVAL, "null problem");
-  const gs_status st = check_params(prm);
+  gs_status st = check_params(prm);
   if (st != GS_OK) return st;
+  if ((st = check_batch_params(prm, p->M)) != GS_OK) return st;
   if (prm->kappa_col != p->prm.kappa_col) {
     for (int s = 0; s < p->S; ++s) p->kq[s] *= prm->kappa_col / p->prm.kappa_col;
     if (p->bound) HIPCHK(hipMemcpyAsync(p->ws + p->lay.kq, p->kq.data(), p->kq.size() * 8, hipMemcpyHostToDevice,

@@ -19,9 +19,12 @@ constexpr int kPcgRowsPerBlock = 256; // default rows per CG block (grid = n / 2
 // beats prefetching and lane sharing) and is not fused with the local step.
 constexpr int kTetQueryWide = 1 << 18;
 constexpr int kMaxPcgGrid = 1024;     // workgroups of the persistent CG kernel at most
+constexpr int kAaMaxMem = 16;         // Anderson memory at most (forward and adjoint)
+constexpr int kFaaRows = 1024;        // rows per block of the acceleration's dot-product kernel
 
 // Completion codes kept on the device (DevStatus::done).
-enum { RUNNING = 0, CONVERGED = 1, MAXITER = 2, BREAKDOWN = 3, FIXED_DONE = 4 };
+// STALLED: a grid barrier of the CG kernel gave up waiting (see grid_barrier).
+enum { RUNNING = 0, CONVERGED = 1, MAXITER = 2, BREAKDOWN = 3, FIXED_DONE = 4, STALLED = 5 };
 
 struct DevStatus {
   int iters;            // outer iterations completed
@@ -42,7 +45,31 @@ struct DevStatus {
   double residual;      // r_k of the last completed iteration
   double energy;        // Eq. 9 at x_k with the iteration's targets
   unsigned bar_count;    // grid-barrier arrivals of the running CG launch (0 between launches)
-  unsigned pad0, pad1, pad2;
+  int aa_pending;        // accelerated iteration: an iteration's position update is due
+  int aa_ticket;         // last-block ticket of the position-update kernel
+  unsigned pad2;
+};
+
+// Anderson acceleration of the local/global iteration: per-mesh state.
+// `act` is the decision the CG kernel's last block takes for the iteration
+// just finished, read by the acceleration kernels that follow it.
+enum { AA_NONE = 0, AA_ACCEPT = 1, AA_REJECT = 2 };
+struct AaMesh {
+  int k;         // difference columns held (<= memory); columns 0..k-1 are valid
+  int head;      // column the next difference goes to
+  int has_prev;  // the last accepted point and its residual are stored
+  int cand;      // the current point is an accelerated one (not yet tested)
+  int act;       // AA_NONE (mesh done or frozen) / AA_ACCEPT / AA_REJECT
+  int rejected;  // accelerated points rejected in this solve
+  int ok;        // the last least-squares solve succeeded
+  int pad;
+  double r_acc;  // residual at the last accepted point (residual guard)
+  double e_acc;  // energy at the last accepted point (energy guard)
+};
+
+// A block of the acceleration's dot-product kernel: rows [v0, v1) of mesh m.
+struct AaBlock {
+  int m, v0, v1, pad;
 };
 
 // Per-mesh constants of a problem made of one or several meshes.
@@ -71,7 +98,13 @@ struct Consts {
   int adj_jt;           // adjoint gather writes (db/dx)^T mu alone to `lam` (unrolled reverse sweep)
   int a_parts;          // energy partials the local step writes per iteration (part_a)
   int cg_soa;           // CG state layout for the current grid: 1 = [3][n] (paired variant), 0 = [n][3]
+  unsigned long long bar_timeout;  // grid-barrier wait limit in wall-clock ticks
+  int faa_m;            // Anderson memory of the local/global iteration (0: plain)
+  int faa_guard;        // GS_AA_GUARD_*
+  int faa_nblk;         // blocks of the acceleration's dot-product kernel
   double c1, c2, kappa, tol, pcg_eta;
+  double pcg_eta_min;   // > 0: forward solves stop at clamp(previous r_k, pcg_eta_min, pcg_eta)
+  double faa_slack;     // relative slack of the guard test
 };
 
 // Device pointers, all inside the caller's workspace except the in/out buffers.
@@ -153,6 +186,17 @@ struct Dev {
   double* aa_gamma;        // [m] least-squares coefficients
   double* aa_part;         // [2m][nparts] block partials of the dot products
   int32_t* aa_k;           // [1] iterations taken by the accelerated loop
+  // Anderson acceleration of the local/global iteration (memory Consts::faa_m;
+  // shares aa_dx / aa_df / aa_xp / aa_fp with the adjoint's)
+  AaMesh* faa;             // [M]
+  double* faa_h;           // [M][kAaMaxMem][kAaMaxMem] Gram matrices of the residual differences
+  double* faa_gam;         // [M][kAaMaxMem] least-squares coefficients
+  const AaBlock* faa_blk;  // [faa_nblk] row ranges of the dot-product kernel, grouped by mesh
+  const int32_t* faa_mblk; // [M+1] first block of each mesh
+  uint8_t* cact_s;         // the active set at the last accepted point (restored on a rejection)
+  double* ctgt_s;
+  double* cnrm_s;
+  int32_t* cprim_s;
   // unrolled reverse sweep
   R* lam;                  // [3][n] adjoint of the positions
   double* ga_acc;          // [nch] dL/dalpha accumulated over the reverse steps
@@ -186,6 +230,8 @@ hipError_t launch_adj_local(const Dev<R>& d, const Consts& c, bool alpha_grad, h
 template <typename R> hipError_t launch_adj_gather(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_adj_chamber_sum(const Dev<R>& d, const Consts& c, R* out, hipStream_t s);
 template <typename R> hipError_t launch_adj_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
+// Anderson step of the local/global iteration, after the CG kernel
+template <typename R> hipError_t launch_fwd_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
 // unrolled adjoint helpers
 enum { ADJ_RESIDUAL = 0, ADJ_ALPHA = 1, ADJ_JT = 2 };
 template <typename R> hipError_t launch_adj_local_mode(const Dev<R>& d, const Consts& c, int mode, hipStream_t s);

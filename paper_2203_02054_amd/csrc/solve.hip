@@ -57,9 +57,16 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
     d.mdone[i] = 0;
     d.mres[i] = 0ull;
     d.mchanged[i] = 0;
+    AaMesh a{};
+    a.act = AA_NONE;
+    a.r_acc = INFINITY;
+    a.e_acc = INFINITY;
+    d.faa[i] = a;
   }
   if (v == 0) {
     DevStatus* st = d.st;
+    st->aa_pending = 0;
+    st->aa_ticket = 0;
     st->n_active = c.M;
     st->iters = 0;
     st->done = RUNNING;
@@ -367,6 +374,9 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
         const W4<R> dv = x[v];
         const R dd[3] = {dv.x, dv.y, dv.z};
         double uq = 0.0, xn[3] = {0.0, 0.0, 0.0};
+        // accelerated local/global iteration: u stays at x_k, the update
+        // (plain, accelerated or the fallback) is taken by k_faa_update
+        const bool move = ADJ || !c.faa_m;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           if (ADJ) {
@@ -374,14 +384,14 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
             const R mm = d.mu[k * n + v] + dd[k];
             if (!c.aa_m) d.mu[k * n + v] = mm;
             uq += (double)mm * (double)mm;
-          } else {
+          } else if (move) {
             const R uu = d.u[k * n + v] + dd[k];
             d.u[k * n + v] = uu;
             xn[k] = d.X0[k * n + v] + (double)uu;
             d.xc[k * n + v] = xn[k];
           }
         }
-        if (!ADJ && c.self_col && d.vq[v] >= 0) hash_insert_entry(d, c, d.vq[v], v, m, xn[0], xn[1], xn[2]);
+        if (!ADJ && move && c.self_col && d.vq[v] >= 0) hash_insert_entry(d, c, d.vq[v], v, m, xn[0], xn[1], xn[2]);
         dm = sqrt(((double)dv.x * dv.x + (double)dv.y * dv.y) + (double)dv.z * dv.z);
         um = sqrt(uq);
       }
@@ -437,6 +447,35 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
       if (c.fixed_iters <= 0 && r <= c.tol && (ADJ || !d.mchanged[mi])) d.mdone[mi] = it;
       if (d.mdone[mi] == 0) active += 1.0;
     }
+    if (!ADJ && c.faa_m > 0) {
+      // the accelerated iteration's decision for the point x_k just
+      // evaluated (a mesh that converged now, or was frozen, takes none):
+      // an accelerated point whose residual grew past (1 + slack) times the
+      // last accepted one's is rejected and the history cleared; an
+      // accepted point clears the history when its active set changed (the
+      // map changed with it).  The energy guard decides below, after the
+      // energy sum.
+      AaMesh* a = d.faa + mi;
+      int act = AA_NONE;
+      if (was_running && d.mdone[mi] == 0) {
+        act = AA_ACCEPT;
+        if (a->cand && (c.faa_guard & 3) == GS_AA_GUARD_RESIDUAL && !(r <= (1.0 + c.faa_slack) * a->r_acc))
+          act = AA_REJECT;
+        if (a->cand && (c.faa_guard & GS_AA_GUARD_SET) && d.mchanged[mi]) act = AA_REJECT;
+        if (act == AA_REJECT) {
+          a->rejected += 1;
+          a->cand = 0;
+        } else {
+          a->r_acc = r;
+        }
+        if (act == AA_REJECT || d.mchanged[mi]) {
+          a->k = 0;
+          a->head = 0;
+          a->has_prev = 0;
+        }
+      }
+      a->act = act;
+    }
     d.mres[mi] = 0ull;
     if (!ADJ) d.mchanged[mi] = 0;
   }
@@ -470,7 +509,8 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   else if (it >= c.max_iter)
     code = MAXITER;
   double E = st->energy;
-  if (!ADJ && (code != RUNNING || it <= c.trace_len)) {  // the same for every thread
+  const bool eguard = !ADJ && c.faa_m > 0 && (c.faa_guard & 3) == GS_AA_GUARD_ENERGY;
+  if (!ADJ && (code != RUNNING || it <= c.trace_len || eguard)) {  // the same for every thread
     double eloc = 0.0;
     const int gl = c.a_parts, gg = gridDim.x;  // spring-energy partials: one per CG block
     for (int b = threadIdx.x; b < gl; b += kPcgBlock) eloc += d.part_a[b];
@@ -484,6 +524,24 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
     if (!(E == E)) code = BREAKDOWN;
   }
   if (threadIdx.x != 0) return;
+  if (eguard) {
+    // one mesh (thread 0 took its decision above): an accelerated point whose
+    // energy exceeds the last accepted one's by more than the slack is rejected
+    AaMesh* a = d.faa;
+    if (a->act == AA_ACCEPT) {
+      if (a->cand && !(E <= a->e_acc + c.faa_slack * fabs(a->e_acc))) {
+        a->act = AA_REJECT;
+        a->rejected += 1;
+        a->cand = 0;
+        a->k = 0;
+        a->head = 0;
+        a->has_prev = 0;
+      } else {
+        a->e_acc = E;
+      }
+    }
+  }
+  if (!ADJ && c.faa_m > 0) st->aa_pending = 1;
   st->residual = res;
   st->energy = E;
   st->iters = it;
@@ -790,7 +848,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       const double q[10] = {tq[0], tq[1], tq[2], tq[3], tq[4], tq[5], tq[6], tq[7], tq[8], acc_b};
       block_sums_store<10>(q, lds2, d.part_c + 2 * G + blockIdx.x, G);
       if (!PAIR && threadIdx.x == 9) d.part_d[blockIdx.x] = d.part_c[11 * G + blockIdx.x];
-      grid_barrier(bc, bar_target, G);
+      if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
       double S[10];
       if constexpr (PAIR) {
         grid_sums<10>(d.part_c + 2 * G, G, G, sh, S);
@@ -811,7 +869,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
       // a batch: each mesh gets its own weights (the meshes' systems are
       // independent), its sums taken by one block in a fixed order
-      grid_barrier(bc, bar_target, G);
+      if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
       const double* q = reinterpret_cast<const double*>(cg0 + 3 * n);
       for (int m = blockIdx.x; m < c.M; m += G) {
         const int v0 = d.mesh[m].vbeg, v1 = d.mesh[m].vend;
@@ -829,7 +887,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           d.mgam[2 * m + 1] = m2;
         }
       }
-      grid_barrier(bc, bar_target, G);
+      if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
     }
     // x_0, r_0 = b - g1 A w1 - g2 A w2 - g3 A w3 and, in the same pass,
     // w_0 = A u_0: the neighbours' r_0 are rebuilt from their
@@ -965,7 +1023,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     cur = 1;
   }
   block_sum2_store(acc_g, acc_d, lds2, d.part_c + blockIdx.x, d.part_e + blockIdx.x);
-  grid_barrier(bc, bar_target, G);
+  if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
   // PAIR: the lane pair's first neighbour gather, issued before the grid
   // sums so the round trips overlap
   // the neighbours' (r, w, s) of the coming iteration, loaded right after the
@@ -990,7 +1048,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   gam = uniform_d(gam);
   del = uniform_d(del);
   rhs = uniform_d(rhs);
-  const double stop = uniform_d(c.pcg_eta * c.pcg_eta * rhs);
+  // inner tolerance: fixed, or (forward solves with pcg_eta_min > 0) the last
+  // outer residual clamped to [pcg_eta_min, pcg_eta]
+  double eta = c.pcg_eta;
+  if (!ADJ && c.pcg_eta_min > 0.0) eta = fmin(c.pcg_eta, fmax(c.pcg_eta_min, d.st->residual));
+  const double stop = uniform_d(eta * eta * rhs);
   int it = 0;
   bool broke = !(rhs >= 0.0) || isinf(rhs) || !(gam >= 0.0) || isinf(gam);
   bool run = !broke && gam > stop;
@@ -1004,10 +1066,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // publish: the iteration's block partials, then the grid barrier (partial
   // sums alternate halves so a slow block still reading the previous
   // iteration's sums is never overwritten)
-  auto publish = [&](double ag, double ad) {
+  // (false: the barrier gave up, and the kernel must end at once)
+  auto publish = [&](double ag, double ad) -> bool {
     const int half = (it & 1) ? 0 : G;
     block_sum2_store(ag, ad, lds2, d.part_c + half + blockIdx.x, d.part_e + half + blockIdx.x);
-    grid_barrier(bc, bar_target, G);
+    return grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout);
   };
   // advance: the grid sums of the published partials and the next step
   // lengths; false ends the solve
@@ -1035,8 +1098,12 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     gam = gn;
     return true;
   };
+  bool stalled = false;
   auto next_step = [&](double ag, double ad) -> bool {
-    publish(ag, ad);
+    if (!publish(ag, ad)) {
+      stalled = true;
+      return false;
+    }
     return advance();
   };
   // PAIR (FP32, ELL width 16, at most kPcgBlock / 2 rows per block):
@@ -1082,7 +1149,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           pwc = wn;
           psc = sv;
         }
-        publish(acc_g, acc_d);
+        if (!publish(acc_g, acc_d)) return;
         gather(ns);
         if (!advance()) break;
       }
@@ -1143,6 +1210,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     }
     if (!next_step(acc_g, acc_d)) break;
   }
+  if (stalled) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.st->pcg_total += it;
     d.st->pcg_last = it;

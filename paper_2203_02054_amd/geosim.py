@@ -6,8 +6,11 @@ built or no GPU is present: there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -18,6 +21,7 @@ OK, NOT_CONVERGED = 0, 1
 EINVAL, EDEGENERATE, EBREAKDOWN, ECAPACITY, ESTATE, EHIP = -1, -2, -3, -4, -5, -6
 BODY, CH_ISO, CH_AX_X, CH_AX_Y, CH_AX_Z = 0, 1, 2, 3, 4
 CONTACT_SELF, CONTACT_SPHERE, CONTACT_PLANE = 0, 1, 2
+AA_GUARD_NONE, AA_GUARD_RESIDUAL, AA_GUARD_ENERGY, AA_GUARD_SET = 0, 1, 2, 4
 
 
 class GeosimError(RuntimeError):
@@ -39,15 +43,18 @@ class Params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("pcg_eta", ctypes.c_double), ("pcg_max", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("pcg_blocks", ctypes.c_int32), ("trace_len", ctypes.c_int32), ("adj_tol", ctypes.c_double),
-                ("adj_max_iter", ctypes.c_int32), ("adj_aa_m", ctypes.c_int32)]
+                ("adj_max_iter", ctypes.c_int32), ("adj_aa_m", ctypes.c_int32), ("aa_m", ctypes.c_int32),
+                ("aa_guard", ctypes.c_int32), ("aa_slack", ctypes.c_double), ("barrier_timeout_ms", ctypes.c_double),
+                ("pcg_eta_min", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32), ("n_contacts", ctypes.c_int32),
-                ("ray_miss", ctypes.c_int32), ("residual", ctypes.c_double), ("energy", ctypes.c_double)]
+                ("ray_miss", ctypes.c_int32), ("residual", ctypes.c_double), ("energy", ctypes.c_double),
+                ("aa_rejected", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
 class Info(ctypes.Structure):
@@ -100,9 +107,26 @@ SIGNATURES = {
     "gs_destroy": (None, [_P]),
 }
 
-N_KERNELS = 11
+N_KERNELS = 12
 
 _lib = None
+
+# Problems not yet closed.  They are closed at interpreter exit, before the
+# HIP runtime tears itself down: a handle's destructor frees pinned host
+# memory and events, which must not run after that teardown (nor from a
+# finaliser during interpreter shutdown).
+_live = weakref.WeakSet()
+
+
+def _close_all():
+    for p in list(_live):
+        try:
+            p.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all)
 
 
 def lib():
@@ -198,6 +222,8 @@ class Problem:
         else:
             _check(lib().gs_create(ctypes.byref(descs[0]), ctypes.byref(self.params), ctypes.byref(h)))
         self._h = h
+        self.state_id = 0   # bumped by every call that replaces the solved state
+        _live.add(self)
         sph = np.ascontiguousarray(np.zeros((0, 4)) if spheres is None else spheres, dtype=np.float64).reshape(-1, 4)
         pln = np.ascontiguousarray(np.zeros((0, 6)) if planes is None else planes, dtype=np.float64).reshape(-1, 6)
         if sph.shape[0] or pln.shape[0]:
@@ -250,11 +276,26 @@ class Problem:
         return t.data_ptr()
 
     def close(self):
+        """Release the library handle (idempotent).  The workspace tensor is
+        released with the object."""
         if getattr(self, "_h", None):
             lib().gs_destroy(self._h)
             self._h = None
+        _live.discard(self)
 
-    def __del__(self):
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter shutdown the atexit hook has closed every live handle;
+        # a finaliser that still runs then must not call into the runtime (the
+        # check is bound at definition: module globals may be gone by then)
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -279,6 +320,7 @@ class Problem:
             x = self.tensor(self._X)
         st = Stats()
         allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        self.state_id += 1
         code = lib().gs_solve(self._h, self._dev(a, (self.n_chambers,)) if self.n_chambers else None,
                               self._dev(x, (3, self.n)), ctypes.byref(st))
         _check(code, allow)
@@ -301,6 +343,7 @@ class Problem:
         gx0 = self.torch.empty((3, self.n), dtype=self.dtype, device=self.device)
         xK = self.torch.empty((3, self.n), dtype=self.dtype, device=self.device)
         st = Stats()
+        self.state_id += 1
         _check(lib().gs_adjoint_unrolled(self._h, self._dev(a, (self.n_chambers,)) if self.n_chambers else None,
                                          self._dev(x0, (3, self.n)), int(K), self._dev(g, (3, self.n)),
                                          ga.data_ptr() if self.n_chambers else None, gx0.data_ptr(),
@@ -315,6 +358,7 @@ class Problem:
             x = self.tensor(self._X)
         g = ctypes.c_int32()
         ms = ctypes.c_double()
+        self.state_id += 1
         _check(lib().gs_autotune(self._h, self._dev(a, (self.n_chambers,)) if self.n_chambers else None,
                                  self._dev(x, (3, self.n)), int(iters), ctypes.byref(g), ctypes.byref(ms)))
         self.params.pcg_blocks = g.value
@@ -342,6 +386,7 @@ class Problem:
         return {lib().gs_kernel_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(N_KERNELS)}
 
     def reset_contacts(self):
+        self.state_id += 1
         _check(lib().gs_reset_contacts(self._h))
 
     def contacts(self):
@@ -363,6 +408,7 @@ class Problem:
         tg = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, 3)
         nr = np.ascontiguousarray(normal, dtype=np.float64).reshape(-1, 3)
         fr = None if fresh is None else np.ascontiguousarray(fresh, dtype=np.int32).reshape(-1)
+        self.state_id += 1
         _check(lib().gs_set_contacts(self._h, rows.shape[0], _ptr(v, ctypes.c_int32), _ptr(t, ctypes.c_int32),
                                      _ptr(p, ctypes.c_int32), _ptr(tg, ctypes.c_double), _ptr(nr, ctypes.c_double),
                                      None if fr is None else _ptr(fr, ctypes.c_int32)))
@@ -431,23 +477,35 @@ def solve_fn():
     """torch.autograd.Function: x = SolveFn.apply(alpha, problem, x0).
 
     Forward runs gs_solve from x0 (rest positions when None) with the stored
-    contact set; backward runs gs_adjoint on the incoming dL/dx and returns
-    dL/dalpha (implicit gradient at the solve's fixed point with its contact
-    set held fixed)."""
+    contact set and raises unless it converged (the implicit gradient is
+    defined only at a fixed point); backward runs gs_adjoint on the incoming
+    dL/dx and returns dL/dalpha (implicit gradient at the solve's fixed point
+    with its contact set held fixed).  The gradient is taken of the state the
+    problem holds, so backward raises if anything replaced that state since
+    this forward (another solve, an autotune, an unrolled adjoint, contacts
+    set or reset); it warns if the adjoint iteration hit its cap."""
     if _SolveFn.fn is None:
+        import warnings
+
         import torch
 
         class SolveFn(torch.autograd.Function):
             @staticmethod
             def forward(ctx, alpha, problem, x0=None):
                 x = problem.tensor(problem._X) if x0 is None else x0.detach().clone().contiguous()
-                problem.solve(alpha.detach().contiguous(), x)
+                problem.solve(alpha.detach().contiguous(), x, allow_not_converged=False)
                 ctx.problem = problem
+                ctx.state_id = problem.state_id
                 return x
 
             @staticmethod
             def backward(ctx, gx):
-                ga, _ = ctx.problem.adjoint(gx.detach().to(ctx.problem.dtype).contiguous())
+                if ctx.problem.state_id != ctx.state_id:
+                    raise RuntimeError("the problem was solved again (or its state replaced) after this "
+                                       "forward: its adjoint would differentiate another state")
+                ga, st = ctx.problem.adjoint(gx.detach().to(ctx.problem.dtype).contiguous())
+                if st["status"] != OK:
+                    warnings.warn(f"adjoint iteration did not converge (residual {st['residual']:.3e})")
                 return ga, None, None
 
         _SolveFn.fn = SolveFn

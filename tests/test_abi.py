@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
     for n in names:
         assert hasattr(L, n), n
     assert sorted(G.SIGNATURES) == names
-    assert L.gs_version() == 100
+    assert L.gs_version() == 200
 
 
 def _desc(m, precision=4):
@@ -150,4 +150,30 @@ def test_batch_setup_concatenates_meshes():
         nf = q.faces.shape[0]
         np.testing.assert_array_equal(f[:, fo:fo + nf].T, q.faces + vo[m])
         fo += nf
+    G.lib().gs_destroy(h)
+
+
+def test_acceleration_and_barrier_parameters_are_validated():
+    m = voxel_box(2, 1, 1)
+    for kw in (dict(aa_m=-1), dict(aa_m=17), dict(aa_guard=3), dict(aa_guard=8), dict(aa_slack=-0.1),
+               dict(aa_slack=float("nan")), dict(barrier_timeout_ms=-1.0)):
+        assert _create(m, **kw)[0] == G.EINVAL, kw
+    code, h, _ = _create(m, aa_m=16, aa_guard=G.AA_GUARD_ENERGY, aa_slack=0.0, barrier_timeout_ms=0.0)
+    assert code == G.OK
+    G.lib().gs_destroy(h)
+    p = G.default_params()
+    assert (p.aa_m, p.aa_guard, p.aa_slack, p.barrier_timeout_ms) == (
+        8, G.AA_GUARD_RESIDUAL | G.AA_GUARD_SET, 0.5, 2000.0)
+
+
+def test_energy_guard_is_refused_for_a_batch():
+    m = voxel_box(2, 1, 1)
+    d0, k0 = _desc(m)
+    d1, k1 = _desc(m)
+    descs = (G.MeshDesc * 2)(d0, d1)
+    h = ctypes.c_void_p()
+    p = G.default_params(aa_guard=G.AA_GUARD_ENERGY)
+    assert G.lib().gs_create_batch(2, descs, ctypes.byref(p), ctypes.byref(h)) == G.EINVAL
+    p = G.default_params(aa_guard=G.AA_GUARD_ENERGY, aa_m=0)
+    assert G.lib().gs_create_batch(2, descs, ctypes.byref(p), ctypes.byref(h)) == G.OK
     G.lib().gs_destroy(h)

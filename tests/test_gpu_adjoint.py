@@ -64,6 +64,7 @@ def test_adjoint_matches_oracle_at_contact_state(G, precision, aa_m):
     prob = oracle.Problem.from_workload(w)
     kw = dict(pcg_eta=1e-13, pcg_max=5000, adj_tol=1e-13) if precision == 8 else dict(adj_tol=1e-6)
     kw["adj_aa_m"] = aa_m
+    kw["aa_m"] = 0  # the state is the plain iteration's, as the oracle's
     # 62 iterations: the stored set is the one found at x_61, which holds new
     # self-contact targets (the set cycles with a period of about 20 iterations)
     gp = G.Problem.from_workload(w, precision=precision, fixed_iters=62, **kw)

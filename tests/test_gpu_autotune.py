@@ -22,7 +22,7 @@ def G():
 
 def test_autotune_keeps_state_and_result(G):
     w = mg.finger(4.0, 3, 2.0)
-    gp = G.Problem.from_workload(w, precision=8, fixed_iters=30, pcg_eta=1e-12, pcg_max=5000)
+    gp = G.Problem.from_workload(w, precision=8, fixed_iters=30, pcg_eta=1e-12, pcg_max=5000, aa_m=0)
     x1, st1 = gp.solve(w.alpha)
     c1 = gp.contacts()
     default_grid = gp.info["pcg_grid"]

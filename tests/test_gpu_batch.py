@@ -48,7 +48,8 @@ def _split(x, lay, m):
 def test_batch_fp64_matches_oracle_per_mesh(G):
     wls = _batch_workloads()
     K = 25
-    gp = G.Problem.batch(wls, precision=8, self_collision=1, fixed_iters=K, pcg_eta=1e-13, pcg_max=5000)
+    gp = G.Problem.batch(wls, precision=8, self_collision=1, fixed_iters=K, pcg_eta=1e-13, pcg_max=5000,
+                         aa_m=0)
     alpha = np.concatenate([w.alpha for w in wls])
     say("batch fp64", [w.n_tets for w in wls])
     xg, st = gp.solve(alpha)

@@ -62,7 +62,7 @@ def finger_oracle_150():
 def test_cg_variants_and_launch_kinds_follow_the_oracle(G, finger_oracle_150, blocks):
     wl, prob, xo, orows = finger_oracle_150
     gp = G.Problem.from_workload(wl, precision=4, pcg_eta=1e-7, pcg_max=3000, fixed_iters=150,
-                                 pcg_blocks=blocks)
+                                 pcg_blocks=blocks, aa_m=0)
     grid = gp.info["pcg_grid"]
     rows_per_block = ((gp.n + grid - 1) // grid + 63) // 64 * 64
     say("finger fp32, pcg_blocks", blocks, "-> grid", grid, "rows per block", rows_per_block)
@@ -81,7 +81,7 @@ def test_obstacles_without_self_collision_match_oracle(G):
     w = dataclasses.replace(pressed_finger(), self_collision=False)
     prob = oracle.Problem.from_workload(w)
     K = 40
-    gp = G.Problem.from_workload(w, precision=8, pcg_eta=1e-13, pcg_max=5000, fixed_iters=K)
+    gp = G.Problem.from_workload(w, precision=8, pcg_eta=1e-13, pcg_max=5000, fixed_iters=K, aa_m=0)
     xg, st = gp.solve(w.alpha)
     xo, Ao, _ = oracle.solve(prob, w.alpha, fixed_iters=K)
     err = np.abs(xg.cpu().numpy() - xo).max() / prob.diag

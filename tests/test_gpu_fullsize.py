@@ -175,7 +175,7 @@ def test_gripper_unrolled_gradient_vs_central_differences(G):
     K = 20
     verts, y = mg.adjoint_targets(w)
     tight = dict(pcg_eta=1e-13, pcg_max=20000)
-    g64 = G.Problem.from_workload(w, precision=8, fixed_iters=K, **tight)
+    g64 = G.Problem.from_workload(w, precision=8, fixed_iters=K, aa_m=0, **tight)
 
     def loss_and_contacts(alpha):
         g64.reset_contacts()

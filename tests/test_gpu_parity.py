@@ -100,7 +100,7 @@ def test_collision_sets_bit_exact_on_identical_inputs(G):
 def test_fp64_block_matches_oracle_at_50_iterations(G):
     wl = mg.make("block")
     prob = oracle.Problem.from_workload(wl)
-    gp = G.Problem.from_workload(wl, precision=8, pcg_eta=1e-13, pcg_max=5000)
+    gp = G.Problem.from_workload(wl, precision=8, pcg_eta=1e-13, pcg_max=5000, aa_m=0)
     say("block fp64", prob.T)
     xg, st = gp.solve(wl.alpha)
     xo, _, sto = oracle.solve(prob, wl.alpha)
@@ -115,7 +115,7 @@ def test_fp64_finger_with_self_collision_matches_oracle(G):
     wl = mg.finger(4.0, 4, 2.0)
     prob = oracle.Problem.from_workload(wl)
     K = 40
-    gp = G.Problem.from_workload(wl, precision=8, pcg_eta=1e-13, pcg_max=5000, fixed_iters=K)
+    gp = G.Problem.from_workload(wl, precision=8, pcg_eta=1e-13, pcg_max=5000, fixed_iters=K, aa_m=0)
     say("finger fp64 collision", prob.T)
     xg, st = gp.solve(wl.alpha)
     xo, Ao, sto = oracle.solve(prob, wl.alpha, fixed_iters=K)
@@ -132,7 +132,7 @@ def test_fp32_finger_matches_oracle_at_matched_iterations(G):
     wl = mg.finger(4.0, 4, 2.0)
     prob = oracle.Problem.from_workload(wl)
     K = 150
-    gp = G.Problem.from_workload(wl, precision=4, pcg_eta=1e-7, pcg_max=3000, fixed_iters=K)
+    gp = G.Problem.from_workload(wl, precision=4, pcg_eta=1e-7, pcg_max=3000, fixed_iters=K, aa_m=0)
     say("finger fp32 matched", prob.T)
     xg, st = gp.solve(wl.alpha)
     xo, Ao, sto = oracle.solve(prob, wl.alpha, fixed_iters=K)
