@@ -123,7 +123,9 @@ typedef struct {
                              solve stops at clamp(r_{k-1}, pcg_eta_min, pcg_eta)
                              (loose far from the fixed point, tighter near it;
                              the accelerated iteration needs accurate steps
-                             where the map contracts slowly)                     */
+                             where the map contracts slowly); r is the
+                             adjoint's residual in gs_adjoint; the unrolled
+                             sweep's solves always stop at pcg_eta               */
 } gs_params;
 
 /* Safeguards of the accelerated iteration.  Every iteration evaluates the

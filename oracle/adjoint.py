@@ -315,3 +315,38 @@ def unrolled_grad(prob, alpha, path, dLdx):
         lam = np.zeros((3, prob.n))
         lam[:, F] = gx.numpy()[:, F]
     return ga, lam
+
+
+def newton_correction(prob, alpha, x, contacts, fresh, rtol: float = 1e-3, maxiter: int = 80, fz=None):
+    """One Newton step towards the fixed point of the frozen-set map G near x:
+    delta solves (I - G'(x)) delta = G(x) - x on the free coordinates, by
+    GMRES with Jacobian-vector products G'(x) v taken as forward differences
+    (G(x + s v) - G(x)) / s, s = 1e-7 (1 + max|x|) / max|v| (FP64 map, so
+    their error is about 1e-7 relative).  Near a fixed point x + delta is
+    that fixed point up to a term of second order in |delta|, so |delta| is
+    the distance of x from it.  Returns (delta [3, n], info) with the GMRES
+    exit code, its iterations and the map's step max|G(x) - x| / diag."""
+    fz = fz or _Frozen(prob, contacts)
+    F = fz.F
+    x = np.asarray(x, dtype=np.float64)
+    gx = frozen_map(prob, x, alpha, contacts, fresh, fz)
+    f = (gx - x)[:, F].reshape(-1)
+    scale = 1.0 + np.abs(x).max()
+    count = [0]
+
+    def matvec(v):
+        count[0] += 1
+        vm = np.abs(v).max()
+        if vm == 0.0:
+            return np.zeros_like(v)
+        s = 1e-7 * scale / vm
+        xv = x.copy()
+        xv[:, F] += s * v.reshape(3, F.size)
+        gv = frozen_map(prob, xv, alpha, contacts, fresh, fz)
+        return v - ((gv - gx)[:, F].reshape(-1)) / s
+
+    A = spla.LinearOperator((f.size, f.size), matvec=matvec, dtype=np.float64)
+    d, code = spla.gmres(A, f, rtol=rtol, atol=0.0, restart=maxiter, maxiter=1)
+    delta = np.zeros((3, prob.n))
+    delta[:, F] = d.reshape(3, F.size)
+    return delta, dict(gmres=code, matvecs=count[0], step=float(np.abs(f).max() / prob.diag))

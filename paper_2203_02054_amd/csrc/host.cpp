@@ -1256,6 +1256,7 @@ gs_status unrolled_impl(gs_problem* p, const R* alpha, const R* x0, int K, const
   cv.faa_m = 0;
   Consts cc = make_consts(p);
   cc.faa_m = 0;
+  cc.pcg_eta_min = 0.0;  // each reverse solve is one CG to pcg_eta
   cc.mask_done = 0;
   cc.fixed_iters = 0;
   cc.max_iter = 1;

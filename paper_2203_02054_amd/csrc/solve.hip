@@ -1048,10 +1048,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   gam = uniform_d(gam);
   del = uniform_d(del);
   rhs = uniform_d(rhs);
-  // inner tolerance: fixed, or (forward solves with pcg_eta_min > 0) the last
-  // outer residual clamped to [pcg_eta_min, pcg_eta]
+  // inner tolerance: fixed, or (pcg_eta_min > 0) the last outer residual
+  // (the forward r_k, or the adjoint's relative change of mu) clamped to
+  // [pcg_eta_min, pcg_eta]
   double eta = c.pcg_eta;
-  if (!ADJ && c.pcg_eta_min > 0.0) eta = fmin(c.pcg_eta, fmax(c.pcg_eta_min, d.st->residual));
+  if (c.pcg_eta_min > 0.0) eta = fmin(c.pcg_eta, fmax(c.pcg_eta_min, d.st->residual));
   const double stop = uniform_d(eta * eta * rhs);
   int it = 0;
   bool broke = !(rhs >= 0.0) || isinf(rhs) || !(gam >= 0.0) || isinf(gam);

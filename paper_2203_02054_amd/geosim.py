@@ -257,6 +257,8 @@ class Problem:
 
     @classmethod
     def from_workload(cls, wl, precision=None, **kw):
+        for k, v in getattr(wl, "solver", {}).items():
+            kw.setdefault(k, v)
         kw.setdefault("c1", wl.material[0])
         kw.setdefault("c2", wl.material[1])
         kw.setdefault("self_collision", int(wl.self_collision))

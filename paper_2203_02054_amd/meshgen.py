@@ -60,6 +60,9 @@ class Workload:
     fixed_iters: int = 0
     material: tuple = ECOFLEX_0030
     info: dict = field(default_factory=dict)
+    # solver settings the workload is run with (passed to the library's
+    # parameters; none of them is part of the inputs' definition)
+    solver: dict = field(default_factory=dict)
 
     @property
     def n_verts(self) -> int:
@@ -242,6 +245,15 @@ def block(h: float = 4.0) -> Workload:
                     precision=8, fixed_iters=50, info=dict(h=h))
 
 
+# Settings of the accelerated solve for the gripper: its slowest mode (the
+# fingertips sliding along each other on frictionless contacts) contracts at
+# about 0.9998 per plain iteration, so the Anderson steps extrapolate far
+# along it and need accurate global steps (inner tolerance tightened with the
+# outer residual down to 1e-6, CG cap 2000), a memory of 16 and only the
+# active-set guard (aa_guard 4: GS_AA_GUARD_SET).
+GRIPPER_SOLVER = dict(aa_m=16, aa_guard=4, pcg_eta_min=1e-6, pcg_max=2000)
+
+
 def gripper(h: float = 1.2, seed: int = 3, radius: float = 45.0) -> Workload:
     """Three fingers on a palm (z = 0), angles 0/120/240 deg, pointing -z, the
     base layer facing the axis; sphere r = 30 at (0,0,-95); plane z = -125
@@ -279,7 +291,8 @@ def gripper(h: float = 1.2, seed: int = 3, radius: float = 45.0) -> Workload:
                     spheres=np.array([[0.0, 0.0, -95.0, 30.0]]),
                     planes=np.array([[0.0, 0.0, -125.0, 0.0, 0.0, 1.0]]),
                     self_collision=True, obstacle_collision=True, precision=4,
-                    info=dict(h=h, finger_alpha=af, dims=dims, verts_per_finger=lxyz.shape[1]))
+                    info=dict(h=h, finger_alpha=af, dims=dims, verts_per_finger=lxyz.shape[1]),
+                    solver=GRIPPER_SOLVER)
 
 
 def batched_specs(n_mesh: int = 256, seed: int = 4):

@@ -20,28 +20,31 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_cg_bytes_follow_the_documented_terms():
-    # n rows, T tets, nnz ELL entries (diagonal included), S query vertices,
-    # FP32; 3 launches doing 30 CG iterations in all
+    # n rows, T tets, nnz CSR entries (diagonal included), FP32 and FP64:
+    # B_pcg = (W + 4) nnz + 4 (n + 1) + 35 W n per CG iteration
     info = {"n_verts": 100, "n_tets": 300, "nnz": 1500, "n_query_verts": 40}
-    W, n, T, off, S = 4, 100, 300, 1400, 40
-    kb = bench.kernel_bytes(info, W, {"pcg": 3}, 30)
-    gather = 4 * T * 4 * W + n * (4 + 6 * W)                    # phase 0
-    per_it = n * (24 * W + 17 * W) + off * (4 + W)              # per CG iteration
-    startup = n * 81 * W + off * (8 + 3 * W)
-    finish = n * (7 * W + 24) + 36 * S
-    assert kb["gather"] == gather
-    assert kb["pcg"] == pytest.approx(gather + 10 * per_it + startup + finish, rel=0, abs=1e-6)
-    assert kb["hash_insert"] == 60 * S
+    for W in (4, 8):
+        assert bench.pcg_bytes_per_iteration(info, W) == (W + 4) * 1500 + 4 * 101 + 35 * W * 100
+    n, T, off, W = 100, 300, 1400, 4
+    ex = bench.pcg_extra_bytes(info, W)
+    assert ex["gather"] == 4 * T * 4 * W + n * (4 + 6 * W)
+    assert ex["final_update"] == n * (9 * W + 24)
+    assert ex["warm_start"] == n * (13 * W) + off * (4 + W) + n * 9 * W + n * 30 * W + off * W
 
 
 def test_roofline_record_from_kernel_timings():
     info = {"n_verts": 100, "n_tets": 300, "nnz": 1500, "n_query_verts": 40}
     prof = {"pcg": (2.0, 4), "tet_query": (0.5, 4), "ray_cast": (0.1, 4)}  # ms total, launches
-    r = bench.roofline_of(prof, info, 4, 40, workload="no-such-workload")
-    kb = bench.kernel_bytes(info, 4, {k: v[1] for k, v in prof.items()}, 40)["pcg"]
+    r = bench.roofline_of(prof, info, 4, 40, traffic_key="no-such-workload")
+    per_launch = 10 * bench.pcg_bytes_per_iteration(info, 4)           # 40 CG iterations over 4 launches
     assert r["kernel"] == "pcg" and r["bound"] == "hbm" and r["unit"] == "GB/s"
     assert r["avg_launch_us"] == pytest.approx(500.0)
-    assert r["achieved"] == pytest.approx(kb / 500e-6 / 1e9, rel=1e-3)
+    assert r["algorithmic_bytes_per_launch"] == per_launch
+    assert r["achieved"] == pytest.approx(per_launch / 500e-6 / 1e9, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / bench.PEAK_HBM_GBS, abs=1e-5)  # rounded to 5 places
     assert r["traffic"] is None  # counters exist only for the measured workloads
-    assert bench.roofline_of(prof, info, 4, 40, workload="finger")["traffic"] == bench.PMC_TRAFFIC[("finger", "pcg")]
+
+
+def test_physical_core_count_is_within_the_allowed_cpus():
+    cores, allowed = bench.physical_cores()
+    assert 1 <= cores <= allowed == len(os.sched_getaffinity(0))

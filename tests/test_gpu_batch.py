@@ -77,7 +77,7 @@ def test_batch_fp32_converges_every_mesh_to_an_oracle_fixed_point(G):
     them its path and iteration count) differ from a solve of that mesh alone;
     the count is only bounded against the single-mesh one."""
     wls = _converging_workloads()
-    gp = G.Problem.batch(wls, precision=4, self_collision=1, tol=2e-8)
+    gp = G.Problem.batch(wls, precision=4, self_collision=1, tol=2e-8, aa_m=0)
     alpha = np.concatenate([w.alpha for w in wls])
     xg, st = gp.solve(alpha)
     its = gp.mesh_iters()
@@ -87,7 +87,7 @@ def test_batch_fp32_converges_every_mesh_to_an_oracle_fixed_point(G):
     lay = gp.layout()
     cg = gp.contacts()
     for m, w in enumerate(wls):
-        g1 = G.Problem.from_workload(w, precision=4, self_collision=1, tol=2e-8, fixed_iters=0)
+        g1 = G.Problem.from_workload(w, precision=4, self_collision=1, tol=2e-8, fixed_iters=0, aa_m=0)
         _, s1 = g1.solve(w.alpha)
         prob = oracle.Problem.from_workload(w, self_collision=True)
         v0, v1 = lay["vert"][m], lay["vert"][m + 1]
