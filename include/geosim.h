@@ -120,7 +120,7 @@ typedef struct {
                              a workgroup that waits longer gives up and the call
                              returns GS_EHIP (0: give up at the first wait)      */
   double pcg_eta_min;     /* 0: the inner CG stops at pcg_eta; else iteration k's
-                             solve stops at clamp(r_{k-1}, pcg_eta_min, pcg_eta)
+                             solve stops at min(pcg_eta, max(r_{k-1}, pcg_eta_min))
                              (loose far from the fixed point, tighter near it;
                              the accelerated iteration needs accurate steps
                              where the map contracts slowly); r is the

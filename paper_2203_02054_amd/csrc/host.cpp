@@ -199,7 +199,7 @@ gs_status check_params(const gs_params* p) {
   if (!(p->aa_slack >= 0) || !std::isfinite(p->aa_slack)) return fail(GS_EINVAL, "aa_slack must be >= 0");
   if (!(p->barrier_timeout_ms >= 0) || !std::isfinite(p->barrier_timeout_ms))
     return fail(GS_EINVAL, "barrier_timeout_ms must be >= 0");
-  if (!(p->pcg_eta_min >= 0 && p->pcg_eta_min <= p->pcg_eta)) return fail(GS_EINVAL, "need 0 <= pcg_eta_min <= pcg_eta");
+  if (!(p->pcg_eta_min >= 0) || !std::isfinite(p->pcg_eta_min)) return fail(GS_EINVAL, "pcg_eta_min must be >= 0");
   return GS_OK;
 }
 
