@@ -371,6 +371,20 @@ gs_status gs_collide_debug(gs_problem* p, const void* dev_x, int32_t cap, void* 
                            int32_t* cand_tri, int32_t* n_cand_tri, int32_t* contacts,
                            double* target, int32_t* n_contacts);
 
+/* gs_collide_debug for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * allocation): the candidate lists are staged in a static device array of
+ * the library (GS_STATIC_CAND_CAP pairs per list, 2 MiB per device, held by
+ * each device the library runs on until the process ends) instead of a
+ * caller scratch; nothing is allocated.  Arguments and outputs as
+ * gs_collide_debug; GS_EINVAL when cap > GS_STATIC_CAND_CAP, GS_ESTATE when
+ * not bound.  Calls on one device share the array: calls that overlap on one
+ * device race. */
+#define GS_STATIC_CAND_CAP 131072
+gs_status gs_collide_debug_static(gs_problem* p, const void* dev_x, int32_t cap, int32_t* cand_tet,
+                                  int32_t* n_cand_tet, int32_t* cand_tri, int32_t* n_cand_tri,
+                                  int32_t* contacts, double* target, int32_t* n_contacts);
+
 /* Per-iteration trace of the last solve: rows of GS_TRACE_COLS doubles
  * (r_k, E_k, active springs, set changed, inner CG iterations, ray misses)
  * for the first min(iters, trace_len) iterations; trace_len is fixed at

@@ -15,11 +15,42 @@
 // here, and this file is compiled without floating-point contraction, so
 // identical inputs give identical sets on any conforming implementation.
 #include <climits>
+#include <mutex>
 
 #include "contacts.h"
 #include "tet_query.h"
 
 namespace gs {
+
+// Candidate-list staging of the allocation-free collision check
+// (gs_collide_debug_static): the two candidate lists of at most
+// kStaticCandCap pairs each, [2][cap] tet pairs then [2][cap] triangle pairs,
+// exactly the layout gs_collide_debug takes from its caller's scratch (with
+// the 256 bytes of slack its size rule adds).  Each
+// device holds its own copy for the life of the process; calls on one device
+// share it, so overlapping calls on a device race.
+static __device__ __align__(256) int32_t scratch[4 * kStaticCandCap + 64];
+
+// Address of this device's copy of `scratch`, resolved once per device with
+// that device current (the array's name is not a device address in host
+// code).
+hipError_t static_candidate_scratch(void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = a;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 // Insert every query vertex into the bucket of its cell (the first iteration
 // after positions were set; later iterations insert in the CG kernel's final

@@ -1888,6 +1888,21 @@ gs_status gs_collide_debug(gs_problem* p, const void* x, int32_t cap, void* scra
   return GS_OK;
 }
 
+gs_status gs_collide_debug_static(gs_problem* p, const void* x, int32_t cap, int32_t* cand_tet, int32_t* n_cand_tet,
+                                  int32_t* cand_tri, int32_t* n_cand_tri, int32_t* contacts, double* target,
+                                  int32_t* n_contacts) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (cap < 0 || cap > kStaticCandCap)
+    return fail(GS_EINVAL, "cap exceeds the static candidate buffer (" + std::to_string(kStaticCandCap) + " pairs)");
+  if (!p->bound) return fail(GS_ESTATE, "not bound");
+  void* scratch = nullptr;
+  HIPCHK(static_candidate_scratch(&scratch));
+  // the staging layout is [2][cap] tet pairs then [2][cap] triangle pairs:
+  // the whole array serves any cap up to kStaticCandCap
+  return gs_collide_debug(p, x, cap, scratch, gs_collide_debug_scratch(kStaticCandCap), cand_tet, n_cand_tet, cand_tri,
+                          n_cand_tri, contacts, target, n_contacts);
+}
+
 gs_status gs_trace(gs_problem* p, int32_t cap, double* rows, int32_t* count) {
   if (!p || !count || (cap > 0 && !rows)) return fail(GS_EINVAL, "null argument");
   if (!p->bound) return fail(GS_ESTATE, "not bound");

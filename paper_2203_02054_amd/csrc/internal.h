@@ -21,6 +21,8 @@ constexpr int kTetQueryWide = 1 << 18;
 constexpr int kMaxPcgGrid = 1024;     // workgroups of the persistent CG kernel at most
 constexpr int kAaMaxMem = 16;         // Anderson memory at most (forward and adjoint)
 constexpr int kFaaRows = 1024;        // rows per block of the acceleration's dot-product kernel
+constexpr int kStaticCandCap = 1 << 17;  // candidate pairs per list of the allocation-free collision check
+constexpr int kMaxDevices = 64;
 
 // Completion codes kept on the device (DevStatus::done).
 // STALLED: a grid barrier of the CG kernel gave up waiting (see grid_barrier).
@@ -243,6 +245,8 @@ template <typename R>
 hipError_t launch_unr_finish(const Dev<R>& d, const Consts& c, R* dalpha, R* dx0, hipStream_t s);
 template <typename R> hipError_t launch_set_positions(const Dev<R>& d, const Consts& c, const R* x, hipStream_t s);
 template <typename R> int pcg_max_grid(int ell_w);
+// this device's copy of the allocation-free collision check's staging array
+hipError_t static_candidate_scratch(void** ptr);
 
 __host__ __device__ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 

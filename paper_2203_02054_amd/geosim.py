@@ -97,6 +97,7 @@ SIGNATURES = {
     "gs_faces": (_I, [_P, _PI]),
     "gs_collide_debug_scratch": (ctypes.c_size_t, [_I]),
     "gs_collide_debug": (_I, [_P, _P, _I, _P, ctypes.c_size_t, _PI, _PI, _PI, _PI, _PI, _PD, _PI]),
+    "gs_collide_debug_static": (_I, [_P, _P, _I, _PI, _PI, _PI, _PI, _PI, _PD, _PI]),
     "gs_trace": (_I, [_P, _I, _PD, _PI]),
     "gs_create_batch": (_I, [_I, ctypes.POINTER(MeshDesc), ctypes.POINTER(Params), ctypes.POINTER(_P)]),
     "gs_batch_layout": (_I, [_P, _I, _PI, _PI, _PI, _PI]),
@@ -467,6 +468,27 @@ class Problem:
         a, b, k = nct.value, ntr.value, nco.value
         return dict(cand_tet=ct[:, :a].T.copy(), cand_tri=tr[:, :b].T.copy(), contacts=co[:, :k].T.copy(),
                     target=tg[:, :k].T.copy())
+
+
+STATIC_CAND_CAP = 131072
+
+
+def _collide_static(self, x, cap=None):
+    """gs_collide_debug_static: one collision check at x staged in the
+    library's static device array (no allocation); cap <= STATIC_CAND_CAP."""
+    cap = int(cap if cap is not None else STATIC_CAND_CAP)
+    ct, tr, co = np.zeros((2, cap), np.int32), np.zeros((2, cap), np.int32), np.zeros((3, cap), np.int32)
+    tg = np.zeros((3, cap))
+    nct, ntr, nco = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().gs_collide_debug_static(self._h, self._dev(x, (3, self.n)), cap, _ptr(ct, ctypes.c_int32),
+                                         ctypes.byref(nct), _ptr(tr, ctypes.c_int32), ctypes.byref(ntr),
+                                         _ptr(co, ctypes.c_int32), _ptr(tg, ctypes.c_double), ctypes.byref(nco)))
+    a, b, k = nct.value, ntr.value, nco.value
+    return dict(cand_tet=ct[:, :a].T.copy(), cand_tri=tr[:, :b].T.copy(), contacts=co[:, :k].T.copy(),
+                target=tg[:, :k].T.copy())
+
+
+Problem.collide_static = _collide_static
 
 
 class _SolveFn:
