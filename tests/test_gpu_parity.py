@@ -234,9 +234,11 @@ def test_solve_is_deterministic(G):
 
 
 def test_full_finger_fixed_point_and_collision_sets(G):
-    """Full-size finger (26,880 tets) in the benchmark configuration: the FP32 GPU
-    result is a fixed point of the oracle's iteration, its collision sets match the
-    oracle's brute force bit for bit, and sampled local targets agree."""
+    """Full-size finger (26,880 tets), default (accelerated) FP32 path: the
+    result is near the oracle's fixed point for its own active set (1e-5 of
+    the diagonal when stopped at r <= 1e-7; the accuracy the default 1e-6
+    reaches is bounded too), its collision sets match the oracle's brute
+    force bit for bit, and sampled local targets agree."""
     wl = mg.make("finger")
     prob = oracle.Problem.from_workload(wl)
     gp = G.Problem.from_workload(wl, precision=4)
@@ -253,11 +255,28 @@ def test_full_finger_fixed_point_and_collision_sets(G):
     A.target[qidx, 0] = cg["target"]
     A.normal[qidx, 0] = cg["normal"]
     A.prim[qidx, 0] = cg["rows"][:, 2]
-    # one oracle iteration from the GPU fixed point barely moves it
-    xn, A2, _, info = osolver.step(prob, xg, wl.alpha, A)
-    move = np.abs(xn - xg).max() / prob.diag
-    say("  oracle step from gpu x*: r =", info["r"], "max move/diag", move, "set changed", info["changed"])
-    assert move < 2e-5
+    # the oracle's fixed point for the GPU's active set (frozen-set map
+    # iterated to a 1e-11 step from the GPU result), where the oracle's
+    # collision check returns the same set.  The finger's fixed-point problem
+    # has a condition of about 40 (distance to the fixed point over the
+    # stopping residual, measured), so the benchmark's stopping tolerance
+    # r <= 1e-6 reaches 3.7e-5 of the diagonal: that accuracy is asserted
+    # (with margin) for the default solve, and the 1e-5 bar for the same path
+    # stopped at r <= 1e-7 (83 iterations instead of 76).
+    from tests import fixed_point as fp
+    r = fp.check(prob, wl.alpha, xg, cg, max_iter=6000)
+    say("  tol 1e-6: oracle fixed point for the GPU set:", r["iters"], "iterations, step", r["step"], "err/diag",
+        r["err"], "same set", r["same_set"])
+    assert r["step"] <= 1e-11 and r["same_set"]
+    assert r["err"] < 1e-4
+    gt = G.Problem.from_workload(wl, precision=4, tol=1e-7)
+    xt, stt = gt.solve(wl.alpha)
+    assert stt["status"] == G.OK
+    rt = fp.check(prob, wl.alpha, xt.cpu().numpy().astype(np.float64), gt.contacts(), max_iter=6000)
+    say("  tol 1e-7:", stt, "err/diag", rt["err"], "same set", rt["same_set"])
+    assert rt["step"] <= 1e-11 and rt["same_set"]
+    assert rt["err"] < 1e-5
+    gt.close()
     # collision sets at the GPU positions, bit-exact
     gp.set_contacts(cg["rows"], cg["target"], cg["normal"])
     got = gp.collide(xg_t)
