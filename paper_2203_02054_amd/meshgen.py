@@ -295,6 +295,68 @@ def gripper(h: float = 1.2, seed: int = 3, radius: float = 45.0) -> Workload:
                     solver=GRIPPER_SOLVER)
 
 
+# Chamber unit of the membrane rig, in voxels: footprint, height, wall,
+# floor and roof thickness.  The full unit holds 13*13*10 - 7*7*5 = 1,445
+# solid voxels, i.e. 8,670 tets, the per-chamber count of the paper's
+# membrane model (Table I); the coarse one is for quick checks.
+MEMBRANE_UNIT = dict(full=dict(side=13, height=10, wall=3, floor=2, roof=3),
+                     coarse=dict(side=7, height=5, wall=2, floor=1, roof=1))
+
+
+def membrane(h: float = 8.0, seed: int = 6, coarse: bool = False, size: float = 250.0) -> Workload:
+    """Soft membrane over four chambers (Section IV, membrane case).
+
+    A one-voxel-thick square sheet of side ``size`` mm, its rim fixed, hangs
+    half a voxel above a 2 x 2 array of separate chamber units whose floors
+    (z = 0) are fixed.  Each unit is a voxel box around one closed cavity; the
+    voxels that share a face with the cavity are its chamber elements
+    (isotropic), the rest body.  Inflating the units (alpha ~ U[2, 3.5] per
+    chamber, seed 6) lifts their roofs into the sheet: the bodies interact
+    only through contact between different connected components.  Dragon
+    Skin 20 (the rig's material), self-collision on, FP32.
+
+    Voxel layout: the sheet covers M = round(size / h) voxels per side, one
+    voxel above the units' height H, and is then lowered by h/2; the units
+    (side U) sit 2U + g wide with g = max(1, round(16 / h)) voxels between
+    them, centred under the sheet; cavities are centred in x and y.
+    """
+    u = MEMBRANE_UNIT["coarse" if coarse else "full"]
+    if coarse:
+        h = max(h, 16.0)
+    U, H, w, fl, rf = u["side"], u["height"], u["wall"], u["floor"], u["roof"]
+    M = int(round(size / h))
+    g = max(1, int(round(16.0 / h)))
+    o = (M - (2 * U + g)) // 2
+    if o < 0:
+        raise ValueError("the chamber units do not fit under the sheet")
+    nz = H + 2
+    solid = np.zeros((M, M, nz), dtype=bool)
+    cavity = np.full(solid.shape, -1, dtype=np.int32)
+    for c, (i, j) in enumerate(((0, 0), (1, 0), (0, 1), (1, 1))):
+        x0, y0 = o + i * (U + g), o + j * (U + g)
+        solid[x0:x0 + U, y0:y0 + U, 0:H] = True
+        cs = (slice(x0 + w, x0 + U - w), slice(y0 + w, y0 + U - w), slice(fl, H - rf))
+        solid[cs] = False
+        cavity[cs] = c
+    solid[:, :, H + 1] = True                      # the sheet, one voxel above the units
+    cham, gap = _wall_tags(solid, cavity, [(False, False)] * 4)
+    xyz, tets, vijk, _ = kuhn_tets(solid, h)
+    mode, chamber = _tags_from_voxels(vijk, cham, gap)
+    top = (H + 1) * h
+    on_sheet = xyz[2] >= top
+    rim = on_sheet & ((xyz[0] == 0.0) | (xyz[0] == M * h) | (xyz[1] == 0.0) | (xyz[1] == M * h))
+    fixed = ((xyz[2] == 0.0) | rim).astype(np.uint8)
+    xyz[2, on_sheet] -= 0.5 * h                    # half a voxel of clearance above the roofs
+    rng = np.random.default_rng(seed)
+    alpha = rng.uniform(2.0, 3.5, 4)
+    sheet = int(np.count_nonzero(vijk[:, 2] == H + 1))
+    return Workload(name="membrane_coarse" if coarse else "membrane", rest_xyz=xyz, tets=tets,
+                    tet_mode=mode, tet_chamber=chamber, fixed=fixed, alpha=alpha,
+                    self_collision=True, precision=4, material=DRAGON_SKIN_20,
+                    info=dict(h=h, sheet_voxels=M, unit=dict(u), unit_tets=(tets.shape[1] - sheet) // 4,
+                              sheet_tets=sheet))
+
+
 def batched_specs(n_mesh: int = 256, seed: int = 4):
     """Per-mesh (h, n_chambers, alpha[]) for the uneven batch.
 
@@ -378,6 +440,7 @@ CONFIGS = {
     "block": lambda: block(),
     "finger": lambda: finger(2.0, 8, 2.0, name="finger"),
     "gripper": lambda: gripper(),
+    "membrane": lambda: membrane(),
 }
 
 

@@ -69,3 +69,48 @@ def test_batched_specs_deterministic():
         np.testing.assert_array_equal(a["alpha"], b["alpha"])
         assert 4 <= a["n_chambers"] <= 12
         assert np.all((a["alpha"] >= 1.0) & (a["alpha"] <= 2.5))
+
+
+def _components(n, tets):
+    """Connected components of the tet graph (union-find over tet vertices)."""
+    parent = np.arange(n)
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for t in tets.T:
+        r = [find(int(v)) for v in t]
+        for q in r[1:]:
+            parent[find(q)] = find(r[0])
+    return np.array([find(v) for v in range(n)])
+
+
+@pytest.mark.parametrize("coarse", [False, True])
+def test_membrane_layout(coarse):
+    """Four chamber units of 13*13*10 - 7*7*5 = 1,445 voxels (8,670 tets each,
+    Table I's per-chamber count) or 7*7*5 - 3*3*3 = 218 voxels (coarse), one
+    wall layer of chamber elements around each cavity, and a one-voxel sheet
+    of M*M voxels; floors and the sheet's rim fixed; five separate bodies."""
+    wl = mg.membrane(coarse=coarse)
+    h = wl.info["h"]
+    M = wl.info["sheet_voxels"]
+    unit_vox, cav, wall_vox, side = ((218, (3, 3, 3), 2 * 9 + 4 * 9, 7) if coarse
+                                     else (1445, (7, 7, 5), 2 * 49 + 4 * 35, 13))
+    assert wl.info["unit_tets"] == 6 * unit_vox
+    assert wl.n_tets == 4 * 6 * unit_vox + 6 * M * M
+    if not coarse:
+        assert 4 * wl.info["unit_tets"] == 34680
+    assert wl.n_chambers == 4
+    for c in range(4):
+        assert int((wl.tet_chamber == c).sum()) == 6 * wall_vox
+    assert np.all(wl.tet_mode[wl.tet_mode > 0] == mg.CH_ISO)
+    assert int(wl.fixed.sum()) == 4 * (side + 1) ** 2 + 2 * 4 * M
+    comp = _components(wl.n_verts, wl.tets)
+    assert np.unique(comp).size == 5
+    X = wl.rest_xyz
+    sheet = X[2] > wl.info["unit"]["height"] * h + 1e-9
+    assert X[2, sheet].min() - X[2, ~sheet].max() == pytest.approx(0.5 * h)
+    assert np.all(1.5 <= wl.alpha) and np.all(wl.alpha <= 3.5)
