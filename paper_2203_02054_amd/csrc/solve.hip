@@ -594,16 +594,13 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // suits their bandwidth-bound gathers.
   constexpr bool SOA = PAIR;
   const size_t qs = SOA ? n : 1, vs = SOA ? 1 : 3;
-  // state that other blocks read after a barrier: written through (sc1) in
-  // the paired variant, whose wavefront stores cover whole cache lines; the
-  // others' 16-byte stores at a 48-byte stride would write partial lines
-  // through to HBM, so their lines are assembled in L2 and written back
-  auto st_state = [&](W4<R>* base, unsigned i, const W4<R>& v) {
-    if constexpr (SOA)
-      st_wt(base, i, v);
-    else
-      base[i] = v;
-  };
+  // state that other blocks read after a barrier is written through (sc1):
+  // the barrier's release then has little left to write back from L2.  In
+  // the row-record layout a wavefront's 16-byte stores at a 48-byte stride
+  // cover lines only partly, yet writing them through still beat assembling
+  // the lines in L2 (about 10% per CG iteration on the 378,666-tet gripper at
+  // 128 blocks)
+  auto st_state = [&](W4<R>* base, unsigned i, const W4<R>& v) { st_wt(base, i, v); };
   // each block owns one contiguous range of rows (a multiple of 64 long), so
   // the rows spread over all G blocks however many rows a thread gets
   const int chunk = ((c.n + G - 1) / G + 63) & ~63;
