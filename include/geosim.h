@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define GEOSIM_VERSION 200
+#define GEOSIM_VERSION 210
 
 typedef int32_t gs_status;
 
@@ -392,6 +392,54 @@ gs_status gs_collide_debug_static(gs_problem* p, const void* dev_x, int32_t cap,
 #define GS_TRACE_COLS 6
 gs_status gs_trace(gs_problem* p, int32_t cap, double* rows, int32_t* count);
 
+/* Remesh checks (Section III-B; the check that follows each stage of
+ * Algorithm 1's outer loop).  For every chamber element (M_c) at positions
+ * dev_x ([3][n], the precision of the problem) against the reference
+ * positions dev_x_ref (same layout; NULL: the rest shape X0, i.e. the mesh
+ * as last meshed), with D the three edges from the element's first vertex
+ * and F = D_x D_ref^-1:
+ *   GS_REMESH_VOLUME      det(D_x) / det(D_ref) > alpha_max (volume gain);
+ *   GS_REMESH_DISTORTION  norm(Sigma) > d_max, Sigma the singular values of
+ *                         the affine map taking the deformed element back to
+ *                         the reference (F^-1), norm the 2-norm, so
+ *                         norm(Sigma) = 1 / sigma_min(F) (infinite for a
+ *                         flattened element).
+ * Both decisions are taken in FP64.  dev_flags (device, one byte per tet in
+ * the order of gs_tets, caller-owned) receives the or-ed bits, 0 for body
+ * elements; *n_flagged (host, may be NULL) the number of elements with a bit
+ * set.  The paper uses alpha_max = d_max = 4.  Synchronises the bound stream.
+ * GS_EINVAL for null buffers or thresholds that are not finite and > 0,
+ * GS_ESTATE before gs_bind, GS_EHIP. */
+enum { GS_REMESH_VOLUME = 1, GS_REMESH_DISTORTION = 2 };
+gs_status gs_remesh_flags(gs_problem* p, const void* dev_x, const void* dev_x_ref, double alpha_max, double d_max,
+                          uint8_t* dev_flags, int32_t* n_flagged);
+
+/* One stage of gs_solve_progressive. */
+typedef struct {
+  gs_stats solve;          /* the stage's solve                                  */
+  int32_t status;          /* its status: GS_OK or GS_NOT_CONVERGED              */
+  int32_t n_flagged;       /* elements flagged by the remesh checks after it     */
+  double alpha_top;        /* the stage's largest per-chamber actuation          */
+} gs_stage;
+
+/* Progressive actuation (Algorithm 1's outer loop, without the remesher):
+ * stage k = 0, 1, ... solves (gs_solve, warm-started from the previous
+ * stage's positions in dev_x and its active contact set) with the
+ * per-chamber actuation alpha_k = min(alpha, (k+1) alpha_max), rounded to
+ * the problem's precision, then runs gs_remesh_flags against the rest shape
+ * into dev_flags.  The last stage is the first whose actuation reaches
+ * dev_alpha in every chamber (one stage when alpha <= alpha_max).  With
+ * stop_on_flag != 0 the loop ends after the first stage that flags an
+ * element: remeshing is the caller's (a new problem on the new mesh, from the
+ * returned positions).  stages[cap] (host) receives one record per stage run
+ * and *n_stages their number.  Returns GS_OK when every stage converged,
+ * GS_NOT_CONVERGED when one did not (later stages still run), GS_EINVAL for
+ * null buffers, non-finite alpha, thresholds that are not finite and > 0 or
+ * cap below the number of stages, and any error of gs_solve. */
+gs_status gs_solve_progressive(gs_problem* p, const void* dev_alpha, void* dev_x, double alpha_max, double d_max,
+                               int32_t stop_on_flag, uint8_t* dev_flags, int32_t cap, gs_stage* stages,
+                               int32_t* n_stages);
+
 /* Kernel timing.  gs_profile(p, 1) resets the totals and brackets every
  * kernel that gs_solve launches with a pair of HIP events on the bound
  * stream (gs_adjoint likewise: its kernels are named "adj_*");
@@ -405,9 +453,10 @@ gs_status gs_trace(gs_problem* p, int32_t cap, double* rows, int32_t* count);
  * local step ("local" then counts none); "hash_insert" runs only on a solve's
  * first iteration (the CG kernel refills the hash, or, with aa_m > 0, the
  * accelerated iteration's position update); "anderson" is that update with
- * its dot products and least-squares solve (three launches counted as one).
- * gs_profile(p, 0) stops. */
-#define GS_N_KERNELS 12
+ * its dot products and least-squares solve (three launches counted as one);
+ * "remesh_flags" is gs_remesh_flags (two launches: the count is cleared
+ * first).  gs_profile(p, 0) stops. */
+#define GS_N_KERNELS 13
 gs_status gs_profile(gs_problem* p, int32_t enable);
 gs_status gs_profile_read(const gs_problem* p, double* ms, int64_t* launches);
 const char* gs_kernel_name(int32_t k);

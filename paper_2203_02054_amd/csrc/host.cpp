@@ -55,15 +55,16 @@ struct Layout {
   size_t aa_dx, aa_df, aa_xp, aa_fp, aa_h, aa_gamma, aa_part, aa_k;
   size_t lam, ga_acc, st3, st4;
   size_t faa, faa_h, faa_gam, faa_blk, faa_mblk, cact_s, ctgt_s, cnrm_s, cprim_s;
+  size_t rcount, alpha_stage;
   size_t total;
 };
 
-constexpr int kNKernels = 12;
-const char* const kKernelNames[kNKernels] = {"hash_insert", "tet_query", "ray_cast",  "contacts",
-                                             "local",       "gather",    "pcg",       "adj_springs",
-                                             "adj_local",   "adj_gather", "adj_pcg",  "anderson"};
+constexpr int kNKernels = 13;
+const char* const kKernelNames[kNKernels] = {"hash_insert", "tet_query",  "ray_cast", "contacts", "local",
+                                             "gather",      "pcg",        "adj_springs", "adj_local", "adj_gather",
+                                             "adj_pcg",     "anderson",   "remesh_flags"};
 enum { K_CONTACTS = 3, K_LOCAL = 4, K_GATHER = 5, K_PCG = 6, K_ADJ_SPRINGS = 7, K_ADJ_LOCAL = 8, K_ADJ_GATHER = 9,
-       K_ADJ_PCG = 10, K_ANDERSON = 11 };
+       K_ADJ_PCG = 10, K_ANDERSON = 11, K_REMESH = 12 };
 
 // Optional per-kernel timing: each launch is bracketed by two events on the
 // bound stream; elapsed times are collected whenever the driver synchronises.
@@ -299,6 +300,8 @@ Layout make_layout(const gs_problem* p) {
   L.ctgt_s = take(3 * S * sl * 8);
   L.cnrm_s = take(3 * S * sl * 8);
   L.cprim_s = take(S * sl * 4);
+  L.rcount = take(4);
+  L.alpha_stage = take((size_t)p->nch * W);
   L.total = align256(off);
   return L;
 }
@@ -1786,6 +1789,94 @@ gs_status gs_local_step_debug(gs_problem* p, const void* x, const void* alpha, v
                                       (double*)targets, p->stream));
   }
   return GS_OK;
+}
+
+gs_status gs_remesh_flags(gs_problem* p, const void* x, const void* x_ref, double alpha_max, double d_max,
+                          uint8_t* flags, int32_t* n_flagged) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "gs_remesh_flags before gs_bind");
+  if (!x || !flags) return fail(GS_EINVAL, "null device buffer");
+  if (!(alpha_max > 0) || !std::isfinite(alpha_max) || !(d_max > 0) || !std::isfinite(d_max))
+    return fail(GS_EINVAL, "alpha_max and d_max must be finite and > 0");
+  const Consts c = make_consts(p);
+  int* cnt = (int*)(p->ws + p->lay.rcount);
+  hipError_t e;
+  if (p->prec == 4)
+    e = timed(p, K_REMESH, [&] {
+      return launch_remesh_flags<float>(make_dev<float>(p), c, (const float*)x, (const float*)x_ref, alpha_max, d_max,
+                                        flags, cnt, p->stream);
+    });
+  else
+    e = timed(p, K_REMESH, [&] {
+      return launch_remesh_flags<double>(make_dev<double>(p), c, (const double*)x, (const double*)x_ref, alpha_max,
+                                         d_max, flags, cnt, p->stream);
+    });
+  HIPCHK(e);
+  int32_t h = 0;
+  HIPCHK(hipMemcpyAsync(&h, cnt, 4, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  if (n_flagged) *n_flagged = h;
+  return GS_OK;
+}
+
+gs_status gs_solve_progressive(gs_problem* p, const void* alpha, void* x, double alpha_max, double d_max,
+                               int32_t stop_on_flag, uint8_t* flags, int32_t cap, gs_stage* stages,
+                               int32_t* n_stages) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "gs_solve_progressive before gs_bind");
+  if (!x || !flags || (p->nch > 0 && !alpha) || (cap > 0 && !stages)) return fail(GS_EINVAL, "null buffer");
+  if (!(alpha_max > 0) || !std::isfinite(alpha_max) || !(d_max > 0) || !std::isfinite(d_max))
+    return fail(GS_EINVAL, "alpha_max and d_max must be finite and > 0");
+  const size_t W = (size_t)p->prec, nch = (size_t)p->nch;
+  std::vector<double> a(nch);
+  if (nch) {
+    std::vector<char> raw(nch * W);
+    HIPCHK(hipMemcpyAsync(raw.data(), alpha, nch * W, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (size_t i = 0; i < nch; ++i)
+      a[i] = W == 4 ? (double)((const float*)raw.data())[i] : ((const double*)raw.data())[i];
+  }
+  // stage k actuates min(alpha, (k+1) alpha_max) per chamber; the last stage
+  // is the first whose actuation reaches alpha everywhere
+  for (double v : a)
+    if (!std::isfinite(v)) return fail(GS_EINVAL, "non-finite alpha");
+  int K = 0;
+  for (bool reached = false; !reached;) {
+    if (++K > (1 << 20)) return fail(GS_EINVAL, "alpha / alpha_max too large");
+    reached = true;
+    for (double v : a) reached &= std::min(v, K * alpha_max) >= v;
+  }
+  if (K > cap) return fail(GS_EINVAL, "stages array shorter than the number of stages");
+  char* ak = p->ws + p->lay.alpha_stage;
+  std::vector<char> host(nch * W);
+  bool all_converged = true;
+  int done = 0;
+  for (int k = 0; k < K; ++k) {
+    double top = 0.0;
+    for (size_t i = 0; i < nch; ++i) {
+      const double v = std::min(a[i], (k + 1) * alpha_max);
+      top = std::max(top, v);
+      if (W == 4)
+        ((float*)host.data())[i] = (float)v;
+      else
+        ((double*)host.data())[i] = v;
+    }
+    if (nch) HIPCHK(hipMemcpyAsync(ak, host.data(), nch * W, hipMemcpyHostToDevice, p->stream));
+    gs_stage& st = stages[k];
+    std::memset(&st, 0, sizeof(st));
+    const gs_status r = gs_solve(p, nch ? ak : nullptr, x, &st.solve);
+    if (r != GS_OK && r != GS_NOT_CONVERGED) return r;
+    all_converged &= (r == GS_OK);
+    st.status = r;
+    st.alpha_top = top;
+    const gs_status rf = gs_remesh_flags(p, x, nullptr, alpha_max, d_max, flags, &st.n_flagged);
+    if (rf != GS_OK) return rf;
+    done = k + 1;
+    if (n_stages) *n_stages = done;
+    if (stop_on_flag && st.n_flagged > 0) break;
+  }
+  if (n_stages) *n_stages = done;
+  return all_converged ? GS_OK : GS_NOT_CONVERGED;
 }
 
 gs_status gs_tets(const gs_problem* p, int32_t* tets) {

@@ -234,6 +234,9 @@ template <typename R> hipError_t launch_adj_chamber_sum(const Dev<R>& d, const C
 template <typename R> hipError_t launch_adj_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
 // Anderson step of the local/global iteration, after the CG kernel
 template <typename R> hipError_t launch_fwd_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R>
+hipError_t launch_remesh_flags(const Dev<R>& d, const Consts& c, const R* x, const R* xref, double amax, double dmax,
+                               uint8_t* flags, int* count, hipStream_t s);
 // unrolled adjoint helpers
 enum { ADJ_RESIDUAL = 0, ADJ_ALPHA = 1, ADJ_JT = 2 };
 template <typename R> hipError_t launch_adj_local_mode(const Dev<R>& d, const Consts& c, int mode, hipStream_t s);

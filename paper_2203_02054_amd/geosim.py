@@ -57,6 +57,15 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class Stage(ctypes.Structure):
+    _fields_ = [("solve", Stats), ("status", ctypes.c_int32), ("n_flagged", ctypes.c_int32),
+                ("alpha_top", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(solve=self.solve.as_dict(), status=self.status, n_flagged=self.n_flagged,
+                    alpha_top=self.alpha_top)
+
+
 class Info(ctypes.Structure):
     _fields_ = [("n_verts", ctypes.c_int32), ("n_tets", ctypes.c_int32), ("n_surface_faces", ctypes.c_int32),
                 ("n_surface_verts", ctypes.c_int32), ("n_query_verts", ctypes.c_int32), ("nnz", ctypes.c_int32),
@@ -99,6 +108,9 @@ SIGNATURES = {
     "gs_collide_debug": (_I, [_P, _P, _I, _P, ctypes.c_size_t, _PI, _PI, _PI, _PI, _PI, _PD, _PI]),
     "gs_collide_debug_static": (_I, [_P, _P, _I, _PI, _PI, _PI, _PI, _PI, _PD, _PI]),
     "gs_trace": (_I, [_P, _I, _PD, _PI]),
+    "gs_remesh_flags": (_I, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _PI]),
+    "gs_solve_progressive": (_I, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _I, _P, _I,
+                                  ctypes.POINTER(Stage), _PI]),
     "gs_create_batch": (_I, [_I, ctypes.POINTER(MeshDesc), ctypes.POINTER(Params), ctypes.POINTER(_P)]),
     "gs_batch_layout": (_I, [_P, _I, _PI, _PI, _PI, _PI]),
     "gs_mesh_iters": (_I, [_P, _I, _PI]),
@@ -108,7 +120,7 @@ SIGNATURES = {
     "gs_destroy": (None, [_P]),
 }
 
-N_KERNELS = 12
+N_KERNELS = 13
 
 _lib = None
 
@@ -449,6 +461,34 @@ class Problem:
         f = np.zeros((3, self.info["n_surface_faces"]), np.int32)
         _check(lib().gs_faces(self._h, _ptr(f, ctypes.c_int32)))
         return f
+
+    def remesh_flags(self, x, x_ref=None, alpha_max=4.0, d_max=4.0):
+        """Remesh checks of the chamber elements at x against x_ref (default:
+        the rest shape).  Returns (flags uint8 device tensor [T] in the order
+        of oriented_tets, number flagged)."""
+        flags = self.torch.empty(self.T, dtype=self.torch.uint8, device=self.device)
+        nf = ctypes.c_int32()
+        _check(lib().gs_remesh_flags(self._h, self._dev(x, (3, self.n)),
+                                     None if x_ref is None else self._dev(x_ref, (3, self.n)),
+                                     float(alpha_max), float(d_max), flags.data_ptr(), ctypes.byref(nf)))
+        return flags, nf.value
+
+    def solve_progressive(self, alpha, x=None, alpha_max=4.0, d_max=4.0, stop_on_flag=True, cap=64):
+        """Progressive actuation: stages alpha_k = min(alpha, (k+1) alpha_max),
+        each a solve warm-started from the last, then the remesh checks.
+        Returns (x, flags uint8 [T], list of stage dicts, status)."""
+        a = alpha if self.torch.is_tensor(alpha) else self.tensor(np.asarray(alpha, dtype=np.float64).reshape(-1))
+        if x is None:
+            x = self.tensor(self._X)
+        flags = self.torch.empty(self.T, dtype=self.torch.uint8, device=self.device)
+        stages = (Stage * cap)()
+        ns = ctypes.c_int32()
+        self.state_id += 1
+        code = lib().gs_solve_progressive(self._h, self._dev(a, (self.n_chambers,)) if self.n_chambers else None,
+                                          self._dev(x, (3, self.n)), float(alpha_max), float(d_max),
+                                          int(bool(stop_on_flag)), flags.data_ptr(), cap, stages, ctypes.byref(ns))
+        _check(code, (OK, NOT_CONVERGED))
+        return x, flags, [stages[i].as_dict() for i in range(ns.value)], code
 
     def collide(self, x, cap=None):
         """One collision check at x with the stored set as the previous one."""

@@ -316,7 +316,8 @@ def membrane(h: float = 8.0, seed: int = 6, coarse: bool = False, size: float = 
     Skin 20 (the rig's material), self-collision on, FP32.
 
     Voxel layout: the sheet covers M = round(size / h) voxels per side, one
-    voxel above the units' height H, and is then lowered by h/2; the units
+    voxel above the units' height H, and is then lowered by h/2 and shifted
+    by (0.382 h, 0.236 h) in x and y; the units
     (side U) sit 2U + g wide with g = max(1, round(16 / h)) voxels between
     them, centred under the sheet; cavities are centred in x and y.
     """
@@ -346,7 +347,13 @@ def membrane(h: float = 8.0, seed: int = 6, coarse: bool = False, size: float = 
     on_sheet = xyz[2] >= top
     rim = on_sheet & ((xyz[0] == 0.0) | (xyz[0] == M * h) | (xyz[1] == 0.0) | (xyz[1] == M * h))
     fixed = ((xyz[2] == 0.0) | rim).astype(np.uint8)
-    xyz[2, on_sheet] -= 0.5 * h                    # half a voxel of clearance above the roofs
+    # half a voxel of clearance above the roofs; the sheet's lattice is also
+    # shifted off the units' (by 0.382 h and 0.236 h), so that no roof vertex
+    # sits exactly under a sheet vertex or edge (an exact tie between
+    # triangles for the inverse-normal ray, decided by rounding)
+    xyz[0, on_sheet] += 0.382 * h
+    xyz[1, on_sheet] += 0.236 * h
+    xyz[2, on_sheet] -= 0.5 * h
     rng = np.random.default_rng(seed)
     alpha = rng.uniform(2.0, 3.5, 4)
     sheet = int(np.count_nonzero(vijk[:, 2] == H + 1))

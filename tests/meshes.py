@@ -45,3 +45,20 @@ def pressed_finger():
     sph = np.array([[X[0].max() - 8.0, 10.0, X[2].max() + 3.0, 6.0]])
     pl = np.array([[0.0, 0.0, 0.6, 0.0, 0.0, 1.0]])
     return dataclasses.replace(w, spheres=sph, planes=pl, obstacle_collision=True, self_collision=True)
+
+
+def wavy_positions(X, rng, amp, waves=6, noise=0.0):
+    """Rest positions X [3,n] moved by a sum of random sinusoidal fields (and
+    optional per-vertex noise), all scaled by amp: seeded deformed states
+    with a spread of local stretches, squashes and inversions."""
+    ext = X.max(axis=1) - X.min(axis=1)
+    u = np.zeros_like(X)
+    for _ in range(waves):
+        k = rng.normal(size=3) * (2 * np.pi / np.maximum(ext, 1e-9))
+        ph = rng.uniform(0, 2 * np.pi)
+        d = rng.normal(size=3)
+        u += d[:, None] * np.sin(k @ X + ph)[None, :]
+    u *= amp / np.sqrt(waves)
+    if noise:
+        u += noise * rng.normal(size=X.shape)
+    return X + u

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
     for n in names:
         assert hasattr(L, n), n
     assert sorted(G.SIGNATURES) == names
-    assert L.gs_version() == 200
+    assert L.gs_version() == 210
 
 
 def _desc(m, precision=4):
@@ -177,3 +177,20 @@ def test_energy_guard_is_refused_for_a_batch():
     p = G.default_params(aa_guard=G.AA_GUARD_ENERGY, aa_m=0)
     assert G.lib().gs_create_batch(2, descs, ctypes.byref(p), ctypes.byref(h)) == G.OK
     G.lib().gs_destroy(h)
+
+
+def test_remesh_and_progressive_entry_points_validate_on_the_host():
+    L = G.lib()
+    st = (G.Stage * 4)()
+    n = ctypes.c_int32()
+    assert L.gs_remesh_flags(None, None, None, 4.0, 4.0, None, None) == G.EINVAL
+    assert L.gs_solve_progressive(None, None, None, 4.0, 4.0, 1, None, 4, st, ctypes.byref(n)) == G.EINVAL
+    code, h, keep = _create(voxel_box(2, 1, 1))
+    assert code == G.OK
+    try:
+        # not bound to a device: refused before any device work
+        assert L.gs_remesh_flags(h, None, None, 4.0, 4.0, None, None) == G.ESTATE
+        assert L.gs_solve_progressive(h, None, None, 4.0, 4.0, 1, None, 4, st, ctypes.byref(n)) == G.ESTATE
+    finally:
+        L.gs_destroy(h)
+    assert ctypes.sizeof(G.Stage) == ctypes.sizeof(G.Stats) + 16
