@@ -151,6 +151,15 @@ def rhs(prob, x: torch.Tensor, alpha: torch.Tensor, contacts: Contacts, fresh: n
         pl = torch.from_numpy(prob.planes[j].copy())
         sd = _dot(pl[3:6, None], xv[:, sel] - pl[:3, None])
         parts.append((sel, xv[:, sel] - (sd - eps) * pl[3:6, None]))
+    mo = prob.mesh_obstacle
+    if mo is not None:
+        sel = np.nonzero(slot == 1 + ns + prob.planes.shape[0])[0]
+        if sel.size:
+            # closest-point targets on the mesh obstacle: values only (held
+            # constant under differentiation; gradients refuse such contacts)
+            xn = x.detach().numpy()
+            cm = np.stack([mo.target(xn[:, v[i]], eps)[1] for i in sel], axis=1)
+            parts.append((sel, torch.from_numpy(cm)))
     for sel, cc in parts:
         c = c.index_copy(1, torch.from_numpy(sel), cc)
     k = torch.from_numpy(prob.k_spring[v])
@@ -171,7 +180,10 @@ class _Frozen:
 
 def grad(prob, x, alpha, contacts: Contacts, fresh, dLdx, tol: float = 1e-13, restart: int = 300):
     """dL/dalpha [n_chambers] at positions x [3, n] (a fixed point of the
-    frozen-set map) for dL/dx = dLdx [3, n].  Returns (grad, mu [3, n], info)."""
+    frozen-set map) for dL/dx = dLdx [3, n].  Returns (grad, mu [3, n], info).
+    Contacts with a triangle-mesh obstacle are not differentiated (refused)."""
+    if prob.mesh_obstacle is not None and contacts.active[:, prob.n_slots - 1].any():
+        raise NotImplementedError("gradients through triangle-mesh obstacle contacts")
     fz = _Frozen(prob, contacts)
     F, nF = fz.F, fz.F.size
     xt = torch.tensor(np.asarray(x, dtype=np.float64), requires_grad=True)

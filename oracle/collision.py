@@ -14,6 +14,10 @@ all four sub-volumes obtained by replacing one vertex of e with v are
 strictly positive (ties count as outside).  Obstacles: inside a sphere when
 |x - c|^2 < r^2, below a plane when n . (x - p) < 0.
 
+A closed triangle-mesh obstacle (``oracle.obstacle``) is tested through the
+closest point on it: inside when the offset from that point points against
+the feature's pseudonormal.
+
 Response (Eq. 5, Section II-C).  A penetrating vertex gets a virtual spring to
 a target v_c.  Self collision: march from x_v along the inverse vertex normal
 -n(v) (area-weighted sum of the incident boundary-face normals) to the first
@@ -22,7 +26,7 @@ test; ties to the lowest face id), and put the target an offset eps past the
 hit (reading 10).  Obstacles: the closest point on the offset surface.
 
 Active set with release rule (Eq. 8).  For each query vertex (ascending) and
-each contact slot (self, then spheres, then planes): a penetrating vertex gets
+each contact slot (self, then spheres, then planes, then the mesh obstacle): a penetrating vertex gets
 a fresh spring; otherwise a spring it already had is kept unless
 |n_c . (x_v - c)| > eps (n_c = the stored contact normal, reading 11; obstacle
 springs recompute c and n_c first, kept self springs keep their stored target,
@@ -37,7 +41,7 @@ import numpy as np
 
 from .mesh import orient
 
-SELF, SPHERE, PLANE = 0, 1, 2
+SELF, SPHERE, PLANE, MESH = 0, 1, 2, 3
 
 
 @dataclass
@@ -62,7 +66,8 @@ class Contacts:
         s, slot = np.nonzero(self.active)              # row-major = (v ascending, slot ascending)
         v = prob.query_verts[s]
         ns = prob.spheres.shape[0]
-        typ = np.where(slot == 0, SELF, np.where(slot <= ns, SPHERE, PLANE))
+        npl = prob.planes.shape[0]
+        typ = np.where(slot == 0, SELF, np.where(slot <= ns, SPHERE, np.where(slot <= ns + npl, PLANE, MESH)))
         prim = self.prim[s, slot]
         return np.stack([v, typ, prim], axis=1).astype(np.int64), self.target[s, slot]
 
@@ -355,6 +360,19 @@ def collide(prob, x: np.ndarray, prev: Contacts | None = None, want_candidates: 
                     out.target[s, 0], out.normal[s, 0] = prev.target[s, 0], prev.normal[s, 0]
                     out.prim[s, 0] = prev.prim[s, 0]
 
+    mo = prob.mesh_obstacle
+    if p.obstacle_collision and mo is not None:
+        # the triangle-mesh obstacle: candidates are the vertices inside its
+        # box (a vertex outside the box is outside the mesh) and those holding
+        # a contact with it
+        slot = 1 + ns_ + npl
+        xs = x[:, qv]
+        inbox = np.all((xs >= mo.lo[:, None]) & (xs <= mo.hi[:, None]), axis=0)
+        for s in np.nonzero(inbox | prev.active[:, slot])[0]:
+            inside, c, n, t = mo.target(xs[:, s], eps)
+            if inside or (prev.active[s, slot] and not _released(xs[:, s], c, n, eps)):
+                out.active[s, slot] = True
+                out.target[s, slot], out.normal[s, slot], out.prim[s, slot] = c, n, t
     if p.obstacle_collision and (ns_ + npl) > 0:
         xs = x[:, qv]
         for j in range(ns_):

@@ -74,7 +74,7 @@ class Problem:
     """Rest-state data for one mesh (set-up step, done once per mesh)."""
 
     def __init__(self, rest_xyz, tets, tet_mode, tet_chamber, fixed, n_chambers,
-                 params: Params | None = None, spheres=None, planes=None):
+                 params: Params | None = None, spheres=None, planes=None, mesh_obstacle=None):
         self.params = params or Params()
         X = np.ascontiguousarray(rest_xyz, dtype=np.float64)
         tets = np.array(tets, dtype=np.int64, copy=True)
@@ -164,6 +164,11 @@ class Problem:
         if sph.shape[0] and np.any(sph[:, 3] <= 0):
             raise ValueError("sphere with non-positive radius")
         self.spheres, self.planes = sph, pln
+        # a closed triangle-mesh obstacle ((verts [3, m], tris [k, 3]) or None)
+        self.mesh_obstacle = None
+        if mesh_obstacle is not None:
+            from .obstacle import MeshObstacle
+            self.mesh_obstacle = MeshObstacle(*mesh_obstacle)
 
         self.free = ~self.fixed
 
@@ -176,9 +181,10 @@ class Problem:
         if kw:
             p = p.with_(**kw)
         return cls(wl.rest_xyz, wl.tets, wl.tet_mode, wl.tet_chamber, wl.fixed,
-                   wl.n_chambers, p, wl.spheres, wl.planes)
+                   wl.n_chambers, p, wl.spheres, wl.planes, getattr(wl, "mesh_obstacle", None))
 
     @property
     def n_slots(self) -> int:
-        """Contact slots per query vertex: self, then each sphere, then each plane."""
-        return 1 + self.spheres.shape[0] + self.planes.shape[0]
+        """Contact slots per query vertex: self, then each sphere, then each
+        plane, then one for the triangle-mesh obstacle if there is one."""
+        return 1 + self.spheres.shape[0] + self.planes.shape[0] + (self.mesh_obstacle is not None)

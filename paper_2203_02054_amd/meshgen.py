@@ -54,6 +54,9 @@ class Workload:
     alpha: np.ndarray             # [n_chambers] float64 volume ratios
     spheres: np.ndarray = field(default_factory=lambda: np.zeros((0, 4)))  # cx,cy,cz,r
     planes: np.ndarray = field(default_factory=lambda: np.zeros((0, 6)))   # px,py,pz,nx,ny,nz
+    # triangle-mesh obstacle: (verts [3, m], tris [k, 3]) of a closed,
+    # outward-oriented mesh, or None
+    mesh_obstacle: tuple | None = None
     self_collision: bool = False
     obstacle_collision: bool = False
     precision: int = 4
@@ -293,6 +296,60 @@ def gripper(h: float = 1.2, seed: int = 3, radius: float = 45.0) -> Workload:
                     self_collision=True, obstacle_collision=True, precision=4,
                     info=dict(h=h, finger_alpha=af, dims=dims, verts_per_finger=lxyz.shape[1]),
                     solver=GRIPPER_SOLVER)
+
+
+# ---------------------------------------------------------------------------
+# Triangle-mesh obstacles (closed, outward-oriented)
+# ---------------------------------------------------------------------------
+
+def _orient_outward(V, F):
+    """Wind every triangle of a convex mesh so its normal points away from
+    the mesh's vertex centroid."""
+    cen = V.mean(axis=1)
+    a, b, c = V[:, F[:, 0]], V[:, F[:, 1]], V[:, F[:, 2]]
+    n = np.cross((b - a).T, (c - a).T).T
+    flip = np.einsum("ij,ij->j", n, (a + b + c) / 3.0 - cen[:, None]) < 0
+    F = F.copy()
+    F[flip, 1], F[flip, 2] = F[flip, 2].copy(), F[flip, 1].copy()
+    return F
+
+
+def box_mesh(lo, hi):
+    """The box [lo, hi] as 12 triangles: verts [3, 8], tris [12, 3]."""
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    V = np.array([[(hi if (i >> k) & 1 else lo)[k] for k in range(3)] for i in range(8)]).T
+    quads = [(0, 2, 6, 4), (1, 3, 7, 5), (0, 1, 5, 4), (2, 3, 7, 6), (0, 1, 3, 2), (4, 5, 7, 6)]
+    F = np.array([t for q in quads for t in ((q[0], q[1], q[2]), (q[0], q[2], q[3]))], dtype=np.int64)
+    return V, _orient_outward(V, F)
+
+
+def icosphere(center, radius, levels=2):
+    """Sphere of the given radius as a subdivided icosahedron (20 * 4^levels
+    triangles, vertices on the sphere)."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    P = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    pts = [np.array(q, float) / np.linalg.norm(q) for q in P]
+    for _ in range(levels):
+        mid, nf = {}, []
+
+        def m(i, j):
+            k = (min(i, j), max(i, j))
+            if k not in mid:
+                q = pts[i] + pts[j]
+                pts.append(q / np.linalg.norm(q))
+                mid[k] = len(pts) - 1
+            return mid[k]
+
+        for a, b, c in F:
+            ab, bc, ca = m(a, b), m(b, c), m(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = nf
+    V = np.asarray(center, float)[:, None] + radius * np.array(pts).T
+    return V, _orient_outward(V, np.array(F, dtype=np.int64))
 
 
 # Chamber unit of the membrane rig, in voxels: footprint, height, wall,
