@@ -75,7 +75,7 @@ enum {
 enum { GS_BODY = 0, GS_CH_ISO = 1, GS_CH_AX_X = 2, GS_CH_AX_Y = 3, GS_CH_AX_Z = 4 };
 
 /* Contact types of the virtual springs (Section II-C). */
-enum { GS_CONTACT_SELF = 0, GS_CONTACT_SPHERE = 1, GS_CONTACT_PLANE = 2 };
+enum { GS_CONTACT_SELF = 0, GS_CONTACT_SPHERE = 1, GS_CONTACT_PLANE = 2, GS_CONTACT_MESH = 3 };
 
 /* Tet mesh M = M_c + M_b (Section II-A).  Host pointers, copied by gs_create. */
 typedef struct {
@@ -222,6 +222,25 @@ gs_status gs_mesh_iters(gs_problem* p, int32_t cap, int32_t* iters);
  * r <= 0, a zero normal or non-finite values. */
 gs_status gs_set_obstacles(gs_problem* p, int32_t n_sph, const double* sph, int32_t n_pln,
                            const double* pln);
+
+/* A closed, outward-oriented triangle-mesh obstacle (Section II-B, the
+ * obstacle term of Eq. 4; Section II-C): verts [3][n_verts] (host, FP64),
+ * tris [3][n_tris] (host, vertex ids; every edge shared by exactly two
+ * triangles).  Copied; must be called before gs_bind; n_tris = 0 removes it.
+ * With obstacle_collision on, every query vertex inside the obstacle's box
+ * or holding a contact with it is tested against its closest point c on the
+ * mesh (smallest squared distance, ties to the lowest triangle id; found by
+ * a tree built here over the triangles): it is inside when (x - c) . psi < 0,
+ * psi the angle-weighted pseudonormal of the face, edge or vertex c lies on;
+ * the spring target is c + eps_off u and the contact normal u, u the outward
+ * unit direction ((x - c)/|x - c| outside, (c - x)/|x - c| inside, psi on
+ * the surface), recomputed at every check; the release rule is Eq. 8's.
+ * Contacts with it are listed with type GS_CONTACT_MESH and the triangle id
+ * as prim, in the last slot.  Gradients (gs_adjoint, gs_adjoint_unrolled)
+ * refuse a problem whose mesh obstacle is on.  GS_EINVAL for non-finite
+ * vertices, bad indices, a degenerate triangle or an open mesh. */
+gs_status gs_set_mesh_obstacle(gs_problem* p, int32_t n_verts, const double* verts, int32_t n_tris,
+                               const int32_t* tris);
 
 gs_status gs_info_get(const gs_problem* p, gs_info* info);
 
@@ -455,8 +474,9 @@ gs_status gs_solve_progressive(gs_problem* p, const void* dev_alpha, void* dev_x
  * accelerated iteration's position update); "anderson" is that update with
  * its dot products and least-squares solve (three launches counted as one);
  * "remesh_flags" is gs_remesh_flags (two launches: the count is cleared
- * first).  gs_profile(p, 0) stops. */
-#define GS_N_KERNELS 13
+ * first); "mesh_obstacle" the closest-point search of the triangle-mesh
+ * obstacle.  gs_profile(p, 0) stops. */
+#define GS_N_KERNELS 14
 gs_status gs_profile(gs_problem* p, int32_t enable);
 gs_status gs_profile_read(const gs_problem* p, double* ms, int64_t* launches);
 const char* gs_kernel_name(int32_t k);

@@ -111,6 +111,29 @@ __device__ __forceinline__ void contacts_one(const Dev<R>& d, const Consts& c, i
       nact += now;
     }
   }
+  if (c.mo) {
+    // the triangle-mesh obstacle: its kernel tested the vertices inside the
+    // obstacle's box and those holding a contact with it
+    const int slot = base + 1 + c.ns + c.np;
+    const bool old = d.cact[slot] != 0;
+    const int fl = d.mo_flag[s];
+    bool now = false;
+    if (fl) {
+      const double* tc = d.mo_tgt + 3 * s;
+      const double* nc = d.mo_nrm + 3 * s;
+      now = fl == 2 || (old && !released(x, tc, nc, eps));
+      if (now) {
+        for (int k = 0; k < 3; ++k) {
+          d.ctgt[3 * slot + k] = tc[k];
+          d.cnrm[3 * slot + k] = nc[k];
+        }
+        d.cprim[slot] = d.mo_prim[s];
+      }
+    }
+    d.cact[slot] = now ? 1 : 0;
+    changed |= (now != old);
+    nact += now;
+  }
   if (changed) {
     atomicOr(&d.st->changed, 1);
     d.mchanged[m] = 1;

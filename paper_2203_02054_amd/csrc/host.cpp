@@ -9,6 +9,7 @@
 #include <numeric>
 #include <stdexcept>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "geosim.h"
@@ -56,15 +57,16 @@ struct Layout {
   size_t lam, ga_acc, st3, st4;
   size_t faa, faa_h, faa_gam, faa_blk, faa_mblk, cact_s, ctgt_s, cnrm_s, cprim_s;
   size_t rcount, alpha_stage;
+  size_t mo_tri, mo_id, mo_node, mo_flag, mo_tgt, mo_nrm, mo_prim;
   size_t total;
 };
 
-constexpr int kNKernels = 13;
-const char* const kKernelNames[kNKernels] = {"hash_insert", "tet_query",  "ray_cast", "contacts", "local",
-                                             "gather",      "pcg",        "adj_springs", "adj_local", "adj_gather",
-                                             "adj_pcg",     "anderson",   "remesh_flags"};
+constexpr int kNKernels = 14;
+const char* const kKernelNames[kNKernels] = {"hash_insert", "tet_query",  "ray_cast",     "contacts",   "local",
+                                             "gather",      "pcg",        "adj_springs",  "adj_local",  "adj_gather",
+                                             "adj_pcg",     "anderson",   "remesh_flags", "mesh_obstacle"};
 enum { K_CONTACTS = 3, K_LOCAL = 4, K_GATHER = 5, K_PCG = 6, K_ADJ_SPRINGS = 7, K_ADJ_LOCAL = 8, K_ADJ_GATHER = 9,
-       K_ADJ_PCG = 10, K_ANDERSON = 11, K_REMESH = 12 };
+       K_ADJ_PCG = 10, K_ANDERSON = 11, K_REMESH = 12, K_MESH_OBST = 13 };
 
 // Optional per-kernel timing: each launch is bracketed by two events on the
 // bound stream; elapsed times are collected whenever the driver synchronises.
@@ -130,6 +132,11 @@ struct gs_problem {
   int prec = 4;
   int n = 0, T = 0, nch = 0, S = 0, F = 0, slots = 1, H = 0, nnz = 0, nparts = 0;
   int ns = 0, np = 0;
+  // triangle-mesh obstacle: leaf-ordered records, ids and tree (empty: none)
+  std::vector<double> mo_tri;
+  std::vector<int32_t> mo_id;
+  std::vector<MoNode> mo_node;
+  int mo_k = 0;
   gs_params prm{};
   std::vector<double> X0;
   std::vector<int32_t> tets, tag, inc_start, inc_pos, rowptr, col, faces, qverts, vq, qf_start, qf_list, ell_col;
@@ -300,6 +307,13 @@ Layout make_layout(const gs_problem* p) {
   L.ctgt_s = take(3 * S * sl * 8);
   L.cnrm_s = take(3 * S * sl * 8);
   L.cprim_s = take(S * sl * 4);
+  L.mo_tri = take(p->mo_tri.size() * 8);
+  L.mo_id = take(p->mo_id.size() * 4);
+  L.mo_node = take(p->mo_node.size() * sizeof(MoNode));
+  L.mo_flag = take(p->mo_k ? S : 0);
+  L.mo_tgt = take(p->mo_k ? 3 * S * 8 : 0);
+  L.mo_nrm = take(p->mo_k ? 3 * S * 8 : 0);
+  L.mo_prim = take(p->mo_k ? S * 4 : 0);
   L.rcount = take(4);
   L.alpha_stage = take((size_t)p->nch * W);
   L.total = align256(off);
@@ -394,6 +408,13 @@ Dev<R> make_dev(const gs_problem* p) {
   d.cprim_s = (int32_t*)(b + L.cprim_s);
   d.dbg_tet = nullptr;
   d.dbg_tri = nullptr;
+  d.mo_tri = (const double*)(b + L.mo_tri);
+  d.mo_id = (const int32_t*)(b + L.mo_id);
+  d.mo_node = (const MoNode*)(b + L.mo_node);
+  d.mo_flag = (uint8_t*)(b + L.mo_flag);
+  d.mo_tgt = (double*)(b + L.mo_tgt);
+  d.mo_nrm = (double*)(b + L.mo_nrm);
+  d.mo_prim = (int32_t*)(b + L.mo_prim);
   d.dbg_cap = 0;
   return d;
 }
@@ -411,6 +432,7 @@ Consts make_consts(const gs_problem* p) {
   c.np = p->np;
   c.self_col = p->prm.self_collision ? 1 : 0;
   c.obst_col = (p->prm.obstacle_collision && (p->ns + p->np) > 0) ? 1 : 0;
+  c.mo = (p->prm.obstacle_collision && p->mo_k > 0) ? 1 : 0;
   c.hyper = p->prm.hyperelastic ? 1 : 0;
   c.max_iter = p->prm.max_iter;
   c.fixed_iters = p->prm.fixed_iters;
@@ -498,6 +520,9 @@ gs_status bind_impl(gs_problem* p) {
   HIPCHK(upload(b, L.qf_list, p->qf_list, s));
   HIPCHK(upload(b, L.kq, p->kq, s));
   HIPCHK(upload(b, L.obst, p->obst, s));
+  HIPCHK(upload(b, L.mo_tri, p->mo_tri, s));
+  HIPCHK(upload(b, L.mo_id, p->mo_id, s));
+  HIPCHK(upload(b, L.mo_node, p->mo_node, s));
   const std::vector<MeshConst> mt = mesh_table(p);
   HIPCHK(upload(b, L.mesh, mt, s));
   HIPCHK(upload(b, L.vmesh, p->vmesh, s));
@@ -623,6 +648,8 @@ hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, co
   }
   if (!fused_local)
     if ((e = timed(p, K_LOCAL, [&] { return launch_local<R>(d, c, alpha, s); })) != hipSuccess) return e;
+  if (c.mo)
+    if ((e = timed(p, K_MESH_OBST, [&] { return launch_mesh_obstacle<R>(d, c, s); })) != hipSuccess) return e;
   // the CG kernel first updates the contacts and gathers the right-hand side
   if ((e = timed_pcg<R>(p, K_PCG, d, c, false)) != hipSuccess) return e;
   if (c.faa_m > 0) return timed(p, K_ANDERSON, [&] { return launch_fwd_anderson<R>(d, c, s); });
@@ -1005,7 +1032,7 @@ void finalize(gs_problem* p) {
   while (H < 2 * p->S) H <<= 1;
   p->H = H;
   p->nparts = std::max({cdiv(p->T, kBlock), cdiv(n, kBlock), 12 * kMaxPcgGrid});
-  p->slots = 1 + p->ns + p->np;
+  p->slots = 1 + p->ns + p->np + (p->mo_k > 0 ? 1 : 0);
   // chamber -> tets, ascending tet id within a chamber
   p->ch_start.assign(p->nch + 1, 0);
   for (int e = 0; e < p->T; ++e)
@@ -1486,7 +1513,168 @@ gs_status gs_set_obstacles(gs_problem* p, int32_t n_sph, const double* sph, int3
   p->ns = n_sph;
   p->np = n_pln;
   p->obst = ob;
-  p->slots = 1 + n_sph + n_pln;
+  p->slots = 1 + n_sph + n_pln + (p->mo_k > 0 ? 1 : 0);
+  return GS_OK;
+}
+
+namespace {
+
+// Bounding-volume hierarchy over the obstacle's triangles: median split of
+// the centroids along the widest axis, at most 4 triangles per leaf, nodes in
+// depth-first order (root first), boxes exact.
+int build_mo_tree(const std::vector<double>& tri9, std::vector<int32_t>& order, int lo, int hi,
+                  std::vector<MoNode>& nodes, int depth, int& max_depth) {
+  max_depth = std::max(max_depth, depth);
+  const int id = (int)nodes.size();
+  nodes.push_back(MoNode{});
+  MoNode nd{};
+  for (int k = 0; k < 3; ++k) {
+    nd.lo[k] = INFINITY;
+    nd.hi[k] = -INFINITY;
+  }
+  double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int i = lo; i < hi; ++i) {
+    const double* t = &tri9[9 * (size_t)order[i]];
+    for (int k = 0; k < 3; ++k) {
+      for (int v = 0; v < 3; ++v) {
+        nd.lo[k] = std::min(nd.lo[k], t[3 * v + k]);
+        nd.hi[k] = std::max(nd.hi[k], t[3 * v + k]);
+      }
+      const double cen = (t[k] + t[3 + k] + t[6 + k]) / 3.0;
+      clo[k] = std::min(clo[k], cen);
+      chi[k] = std::max(chi[k], cen);
+    }
+  }
+  if (hi - lo <= 4) {
+    nd.left = nd.right = -1;
+    nd.first = lo;
+    nd.count = hi - lo;
+    nodes[id] = nd;
+    return id;
+  }
+  int ax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+  const int mid = (lo + hi) / 2;
+  auto cen = [&](int32_t t) { return tri9[9 * (size_t)t + ax] + tri9[9 * (size_t)t + 3 + ax] + tri9[9 * (size_t)t + 6 + ax]; };
+  std::nth_element(order.begin() + lo, order.begin() + mid, order.begin() + hi,
+                   [&](int32_t a, int32_t b) { return cen(a) < cen(b) || (cen(a) == cen(b) && a < b); });
+  nd.left = build_mo_tree(tri9, order, lo, mid, nodes, depth + 1, max_depth);
+  nd.right = build_mo_tree(tri9, order, mid, hi, nodes, depth + 1, max_depth);
+  nd.first = 0;
+  nd.count = 0;
+  nodes[id] = nd;
+  return id;
+}
+
+inline double dot3h(const double* a, const double* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+}  // namespace
+
+gs_status gs_set_mesh_obstacle(gs_problem* p, int32_t n_verts, const double* verts, int32_t n_tris,
+                               const int32_t* tris) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (p->bound) return fail(GS_ESTATE, "the mesh obstacle must be set before gs_bind");
+  if (n_tris == 0) {
+    p->mo_tri.clear();
+    p->mo_id.clear();
+    p->mo_node.clear();
+    p->mo_k = 0;
+    p->slots = 1 + p->ns + p->np;
+    return GS_OK;
+  }
+  if (n_verts < 3 || n_tris < 4 || !verts || !tris) return fail(GS_EINVAL, "mesh obstacle: too small or null");
+  const size_t m = (size_t)n_verts, k = (size_t)n_tris;
+  for (size_t i = 0; i < 3 * m; ++i)
+    if (!std::isfinite(verts[i])) return fail(GS_EINVAL, "mesh obstacle: non-finite vertex");
+  for (size_t i = 0; i < 3 * k; ++i)
+    if (tris[i] < 0 || tris[i] >= n_verts) return fail(GS_EINVAL, "mesh obstacle: vertex index out of range");
+  // triangles as [k][3] corners and unit face normals (same operation order
+  // as written: n = (b - a) x (c - a), |n| = sqrt((nx^2 + ny^2) + nz^2))
+  std::vector<double> tri9(9 * k), fn(3 * k);
+  for (size_t t = 0; t < k; ++t) {
+    for (int v = 0; v < 3; ++v)
+      for (int c = 0; c < 3; ++c) tri9[9 * t + 3 * v + c] = verts[(size_t)c * m + tris[(size_t)v * k + t]];
+    const double* a = &tri9[9 * t];
+    const double u[3] = {a[3] - a[0], a[4] - a[1], a[5] - a[2]}, w[3] = {a[6] - a[0], a[7] - a[1], a[8] - a[2]};
+    const double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    const double ln = std::sqrt(dot3h(n, n));
+    if (!(ln > 0)) return fail(GS_EINVAL, "mesh obstacle: degenerate triangle");
+    for (int c = 0; c < 3; ++c) fn[3 * t + c] = n[c] / ln;
+  }
+  // edges (ab, ac, bc of every triangle): each must be shared by exactly two
+  // triangles; edge pseudonormal = the sum of their unit normals (ascending
+  // triangle order), normalised
+  std::map<std::pair<int, int>, int> eid;
+  std::vector<int> tedge(3 * k), ecount;
+  std::vector<double> en;
+  const int lp[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  for (size_t t = 0; t < k; ++t)
+    for (int j = 0; j < 3; ++j) {
+      int a = tris[lp[j][0] * k + t], b = tris[lp[j][1] * k + t];
+      if (a > b) std::swap(a, b);
+      auto it = eid.find({a, b});
+      int e;
+      if (it == eid.end()) {
+        e = (int)ecount.size();
+        eid[{a, b}] = e;
+        ecount.push_back(0);
+        en.insert(en.end(), {0.0, 0.0, 0.0});
+      } else {
+        e = it->second;
+      }
+      tedge[3 * t + j] = e;
+      ++ecount[e];
+    }
+  for (int cnt : ecount)
+    if (cnt != 2) return fail(GS_EINVAL, "mesh obstacle: not closed (an edge is not shared by two triangles)");
+  for (size_t t = 0; t < k; ++t)
+    for (int j = 0; j < 3; ++j)
+      for (int c = 0; c < 3; ++c) en[3 * tedge[3 * t + j] + c] += fn[3 * t + c];
+  for (size_t e = 0; e < ecount.size(); ++e) {
+    const double l = std::sqrt(dot3h(&en[3 * e], &en[3 * e]));
+    for (int c = 0; c < 3; ++c) en[3 * e + c] /= l;
+  }
+  // vertex pseudonormals: incident unit normals weighted by the angle at the
+  // vertex, summed corner slot by corner slot in ascending triangle order
+  std::vector<double> vn(3 * m, 0.0);
+  for (int i = 0; i < 3; ++i)
+    for (size_t t = 0; t < k; ++t) {
+      const double* P = &tri9[9 * t];
+      const double* o = P + 3 * i;
+      const double* q1 = P + 3 * ((i + 1) % 3);
+      const double* q2 = P + 3 * ((i + 2) % 3);
+      const double u[3] = {q1[0] - o[0], q1[1] - o[1], q1[2] - o[2]}, w[3] = {q2[0] - o[0], q2[1] - o[1], q2[2] - o[2]};
+      const double cs = dot3h(u, w) / std::sqrt(dot3h(u, u) * dot3h(w, w));
+      const double ang = std::acos(std::min(1.0, std::max(-1.0, cs)));
+      const int vv = tris[(size_t)i * k + t];
+      for (int c = 0; c < 3; ++c) vn[3 * (size_t)vv + c] += fn[3 * t + c] * ang;
+    }
+  std::vector<MoNode> nodes;
+  std::vector<int32_t> order(k);
+  for (size_t t = 0; t < k; ++t) order[t] = (int32_t)t;
+  int depth = 0;
+  build_mo_tree(tri9, order, 0, (int)k, nodes, 0, depth);
+  if (depth > 60) return fail(GS_EINVAL, "mesh obstacle: tree too deep");
+  std::vector<double> rec(30 * k);
+  for (size_t i = 0; i < k; ++i) {
+    const size_t t = (size_t)order[i];
+    double* r = &rec[30 * i];
+    for (int j = 0; j < 9; ++j) r[j] = tri9[9 * t + j];
+    for (int c = 0; c < 3; ++c) r[9 + c] = fn[3 * t + c];
+    for (int j = 0; j < 3; ++j)
+      for (int c = 0; c < 3; ++c) r[12 + 3 * j + c] = en[3 * (size_t)tedge[3 * t + j] + c];
+    for (int j = 0; j < 3; ++j) {
+      const double* q = &vn[3 * (size_t)tris[(size_t)j * k + t]];
+      const double l = std::sqrt(dot3h(q, q));
+      for (int c = 0; c < 3; ++c) r[21 + 3 * j + c] = q[c] / l;
+    }
+  }
+  p->mo_tri = std::move(rec);
+  p->mo_id = std::move(order);
+  p->mo_node = std::move(nodes);
+  p->mo_k = n_tris;
+  p->slots = 1 + p->ns + p->np + 1;
   return GS_OK;
 }
 
@@ -1672,6 +1860,8 @@ gs_status gs_adjoint_unrolled(gs_problem* p, const void* alpha, const void* x0, 
   if (!p->bound) return fail(GS_ESTATE, "gs_adjoint_unrolled before gs_bind");
   if (K < 1 || !x0 || !dLdx || !scratch || (p->nch > 0 && (!alpha || !dLdalpha)))
     return fail(GS_EINVAL, "bad argument");
+  if (p->mo_k > 0 && p->prm.obstacle_collision)
+    return fail(GS_EINVAL, "gradients through a triangle-mesh obstacle are not supported");
   if (((uintptr_t)scratch & 255) != 0) return fail(GS_EINVAL, "scratch must be 256-byte aligned");
   if (scratch_bytes < gs_unrolled_scratch_size(p, K)) return fail(GS_EINVAL, "scratch too small");
   if (p->prec == 4)
@@ -1686,6 +1876,8 @@ gs_status gs_adjoint(gs_problem* p, const void* dLdx, void* dLdalpha, void* mu, 
   if (!p->bound) return fail(GS_ESTATE, "gs_adjoint before gs_bind");
   if (!p->solved) return fail(GS_ESTATE, "gs_adjoint needs a gs_solve first");
   if (!dLdx || (p->nch > 0 && !dLdalpha)) return fail(GS_EINVAL, "null device buffer");
+  if (p->mo_k > 0 && p->prm.obstacle_collision)
+    return fail(GS_EINVAL, "gradients through a triangle-mesh obstacle are not supported");
   if (p->prec == 4) return adjoint_impl<float>(p, (const float*)dLdx, (float*)dLdalpha, (float*)mu, stats);
   return adjoint_impl<double>(p, (const double*)dLdx, (double*)dLdalpha, (double*)mu, stats);
 }
@@ -1721,7 +1913,9 @@ gs_status gs_contacts(gs_problem* p, int32_t cap, int32_t* v, int32_t* type, int
       const size_t i = (size_t)s * p->slots + sl;
       if (!act[i]) continue;
       if (v) v[o] = p->qverts[s];
-      if (type) type[o] = sl == 0 ? GS_CONTACT_SELF : (sl <= p->ns ? GS_CONTACT_SPHERE : GS_CONTACT_PLANE);
+      if (type)
+        type[o] = sl == 0 ? GS_CONTACT_SELF
+                          : (sl <= p->ns ? GS_CONTACT_SPHERE : (sl <= p->ns + p->np ? GS_CONTACT_PLANE : GS_CONTACT_MESH));
       if (prim) prim[o] = pr[i];
       if (fresh) fresh[o] = act[i] == 2 ? 1 : 0;
       for (int c = 0; c < 3; ++c) {
@@ -1754,6 +1948,9 @@ gs_status gs_set_contacts(gs_problem* p, int32_t count, const int32_t* v, const 
     } else if (type[i] == GS_CONTACT_PLANE) {
       if (prim[i] < 0 || prim[i] >= p->np) return fail(GS_EINVAL, "plane index out of range");
       sl = 1 + p->ns + prim[i];
+    } else if (type[i] == GS_CONTACT_MESH && p->mo_k > 0) {
+      if (prim[i] < 0 || prim[i] >= p->mo_k) return fail(GS_EINVAL, "mesh obstacle triangle out of range");
+      sl = 1 + p->ns + p->np;
     } else {
       return fail(GS_EINVAL, "bad contact type");
     }
@@ -1924,7 +2121,8 @@ gs_status gs_collide_debug(gs_problem* p, const void* x, int32_t cap, void* scra
     p->hash_ready = false;
     if (c.self_col)
       for (int stg = 0; stg < N_COLLIDE_STAGES; ++stg) HIPCHK(launch_collide_stage<R>(d, c, stg, true, s));
-    if (c.self_col || c.obst_col) HIPCHK(launch_contacts<R>(d, c, s));
+    if (c.mo) HIPCHK(launch_mesh_obstacle<R>(d, c, s));
+    if (c.self_col || c.obst_col || c.mo) HIPCHK(launch_contacts<R>(d, c, s));
     HIPCHK(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return GS_OK;

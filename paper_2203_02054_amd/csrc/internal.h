@@ -11,7 +11,7 @@ namespace gs {
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
 constexpr int kCellCap = 64;         // hash cells a tet box may span before the brute-force path
 constexpr int kHashCap = 8;          // entries stored in a hash bucket before the overflow list
-constexpr int kMaxSlots = 1 + 8 + 8; // self + spheres + planes
+constexpr int kMaxSlots = 1 + 8 + 8 + 1; // self + spheres + planes + the triangle-mesh obstacle
 constexpr int kPcgThreads = 512;     // threads per block of the persistent CG kernel
 constexpr int kPcgRowsPerBlock = 256; // default rows per CG block (grid = n / 256, capped)
 // Tet count from which the tet query runs its one-lane-per-tet,
@@ -74,6 +74,14 @@ struct AaBlock {
   int m, v0, v1, pad;
 };
 
+// A node of the triangle-mesh obstacle's bounding-volume hierarchy: a leaf
+// (count > 0) holds triangles [first, first + count) of the leaf-ordered
+// records; an inner node (count == 0) its two children.
+struct MoNode {
+  double lo[3], hi[3];
+  int left, right, first, count;
+};
+
 // Per-mesh constants of a problem made of one or several meshes.
 struct MeshConst {
   double eps;       // offset of the collided boundary (eps_rel * h_ref)
@@ -92,6 +100,7 @@ struct Consts {
   int M;                // meshes
   int mask_done;        // freeze meshes once they converge (not with fixed_iters)
   int self_col, obst_col, hyper;
+  int mo;               // the triangle-mesh obstacle is on (its slot is the last one)
   int max_iter, fixed_iters, pcg_max;
   int nparts;           // partial-sum slots per reduction array
   int ell_w;            // off-diagonal entries per row of the ELL matrix (16, 32 or 64)
@@ -202,6 +211,15 @@ struct Dev {
   // unrolled reverse sweep
   R* lam;                  // [3][n] adjoint of the positions
   double* ga_acc;          // [nch] dL/dalpha accumulated over the reverse steps
+  // triangle-mesh obstacle (static tree; per-query-vertex results of its kernel)
+  const double* mo_tri;    // [k][30] leaf-ordered triangles: a, b, c, face, edge (ab, ac, bc) and vertex
+                           //   (a, b, c) pseudonormals
+  const int32_t* mo_id;    // [k] triangle id of each record
+  const MoNode* mo_node;   // tree nodes, root first
+  uint8_t* mo_flag;        // [S] 0 not tested, 1 tested and outside, 2 inside
+  double* mo_tgt;          // [S][3] target c + eps u
+  double* mo_nrm;          // [S][3] outward direction u
+  int32_t* mo_prim;        // [S] triangle of the closest point
   // debug candidate buffers (null outside gs_collide_debug)
   int32_t* dbg_tet;        // [2][cap]
   int32_t* dbg_tri;        // [2][cap]
@@ -234,6 +252,7 @@ template <typename R> hipError_t launch_adj_chamber_sum(const Dev<R>& d, const C
 template <typename R> hipError_t launch_adj_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
 // Anderson step of the local/global iteration, after the CG kernel
 template <typename R> hipError_t launch_fwd_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
+template <typename R> hipError_t launch_mesh_obstacle(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R>
 hipError_t launch_remesh_flags(const Dev<R>& d, const Consts& c, const R* x, const R* xref, double amax, double dmax,
                                uint8_t* flags, int* count, hipStream_t s);

@@ -659,7 +659,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       double esp = 0.0;
       if constexpr (PAIR) {
         if (pv_has) {
-          if (pv_half == 0 && (c.self_col || c.obst_col)) {
+          if (pv_half == 0 && (c.self_col || c.obst_col || c.mo)) {
             const int s = d.vq[pv_row];
             if (s >= 0) contacts_one(d, c, s);
           }
@@ -667,7 +667,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         }
       } else {
         for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
-          if (c.self_col || c.obst_col) {
+          if (c.self_col || c.obst_col || c.mo) {
             const int s = d.vq[v];
             if (s >= 0) contacts_one(d, c, s);
           }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgeosim.so")
 OK, NOT_CONVERGED = 0, 1
 EINVAL, EDEGENERATE, EBREAKDOWN, ECAPACITY, ESTATE, EHIP = -1, -2, -3, -4, -5, -6
 BODY, CH_ISO, CH_AX_X, CH_AX_Y, CH_AX_Z = 0, 1, 2, 3, 4
-CONTACT_SELF, CONTACT_SPHERE, CONTACT_PLANE = 0, 1, 2
+CONTACT_SELF, CONTACT_SPHERE, CONTACT_PLANE, CONTACT_MESH = 0, 1, 2, 3
 AA_GUARD_NONE, AA_GUARD_RESIDUAL, AA_GUARD_ENERGY, AA_GUARD_SET = 0, 1, 2, 4
 
 
@@ -89,6 +89,7 @@ SIGNATURES = {
     "gs_default_params": (None, [ctypes.POINTER(Params)]),
     "gs_create": (_I, [ctypes.POINTER(MeshDesc), ctypes.POINTER(Params), ctypes.POINTER(_P)]),
     "gs_set_obstacles": (_I, [_P, _I, _PD, _I, _PD]),
+    "gs_set_mesh_obstacle": (_I, [_P, _I, _PD, _I, _PI]),
     "gs_info_get": (_I, [_P, ctypes.POINTER(Info)]),
     "gs_workspace_size": (_I, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "gs_bind": (_I, [_P, _P, ctypes.c_size_t, _P]),
@@ -120,7 +121,7 @@ SIGNATURES = {
     "gs_destroy": (None, [_P]),
 }
 
-N_KERNELS = 13
+N_KERNELS = 14
 
 _lib = None
 
@@ -188,12 +189,14 @@ class Problem:
     """One tet mesh bound to a device workspace and a stream."""
 
     def __init__(self, rest_xyz, tets, tet_mode, tet_chamber, fixed, n_chambers, precision=4, params=None,
-                 spheres=None, planes=None, device=None, stream=None, **kw):
+                 spheres=None, planes=None, device=None, stream=None, mesh_obstacle=None, **kw):
         self._setup([dict(rest_xyz=rest_xyz, tets=tets, tet_mode=tet_mode, tet_chamber=tet_chamber, fixed=fixed,
-                          n_chambers=n_chambers)], precision, params, spheres, planes, device, stream, kw)
+                          n_chambers=n_chambers)], precision, params, spheres, planes, device, stream, kw,
+                    mesh_obstacle=mesh_obstacle)
 
     @classmethod
-    def batch(cls, meshes, precision=4, params=None, spheres=None, planes=None, device=None, stream=None, **kw):
+    def batch(cls, meshes, precision=4, params=None, spheres=None, planes=None, device=None, stream=None,
+              mesh_obstacle=None, **kw):
         """Several meshes solved together (dicts with the Problem arguments, or
         workloads); arrays are concatenated in mesh order."""
         self = cls.__new__(cls)
@@ -203,10 +206,12 @@ class Problem:
                 m = dict(rest_xyz=m.rest_xyz, tets=m.tets, tet_mode=m.tet_mode, tet_chamber=m.tet_chamber,
                          fixed=m.fixed, n_chambers=m.n_chambers)
             ms.append(m)
-        self._setup(ms, precision, params, spheres, planes, device, stream, kw, batch=True)
+        self._setup(ms, precision, params, spheres, planes, device, stream, kw, batch=True,
+                    mesh_obstacle=mesh_obstacle)
         return self
 
-    def _setup(self, meshes, precision, params, spheres, planes, device, stream, kw, batch=False):
+    def _setup(self, meshes, precision, params, spheres, planes, device, stream, kw, batch=False,
+               mesh_obstacle=None):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device or "cuda")
@@ -242,6 +247,11 @@ class Problem:
         if sph.shape[0] or pln.shape[0]:
             _check(lib().gs_set_obstacles(h, sph.shape[0], _ptr(sph, ctypes.c_double), pln.shape[0],
                                           _ptr(pln, ctypes.c_double)))
+        if mesh_obstacle is not None:
+            mv = np.ascontiguousarray(mesh_obstacle[0], dtype=np.float64)
+            mt = np.ascontiguousarray(np.asarray(mesh_obstacle[1]).T, dtype=np.int32)   # [3][k]
+            _check(lib().gs_set_mesh_obstacle(h, mv.shape[1], _ptr(mv, ctypes.c_double), mt.shape[1],
+                                              _ptr(mt, ctypes.c_int32)))
         nb = ctypes.c_size_t()
         _check(lib().gs_workspace_size(h, ctypes.byref(nb)))
         self.ws_bytes = nb.value
@@ -278,7 +288,8 @@ class Problem:
         kw.setdefault("obstacle_collision", int(wl.obstacle_collision))
         kw.setdefault("fixed_iters", wl.fixed_iters)
         return cls(wl.rest_xyz, wl.tets, wl.tet_mode, wl.tet_chamber, wl.fixed, wl.n_chambers,
-                   precision=precision or wl.precision, spheres=wl.spheres, planes=wl.planes, **kw)
+                   precision=precision or wl.precision, spheres=wl.spheres, planes=wl.planes,
+                   mesh_obstacle=getattr(wl, "mesh_obstacle", None), **kw)
 
     # -- helpers -----------------------------------------------------------
     def tensor(self, a):

@@ -21,10 +21,10 @@ def oracle_contacts(prob, cg, lo=0):
     offset by lo."""
     A = Contacts.empty(prob.query_verts.size, prob.n_slots)
     fresh = np.zeros(prob.query_verts.size, bool)
-    ns = prob.spheres.shape[0]
+    ns, npl = prob.spheres.shape[0], prob.planes.shape[0]
     for i, ((v, typ, prim), t, nrm) in enumerate(zip(cg["rows"], cg["target"], cg["normal"])):
         s = int(np.searchsorted(prob.query_verts, v - lo))
-        sl = 0 if typ == 0 else (1 + prim if typ == 1 else 1 + ns + prim)
+        sl = 0 if typ == 0 else (1 + prim if typ == 1 else (1 + ns + prim if typ == 2 else 1 + ns + npl))
         A.active[s, sl] = True
         A.target[s, sl], A.normal[s, sl], A.prim[s, sl] = t, nrm, prim
         if typ == 0 and "fresh" in cg and cg["fresh"][i]:
