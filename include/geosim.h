@@ -404,6 +404,23 @@ gs_status gs_collide_debug_static(gs_problem* p, const void* dev_x, int32_t cap,
                                   int32_t* n_cand_tet, int32_t* cand_tri, int32_t* n_cand_tri,
                                   int32_t* contacts, double* target, int32_t* n_contacts);
 
+/* Self-collision broadphase by a refit-only AABB tree over the tets
+ * (Section II-B: the tree keeps its structure through the deformation and
+ * only its boxes follow the positions).  The topology is built once, on the
+ * first call, by median splits of the rest centroids (at most 4 tets per
+ * leaf); every call refits the boxes to dev_x ([3][n], exact min/max of the
+ * FP64 positions, bottom-up one depth per launch) and walks it for every
+ * query vertex, returning C_tet = {(v, e): v not a vertex of e, lo_e <= x_v
+ * <= hi_e}, the same set as the spatial hash the solver uses (see
+ * gs_collide_debug).  cand [2][cap] (host) receives the pairs sorted by
+ * (v, e), *n_cand their number (GS_ECAPACITY when above cap, pairs not
+ * written); ms_refit / ms_query (may be NULL) the two phases' device times.
+ * dev_scratch holds gs_tree_candidates_scratch(p, cap) bytes (caller-owned).
+ * Problems of one mesh only.  Synchronises the bound stream. */
+size_t gs_tree_candidates_scratch(const gs_problem* p, int32_t cap);
+gs_status gs_tree_candidates(gs_problem* p, const void* dev_x, int32_t cap, void* dev_scratch, size_t scratch_bytes,
+                             int32_t* cand, int32_t* n_cand, double* ms_refit, double* ms_query);
+
 /* Per-iteration trace of the last solve: rows of GS_TRACE_COLS doubles
  * (r_k, E_k, active springs, set changed, inner CG iterations, ray misses)
  * for the first min(iters, trace_len) iterations; trace_len is fixed at

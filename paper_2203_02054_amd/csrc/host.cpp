@@ -9,6 +9,7 @@
 #include <numeric>
 #include <stdexcept>
 #include <string>
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -137,6 +138,11 @@ struct gs_problem {
   std::vector<int32_t> mo_id;
   std::vector<MoNode> mo_node;
   int mo_k = 0;
+  // refit-only AABB tree over the tets (built on first use): nodes in
+  // breadth-first order, leaf tet order, first node of every depth
+  std::vector<MoNode> tree_node;
+  std::vector<int32_t> tree_order;
+  std::vector<int> tree_level;
   gs_params prm{};
   std::vector<double> X0;
   std::vector<int32_t> tets, tag, inc_start, inc_pos, rowptr, col, faces, qverts, vq, qf_start, qf_list, ell_col;
@@ -1675,6 +1681,171 @@ gs_status gs_set_mesh_obstacle(gs_problem* p, int32_t n_verts, const double* ver
   p->mo_node = std::move(nodes);
   p->mo_k = n_tris;
   p->slots = 1 + p->ns + p->np + 1;
+  return GS_OK;
+}
+
+namespace {
+
+// Median-split tree over the tets' rest centroids (4 tets per leaf), then
+// relabelled breadth first so that each depth is one contiguous node range.
+void build_tet_tree(gs_problem* p) {
+  const int T = p->T;
+  const size_t n = (size_t)p->n;
+  std::vector<double> cen(3 * (size_t)T);
+  for (int e = 0; e < T; ++e)
+    for (int k = 0; k < 3; ++k) {
+      double acc = 0.0;
+      for (int q = 0; q < 4; ++q) acc += p->X0[k * n + p->tets[(size_t)q * T + e]];
+      cen[3 * (size_t)e + k] = acc;
+    }
+  struct Tmp {
+    int left, right, first, count;
+  };
+  std::vector<Tmp> tmp;
+  std::vector<int32_t> order(T);
+  std::iota(order.begin(), order.end(), 0);
+  std::function<int(int, int)> rec = [&](int lo, int hi) -> int {
+    const int id = (int)tmp.size();
+    tmp.push_back(Tmp{-1, -1, lo, hi - lo});
+    if (hi - lo <= 4) return id;
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = lo; i < hi; ++i)
+      for (int k = 0; k < 3; ++k) {
+        clo[k] = std::min(clo[k], cen[3 * (size_t)order[i] + k]);
+        chi[k] = std::max(chi[k], cen[3 * (size_t)order[i] + k]);
+      }
+    int ax = 0;
+    for (int k = 1; k < 3; ++k)
+      if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+    const int mid = (lo + hi) / 2;
+    std::nth_element(order.begin() + lo, order.begin() + mid, order.begin() + hi, [&](int32_t a, int32_t b) {
+      const double ca = cen[3 * (size_t)a + ax], cb = cen[3 * (size_t)b + ax];
+      return ca < cb || (ca == cb && a < b);
+    });
+    const int l = rec(lo, mid), r = rec(mid, hi);
+    tmp[id] = Tmp{l, r, 0, 0};
+    return id;
+  };
+  rec(0, T);
+  // breadth-first relabelling
+  std::vector<int> bfs{0}, depth{0}, newid(tmp.size(), -1);
+  for (size_t h = 0; h < bfs.size(); ++h) {
+    const Tmp& t = tmp[bfs[h]];
+    if (t.count == 0) {
+      bfs.push_back(t.left);
+      depth.push_back(depth[h] + 1);
+      bfs.push_back(t.right);
+      depth.push_back(depth[h] + 1);
+    }
+  }
+  for (size_t h = 0; h < bfs.size(); ++h) newid[bfs[h]] = (int)h;
+  p->tree_node.assign(bfs.size(), MoNode{});
+  p->tree_level.assign((size_t)depth.back() + 2, 0);
+  for (size_t h = 0; h < bfs.size(); ++h) {
+    const Tmp& t = tmp[bfs[h]];
+    MoNode& nd = p->tree_node[h];
+    nd.left = t.count ? -1 : newid[t.left];
+    nd.right = t.count ? -1 : newid[t.right];
+    nd.first = t.first;
+    nd.count = t.count;
+    p->tree_level[(size_t)depth[h] + 1] = (int)h + 1;
+  }
+  p->tree_order = std::move(order);
+}
+
+struct TreeScratch {
+  size_t node, order, tbox, pairs, count, total;
+};
+
+TreeScratch tree_scratch(int64_t nodes, int64_t T, int64_t cap) {
+  TreeScratch t{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    off = align256(off);
+    const size_t o = off;
+    off += std::max<size_t>(b, 1);
+    return o;
+  };
+  t.node = take((size_t)nodes * sizeof(MoNode));
+  t.order = take((size_t)T * 4);
+  t.tbox = take((size_t)T * 48);
+  t.pairs = take(2 * (size_t)cap * 4);
+  t.count = take(4);
+  t.total = align256(off);
+  return t;
+}
+
+}  // namespace
+
+size_t gs_tree_candidates_scratch(const gs_problem* p, int32_t cap) {
+  if (!p || cap < 0) return 0;
+  // a median-split tree with at most 4 tets per leaf has fewer than 2T nodes
+  return tree_scratch(2 * (int64_t)p->T, p->T, cap).total;
+}
+
+gs_status gs_tree_candidates(gs_problem* p, const void* x, int32_t cap, void* scratch, size_t scratch_bytes,
+                             int32_t* cand, int32_t* n_cand, double* ms_refit, double* ms_query) {
+  if (!p) return fail(GS_EINVAL, "null problem");
+  if (!p->bound) return fail(GS_ESTATE, "not bound");
+  if (!x || !scratch || cap < 0 || !n_cand) return fail(GS_EINVAL, "null argument");
+  if (p->M != 1) return fail(GS_EINVAL, "the tet tree serves a problem of one mesh");
+  if (scratch_bytes < gs_tree_candidates_scratch(p, cap)) return fail(GS_EINVAL, "tree scratch too small");
+  if (p->tree_node.empty()) build_tet_tree(p);
+  if ((int)p->tree_level.size() - 1 > 60) return fail(GS_EINVAL, "tet tree too deep");
+  const TreeScratch ts = tree_scratch((int64_t)p->tree_node.size(), p->T, cap);
+  char* b = (char*)scratch;
+  hipStream_t s = p->stream;
+  HIPCHK(hipMemcpyAsync(b + ts.node, p->tree_node.data(), p->tree_node.size() * sizeof(MoNode),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(b + ts.order, p->tree_order.data(), p->tree_order.size() * 4, hipMemcpyHostToDevice, s));
+  const Consts c = make_consts(p);
+  hipEvent_t e0, e1, e2;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventCreate(&e2));
+  auto run = [&](auto tag) -> hipError_t {
+    using R = decltype(tag);
+    Dev<R> d = make_dev<R>(p);
+    hipError_t e = launch_set_positions<R>(d, c, (const R*)x, s);
+    if (e != hipSuccess) return e;
+    p->hash_ready = false;
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+    if ((e = launch_tree_refit<R>(d, c, (MoNode*)(b + ts.node), (const int32_t*)(b + ts.order),
+                                  (double*)(b + ts.tbox), p->tree_level.data(), (int)p->tree_level.size() - 1,
+                                  s)) != hipSuccess)
+      return e;
+    if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+    if ((e = launch_tree_query<R>(d, c, (const MoNode*)(b + ts.node), (const int32_t*)(b + ts.order),
+                                  (const double*)(b + ts.tbox), (int32_t*)(b + ts.pairs), cap,
+                                  (int*)(b + ts.count), s)) != hipSuccess)
+      return e;
+    return hipEventRecord(e2, s);
+  };
+  hipError_t e = p->prec == 4 ? run(float{}) : run(double{});
+  int32_t cnt = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&cnt, b + ts.count, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  float t1 = 0.f, t2 = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t1, e0, e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&t2, e1, e2);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipEventDestroy(e2);
+  HIPCHK(e);
+  if (ms_refit) *ms_refit = t1;
+  if (ms_query) *ms_query = t2;
+  *n_cand = cnt;
+  if (cnt > cap) return fail(GS_ECAPACITY, "candidate capacity too small");
+  std::vector<int32_t> buf(2 * (size_t)cap);
+  if (cap > 0) HIPCHK(hipMemcpy(buf.data(), b + ts.pairs, 2 * (size_t)cap * 4, hipMemcpyDeviceToHost));
+  std::vector<std::pair<int32_t, int32_t>> pr(cnt);
+  for (int i = 0; i < cnt; ++i) pr[i] = {buf[i], buf[cap + i]};
+  std::sort(pr.begin(), pr.end());
+  if (cand)
+    for (int i = 0; i < cnt; ++i) {
+      cand[i] = pr[i].first;
+      cand[cap + i] = pr[i].second;
+    }
   return GS_OK;
 }
 

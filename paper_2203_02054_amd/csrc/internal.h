@@ -254,6 +254,12 @@ template <typename R> hipError_t launch_adj_anderson(const Dev<R>& d, const Cons
 template <typename R> hipError_t launch_fwd_anderson(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_mesh_obstacle(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R>
+hipError_t launch_tree_refit(const Dev<R>& d, const Consts& c, MoNode* nodes, const int32_t* order, double* tbox,
+                             const int* level_start, int levels, hipStream_t s);
+template <typename R>
+hipError_t launch_tree_query(const Dev<R>& d, const Consts& c, const MoNode* nodes, const int32_t* order,
+                             const double* tbox, int32_t* pairs, int cap, int* count, hipStream_t s);
+template <typename R>
 hipError_t launch_remesh_flags(const Dev<R>& d, const Consts& c, const R* x, const R* xref, double amax, double dmax,
                                uint8_t* flags, int* count, hipStream_t s);
 // unrolled adjoint helpers

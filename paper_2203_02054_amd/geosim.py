@@ -109,6 +109,8 @@ SIGNATURES = {
     "gs_collide_debug": (_I, [_P, _P, _I, _P, ctypes.c_size_t, _PI, _PI, _PI, _PI, _PI, _PD, _PI]),
     "gs_collide_debug_static": (_I, [_P, _P, _I, _PI, _PI, _PI, _PI, _PI, _PD, _PI]),
     "gs_trace": (_I, [_P, _I, _PD, _PI]),
+    "gs_tree_candidates_scratch": (ctypes.c_size_t, [_P, _I]),
+    "gs_tree_candidates": (_I, [_P, _P, _I, _P, ctypes.c_size_t, _PI, _PI, _PD, _PD]),
     "gs_remesh_flags": (_I, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _PI]),
     "gs_solve_progressive": (_I, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _I, _P, _I,
                                   ctypes.POINTER(Stage), _PI]),
@@ -500,6 +502,23 @@ class Problem:
                                           int(bool(stop_on_flag)), flags.data_ptr(), cap, stages, ctypes.byref(ns))
         _check(code, (OK, NOT_CONVERGED))
         return x, flags, [stages[i].as_dict() for i in range(ns.value)], code
+
+    def tree_candidates(self, x, cap=None):
+        """C_tet at x from the refit-only tet tree: (pairs [k, 2] sorted by
+        (v, e), refit ms, query ms)."""
+        cap = int(cap or max(4 * self.info["n_query_verts"] * 8, 1024))
+        nb = int(lib().gs_tree_candidates_scratch(self._h, cap))
+        scratch = self.torch.empty(nb + 256, dtype=self.torch.uint8, device=self.device)
+        sp = (scratch.data_ptr() + 255) & ~255
+        out = np.zeros((2, cap), np.int32)
+        cnt = ctypes.c_int32()
+        t1, t2 = ctypes.c_double(), ctypes.c_double()
+        code = lib().gs_tree_candidates(self._h, self._dev(x, (3, self.n)), cap, sp, nb, _ptr(out, ctypes.c_int32),
+                                        ctypes.byref(cnt), ctypes.byref(t1), ctypes.byref(t2))
+        if code == ECAPACITY:
+            return self.tree_candidates(x, cap=2 * max(cap, cnt.value))
+        _check(code)
+        return out[:, :cnt.value].T.copy(), t1.value, t2.value
 
     def collide(self, x, cap=None):
         """One collision check at x with the stored set as the previous one."""
