@@ -24,7 +24,8 @@
 //   sphere/plane  closed-form targets (per vertex, in the gather)
 //   self contact  given a new target this iteration: c = x_v + (t + eps) d,
 //                 d = -n_v/|n_v|, t the Moller-Trumbore distance to the hit
-//                 face (per contact, scattered with double atomics: the few
+//                 face (per contact, scattered as fixed-point integers, so the
+//                 sums do not depend on the order of the atomic adds: the few
 //                 such contacts touch the vertex, its boundary-face ring and
 //                 the hit face's vertices); kept self contacts are constant.
 #include "anderson.h"
@@ -34,7 +35,12 @@ namespace gs {
 
 // z = (tr(S) I - S)^-1 a for symmetric S (cofactor inverse; the matrix is
 // positive definite for a proper polar factor, its eigenvalues being the
-// sums of pairs of singular values).
+// sums of pairs of singular values).  For a reflected element the signed
+// singular values make one eigenvalue sigma_2 - sigma_3, zero when the two
+// smallest singular values are equal: the rotation is then not
+// differentiable, and where |det| falls below a relative 1e-12 (1e-6 in
+// FP32) of tr(S)^3 its derivative is taken as zero (Mbar = 0) rather than
+// dividing by the vanishing determinant.
 template <typename R>
 __device__ __forceinline__ void polar_adjoint(const R (&Rot)[3][3], const R (&M)[3][3], const R (&Rbar)[3][3],
                                               R (&Mbar)[3][3]) {
@@ -58,6 +64,14 @@ __device__ __forceinline__ void polar_adjoint(const R (&Rot)[3][3], const R (&M)
   const R c11 = K[0][0] * K[2][2] - K[0][2] * K[2][0], c12 = K[0][1] * K[2][0] - K[0][0] * K[2][1];
   const R c22 = K[0][0] * K[1][1] - K[0][1] * K[1][0];
   const R det = K[0][0] * c00 + K[0][1] * c01 + K[0][2] * c02;
+  const R guard = (sizeof(R) == 4 ? R(1e-6) : R(1e-12)) * fabs(tr * tr * tr);
+  if (!(fabs(det) > guard)) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Mbar[i][j] = R(0);
+    return;
+  }
   const R id = R(1) / det;
   // K symmetric: its inverse is the symmetric cofactor matrix over det
   const R z0 = (c00 * a[0] + c01 * a[1] + c02 * a[2]) * id;
@@ -328,16 +342,42 @@ __device__ __forceinline__ void sub3(const double* a, const double* b, double* o
   o[1] = a[1] - b[1];
   o[2] = a[2] - b[2];
 }
-__device__ __forceinline__ void add_to(double* acc, size_t n, int v, const double* g, double sgn) {
-  atomicAdd(&acc[v], sgn * g[0]);
-  atomicAdd(&acc[n + v], sgn * g[1]);
-  atomicAdd(&acc[2 * n + v], sgn * g[2]);
+// The scatter of the new self-contact targets' adjoint is deterministic: its
+// contributions are added as 64-bit fixed-point integers (integer addition
+// is associative), on a scale set by the largest contribution magnitude M of
+// the iteration (found by a first pass): scale = 2^(41 - ilogb(M)), so one
+// contribution stays below 2^42 and up to 2^20 of them can meet at a vertex
+// without overflow; the quantum is below 2^-41 M.
+__device__ __forceinline__ double acc_scale(unsigned long long mbits) {
+  const double M = __longlong_as_double((long long)mbits);
+  return M > 0.0 ? ldexp(1.0, 41 - ilogb(M)) : 0.0;
 }
+
+template <int PASS>
+struct AccAdd {
+  unsigned long long* acc;
+  size_t n;
+  double scale;  // PASS 1
+  double mx;     // PASS 0: largest magnitude seen by this thread
+  __device__ __forceinline__ void operator()(int v, const double* g, double sgn) {
+    if (PASS == 0) {
+      mx = fmax(mx, fmax(fabs(g[0]), fmax(fabs(g[1]), fabs(g[2]))));
+      if (!(g[0] == g[0] && g[1] == g[1] && g[2] == g[2])) mx = INFINITY;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        atomicAdd(&acc[k * n + v], (unsigned long long)llrint(sgn * g[k] * scale));
+    }
+  }
+};
+
+__global__ void k_acc_reset(unsigned long long* acc_max) { *acc_max = 0ull; }
 
 // Adjoint of the new self-contact targets (one thread per query vertex with
 // such a contact): the spring adds k c(x) to b_v, so the adjoint input is
-// cbar = k mu_v; the products with dc/dx are scattered into acc3.
-template <typename R>
+// cbar = k mu_v; the products with dc/dx are scattered into acc3 (pass 0:
+// their largest magnitude only; pass 1: the fixed-point sums).
+template <typename R, int PASS>
 __global__ __launch_bounds__(kBlock) void k_adj_springs(Dev<R> d, Consts c) {
   if (is_done(d.st)) return;
   const int s = blockIdx.x * kBlock + threadIdx.x;
@@ -348,6 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_springs(Dev<R> d, Consts c) {
   const int m = d.vmesh[v];
   if (mesh_frozen(d, c.mask_done, m)) return;
   const size_t n = (size_t)c.n;
+  AccAdd<PASS> add_to{reinterpret_cast<unsigned long long*>(d.acc3), n, PASS ? acc_scale(*d.acc_max) : 0.0, 0.0};
   const double eps = d.mesh[m].eps;
   const double k = d.kq[s];
   const double cbar[3] = {k * (double)d.mu[v], k * (double)d.mu[n + v], k * (double)d.mu[2 * n + v]};
@@ -415,10 +456,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_springs(Dev<R> d, Consts c) {
   obar[2] += tvbar[2];
   const double a0bar[3] = {-tvbar[0] - e1bar[0] - e2bar[0], -tvbar[1] - e1bar[1] - e2bar[1],
                            -tvbar[2] - e1bar[2] - e2bar[2]};
-  add_to(d.acc3, n, v, obar, 1.0);
-  add_to(d.acc3, n, h0, a0bar, 1.0);
-  add_to(d.acc3, n, h1, e1bar, 1.0);
-  add_to(d.acc3, n, h2, e2bar, 1.0);
+  add_to(v, obar, 1.0);
+  add_to(h0, a0bar, 1.0);
+  add_to(h1, e1bar, 1.0);
+  add_to(h2, e2bar, 1.0);
   // d = -n / |n|: nbar = -(dbar - (dbar . nh) nh) / |n|
   const double dn = dot3(dbar, nh);
   const double nbar[3] = {-(dbar[0] - dn * nh[0]) / ln, -(dbar[1] - dn * nh[1]) / ln, -(dbar[2] - dn * nh[2]) / ln};
@@ -435,10 +476,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_springs(Dev<R> d, Consts c) {
     cross3(E2, nbar, E1b);
     cross3(nbar, E1, E2b);
     const double sb[3] = {E1b[0] + E2b[0], E1b[1] + E2b[1], E1b[2] + E2b[2]};
-    add_to(d.acc3, n, i1, E1b, 1.0);
-    add_to(d.acc3, n, i2, E2b, 1.0);
-    add_to(d.acc3, n, i0, sb, -1.0);
+    add_to(i1, E1b, 1.0);
+    add_to(i2, E2b, 1.0);
+    add_to(i0, sb, -1.0);
   }
+  if (PASS == 0) atomicMax(d.acc_max, (unsigned long long)__double_as_longlong(add_to.mx));
 }
 
 // Per-tet adjoint columns omega_e ((dT_e/dx_e)^T mu_e - mu_e N) in incidence
@@ -516,12 +558,22 @@ __global__ __launch_bounds__(kBlock) void k_adj_gather(Dev<R> d, Consts c) {
   const size_t n = (size_t)c.n;
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
   sum_columns(reinterpret_cast<const W4<R>*>(d.res4), d.inc_start[v], d.inc_start[v + 1], r0, r1, r2);
-  r0 += d.acc3[v];
-  r1 += d.acc3[n + v];
-  r2 += d.acc3[2 * n + v];
-  d.acc3[v] = 0.0;
-  d.acc3[n + v] = 0.0;
-  d.acc3[2 * n + v] = 0.0;
+  {
+    // fixed-point sums of the self-contact scatter (see acc_scale)
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(d.acc3);
+    const double M = __longlong_as_double((long long)*d.acc_max);
+    if (M > 0.0 && M < INFINITY) {
+      const double inv = 1.0 / acc_scale(*d.acc_max);
+      r0 += (double)(long long)acc[v] * inv;
+      r1 += (double)(long long)acc[n + v] * inv;
+      r2 += (double)(long long)acc[2 * n + v] * inv;
+    } else if (!(M == 0.0)) {
+      r0 = r1 = r2 = NAN;  // a non-finite contribution: the CG reports the breakdown
+    }
+    acc[v] = 0ull;
+    acc[n + v] = 0ull;
+    acc[2 * n + v] = 0ull;
+  }
   double ds = 0.0;
   const bool frozen = mesh_frozen(d, c.mask_done, d.vmesh[v]);
   if (!d.freem[v] || frozen) {
@@ -843,8 +895,10 @@ hipError_t launch_adj_init(const Dev<R>& d, const Consts& c, hipStream_t s) {
 }
 template <typename R>
 hipError_t launch_adj_springs(const Dev<R>& d, const Consts& c, hipStream_t s) {
-  if (!c.self_col || c.S == 0) return hipSuccess;
-  k_adj_springs<R><<<max(1, cdiv(c.S, kBlock)), kBlock, 0, s>>>(d, c);
+  k_acc_reset<<<1, 1, 0, s>>>(d.acc_max);
+  if (!c.self_col || c.S == 0) return hipGetLastError();
+  k_adj_springs<R, 0><<<max(1, cdiv(c.S, kBlock)), kBlock, 0, s>>>(d, c);
+  k_adj_springs<R, 1><<<max(1, cdiv(c.S, kBlock)), kBlock, 0, s>>>(d, c);
   return hipGetLastError();
 }
 template <typename R>

@@ -57,7 +57,7 @@ struct Layout {
   size_t aa_dx, aa_df, aa_xp, aa_fp, aa_h, aa_gamma, aa_part, aa_k;
   size_t lam, ga_acc, st3, st4;
   size_t faa, faa_h, faa_gam, faa_blk, faa_mblk, cact_s, ctgt_s, cnrm_s, cprim_s;
-  size_t rcount, alpha_stage;
+  size_t rcount, alpha_stage, acc_max;
   size_t mo_tri, mo_id, mo_node, mo_flag, mo_tgt, mo_nrm, mo_prim;
   size_t total;
 };
@@ -321,6 +321,7 @@ Layout make_layout(const gs_problem* p) {
   L.mo_nrm = take(p->mo_k ? 3 * S * 8 : 0);
   L.mo_prim = take(p->mo_k ? S * 4 : 0);
   L.rcount = take(4);
+  L.acc_max = take(8);
   L.alpha_stage = take((size_t)p->nch * W);
   L.total = align256(off);
   return L;
@@ -414,6 +415,7 @@ Dev<R> make_dev(const gs_problem* p) {
   d.cprim_s = (int32_t*)(b + L.cprim_s);
   d.dbg_tet = nullptr;
   d.dbg_tri = nullptr;
+  d.acc_max = (unsigned long long*)(b + L.acc_max);
   d.mo_tri = (const double*)(b + L.mo_tri);
   d.mo_id = (const int32_t*)(b + L.mo_id);
   d.mo_node = (const MoNode*)(b + L.mo_node);

@@ -181,7 +181,9 @@ struct Dev {
   // status block and per-mesh done flags in place of st / mdone
   R* mu;                   // [3][n] adjoint iterate
   const R* gL;             // [3][n] dL/dx (caller's buffer)
-  double* acc3;            // [3][n] adjoint of the new self-contact targets, scattered (cleared by the gather)
+  double* acc3;            // [3][n] adjoint of the new self-contact targets, scattered as 64-bit fixed-point
+                           //   integers (cleared by the gather)
+  unsigned long long* acc_max;  // [1] largest scattered magnitude of the iteration (double bits)
   double* ga;              // [T] per-tet contribution to dL/dalpha
   const int32_t* ch_start; // [nch+1] chamber -> tets
   const int32_t* ch_tets;  // chamber tets grouped by chamber, ascending

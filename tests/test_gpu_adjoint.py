@@ -190,3 +190,45 @@ def test_unrolled_adjoint_closed_form(G):
     exact = (2.0 / 3.0) * alpha ** (-1.0 / 3.0) * ((X - xf) ** 2).sum()
     say("unrolled closed form", st, float(ga[0]), exact, "xK err", float((xK.cpu() - __import__("torch").tensor(xs)).abs().max()))
     assert float(ga[0]) == pytest.approx(exact, rel=1e-9)
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_adjoints_are_deterministic(G, precision):
+    """The self-contact scatter adds fixed-point integers, so repeated
+    gradients are bitwise identical (unrolled through new self contacts, and
+    implicit at the converged state)."""
+    w = pressed_finger()
+    prob = oracle.Problem.from_workload(w)
+    g = _seeded_loss_grad(prob, seed=6)
+    with G.Problem.from_workload(w, precision=precision) as gp:
+        outs = []
+        for _ in range(2):
+            gp.reset_contacts()
+            ga, gx0, xK, st = gp.adjoint_unrolled(w.alpha, 30, g)
+            outs.append((ga.cpu().numpy(), gx0.cpu().numpy()))
+        fresh = int(np.sum(gp.contacts()["fresh"]))
+        say("unrolled", precision, "fresh self contacts at the end", fresh)
+        np.testing.assert_array_equal(outs[0][0], outs[1][0])
+        np.testing.assert_array_equal(outs[0][1], outs[1][1])
+        gp.reset_contacts()
+        gp.solve(w.alpha)
+        a1, _ = gp.adjoint(g)
+        a2, _ = gp.adjoint(g)
+        np.testing.assert_array_equal(a1.cpu().numpy(), a2.cpu().numpy())
+
+
+def test_reflected_elements_give_finite_gradients(G):
+    """Every element reflected (x0 mirrored through z = 0) has the signed
+    singular values (1, 1, -1): the polar factor's derivative is undefined
+    there (tr(S) I - S is singular), and the guarded adjoint returns finite
+    gradients instead of dividing by zero."""
+    w = mg.finger(4.0, 3, 2.0, self_collision=False)
+    X = w.rest_xyz
+    x0 = X * np.array([[1.0], [1.0], [-1.0]])
+    rng = np.random.default_rng(7)
+    g = rng.normal(size=X.shape)
+    with G.Problem.from_workload(w, precision=8, pcg_eta=1e-13, pcg_max=5000) as gp:
+        ga, gx0, xK, st = gp.adjoint_unrolled(w.alpha, 1, g, x0=gp.tensor(x0))
+        ga, gx0 = ga.cpu().numpy(), gx0.cpu().numpy()
+        say("reflected start:", st, "dL/dalpha", ga)
+        assert np.all(np.isfinite(ga)) and np.all(np.isfinite(gx0))
