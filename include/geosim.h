@@ -126,6 +126,12 @@ typedef struct {
                              where the map contracts slowly); r is the
                              adjoint's residual in gs_adjoint; the unrolled
                              sweep's solves always stop at pcg_eta               */
+  int32_t pcg_coarse;     /* 1: the global step's CG adds a coarse correction to
+                             its Jacobi preconditioner (one unknown per CG
+                             workgroup's row range, its matrix from A_el; one
+                             mesh, rows-of-three-vectors kernel variant, at
+                             most 256 workgroups); 0 (default): Jacobi alone */
+  int32_t pad_p;
 } gs_params;
 
 /* Safeguards of the accelerated iteration.  Every iteration evaluates the

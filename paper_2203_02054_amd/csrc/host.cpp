@@ -58,6 +58,7 @@ struct Layout {
   size_t lam, ga_acc, st3, st4;
   size_t faa, faa_h, faa_gam, faa_blk, faa_mblk, cact_s, ctgt_s, cnrm_s, cprim_s;
   size_t rcount, alpha_stage, acc_max;
+  size_t cz_inv, cz_nb, cz_rho, cz_ri;
   size_t mo_tri, mo_id, mo_node, mo_flag, mo_tgt, mo_nrm, mo_prim;
   size_t total;
 };
@@ -138,6 +139,9 @@ struct gs_problem {
   std::vector<int32_t> mo_id;
   std::vector<MoNode> mo_node;
   int mo_k = 0;
+  // coarse correction: built for this CG grid (0: none yet), and whether it applies
+  int coarse_G = 0;
+  bool coarse_ok = false;
   // refit-only AABB tree over the tets (built on first use): nodes in
   // breadth-first order, leaf tet order, first node of every depth
   std::vector<MoNode> tree_node;
@@ -214,6 +218,7 @@ gs_status check_params(const gs_params* p) {
   if (!(p->barrier_timeout_ms >= 0) || !std::isfinite(p->barrier_timeout_ms))
     return fail(GS_EINVAL, "barrier_timeout_ms must be >= 0");
   if (!(p->pcg_eta_min >= 0) || !std::isfinite(p->pcg_eta_min)) return fail(GS_EINVAL, "pcg_eta_min must be >= 0");
+  if (p->pcg_coarse != 0 && p->pcg_coarse != 1) return fail(GS_EINVAL, "pcg_coarse must be 0 or 1");
   return GS_OK;
 }
 
@@ -322,6 +327,10 @@ Layout make_layout(const gs_problem* p) {
   L.mo_prim = take(p->mo_k ? S * 4 : 0);
   L.rcount = take(4);
   L.acc_max = take(8);
+  L.cz_inv = take(p->M == 1 ? (size_t)kCoarseMaxG * kCoarseMaxG * 8 : 0);
+  L.cz_nb = take(p->M == 1 ? (size_t)kCoarseMaxG * kCoarseNb * 4 : 0);
+  L.cz_rho = take(p->M == 1 ? 4 * n * W : 0);
+  L.cz_ri = take(p->M == 1 ? n * 4 : 0);
   L.alpha_stage = take((size_t)p->nch * W);
   L.total = align256(off);
   return L;
@@ -416,6 +425,10 @@ Dev<R> make_dev(const gs_problem* p) {
   d.dbg_tet = nullptr;
   d.dbg_tri = nullptr;
   d.acc_max = (unsigned long long*)(b + L.acc_max);
+  d.cz_inv = (const double*)(b + L.cz_inv);
+  d.cz_nb = (const int32_t*)(b + L.cz_nb);
+  d.cz_rho = (const R*)(b + L.cz_rho);
+  d.cz_ri = (const int32_t*)(b + L.cz_ri);
   d.mo_tri = (const double*)(b + L.mo_tri);
   d.mo_id = (const int32_t*)(b + L.mo_id);
   d.mo_node = (const MoNode*)(b + L.mo_node);
@@ -425,6 +438,130 @@ Dev<R> make_dev(const gs_problem* p) {
   d.mo_prim = (int32_t*)(b + L.mo_prim);
   d.dbg_cap = 0;
   return d;
+}
+
+// The coarse correction applies to one-mesh problems whose CG grid runs the
+// rows-of-three-vectors kernel variant on at most kCoarseMaxG workgroups.
+bool coarse_wanted(const gs_problem* p) {
+  const int G = p->pcg_grid;
+  return p->prm.pcg_coarse && p->M == 1 && G >= 2 && G <= kCoarseMaxG && !pcg_paired(p->prec, p->ell_w, p->n, G);
+}
+
+// Two-level preconditioner D^-1 + R0^T A0^-1 R0 of the CG kernel (an
+// additive coarse correction, Nicolaides-style aggregation): R0 sums
+// the free rows of each workgroup's row range (the ranges the kernel uses:
+// 64-aligned chunks of ceil(n / G) rows), A0 = R0 A_el R0^T from the elastic
+// matrix (the springs of the current contact set stay in D only; the
+// preconditioner need not match the matrix, only stay symmetric positive
+// definite and fixed during a solve).  Built on the host in FP64 (Cholesky,
+// then the explicit inverse, which the kernel applies as matrix-vector
+// products); also each workgroup's list of the ranges its rows reach and
+// each row's couplings (its off-diagonal sums per range: its own and at most
+// two others, else the correction is not used).  Rebuilt when the grid
+// changes.
+gs_status ensure_coarse(gs_problem* p) {
+  if (!coarse_wanted(p) || p->coarse_G == p->pcg_grid) return GS_OK;
+  const int G = p->pcg_grid, n = p->n, w = p->ell_w;
+  const int chunk = ((n + G - 1) / G + 63) & ~63;
+  std::vector<double> A0((size_t)G * G, 0.0), rho(4 * (size_t)n, 0.0);
+  std::vector<int32_t> ri(n, 0);
+  std::vector<std::vector<int>> reach(G);
+  for (int b = 0; b < G; ++b) reach[b].push_back(b);
+  bool ok = true;
+  for (int v = 0; v < n; ++v) {
+    const int b = v / chunk;
+    int oth[2] = {b, b};  // the other ranges the row couples to (at most two)
+    ri[v] = b | (b << 16);
+    if (!p->freem[v]) continue;
+    A0[(size_t)b * G + b] += p->adiag[v];
+    for (int k = 0; k < w; ++k) {
+      const int j = p->ell_col[(size_t)k * n + v];
+      const double a = p->ell_val[(size_t)k * n + v];
+      if (a == 0.0) continue;  // padding
+      const int bj = j / chunk;
+      A0[(size_t)b * G + bj] += a;
+      if (bj == b) {
+        rho[4 * (size_t)v] += a;
+        continue;
+      }
+      int slot = bj == oth[0] && oth[0] != b ? 0 : (bj == oth[1] && oth[1] != b ? 1 : -1);
+      if (slot < 0) {
+        if (oth[0] == b) slot = 0;
+        else if (oth[1] == b) slot = 1;
+        else {
+          ok = false;  // a third other range: the per-row record cannot hold it
+          continue;
+        }
+        oth[slot] = bj;
+      }
+      rho[4 * (size_t)v + 1 + slot] += a;
+      if (std::find(reach[b].begin(), reach[b].end(), bj) == reach[b].end()) reach[b].push_back(bj);
+    }
+    ri[v] = oth[0] | (oth[1] << 16);
+  }
+  for (int b = 0; b < G; ++b) {
+    if ((int)reach[b].size() > kCoarseNb) ok = false;
+    if (A0[(size_t)b * G + b] == 0.0) A0[(size_t)b * G + b] = 1.0;  // a range of fixed rows only
+  }
+  // Cholesky A0 = L L^T, then A0^-1 column by column
+  std::vector<double> L(A0);
+  for (int j = 0; j < G && ok; ++j) {
+    double d = L[(size_t)j * G + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * G + k] * L[(size_t)j * G + k];
+    if (!(d > 0.0)) {
+      ok = false;
+      break;
+    }
+    d = std::sqrt(d);
+    L[(size_t)j * G + j] = d;
+    for (int i = j + 1; i < G; ++i) {
+      double t = L[(size_t)i * G + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * G + k] * L[(size_t)j * G + k];
+      L[(size_t)i * G + j] = t / d;
+    }
+  }
+  std::vector<double> inv((size_t)G * G, 0.0);
+  if (ok) {
+    std::vector<double> y(G);
+    for (int c = 0; c < G; ++c) {
+      for (int i = 0; i < G; ++i) {
+        double t = (i == c) ? 1.0 : 0.0;
+        for (int k = 0; k < i; ++k) t -= L[(size_t)i * G + k] * y[k];
+        y[i] = t / L[(size_t)i * G + i];
+      }
+      for (int i = G - 1; i >= 0; --i) {
+        double t = y[i];
+        for (int k = i + 1; k < G; ++k) t -= L[(size_t)k * G + i] * inv[(size_t)k * G + c];
+        inv[(size_t)i * G + c] = t / L[(size_t)i * G + i];
+      }
+    }
+    // exactly symmetric, so every workgroup applies the same operator
+    for (int i = 0; i < G; ++i)
+      for (int j = i + 1; j < G; ++j) {
+        const double m = 0.5 * (inv[(size_t)i * G + j] + inv[(size_t)j * G + i]);
+        inv[(size_t)i * G + j] = inv[(size_t)j * G + i] = m;
+      }
+  }
+  p->coarse_G = G;
+  p->coarse_ok = ok;
+  if (!ok) return GS_OK;
+  std::vector<int32_t> nb((size_t)G * kCoarseNb, -1);
+  for (int b = 0; b < G; ++b)
+    for (size_t i = 0; i < reach[b].size(); ++i) nb[(size_t)b * kCoarseNb + i] = reach[b][i];
+  hipStream_t s = p->stream;
+  char* base = p->ws;
+  HIPCHK(hipMemcpyAsync(base + p->lay.cz_inv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + p->lay.cz_nb, nb.data(), nb.size() * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + p->lay.cz_ri, ri.data(), ri.size() * 4, hipMemcpyHostToDevice, s));
+  if (p->prec == 4) {
+    std::vector<float> r(rho.begin(), rho.end());
+    HIPCHK(hipMemcpyAsync(base + p->lay.cz_rho, r.data(), r.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  } else {
+    HIPCHK(hipMemcpyAsync(base + p->lay.cz_rho, rho.data(), rho.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return GS_OK;
 }
 
 Consts make_consts(const gs_problem* p) {
@@ -441,6 +578,7 @@ Consts make_consts(const gs_problem* p) {
   c.self_col = p->prm.self_collision ? 1 : 0;
   c.obst_col = (p->prm.obstacle_collision && (p->ns + p->np) > 0) ? 1 : 0;
   c.mo = (p->prm.obstacle_collision && p->mo_k > 0) ? 1 : 0;
+  c.coarse = (coarse_wanted(p) && p->coarse_G == p->pcg_grid && p->coarse_ok) ? 1 : 0;
   c.hyper = p->prm.hyperelastic ? 1 : 0;
   c.max_iter = p->prm.max_iter;
   c.fixed_iters = p->prm.fixed_iters;
@@ -679,6 +817,10 @@ const char* kStalledMsg =
 
 template <typename R>
 gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
+  {
+    const gs_status r = ensure_coarse(p);
+    if (r != GS_OK) return r;
+  }
   const Dev<R> d = make_dev<R>(p);
   const Consts c = make_consts(p);
   hipStream_t s = p->stream;
@@ -1394,6 +1536,8 @@ void gs_default_params(gs_params* p) {
   p->aa_slack = 0.5;
   p->barrier_timeout_ms = 2000.0;
   p->pcg_eta_min = 0.0;
+  p->pcg_coarse = 0;
+  p->pad_p = 0;
 }
 
 gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** out) {
@@ -1889,6 +2033,7 @@ gs_status gs_bind(gs_problem* p, void* ws, size_t bytes, void* stream) {
   p->stream = (hipStream_t)stream;
   p->bound = false;
   p->solved = false;
+  p->coarse_G = 0;  // the coarse operator lives in the workspace
   if (!p->hstat) {
     void* h = nullptr;
     if (hipHostMalloc(&h, 2 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)

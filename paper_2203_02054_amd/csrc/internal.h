@@ -23,6 +23,8 @@ constexpr int kAaMaxMem = 16;         // Anderson memory at most (forward and ad
 constexpr int kFaaRows = 1024;        // rows per block of the acceleration's dot-product kernel
 constexpr int kStaticCandCap = 1 << 17;  // candidate pairs per list of the allocation-free collision check
 constexpr int kMaxDevices = 64;
+constexpr int kCoarseNb = 8;          // coarse unknowns a CG workgroup's rows reach (its own first)
+constexpr int kCoarseMaxG = 256;      // CG workgroups at most with the coarse correction
 
 // Completion codes kept on the device (DevStatus::done).
 // STALLED: a grid barrier of the CG kernel gave up waiting (see grid_barrier).
@@ -101,6 +103,7 @@ struct Consts {
   int mask_done;        // freeze meshes once they converge (not with fixed_iters)
   int self_col, obst_col, hyper;
   int mo;               // the triangle-mesh obstacle is on (its slot is the last one)
+  int coarse;           // the CG preconditioner has the coarse correction (built for this grid)
   int max_iter, fixed_iters, pcg_max;
   int nparts;           // partial-sum slots per reduction array
   int ell_w;            // off-diagonal entries per row of the ELL matrix (16, 32 or 64)
@@ -213,6 +216,15 @@ struct Dev {
   // unrolled reverse sweep
   R* lam;                  // [3][n] adjoint of the positions
   double* ga_acc;          // [nch] dL/dalpha accumulated over the reverse steps
+  // coarse correction of the CG preconditioner (one unknown per workgroup's
+  // row range): the inverse of R0 A_el R0^T [G][G], the coarse unknowns each
+  // workgroup's rows reach [G][kCoarseNb] (own first, -1 padded), and per
+  // row its couplings (x: off-diagonal sum over its own range; y, z: sums
+  // over the other ranges cz_ri names, low and high 16 bits)
+  const double* cz_inv;
+  const int32_t* cz_nb;
+  const R* cz_rho;         // [n][4]
+  const int32_t* cz_ri;
   // triangle-mesh obstacle (static tree; per-query-vertex results of its kernel)
   const double* mo_tri;    // [k][30] leaf-ordered triangles: a, b, c, face, edge (ab, ac, bc) and vertex
                            //   (a, b, c) pseudonormals

@@ -575,13 +575,20 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
 template <typename R> struct Chunk { static constexpr int n = 16; };
 template <> struct Chunk<double> { static constexpr int n = 4; };
 
-template <typename R, int MW, bool ADJ, bool PAIR>
+template <typename R, int MW, bool ADJ, bool PAIR, bool CZ>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   static_assert(!PAIR || (std::is_same<R, float>::value && MW == 16), "paired lanes: FP32, ELL width 16");
   constexpr int CH = Chunk<R>::n;
   __shared__ double lds[kPcgBlock / 64];
-  __shared__ double lds2[10][kPcgBlock / 64];
+  __shared__ double lds2[12][kPcgBlock / 64];
   __shared__ double sh[16];
+  // coarse correction (unpaired kernels): the coarse residual c = R0 r of
+  // every row range, and the coarse solution y = A0^-1 c of the ranges this
+  // workgroup's rows reach, in two buffers (iteration i's and i+1's)
+  static_assert(!(PAIR && CZ), "the coarse correction runs in the unpaired kernels");
+  constexpr int CZG = CZ ? kCoarseMaxG : 1;
+  __shared__ double cz_c[3][CZG];
+  __shared__ double cz_y[2][3][CZG];
   if (is_done(d.st)) return;
   const int G = gridDim.x;
   const int stride = G * kPcgBlock;
@@ -605,6 +612,69 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // the rows spread over all G blocks however many rows a thread gets
   const int chunk = ((c.n + G - 1) / G + 63) & ~63;
   const int row0 = min(c.n, (int)blockIdx.x * chunk), row1 = min(c.n, row0 + chunk);
+  // coarse correction: u = D^-1 r + R0^T y, y = A0^-1 R0 r, with R0 summing
+  // the free rows of each workgroup's range.  Every workgroup holds the whole
+  // coarse residual (thread t that of range t) and forms y for the ranges its
+  // rows reach, one wavefront per range, in the same order in every
+  // workgroup (so a row's u is the same wherever it is formed).
+  constexpr bool cz = CZ;
+  R czq[9];  // coarse: this thread's sums of r, w and s over its free rows
+#pragma unroll
+  for (int i = 0; i < 9; ++i) czq[i] = R(0);
+  auto coarse_solve = [&](int buf) {
+    if constexpr (CZ) {
+      const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+      if (wv < kCoarseNb) {
+        const int bb = d.cz_nb[blockIdx.x * kCoarseNb + wv];
+        if (bb >= 0) {
+          const double* Ar = d.cz_inv + (size_t)bb * G;
+          double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+          for (int k = l; k < G; k += 64) {
+            const double a = Ar[k];
+            t0 += a * cz_c[0][k];
+            t1 += a * cz_c[1][k];
+            t2 += a * cz_c[2][k];
+          }
+          t0 = wave_sum(t0);
+          t1 = wave_sum(t1);
+          t2 = wave_sum(t2);
+          if (l == 0) {
+            cz_y[buf][0][bb] = t0;
+            cz_y[buf][1][bb] = t1;
+            cz_y[buf][2][bb] = t2;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  };
+  // block sums of gamma, delta and the range's sums of r, w and s (free rows)
+  // in one LDS round, stored write-through by threads 0-10 (the order of
+  // block_sum2_store): the next iteration forms the coarse residual
+  // R0 r_{i+1} = R0 r_i - alpha (R0 w_i + beta R0 s_{i-1}) from these exact
+  // sums, so it never drifts from the stored residual by more than one
+  // step's rounding
+  auto store11 = [&](double ag, double ad, double* og, double* od, double* oq) {
+    double q[11];
+    q[0] = ag;
+    q[1] = ad;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) q[2 + i] = (double)czq[i];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 11; ++i) {
+      const double t = wave_sum(q[i]);
+      if (lane == 0) lds2[i][wv] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 11) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < kPcgBlock / 64; ++i) t += lds2[threadIdx.x][i];
+      double* dst = threadIdx.x == 0 ? og : (threadIdx.x == 1 ? od : oq + (size_t)(threadIdx.x - 2) * G);
+      st_wt(dst, t);
+    }
+  };
   if (PAIR && 2 * chunk > kPcgBlock) {
     // launched for a grid with more rows per block than lane pairs (the host
     // chooses the variant from the same formula): refuse, uniformly
@@ -686,6 +756,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     W4<R>* __restrict__ xp = reinterpret_cast<W4<R>*>(d.dlp);
     W4<R>* __restrict__ xpp = reinterpret_cast<W4<R>*>(d.dlpp);
     double tq[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // e1 e2 e3 h11 h12 h13 h22 h23 h33
+    double czb[12] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     // unpaired kernels: 8 neighbour slots per gather round (the CG loop sets
     // their registers); the paired kernel's lanes take 8 slots each
     constexpr int CH1 = CH < 8 ? CH : 8;
@@ -805,6 +876,13 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         }
         const W4<R> b = cg0[v * vs];
         acc_b += ((double)b.x * (double)(b.x * idg) + (double)b.y * (double)(b.y * idg)) + (double)b.z * (double)(b.z * idg);
+        if constexpr (cz) if (d.freem[v]) {
+          // range sums of b, A w1, A w2, A w3: the coarse residual of the start
+          czb[0] += b.x, czb[1] += b.y, czb[2] += b.z;
+          czb[3] += a10, czb[4] += a11, czb[5] += a12;
+          czb[6] += a20, czb[7] += a21, czb[8] += a22;
+          czb[9] += a30, czb[10] += a31, czb[11] += a32;
+        }
         const double t[9] = {((double)w1.x * b.x + (double)w1.y * b.y) + (double)w1.z * b.z,
                              ((double)w2.x * b.x + (double)w2.y * b.y) + (double)w2.z * b.z,
                              ((double)w3.x * b.x + (double)w3.y * b.y) + (double)w3.z * b.z,
@@ -845,6 +923,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       const double q[10] = {tq[0], tq[1], tq[2], tq[3], tq[4], tq[5], tq[6], tq[7], tq[8], acc_b};
       block_sums_store<10>(q, lds2, d.part_c + 2 * G + blockIdx.x, G);
       if (!PAIR && threadIdx.x == 9) d.part_d[blockIdx.x] = d.part_c[11 * G + blockIdx.x];
+      if constexpr (cz) {
+        __syncthreads();  // lds2 is read above before it is written again
+        block_sums_store<12>(czb, lds2, d.part_f + 18 * G + blockIdx.x, G);
+      }
       if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
       double S[10];
       if constexpr (PAIR) {
@@ -861,6 +943,17 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       }
       // every block takes the same decision from the same sums
       galerkin_weights3(S[0], S[1], S[2], S[3], S[4], S[5], S[6], S[7], S[8], g1, g2, g3);
+      if constexpr (cz) {
+        // c_0 = R0 (b - g1 A w1 - g2 A w2 - g3 A w3), every range's by its thread
+        for (int t = threadIdx.x; t < G; t += kPcgBlock)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const double* P = d.part_f + 18 * G + t;
+            cz_c[k][t] = ((P[k * G] - g1 * P[(3 + k) * G]) - g2 * P[(6 + k) * G]) - g3 * P[(9 + k) * G];
+          }
+        __syncthreads();
+        coarse_solve(0);
+      }
     } else {
       const double bs = block_sum<kPcgBlock>(acc_b, lds);
       if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
@@ -978,6 +1071,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
             jj[k] = ecol[(size_t)(k0 + k) * n + v];
             aa[k] = evl[(size_t)(k0 + k) * n + v];
           }
+
           W4<R> nb[CH2], n1[CH2], n2[CH2], n3[CH2];
   #pragma unroll
           for (int k = 0; k < CH2; ++k) {
@@ -1007,19 +1101,43 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         st_state(x + row0, vi,
               w4<R>(r1 * w1.x + r2 * w2.x + r3 * w3.x, r1 * w1.y + r2 * w2.y + r3 * w3.y,
                     r1 * w1.z + r2 * w2.z + r3 * w3.z));
+        R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
+        if constexpr (cz) {
+          // w_0 = A u_0 with u_0 = D^-1 r_0 + R0^T y_0: the row's own range
+          // (its diagonal and its neighbours there) and the other ranges
+          const R fr = d.freem[v] ? R(1) : R(0);
+          const W4<R> q = reinterpret_cast<const W4<R>*>(d.cz_rho)[v];
+          const int i1 = d.cz_ri[v] & 0xffff, i2 = d.cz_ri[v] >> 16;
+          const R cf = dg[v] * fr + q.x;
+          const R y0 = (R)cz_y[0][0][blockIdx.x], y1 = (R)cz_y[0][1][blockIdx.x], y2 = (R)cz_y[0][2][blockIdx.x];
+          a0 += (cf * y0 + q.y * (R)cz_y[0][0][i1]) + q.z * (R)cz_y[0][0][i2];
+          a1 += (cf * y1 + q.y * (R)cz_y[0][1][i1]) + q.z * (R)cz_y[0][1][i2];
+          a2 += (cf * y2 + q.y * (R)cz_y[0][2][i1]) + q.z * (R)cz_y[0][2][i2];
+          u0 += fr * y0;
+          u1 += fr * y1;
+          u2 += fr * y2;
+          czq[0] += fr * rv.x;
+          czq[1] += fr * rv.y;
+          czq[2] += fr * rv.z;
+          czq[3] += fr * a0;
+          czq[4] += fr * a1;
+          czq[5] += fr * a2;  // s_{-1} = 0: czq[6..8] stay 0
+        }
         st_state(xpp + row0, vi, wp);
         st_state(xp + row0, vi, w1);
         st_state(ns + row0 * vs, (unsigned)(vi * vs), rv);
         st_state(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
         st_state(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), w4<R>(R(0), R(0), R(0)));
-        const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
         acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
         acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
       }
     }
     cur = 1;
   }
-  block_sum2_store(acc_g, acc_d, lds2, d.part_c + blockIdx.x, d.part_e + blockIdx.x);
+  if constexpr (cz)
+    store11(acc_g, acc_d, d.part_c + blockIdx.x, d.part_e + blockIdx.x, d.part_f + blockIdx.x);
+  else
+    block_sum2_store(acc_g, acc_d, lds2, d.part_c + blockIdx.x, d.part_e + blockIdx.x);
   if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
   // PAIR: the lane pair's first neighbour gather, issued before the grid
   // sums so the round trips overlap
@@ -1067,8 +1185,28 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // (false: the barrier gave up, and the kernel must end at once)
   auto publish = [&](double ag, double ad) -> bool {
     const int half = (it & 1) ? 0 : G;
-    block_sum2_store(ag, ad, lds2, d.part_c + half + blockIdx.x, d.part_e + half + blockIdx.x);
+    if constexpr (cz)
+      store11(ag, ad, d.part_c + half + blockIdx.x, d.part_e + half + blockIdx.x,
+              d.part_f + ((it & 1) ? 0 : 9 * G) + blockIdx.x);
+    else
+      block_sum2_store(ag, ad, lds2, d.part_c + half + blockIdx.x, d.part_e + half + blockIdx.x);
     return grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout);
+  };
+  // coarse: at the top of iteration i, c_{i+1} = R0 r_i - alpha (R0 w_i +
+  // beta R0 s_{i-1}) for every range (thread t: range t) from the sums
+  // published with the last barrier (the start-up's at offset 0, iteration
+  // i-1's at its half), then y_{i+1} into the other buffer
+  int ycur = 0;
+  auto coarse_advance = [&]() {
+    const int src = it == 0 ? 0 : (((it - 1) & 1) ? 0 : 9 * G);
+    for (int t = threadIdx.x; t < G; t += kPcgBlock) {
+      const double* P = d.part_f + src + t;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        cz_c[k][t] = P[(size_t)k * G] - al * (P[(size_t)(3 + k) * G] + be * P[(size_t)(6 + k) * G]);
+    }
+    __syncthreads();
+    coarse_solve(ycur ^ 1);
   };
   // advance: the grid sums of the published partials and the next step
   // lengths; false ends the solve
@@ -1164,12 +1302,28 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     const R ra = (R)al, rb = (R)be;
     acc_g = 0.0;
     acc_d = 0.0;
+    R yc0 = R(0), yc1 = R(0), yc2 = R(0), yn0 = R(0), yn1 = R(0), yn2 = R(0);
+    if constexpr (cz) {
+      coarse_advance();
+#pragma unroll
+      for (int i = 0; i < 9; ++i) czq[i] = R(0);
+      yc0 = (R)cz_y[ycur][0][blockIdx.x];
+      yc1 = (R)cz_y[ycur][1][blockIdx.x];
+      yc2 = (R)cz_y[ycur][2][blockIdx.x];
+      yn0 = (R)cz_y[ycur ^ 1][0][blockIdx.x];
+      yn1 = (R)cz_y[ycur ^ 1][1][blockIdx.x];
+      yn2 = (R)cz_y[ycur ^ 1][2][blockIdx.x];
+    }
     for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
       const R idg = R(1) / dg[v];
       const W4<R> rc = cs[v * vs], wc = cs[qs + v * vs], sc = cs[2 * qs + v * vs];
       const W4<R> pv0 = p[v];  // at i = 0 b_0 = 0: p_{-1} enters as 0 * (finite start-up data)
       const W4<R> xv = x[v];
-      const W4<R> pv = w4<R>(rc.x * idg + rb * pv0.x, rc.y * idg + rb * pv0.y, rc.z * idg + rb * pv0.z);
+      // u_i = D^-1 r_i (+ R0^T y_i with the coarse correction)
+      const R fr = (cz && d.freem[v]) ? R(1) : R(0);
+      const W4<R> pv = cz ? w4<R>((rc.x * idg + fr * yc0) + rb * pv0.x, (rc.y * idg + fr * yc1) + rb * pv0.y,
+                                  (rc.z * idg + fr * yc2) + rb * pv0.z)
+                          : w4<R>(rc.x * idg + rb * pv0.x, rc.y * idg + rb * pv0.y, rc.z * idg + rb * pv0.z);
       const W4<R> sv = w4<R>(wc.x + rb * sc.x, wc.y + rb * sc.y, wc.z + rb * sc.z);
       const W4<R> rv = w4<R>(rc.x - ra * sv.x, rc.y - ra * sv.y, rc.z - ra * sv.z);
       const unsigned vi = (unsigned)(v - row0);
@@ -1185,6 +1339,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           jj[k] = ecol[(size_t)(k0 + k) * n + v];
           aa[k] = evs[(size_t)(k0 + k) * n + v];
         }
+
         W4<R> nr[CH], nw[CH], nsv[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
@@ -1199,13 +1354,37 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           a2 += aa[k] * (nr[k].z - ra * (nw[k].z + rb * nsv[k].z));
         }
       }
+      R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
+      if constexpr (cz) {
+        // w_{i+1} = A u_{i+1}: A R0^T y_{i+1} from the row's couplings to its
+        // own range (with the diagonal) and to at most two others
+        const W4<R> q = reinterpret_cast<const W4<R>*>(d.cz_rho)[v];
+        const int i1 = d.cz_ri[v] & 0xffff, i2 = d.cz_ri[v] >> 16;
+        const R cf = dg[v] * fr + q.x;
+        const int nb = ycur ^ 1;
+        a0 += (cf * yn0 + q.y * (R)cz_y[nb][0][i1]) + q.z * (R)cz_y[nb][0][i2];
+        a1 += (cf * yn1 + q.y * (R)cz_y[nb][1][i1]) + q.z * (R)cz_y[nb][1][i2];
+        a2 += (cf * yn2 + q.y * (R)cz_y[nb][2][i1]) + q.z * (R)cz_y[nb][2][i2];
+        u0 += fr * yn0;
+        u1 += fr * yn1;
+        u2 += fr * yn2;
+        czq[0] += fr * rv.x;
+        czq[1] += fr * rv.y;
+        czq[2] += fr * rv.z;
+        czq[3] += fr * a0;
+        czq[4] += fr * a1;
+        czq[5] += fr * a2;
+        czq[6] += fr * sv.x;
+        czq[7] += fr * sv.y;
+        czq[8] += fr * sv.z;
+      }
       st_state(ns + row0 * vs, (unsigned)(vi * vs), rv);
       st_state(ns + qs + row0 * vs, (unsigned)(vi * vs), w4<R>(a0, a1, a2));
       st_state(ns + 2 * qs + row0 * vs, (unsigned)(vi * vs), sv);
-      const R u0 = rv.x * idg, u1 = rv.y * idg, u2 = rv.z * idg;
       acc_g += ((double)rv.x * u0 + (double)rv.y * u1) + (double)rv.z * u2;
       acc_d += ((double)a0 * u0 + (double)a1 * u1) + (double)a2 * u2;
     }
+    ycur ^= 1;
     if (!next_step(acc_g, acc_d)) break;
   }
   if (stalled) return;
@@ -1248,17 +1427,30 @@ hipError_t launch_output(const Dev<R>& d, const Consts& c, R* xout, hipStream_t 
 
 
 // The CG kernel for a matrix of ELL width ell_w; pair selects the
-// paired-lane variant (FP32, width 16 only).
+// paired-lane variant (FP32, width 16 only), cz the unpaired variant with the
+// coarse correction.
 template <typename R>
-const void* pcg_kernel(int ell_w, bool adjoint, bool pair) {
+const void* pcg_kernel(int ell_w, bool adjoint, bool pair, bool cz) {
   if constexpr (std::is_same<R, float>::value) {
-    if (pair && ell_w <= 16) return adjoint ? (const void*)k_pcg<R, 16, true, true> : (const void*)k_pcg<R, 16, false, true>;
+    if (pair && ell_w <= 16)
+      return adjoint ? (const void*)k_pcg<R, 16, true, true, false> : (const void*)k_pcg<R, 16, false, true, false>;
+  }
+  if (cz) {
+    if (adjoint)
+      return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, true>
+                         : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false, true>
+                                       : (const void*)k_pcg<R, 64, true, false, true>;
+    return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false, true>
+                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false, true>
+                                     : (const void*)k_pcg<R, 64, false, false, true>;
   }
   if (adjoint)
-    return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false>
-                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false> : (const void*)k_pcg<R, 64, true, false>;
-  return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false>
-                     : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false> : (const void*)k_pcg<R, 64, false, false>;
+    return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, false>
+                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false, false>
+                                     : (const void*)k_pcg<R, 64, true, false, false>;
+  return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false, false>
+                     : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false, false>
+                                   : (const void*)k_pcg<R, 64, false, false, false>;
 }
 
 template <typename R>
@@ -1269,7 +1461,7 @@ hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s,
   // the adjoint kernels wrote the right-hand side in the layout of the grid
   // the constants were made for
   if (adjoint && c.cg_soa != (pair ? 1 : 0)) return hipErrorInvalidValue;
-  const void* f = pcg_kernel<R>(c.ell_w, adjoint, pair);
+  const void* f = pcg_kernel<R>(c.ell_w, adjoint, pair, c.coarse && !pair);
   if (cooperative) return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
   if (ev_start || ev_stop)  // the events take the kernel's own start and end times
     return hipExtLaunchKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s, ev_start, ev_stop, 0);
@@ -1278,15 +1470,16 @@ hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s,
 
 
 // Workgroups of the CG kernel that can be resident at once for a matrix of
-// ELL width ell_w: the smallest occupancy of its variants times the compute
+// ELL width ell_w: the smallest occupancy of its variants (forward and
+// adjoint; unpaired, paired and with the coarse correction) times the compute
 // units (0 on a runtime error).
 template <typename R>
 int pcg_max_grid(int ell_w) {
   int occ = 1 << 30, dev = 0, cus = 0;
-  for (int v = 0; v < 4; ++v) {
+  for (int v = 0; v < 6; ++v) {
     int o = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, pcg_kernel<R>(ell_w, v & 1, v >> 1), kPcgBlock, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, pcg_kernel<R>(ell_w, v & 1, (v >> 1) == 1, (v >> 1) == 2),
+                                                     kPcgBlock, 0) != hipSuccess)
       return 0;
     occ = std::min(occ, o);
   }

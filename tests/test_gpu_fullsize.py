@@ -105,12 +105,15 @@ def test_gripper_collision_sampled(G, gripper_state):
                 assert len(r) == 1 and r[0, 2] == f
 
 
-def test_gripper_global_step_fp64(G, gripper_state):
+@pytest.mark.parametrize("coarse", [0, 1])
+def test_gripper_global_step_fp64(G, gripper_state, coarse):
     """One FP64 iteration from the FP32 state with the GPU's contacts, against
     the oracle's local step plus sparse direct global step with the contact
-    set the GPU found in that iteration."""
+    set the GPU found in that iteration; with and without the CG's coarse
+    correction (on 128 workgroups)."""
     w, prob, _, x = gripper_state
-    gp = G.Problem.from_workload(w, precision=8, fixed_iters=1, pcg_eta=1e-13, pcg_max=20000)
+    kw = dict(pcg_coarse=1, pcg_blocks=128) if coarse else {}
+    gp = G.Problem.from_workload(w, precision=8, fixed_iters=1, pcg_eta=1e-13, pcg_max=20000, **kw)
     x0 = x.double().contiguous()
     x1, st = gp.solve(w.alpha, x0.clone())
     # the solve holds fixed vertices at their rest positions (not at their
