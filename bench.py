@@ -15,6 +15,9 @@ without per-kernel events.  One more solve is run with per-kernel events for
 the kernel table and the roofline of the dominant kernel (the CG kernel).
 
 Extra legs (same JSON line):
+  coarse   the headline workload's first 200 outer iterations with the
+           Jacobi and with the coarse-corrected CG (fixed count).
+  membrane the four-chamber membrane rig solved to 1e-6.
   adjoint  gs_adjoint at the converged gripper for the fingertip loss (30
            tip vertices to seeded targets, gradient w.r.t. the 24 chamber
            ratios): gradients per second, and the speedup over a
@@ -46,7 +49,7 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a 256 MiB copy) on
 # the build the counters were taken with, keyed by workload; an entry is
 # removed when its kernel changes.
-PMC_TRAFFIC = {}
+PMC_TRAFFIC = {"gripper": 7178245661}  # profiles/gripper_pcg_hbm_traffic.md
 
 
 def pcg_bytes_per_iteration(info, W):
@@ -276,6 +279,42 @@ def run_adjoint(G, mg, wl, gp, x, alpha, t_solve_ms, reps=3):
             "kernels": {k: v for k, v in kernel_table(prof).items() if k.startswith("adj_")}}
 
 
+def run_coarse(G, wl, grid, iters):
+    """The first `iters` outer iterations of the workload from rest on the
+    headline's CG grid, with the Jacobi and with the coarse-corrected CG
+    preconditioner (same solver settings otherwise): CG iterations and
+    tet-iterations/s.  A fixed iteration count, not a converged solve (see the
+    design notes on the gripper's path-fragile convergence)."""
+    res = {"outer_iterations": iters, "pcg_grid": grid}
+    for cz in (0, 1):
+        with G.Problem.from_workload(wl, precision=wl.precision, pcg_blocks=grid, fixed_iters=iters,
+                                     pcg_coarse=cz) as p:
+            xa, aa = p.tensor(wl.rest_xyz), p.tensor(wl.alpha)
+            p.solve(aa, xa.clone())
+            p.reset_contacts()
+            ms, (_, st) = timed_on(p.stream, lambda: p.solve(aa, xa.clone()))
+        key = "coarse" if cz else "jacobi"
+        res[key] = {"ms": round(ms, 3), "pcg_iters": st["pcg_iters_total"],
+                    "value": round(wl.n_tets * st["iters"] / (ms / 1e3), 1), "unit": "tet-iterations/s",
+                    "residual": st["residual"]}
+    res["speedup"] = round(res["jacobi"]["ms"] / res["coarse"]["ms"], 3)
+    return res
+
+
+def run_membrane(G, mg):
+    """The membrane rig (40,446 tets: four chamber units under a sheet) solved
+    from rest to 1e-6: tet-iterations/s, as the headline."""
+    wl = mg.make("membrane")
+    with G.Problem.from_workload(wl, precision=wl.precision) as p:
+        xa, aa = p.tensor(wl.rest_xyz), p.tensor(wl.alpha)
+        p.solve(aa, xa.clone())
+        p.reset_contacts()
+        ms, (_, st) = timed_on(p.stream, lambda: p.solve(aa, xa.clone()))
+    return {"tets": wl.n_tets, "ms": round(ms, 3), "iters": st["iters"], "pcg_iters": st["pcg_iters_total"],
+            "converged": st["status"] == G.OK, "residual": st["residual"], "contacts": st["n_contacts"],
+            "value": round(wl.n_tets * st["iters"] / (ms / 1e3), 1), "unit": "tet-iterations/s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,6 +327,8 @@ def main():
     ap.add_argument("--batched-max-iter", type=int, default=1000)
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="skip the coarse-correction and membrane legs")
+    ap.add_argument("--coarse-iters", type=int, default=200)
     ap.add_argument("--adjoint-max-iter", type=int, default=600)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default CG grid (counter runs)")
     ap.add_argument("--pcg-blocks", type=int, default=0, help="CG grid for the headline solve (no autotune)")
@@ -415,6 +456,11 @@ def main():
             fp.reset_contacts()
             ms_f, (xf, _) = timed_on(fp.stream, lambda: fp.solve(fa, fx.clone()))
             out["adjoint_finger"] = run_adjoint(G, mg, fw, fp, xf, fa, ms_f)
+    if not a.no_legs and a.workload == "gripper":
+        print("# coarse correction, fixed iterations", file=sys.stderr, flush=True)
+        out["coarse"] = run_coarse(G, wl, grid, a.coarse_iters)
+        print("# membrane", file=sys.stderr, flush=True)
+        out["membrane"] = run_membrane(G, mg)
     if not a.no_batched:
         out["batched"] = run_batched(G, mg, a.batched_meshes, a.batched_max_iter, a.plain_sample,
                                      autotune=not a.no_autotune)
