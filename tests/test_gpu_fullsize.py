@@ -139,19 +139,32 @@ def test_gripper_global_step_fp64(G, gripper_state, coarse):
 
 
 def test_batch_sampled_meshes_are_oracle_fixed_points(G):
+    """The 256-mesh batch (5.56M tets, accelerated): 16 of the meshes that
+    converged within the cap, spread over the size range (every 1/16 quantile
+    of their tet counts), are fixed points of the oracle's map to the
+    tolerance scale with their own contact sets: one oracle step from the GPU
+    result moves it by at most 2e-6 of the diagonal and keeps the set.  How
+    far such a point lies from the exact fixed point depends on the mesh's
+    condition: for the smallest converged mesh (4,752 tets, a 6.4e-7 step)
+    the oracle's frozen-set iteration lands 2.9e-4 of the diagonal away
+    (measured), so the distance is not asserted here.  The meshes that did
+    not converge are counted (active-set cycles, see the design notes)."""
     wls = mg.batched(256)
     gb = G.Problem.batch(wls, precision=4, self_collision=1, max_iter=1000)
     alpha = np.concatenate([w.alpha for w in wls])
     xg, st = gb.solve(alpha)
     its = gb.mesh_iters()
-    say("batch", sum(w.n_tets for w in wls), "tets:", st, "converged", int((its > 0).sum()))
+    conv = np.nonzero(its > 0)[0]
+    say("batch", sum(w.n_tets for w in wls), "tets:", st, "converged", conv.size, "not converged",
+        int((its == 0).sum()))
     lay = gb.layout()
     cg = gb.contacts()
     xg = xg.cpu().numpy().astype(np.float64)
-    conv = np.nonzero(its > 0)[0]
     Ts = np.array([wls[m].n_tets for m in conv])
-    picks = [conv[np.argmin(Ts)], conv[np.argsort(Ts)[len(Ts) // 2]]]
-    for m in picks:
+    order = conv[np.argsort(Ts, kind="stable")]
+    picks = list(dict.fromkeys(order[np.linspace(0, order.size - 1, 16).round().astype(int)].tolist()))
+    assert len(picks) >= 12
+    for m in picks:   # smallest first
         w = wls[m]
         prob = oracle.Problem.from_workload(w, self_collision=True)
         v0, v1 = lay["vert"][m], lay["vert"][m + 1]
@@ -163,7 +176,7 @@ def test_batch_sampled_meshes_are_oracle_fixed_points(G):
         move = np.abs(xn - x).max() / prob.diag
         say("  mesh", m, w.n_tets, "tets, converged at", its[m], ": oracle step moves", move,
             "set changed", info["changed"])
-        assert not info["changed"] and move < 5e-6
+        assert not info["changed"] and move < 2e-6
 
 
 def test_gripper_unrolled_gradient_vs_central_differences(G):
