@@ -231,6 +231,25 @@ def run_batched(G, mg, n_mesh, max_iter, sample, autotune=True):
             t_plain += ms1 / 1e3
             work_plain += w.n_tets * st1["iters"]
     rate_plain = work_plain / t_plain if t_plain > 0 else None
+    # the same batch with the per-mesh CG (each mesh's own workgroups and CG
+    # scalars), its workgroup budget autotuned the same way
+    gb.set_params(max_iter=max_iter, pcg_per_mesh=1, pcg_blocks=0)
+    budget_pm = gb.autotune(alpha, x, iters=8)[0] if autotune else None
+    plan_pm = gb.cg_plan()
+    solve()
+    torch.cuda.synchronize()
+    ms_pm, st_pm = timed_on(gb.stream, solve)
+    its_pm = gb.mesh_iters().astype(np.int64)
+    conv_pm = its_pm > 0
+    value_pm = float((Ts[conv_pm] * its_pm[conv_pm]).sum() / (ms_pm / 1e3))
+    per_mesh = {"value": round(value_pm, 1), "unit": "tet-iterations/s", "ms_per_step": round(ms_pm, 3),
+                "outer_iters": st_pm["iters"], "pcg_iters": st_pm["pcg_iters_total"],
+                "converged_meshes": int(conv_pm.sum()), "capped_meshes": int((~conv_pm).sum()),
+                "capped_tet_iterations": float(Ts[~conv_pm].sum() * st_pm["iters"]),
+                "aa_rejected": st_pm["aa_rejected"], "workgroups": int(plan_pm.sum()),
+                "max_workgroups_per_mesh": int(plan_pm.max()),
+                "note": "pcg_per_mesh=1: each mesh's CG on its own workgroups, a mesh's path is its path alone"}
+    gb.set_params(pcg_per_mesh=0, pcg_blocks=grid)
     out = {"value": round(value, 1), "unit": "tet-iterations/s", "ms_per_step": round(ms, 3),
            "note": "converged meshes only: sum over meshes that reached 1e-6 of T_i x their iterations, over the "
                    "batch's time",
@@ -242,6 +261,7 @@ def run_batched(G, mg, n_mesh, max_iter, sample, autotune=True):
                             "unit": "tet-iterations/s",
                             "note": "each sampled mesh solved alone (same settings), converged ones counted"},
            "speedup_vs_alone": round(value / rate_plain, 3) if rate_plain else None,
+           "per_mesh_cg": per_mesh,
            "roofline": roof, "kernels": kernel_table(prof)}
     gb.close()
     return out

@@ -131,7 +131,14 @@ typedef struct {
                              workgroup's row range, its matrix from A_el; one
                              mesh, rows-of-three-vectors kernel variant, at
                              most 256 workgroups); 0 (default): Jacobi alone */
-  int32_t pad_p;
+  int32_t pcg_per_mesh;   /* a batch (M > 1) only.  1: the global step's CG runs
+                             one workgroup per mesh, each with its own scalars,
+                             stopping test and iteration count (a mesh's
+                             iterations and positions are those of solving it
+                             alone with pcg_blocks = 1); pcg_blocks is not
+                             used.  0 (default): one CG over the whole batch's
+                             rows with per-mesh warm starts and a shared
+                             stopping test.  Ignored for one mesh.          */
 } gs_params;
 
 /* Safeguards of the accelerated iteration.  Every iteration evaluates the
@@ -336,11 +343,25 @@ gs_status gs_adjoint_unrolled(gs_problem* p, const void* dev_alpha, const void* 
  * (about 256 rows per block) and every power-of-two grid that can be
  * resident, keeps the fastest in params.pcg_blocks, and restores dev_x and
  * the stored contact set.  *chosen (may be NULL) receives the grid,
- * *ms_per_iter (may be NULL) its time per outer iteration.  Errors as
+ * *ms_per_iter (may be NULL) its time per outer iteration.  With
+ * pcg_per_mesh on a batch the candidates are budgets the per-mesh plan
+ * shares out (gs_cg_plan), and *chosen is the budget kept.  Errors as
  * gs_solve; the last solve's adjoint state is discarded (gs_adjoint then
  * needs a new gs_solve). */
 gs_status gs_autotune(gs_problem* p, const void* dev_alpha, void* dev_x, int32_t iters, int32_t* chosen,
                       double* ms_per_iter);
+
+/* The per-mesh CG plan of a bound batch (params.pcg_per_mesh = 1, M > 1):
+ * blocks[m] (host array of M int32, caller-owned) receives the number of CG
+ * workgroups mesh m gets.  A mesh's global step (Eq. 8's linear system, one
+ * per mesh) is then solved as a solve of that mesh alone with pcg_blocks =
+ * blocks[m] would solve it.  The plan gives each mesh one workgroup plus
+ * its share, by rows, of the budget (pcg_blocks, else the workgroups that
+ * can be resident at once) beyond one per mesh, at most one workgroup per
+ * 512 rows.  Without the per-mesh CG every entry is 1.  GS_EINVAL for a null
+ * argument or M other than the problem's mesh count; GS_ESTATE before
+ * gs_bind. */
+gs_status gs_cg_plan(const gs_problem* p, int32_t M, int32_t* blocks);
 
 /* Implicit adjoint of the last gs_solve (not in the paper: the gradient of
  * its fixed point).  At the positions x the solve returned, with the stored

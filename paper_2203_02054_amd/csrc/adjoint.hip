@@ -311,6 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(Dev<R> d, Consts c) {
     d.mdone[i] = 0;
     d.mres[i] = 0ull;
     d.mmax[i] = 0ull;
+    d.mbar[i] = 0u;
   }
   if (v == 0 && c.aa_m > 0) d.aa_k[0] = 0;
   if (v == 0) {
@@ -334,6 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(Dev<R> d, Consts c) {
     st->residual = INFINITY;
     st->energy = 0.0;
     st->bar_count = 0;
+    st->mb_last = 0u;
   }
 }
 

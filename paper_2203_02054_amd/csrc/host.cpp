@@ -60,6 +60,7 @@ struct Layout {
   size_t rcount, alpha_stage, acc_max;
   size_t cz_inv, cz_nb, cz_rho, cz_ri;
   size_t mo_tri, mo_id, mo_node, mo_flag, mo_tgt, mo_nrm, mo_prim;
+  size_t seg, mbar;
   size_t total;
 };
 
@@ -163,6 +164,8 @@ struct gs_problem {
   std::vector<int32_t> ch_start, ch_tets;  // chamber -> tets (ascending)
   std::vector<AaBlock> faa_blk;            // blocks of the acceleration's dot-product kernel
   std::vector<int32_t> faa_mblk;           // [M+1] first block of each mesh
+  std::vector<int4> seg;                   // per-mesh CG: {mesh, index, workgroups, first} per workgroup
+  std::vector<int32_t> seg_k;              // per-mesh CG: workgroups of each mesh
   // device binding
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -219,6 +222,7 @@ gs_status check_params(const gs_params* p) {
     return fail(GS_EINVAL, "barrier_timeout_ms must be >= 0");
   if (!(p->pcg_eta_min >= 0) || !std::isfinite(p->pcg_eta_min)) return fail(GS_EINVAL, "pcg_eta_min must be >= 0");
   if (p->pcg_coarse != 0 && p->pcg_coarse != 1) return fail(GS_EINVAL, "pcg_coarse must be 0 or 1");
+  if (p->pcg_per_mesh != 0 && p->pcg_per_mesh != 1) return fail(GS_EINVAL, "pcg_per_mesh must be 0 or 1");
   return GS_OK;
 }
 
@@ -332,6 +336,8 @@ Layout make_layout(const gs_problem* p) {
   L.cz_rho = take(p->M == 1 ? 4 * n * W : 0);
   L.cz_ri = take(p->M == 1 ? n * 4 : 0);
   L.alpha_stage = take((size_t)p->nch * W);
+  L.seg = take((size_t)std::max(p->M, kMaxPcgGrid) * sizeof(int4));
+  L.mbar = take((size_t)p->M * 4);
   L.total = align256(off);
   return L;
 }
@@ -437,11 +443,45 @@ Dev<R> make_dev(const gs_problem* p) {
   d.mo_nrm = (double*)(b + L.mo_nrm);
   d.mo_prim = (int32_t*)(b + L.mo_prim);
   d.dbg_cap = 0;
+  d.seg = (const int4*)(b + L.seg);
+  d.mbar = (unsigned*)(b + L.mbar);
   return d;
 }
 
 // The coarse correction applies to one-mesh problems whose CG grid runs the
 // rows-of-three-vectors kernel variant on at most kCoarseMaxG workgroups.
+template <typename T>
+hipError_t upload(char* base, size_t off, const std::vector<T>& v, hipStream_t s) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+// A batch's CG with its own workgroups per mesh.
+bool per_mesh_cg(const gs_problem* p) { return p->prm.pcg_per_mesh && p->M > 1; }
+
+// The per-mesh CG plan: mesh m gets k_m consecutive workgroups, one plus its
+// share, by rows, of the budget beyond one per mesh (pcg_blocks, else what
+// can be resident), and at most one per kSegMinRows rows, so its rows split
+// as the rows of that mesh alone split over k_m workgroups of the unpaired
+// kernel.  Uploaded on the problem's stream.
+constexpr int kSegMinRows = 512;
+gs_status plan_segments(gs_problem* p, int maxg) {
+  p->seg_k.assign(p->M, 1);
+  p->seg.clear();
+  if (!per_mesh_cg(p)) return GS_OK;
+  const int budget = std::min({p->prm.pcg_blocks > 0 ? p->prm.pcg_blocks : maxg, maxg, kMaxPcgGrid});
+  const long extra = std::max(0L, (long)budget - p->M);
+  for (int m = 0; m < p->M; ++m) {
+    const long nm = p->vbeg[m + 1] - p->vbeg[m];
+    const int k = (int)std::min(1 + extra * nm / std::max(1, p->n), std::max(1L, nm / kSegMinRows));
+    p->seg_k[m] = k;
+    const int b0 = (int)p->seg.size();
+    for (int j = 0; j < k; ++j) p->seg.push_back(make_int4(m, j, k, b0));
+  }
+  HIPCHK(upload(p->ws, p->lay.seg, p->seg, p->stream));
+  return GS_OK;
+}
+
 bool coarse_wanted(const gs_problem* p) {
   const int G = p->pcg_grid;
   return p->prm.pcg_coarse && p->M == 1 && G >= 2 && G <= kCoarseMaxG && !pcg_paired(p->prec, p->ell_w, p->n, G);
@@ -588,7 +628,8 @@ Consts make_consts(const gs_problem* p) {
   // kTetQueryWide tets with self-collision, else on its own (one per tet)
   c.a_parts = (p->prm.self_collision && p->T < kTetQueryWide) ? cdiv(4L * p->T, kBlock) : cdiv(p->T, kBlock);
   c.ell_w = p->ell_w;
-  c.cg_soa = pcg_paired(p->prec, p->ell_w, p->n, p->pcg_grid) ? 1 : 0;
+  c.per_mesh = per_mesh_cg(p) ? 1 : 0;
+  c.cg_soa = (!c.per_mesh && pcg_paired(p->prec, p->ell_w, p->n, p->pcg_grid)) ? 1 : 0;
   c.trace_len = p->trace_len;
   c.c1 = p->prm.c1;
   c.c2 = p->prm.c2;
@@ -604,12 +645,6 @@ Consts make_consts(const gs_problem* p) {
   c.faa_nblk = (int)p->faa_blk.size();
   c.bar_timeout = (unsigned long long)(p->prm.barrier_timeout_ms * (double)p->wclk_khz);
   return c;
-}
-
-template <typename T>
-hipError_t upload(char* base, size_t off, const std::vector<T>& v, hipStream_t s) {
-  if (v.empty()) return hipSuccess;
-  return hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
 template <typename R>
@@ -680,6 +715,7 @@ gs_status bind_impl(gs_problem* p) {
   HIPCHK(hipMemsetAsync(b + L.mres, 0, (size_t)p->M * 8, s));
   HIPCHK(hipMemsetAsync(b + L.mchanged, 0, (size_t)p->M * 4, s));
   HIPCHK(hipMemsetAsync(b + L.mdone, 0, (size_t)p->M * 4, s));
+  HIPCHK(hipMemsetAsync(b + L.mbar, 0, (size_t)p->M * 4, s));
   HIPCHK(hipMemsetAsync(b + L.cact, 0, (size_t)p->S * p->slots, s));
   HIPCHK(hipMemsetAsync(b + L.st, 0, sizeof(DevStatus), s));
   HIPCHK(hipMemsetAsync(b + L.hcount, 0, (size_t)p->H * 4, s));
@@ -689,6 +725,10 @@ gs_status bind_impl(gs_problem* p) {
   if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
   p->pcg_maxg = maxg;
   p->pcg_grid = pcg_grid_for(p, maxg);
+  {
+    const gs_status r = plan_segments(p, maxg);
+    if (r != GS_OK) return r;
+  }
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&p->wclk_khz, hipDeviceAttributeWallClockRate, dev));
@@ -701,7 +741,14 @@ gs_status bind_impl(gs_problem* p) {
 // an otherwise idle device every workgroup is placed at once, and work of
 // other streams only delays some of them, it cannot hold them off for
 // good); a larger one the cooperative launch, which guarantees it.
-bool pcg_cooperative(const gs_problem* p) { return 2 * p->pcg_grid > p->pcg_maxg; }
+// Per-mesh CG: workgroups of a mesh wait for each other only, so a plan of
+// one workgroup per mesh needs no co-residency at all; otherwise the plan
+// fits what can be resident and the same rule applies.
+bool pcg_cooperative(const gs_problem* p) {
+  if (per_mesh_cg(p)) return (int)p->seg.size() > p->M && 2 * (int)p->seg.size() > p->pcg_maxg;
+  return 2 * p->pcg_grid > p->pcg_maxg;
+}
+int pcg_launch_grid(const gs_problem* p) { return per_mesh_cg(p) ? (int)p->seg.size() : p->pcg_grid; }
 
 // Launch one kernel, bracketed by timing events when profiling is on.
 template <typename F>
@@ -720,11 +767,12 @@ template <typename R>
 hipError_t timed_pcg(gs_problem* p, int k, const Dev<R>& d, const Consts& c, bool adjoint) {
   const bool coop = pcg_cooperative(p);
   if (!p->prof.on || coop)
-    return timed(p, k, [&] { return launch_pcg<R>(d, c, p->pcg_grid, p->stream, adjoint, coop); });
+    return timed(p, k, [&] { return launch_pcg<R>(d, c, pcg_launch_grid(p), p->stream, adjoint, coop); });
   hipEvent_t a, b;
   hipError_t e = p->prof.pair(k, a, b);
   if (e != hipSuccess) return e;
-  if ((e = launch_pcg<R>(d, c, p->pcg_grid, p->stream, adjoint, false, a, b)) != hipSuccess) p->prof.drop_last();
+  if ((e = launch_pcg<R>(d, c, pcg_launch_grid(p), p->stream, adjoint, false, a, b)) != hipSuccess)
+    p->prof.drop_last();
   return e;
 }
 
@@ -797,6 +845,9 @@ hipError_t enqueue_iteration(gs_problem* p, const Dev<R>& d, const Consts& c, co
   if (c.mo)
     if ((e = timed(p, K_MESH_OBST, [&] { return launch_mesh_obstacle<R>(d, c, s); })) != hipSuccess) return e;
   // the CG kernel first updates the contacts and gathers the right-hand side
+  // (the per-mesh kernel finds the spatial hash already cleared)
+  if (c.self_col && c.per_mesh)
+    if ((e = launch_hash_clear<R>(d, c, s)) != hipSuccess) return e;
   if ((e = timed_pcg<R>(p, K_PCG, d, c, false)) != hipSuccess) return e;
   if (c.faa_m > 0) return timed(p, K_ANDERSON, [&] { return launch_fwd_anderson<R>(d, c, s); });
   return hipSuccess;
@@ -1181,7 +1232,8 @@ void finalize(gs_problem* p) {
   int H = 1024;
   while (H < 2 * p->S) H <<= 1;
   p->H = H;
-  p->nparts = std::max({cdiv(p->T, kBlock), cdiv(n, kBlock), 12 * kMaxPcgGrid});
+  // the CG's partial sums: 12 per workgroup, one workgroup per mesh at most
+  p->nparts = std::max({cdiv(p->T, kBlock), cdiv(n, kBlock), 12 * kMaxPcgGrid, 12 * p->M});
   p->slots = 1 + p->ns + p->np + (p->mo_k > 0 ? 1 : 0);
   // chamber -> tets, ascending tet id within a chamber
   p->ch_start.assign(p->nch + 1, 0);
@@ -1537,7 +1589,7 @@ void gs_default_params(gs_params* p) {
   p->barrier_timeout_ms = 2000.0;
   p->pcg_eta_min = 0.0;
   p->pcg_coarse = 0;
-  p->pad_p = 0;
+  p->pcg_per_mesh = 0;
 }
 
 gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** out) {
@@ -2071,6 +2123,8 @@ gs_status gs_set_params(gs_problem* p, const gs_params* prm) {
     if (maxg < 1) return fail(GS_EHIP, "cannot size the cooperative CG grid");
     p->pcg_maxg = maxg;
     p->pcg_grid = pcg_grid_for(p, maxg);
+    const gs_status r = plan_segments(p, maxg);
+    if (r != GS_OK) return r;
     HIPCHK(hipStreamSynchronize(p->stream));
   }
   return GS_OK;
@@ -2082,6 +2136,14 @@ gs_status gs_solve(gs_problem* p, const void* alpha, void* x, gs_stats* stats) {
   if (!x || (p->nch > 0 && !alpha)) return fail(GS_EINVAL, "null device buffer");
   if (p->prec == 4) return solve_impl<float>(p, (const float*)alpha, (float*)x, stats);
   return solve_impl<double>(p, (const double*)alpha, (double*)x, stats);
+}
+
+gs_status gs_cg_plan(const gs_problem* p, int32_t M, int32_t* blocks) {
+  if (!p || !blocks) return fail(GS_EINVAL, "null argument");
+  if (!p->bound) return fail(GS_ESTATE, "gs_cg_plan before gs_bind");
+  if (M != p->M) return fail(GS_EINVAL, "M is not the problem's mesh count");
+  for (int m = 0; m < M; ++m) blocks[m] = p->seg_k[m];
+  return GS_OK;
 }
 
 gs_status gs_autotune(gs_problem* p, const void* alpha, void* x, int32_t iters, int32_t* chosen, double* ms_per_iter) {
@@ -2132,6 +2194,7 @@ gs_status gs_autotune(gs_problem* p, const void* alpha, void* x, int32_t iters, 
     p->prm.fixed_iters = iters;
     p->prm.pcg_blocks = g;
     p->pcg_grid = g;
+    if ((st = plan_segments(p, maxg)) != GS_OK) break;
     for (int rep = 0; rep < 2 && st == GS_OK; ++rep) {  // the first run warms up
       if ((st = restore()) != GS_OK) break;
       if (hipEventRecord(e0, s) != hipSuccess) st = fail(GS_EHIP, "event record");
@@ -2157,11 +2220,13 @@ gs_status gs_autotune(gs_problem* p, const void* alpha, void* x, int32_t iters, 
   p->solved = false;
   if (st != GS_OK) {
     p->pcg_grid = pcg_grid_for(p, maxg);
+    (void)plan_segments(p, maxg);
     return st;
   }
   p->prm.pcg_blocks = best;
   p->pcg_grid = pcg_grid_for(p, maxg);
-  if (chosen) *chosen = p->pcg_grid;
+  if ((st = plan_segments(p, maxg)) != GS_OK) return st;
+  if (chosen) *chosen = per_mesh_cg(p) ? best : p->pcg_grid;
   if (ms_per_iter) *ms_per_iter = best_ms / iters;
   return GS_OK;
 }

@@ -51,7 +51,7 @@ struct DevStatus {
   unsigned bar_count;    // grid-barrier arrivals of the running CG launch (0 between launches)
   int aa_pending;        // accelerated iteration: an iteration's position update is due
   int aa_ticket;         // last-block ticket of the position-update kernel
-  unsigned pad2;
+  unsigned mb_last;      // one-workgroup-per-mesh CG: the longest mesh's iterations, bit 31 a breakdown
 };
 
 // Anderson acceleration of the local/global iteration: per-mesh state.
@@ -116,6 +116,7 @@ struct Consts {
   int faa_m;            // Anderson memory of the local/global iteration (0: plain)
   int faa_guard;        // GS_AA_GUARD_*
   int faa_nblk;         // blocks of the acceleration's dot-product kernel
+  int per_mesh;         // a batch's CG runs one workgroup per mesh (grid = M, no grid barrier)
   double c1, c2, kappa, tol, pcg_eta;
   double pcg_eta_min;   // > 0: forward solves stop at clamp(previous r_k, pcg_eta_min, pcg_eta)
   double faa_slack;     // relative slack of the guard test
@@ -238,11 +239,17 @@ struct Dev {
   int32_t* dbg_tet;        // [2][cap]
   int32_t* dbg_tri;        // [2][cap]
   int dbg_cap;
+  // per-mesh CG (a batch): each workgroup's {mesh, index within the mesh,
+  // the mesh's workgroups, the mesh's first workgroup}; barrier counters
+  const int4* seg;         // [grid]
+  unsigned* mbar;          // [M] arrivals at the mesh's barrier in the running launch (0 between launches)
 };
 
 // ---------------------------------------------------------------------------
 // launchers (one per kernel family); all enqueue on `s` and return hipError_t
 template <typename R> hipError_t launch_init(const Dev<R>& d, const Consts& c, const R* xin, hipStream_t s);
+template <typename R>
+hipError_t launch_hash_clear(const Dev<R>& d, const Consts& c, hipStream_t s);
 template <typename R> hipError_t launch_output(const Dev<R>& d, const Consts& c, R* xout, hipStream_t s);
 // collision stages, in launch order
 enum { STAGE_HASH_INSERT = 0, STAGE_TET_QUERY, STAGE_RAY, N_COLLIDE_STAGES };

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
     d.mdone[i] = 0;
     d.mres[i] = 0ull;
     d.mchanged[i] = 0;
+    d.mbar[i] = 0u;
     AaMesh a{};
     a.act = AA_NONE;
     a.r_acc = INFINITY;
@@ -86,6 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
     st->residual = INFINITY;
     st->energy = 0.0;
     st->bar_count = 0;
+    st->mb_last = 0u;
   }
 }
 
@@ -116,6 +118,16 @@ __global__ __launch_bounds__(kBlock) void k_set_positions(Dev<R> d, Consts c, co
     st->cand_tet = 0;
     st->cand_tri = 0;
   }
+}
+
+// The spatial hash cleared for the CG kernel's final insertions, before a
+// per-mesh CG launch (the whole-grid kernel clears it itself).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_hash_clear(Dev<R> d, Consts c) {
+  if (is_done(d.st)) return;
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  for (int i = v; i < c.H; i += gridDim.x * kBlock) d.hcount[i] = 0;
+  if (v == 0) d.st->n_over = 0;
 }
 
 template <typename R>
@@ -348,12 +360,17 @@ __device__ __forceinline__ void galerkin_weights3(double e1, double e2, double e
 // block to arrive (ticket).
 // In the adjoint iteration (ADJ) the update is mu += d and a mesh is done once
 // max|d| <= tol max|mu| over its vertices.
-template <typename R, bool ADJ>
-__device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, int row0, int row1, double* lds) {
+// MB (one workgroup per mesh): a workgroup whose CG broke down (skip) leaves
+// its mesh as it is but still takes its ticket, so the last block's decisions
+// see every block; the breakdown it flagged becomes the solve's status.
+template <typename R, bool ADJ, bool MB>
+__device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, int row0, int row1, double* lds,
+                                            bool skip) {
   __shared__ int last;
   const size_t n = (size_t)c.n;
   const W4<R>* x = reinterpret_cast<const W4<R>*>(d.dl);
   double dmax = 0.0;
+  if (MB && skip) row1 = row0;
   for (int v0 = row0 + (int)(threadIdx.x & ~63u); v0 < row1; v0 += kPcgBlock) {
     // one wavefront handles 64 consecutive rows: the per-mesh maximum of |d|
     // is reduced in the wavefront when all its rows share a mesh
@@ -423,6 +440,8 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   }
   __syncthreads();
   if (!last) return;
+  // read by every thread before thread 0 clears it below
+  const unsigned mbl = MB ? d.st->mb_last : 0u;
   // the last block: the per-mesh convergence decisions (r = max|d| / diag,
   // active set unchanged), then, when the iteration is the last or traced,
   // the energy (fixed order per thread, then a fixed tree); the energy is
@@ -478,6 +497,7 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
     }
     d.mres[mi] = 0ull;
     if (!ADJ) d.mchanged[mi] = 0;
+    if (MB) d.mbar[mi] = 0u;  // every block is past its mesh's last barrier
   }
   // the three block reductions in one LDS round (per-wave order and fixed
   // tree of block_sum / block_max); every thread reads the results
@@ -500,6 +520,7 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
     nbad += lds4[3][i];
   }
   int code = RUNNING;
+  if (MB && (mbl >> 31)) nbad = 1.0;
   if (nbad > 0.0)
     code = BREAKDOWN;
   else if (c.fixed_iters > 0)
@@ -524,6 +545,10 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
     if (!(E == E)) code = BREAKDOWN;
   }
   if (threadIdx.x != 0) return;
+  if constexpr (MB) {
+    st->pcg_last = (int)(mbl & 0x7fffffffu);
+    st->mb_last = 0u;
+  }
   if (eguard) {
     // one mesh (thread 0 took its decision above): an accelerated point whose
     // energy exceeds the last accepted one's by more than the slack is rejected
@@ -575,7 +600,7 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
 template <typename R> struct Chunk { static constexpr int n = 16; };
 template <> struct Chunk<double> { static constexpr int n = 4; };
 
-template <typename R, int MW, bool ADJ, bool PAIR, bool CZ>
+template <typename R, int MW, bool ADJ, bool PAIR, bool CZ, bool MB>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   static_assert(!PAIR || (std::is_same<R, float>::value && MW == 16), "paired lanes: FP32, ELL width 16");
   constexpr int CH = Chunk<R>::n;
@@ -586,6 +611,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // every row range, and the coarse solution y = A0^-1 c of the ranges this
   // workgroup's rows reach, in two buffers (iteration i's and i+1's)
   static_assert(!(PAIR && CZ), "the coarse correction runs in the unpaired kernels");
+  static_assert(!(MB && (PAIR || CZ)), "one workgroup per mesh: the unpaired kernel, Jacobi");
   constexpr int CZG = CZ ? kCoarseMaxG : 1;
   __shared__ double cz_c[3][CZG];
   __shared__ double cz_y[2][3][CZG];
@@ -611,7 +637,24 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // each block owns one contiguous range of rows (a multiple of 64 long), so
   // the rows spread over all G blocks however many rows a thread gets
   const int chunk = ((c.n + G - 1) / G + 63) & ~63;
-  const int row0 = min(c.n, (int)blockIdx.x * chunk), row1 = min(c.n, row0 + chunk);
+  // MB (a batch, per-mesh CG): the k workgroups of a mesh split its rows as
+  // k workgroups split the rows of that mesh alone, and run its CG with its
+  // own scalars and stopping test: their reductions are over the mesh's k
+  // partials, their barriers wait for the mesh's workgroups only (a block
+  // barrier when k = 1)
+  const int4 sg = MB ? d.seg[blockIdx.x] : make_int4(0, 0, 0, 0);
+  int row0, row1;
+  if constexpr (MB) {
+    const int vb = d.mesh[sg.x].vbeg, ve = d.mesh[sg.x].vend;
+    const int ch = ((ve - vb + sg.z - 1) / sg.z + 63) & ~63;
+    row0 = min(ve, vb + sg.y * ch);
+    row1 = min(ve, row0 + ch);
+  } else {
+    row0 = min(c.n, (int)blockIdx.x * chunk);
+    row1 = min(c.n, row0 + chunk);
+  }
+  const int Gr = MB ? sg.z : G;   // partials a reduction sums
+  const int pg0 = MB ? sg.w : 0;  // and where they start
   // coarse correction: u = D^-1 r + R0^T y, y = A0^-1 R0 r, with R0 summing
   // the free rows of each workgroup's range.  Every workgroup holds the whole
   // coarse residual (thread t that of range t) and forms y for the ranges its
@@ -684,6 +727,18 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   }
   unsigned* bc = &d.st->bar_count;
   unsigned bar_target = 0;  // arrivals the next grid barrier waits for
+  // the barrier that publishes the partials: grid-wide, or (MB) the block's
+  auto gbar = [&]() -> bool {
+    if constexpr (MB) {
+      if (sg.z == 1) {
+        __syncthreads();
+        return true;
+      }
+      return grid_barrier(d.mbar + sg.x, bar_target, sg.z, &d.st->done, c.bar_timeout);
+    } else {
+      return grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout);
+    }
+  };
   W4<R>* __restrict__ x = reinterpret_cast<W4<R>*>(d.dl);
   W4<R>* __restrict__ p = reinterpret_cast<W4<R>*>(d.p);
   W4<R>* const cg0 = reinterpret_cast<W4<R>*>(d.cg);
@@ -744,7 +799,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           esp += gather_row<SOA>(d, c, v);
         }
       }
-      if (c.self_col) {
+      // (MB: workgroups do not wait for each other, so one could clear what
+      // another has already inserted; the host clears the hash before the
+      // launch instead)
+      if (c.self_col && !MB) {
         for (int i = tid0; i < c.H; i += stride) d.hcount[i] = 0;
         if (tid0 == 0) d.st->n_over = 0;
       }
@@ -822,7 +880,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           st_state(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), paw1);
           st_state(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), paw2);
           st_state(p + row0, (unsigned)(v - row0), paw3);
-          if (c.M > 1) {
+          if (c.M > 1 && !MB) {
             double* q = reinterpret_cast<double*>(cg0 + 3 * n);
             q[v] = t[0];
             q[n + v] = t[1];
@@ -898,7 +956,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         st_state(cg0 + qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a10, a11, a12));
         st_state(cg0 + 2 * qs + row0 * vs, (unsigned)((v - row0) * vs), w4<R>(a20, a21, a22));
         st_state(p + row0, (unsigned)(v - row0), w4<R>(a30, a31, a32));
-        if (c.M > 1) {
+        if (c.M > 1 && !MB) {
           // a batch projects on (w1, w2): per-row terms, summed per mesh below,
           // in the half of the CG state the first iteration has yet to write
           double* q = reinterpret_cast<double*>(cg0 + 3 * n);
@@ -914,7 +972,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       }
     }
     double g1 = 0.0, g2 = 0.0, g3 = 0.0;
-    if (c.M == 1) {
+    if (c.M == 1 || MB) {
       // partials at part_c[(2 + i) G + block]: the nine terms, then b' M^-1 b
       // (also in part_d).  The paired kernel reads the ten grid sums in one
       // round after the barrier; the unpaired kernels, whose registers the CG
@@ -927,15 +985,15 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         __syncthreads();  // lds2 is read above before it is written again
         block_sums_store<12>(czb, lds2, d.part_f + 18 * G + blockIdx.x, G);
       }
-      if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
+      if (!gbar()) return;
       double S[10];
       if constexpr (PAIR) {
-        grid_sums<10>(d.part_c + 2 * G, G, G, sh, S);
+        grid_sums<10>(d.part_c + 2 * G + pg0, G, Gr, sh, S);
         rhs1 = S[9];
       } else {
         double S1[5], S2[4];
-        grid_sums<5>(d.part_c + 2 * G, G, G, sh, S1);
-        grid_sums<4>(d.part_c + 7 * G, G, G, sh + 8, S2);
+        grid_sums<5>(d.part_c + 2 * G + pg0, G, Gr, sh, S1);
+        grid_sums<4>(d.part_c + 7 * G + pg0, G, Gr, sh + 8, S2);
 #pragma unroll
         for (int i = 0; i < 5; ++i) S[i] = S1[i];
 #pragma unroll
@@ -991,7 +1049,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       if (pv_has) {
         const int v = pv_row;
         R r1 = (R)g1, r2 = (R)g2, r3 = (R)g3;
-        if (c.M > 1) {
+        if (c.M > 1 && !MB) {
           const int m = d.vmesh[v];
           r1 = (R)d.mgam[2 * m];
           r2 = (R)d.mgam[2 * m + 1];
@@ -1050,7 +1108,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     } else {
       for (int v = row0 + (int)threadIdx.x; v < row1; v += kPcgBlock) {
         R r1 = (R)g1, r2 = (R)g2, r3 = (R)g3;
-        if (c.M > 1) {
+        if (c.M > 1 && !MB) {
           const int m = d.vmesh[v];
           r1 = (R)d.mgam[2 * m];
           r2 = (R)d.mgam[2 * m + 1];
@@ -1138,7 +1196,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     store11(acc_g, acc_d, d.part_c + blockIdx.x, d.part_e + blockIdx.x, d.part_f + blockIdx.x);
   else
     block_sum2_store(acc_g, acc_d, lds2, d.part_c + blockIdx.x, d.part_e + blockIdx.x);
-  if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
+  if (!gbar()) return;
   // PAIR: the lane pair's first neighbour gather, issued before the grid
   // sums so the round trips overlap
   // the neighbours' (r, w, s) of the coming iteration, loaded right after the
@@ -1158,8 +1216,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     gather(cg0 + cur * 3 * n);
   }
   double gam, del, rhs = rhs1, dummy;
-  grid_sum2(d.part_c, d.part_e, G, sh, gam, del);
-  if (!PAIR || c.M > 1) grid_sum2(d.part_d, d.part_d, G, sh, rhs, dummy);
+  grid_sum2(d.part_c + pg0, d.part_e + pg0, Gr, sh, gam, del);
+  if (!PAIR || c.M > 1) grid_sum2(d.part_d + pg0, d.part_d + pg0, Gr, sh, rhs, dummy);
   gam = uniform_d(gam);
   del = uniform_d(del);
   rhs = uniform_d(rhs);
@@ -1190,7 +1248,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
               d.part_f + ((it & 1) ? 0 : 9 * G) + blockIdx.x);
     else
       block_sum2_store(ag, ad, lds2, d.part_c + half + blockIdx.x, d.part_e + half + blockIdx.x);
-    return grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout);
+    return gbar();
   };
   // coarse: at the top of iteration i, c_{i+1} = R0 r_i - alpha (R0 w_i +
   // beta R0 s_{i-1}) for every range (thread t: range t) from the sums
@@ -1213,7 +1271,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   auto advance = [&]() -> bool {
     const int half = (it & 1) ? 0 : G;
     double gn, dn;
-    grid_sum2<false>(d.part_c + half, d.part_e + half, G, sh + 2 * (it & 1), gn, dn);
+    grid_sum2<false>(d.part_c + half + pg0, d.part_e + half + pg0, Gr, sh + 2 * (it & 1), gn, dn);
     gn = uniform_d(gn);
     dn = uniform_d(dn);
     ++it;
@@ -1388,13 +1446,19 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     if (!next_step(acc_g, acc_d)) break;
   }
   if (stalled) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (MB && threadIdx.x == 0 && sg.y == 0) {
+    // each mesh's CG iterations summed over the batch; the longest one, and a
+    // breakdown, for the last block (the status is stored only there, so a
+    // workgroup that starts late still runs)
+    atomicAdd(&d.st->pcg_total, it);
+    atomicMax(&d.st->mb_last, (unsigned)it | (broke ? 0x80000000u : 0u));
+  } else if (!MB && blockIdx.x == 0 && threadIdx.x == 0) {
     d.st->pcg_total += it;
     d.st->pcg_last = it;
     if (broke) __hip_atomic_store(&d.st->done, (int)BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (!broke) {
-    finish_tail<R, ADJ>(d, c, row0, row1, lds);
+  if (!broke || MB) {
+    finish_tail<R, ADJ, MB>(d, c, row0, row1, lds, broke);
   } else if (threadIdx.x == 0) {
     // every block leaves after the same barrier; the last one out clears the
     // barrier counter for the next launch
@@ -1404,6 +1468,12 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       d.st->bar_count = 0u;
     }
   }
+}
+
+template <typename R>
+hipError_t launch_hash_clear(const Dev<R>& d, const Consts& c, hipStream_t s) {
+  k_hash_clear<R><<<max(1, min(cdiv(c.H, kBlock), 1024)), kBlock, 0, s>>>(d, c);
+  return hipGetLastError();
 }
 
 template <typename R>
@@ -1428,40 +1498,52 @@ hipError_t launch_output(const Dev<R>& d, const Consts& c, R* xout, hipStream_t 
 
 // The CG kernel for a matrix of ELL width ell_w; pair selects the
 // paired-lane variant (FP32, width 16 only), cz the unpaired variant with the
-// coarse correction.
+// coarse correction, mb the unpaired variant that runs one workgroup per mesh.
 template <typename R>
-const void* pcg_kernel(int ell_w, bool adjoint, bool pair, bool cz) {
+const void* pcg_kernel(int ell_w, bool adjoint, bool pair, bool cz, bool mb = false) {
+  if (mb) {
+    if (adjoint)
+      return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, false, true>
+                         : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false, false, true>
+                                       : (const void*)k_pcg<R, 64, true, false, false, true>;
+    return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false, false, true>
+                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false, false, true>
+                                     : (const void*)k_pcg<R, 64, false, false, false, true>;
+  }
   if constexpr (std::is_same<R, float>::value) {
     if (pair && ell_w <= 16)
-      return adjoint ? (const void*)k_pcg<R, 16, true, true, false> : (const void*)k_pcg<R, 16, false, true, false>;
+      return adjoint ? (const void*)k_pcg<R, 16, true, true, false, false> : (const void*)k_pcg<R, 16, false, true, false, false>;
   }
   if (cz) {
     if (adjoint)
-      return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, true>
-                         : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false, true>
-                                       : (const void*)k_pcg<R, 64, true, false, true>;
-    return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false, true>
-                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false, true>
-                                     : (const void*)k_pcg<R, 64, false, false, true>;
+      return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, true, false>
+                         : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false, true, false>
+                                       : (const void*)k_pcg<R, 64, true, false, true, false>;
+    return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false, true, false>
+                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false, true, false>
+                                     : (const void*)k_pcg<R, 64, false, false, true, false>;
   }
   if (adjoint)
-    return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, false>
-                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false, false>
-                                     : (const void*)k_pcg<R, 64, true, false, false>;
-  return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false, false>
-                     : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false, false>
-                                   : (const void*)k_pcg<R, 64, false, false, false>;
+    return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, false, false>
+                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false, false, false>
+                                     : (const void*)k_pcg<R, 64, true, false, false, false>;
+  return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false, false, false>
+                     : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false, false, false>
+                                   : (const void*)k_pcg<R, 64, false, false, false, false>;
 }
 
 template <typename R>
 hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s, bool adjoint, bool cooperative,
                       hipEvent_t ev_start, hipEvent_t ev_stop) {
   void* args[] = {(void*)&d, (void*)&c};
-  const bool pair = pcg_paired((int)sizeof(R), c.ell_w, c.n, grid);
+  // per-mesh CG: the grid is the plan's workgroups, at least one per mesh
+  const bool mb = c.per_mesh && c.M > 1;
+  if (mb && (grid < c.M || c.coarse)) return hipErrorInvalidValue;
+  const bool pair = !mb && pcg_paired((int)sizeof(R), c.ell_w, c.n, grid);
   // the adjoint kernels wrote the right-hand side in the layout of the grid
   // the constants were made for
   if (adjoint && c.cg_soa != (pair ? 1 : 0)) return hipErrorInvalidValue;
-  const void* f = pcg_kernel<R>(c.ell_w, adjoint, pair, c.coarse && !pair);
+  const void* f = pcg_kernel<R>(c.ell_w, adjoint, pair, c.coarse && !pair, mb);
   if (cooperative) return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
   if (ev_start || ev_stop)  // the events take the kernel's own start and end times
     return hipExtLaunchKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s, ev_start, ev_stop, 0);
@@ -1471,14 +1553,15 @@ hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s,
 
 // Workgroups of the CG kernel that can be resident at once for a matrix of
 // ELL width ell_w: the smallest occupancy of its variants (forward and
-// adjoint; unpaired, paired and with the coarse correction) times the compute
-// units (0 on a runtime error).
+// adjoint; unpaired, paired, with the coarse correction and per mesh) times
+// the compute units (0 on a runtime error).
 template <typename R>
 int pcg_max_grid(int ell_w) {
   int occ = 1 << 30, dev = 0, cus = 0;
-  for (int v = 0; v < 6; ++v) {
+  for (int v = 0; v < 8; ++v) {
     int o = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, pcg_kernel<R>(ell_w, v & 1, (v >> 1) == 1, (v >> 1) == 2),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, pcg_kernel<R>(ell_w, v & 1, (v >> 1) == 1, (v >> 1) == 2,
+                                                                      (v >> 1) == 3),
                                                      kPcgBlock, 0) != hipSuccess)
       return 0;
     occ = std::min(occ, o);
@@ -1492,6 +1575,7 @@ int pcg_max_grid(int ell_w) {
   template hipError_t launch_init<R>(const Dev<R>&, const Consts&, const R*, hipStream_t);      \
   template hipError_t launch_set_positions<R>(const Dev<R>&, const Consts&, const R*, hipStream_t); \
   template hipError_t launch_output<R>(const Dev<R>&, const Consts&, R*, hipStream_t);          \
+  template hipError_t launch_hash_clear<R>(const Dev<R>&, const Consts&, hipStream_t);          \
   template hipError_t launch_pcg<R>(const Dev<R>&, const Consts&, int, hipStream_t, bool, bool, hipEvent_t, hipEvent_t); \
   template int pcg_max_grid<R>(int);
 INST(float)

@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
                 ("pcg_blocks", ctypes.c_int32), ("trace_len", ctypes.c_int32), ("adj_tol", ctypes.c_double),
                 ("adj_max_iter", ctypes.c_int32), ("adj_aa_m", ctypes.c_int32), ("aa_m", ctypes.c_int32),
                 ("aa_guard", ctypes.c_int32), ("aa_slack", ctypes.c_double), ("barrier_timeout_ms", ctypes.c_double),
-                ("pcg_eta_min", ctypes.c_double), ("pcg_coarse", ctypes.c_int32), ("pad_p", ctypes.c_int32)]
+                ("pcg_eta_min", ctypes.c_double), ("pcg_coarse", ctypes.c_int32), ("pcg_per_mesh", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -100,6 +100,7 @@ SIGNATURES = {
     "gs_set_contacts": (_I, [_P, _I, _PI, _PI, _PI, _PD, _PD, _PI]),
     "gs_adjoint": (_I, [_P, _P, _P, _P, ctypes.POINTER(Stats)]),
     "gs_autotune": (_I, [_P, _P, _P, _I, _PI, _PD]),
+    "gs_cg_plan": (_I, [_P, _I, _PI]),
     "gs_unrolled_scratch_size": (ctypes.c_size_t, [_P, _I]),
     "gs_adjoint_unrolled": (_I, [_P, _P, _P, _I, _P, _P, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(Stats)]),
     "gs_local_step_debug": (_I, [_P, _P, _P, _P]),
@@ -274,6 +275,12 @@ class Problem:
         _check(lib().gs_batch_layout(self._h, cap, _ptr(v, ctypes.c_int32), _ptr(t, ctypes.c_int32),
                                      _ptr(c, ctypes.c_int32), ctypes.byref(nm)))
         return dict(vert=v, tet=t, chamber=c)
+
+    def cg_plan(self):
+        """Workgroups of the per-mesh CG for each mesh (all 1 without it)."""
+        k = np.zeros(self.n_mesh, np.int32)
+        _check(lib().gs_cg_plan(self._h, self.n_mesh, _ptr(k, ctypes.c_int32)))
+        return k
 
     def mesh_iters(self):
         it = np.zeros(self.n_mesh, np.int32)

@@ -194,3 +194,20 @@ def test_remesh_and_progressive_entry_points_validate_on_the_host():
     finally:
         L.gs_destroy(h)
     assert ctypes.sizeof(G.Stage) == ctypes.sizeof(G.Stats) + 16
+
+
+def test_per_mesh_cg_parameter_and_plan_validate_on_the_host():
+    m = voxel_box(2, 1, 1)
+    for v in (-1, 2):
+        assert _create(m, pcg_per_mesh=v)[0] == G.EINVAL, v
+    assert G.default_params().pcg_per_mesh == 0
+    L = G.lib()
+    k = (ctypes.c_int32 * 1)()
+    assert L.gs_cg_plan(None, 1, k) == G.EINVAL
+    code, h, keep = _create(m, pcg_per_mesh=1)
+    assert code == G.OK
+    try:
+        assert L.gs_cg_plan(h, 1, None) == G.EINVAL
+        assert L.gs_cg_plan(h, 1, k) == G.ESTATE  # not bound to a device
+    finally:
+        L.gs_destroy(h)
