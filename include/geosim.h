@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define GEOSIM_VERSION 210
+#define GEOSIM_VERSION 211
 
 typedef int32_t gs_status;
 
@@ -139,6 +139,15 @@ typedef struct {
                              used.  0 (default): one CG over the whole batch's
                              rows with per-mesh warm starts and a shared
                              stopping test.  Ignored for one mesh.          */
+  int32_t graph;          /* 1: gs_solve runs each chunk of check_every outer
+                             iterations after the first as one HIP graph
+                             launch (the chunk's kernels, captured once and
+                             kept while the problem, its binding and its
+                             parameters stay the same), when every kernel of
+                             the iteration takes an ordinary launch and
+                             profiling is off.  Results are the same as with
+                             0 (default): each kernel launched on its own.  */
+  int32_t pad_g;
 } gs_params;
 
 /* Safeguards of the accelerated iteration.  Every iteration evaluates the

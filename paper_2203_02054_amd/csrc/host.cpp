@@ -185,7 +185,22 @@ struct gs_problem {
   // the events that mark their copies (created at gs_bind)
   DevStatus* hstat = nullptr;
   hipEvent_t hev[2] = {nullptr, nullptr};
+  // a chunk of outer iterations captured as a HIP graph, and what it was
+  // captured for (the kernels' arguments); replaced when they change
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::string gkey;
+  hipStream_t cap_stream = nullptr;  // the capture's own stream (the caller's may be the null stream)
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    gkey.clear();
+  }
   ~gs_problem() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hstat) (void)hipHostFree(hstat);
     for (hipEvent_t e : hev)
       if (e) (void)hipEventDestroy(e);
@@ -223,6 +238,7 @@ gs_status check_params(const gs_params* p) {
   if (!(p->pcg_eta_min >= 0) || !std::isfinite(p->pcg_eta_min)) return fail(GS_EINVAL, "pcg_eta_min must be >= 0");
   if (p->pcg_coarse != 0 && p->pcg_coarse != 1) return fail(GS_EINVAL, "pcg_coarse must be 0 or 1");
   if (p->pcg_per_mesh != 0 && p->pcg_per_mesh != 1) return fail(GS_EINVAL, "pcg_per_mesh must be 0 or 1");
+  if (p->graph != 0 && p->graph != 1) return fail(GS_EINVAL, "graph must be 0 or 1");
   return GS_OK;
 }
 
@@ -784,14 +800,41 @@ hipError_t timed_pcg(gs_problem* p, int k, const Dev<R>& d, const Consts& c, boo
 // With per-kernel profiling on, each chunk is waited for (its events must be
 // complete before they are read).  `h` receives the final status.
 template <typename F>
-gs_status drive(gs_problem* p, const DevStatus* dstat, int limit, F&& enqueue_one, DevStatus& h) {
+gs_status drive(gs_problem* p, const DevStatus* dstat, int limit, F&& enqueue_one, DevStatus& h,
+                const std::string& gkey = std::string()) {
   hipStream_t s = p->stream;
   const int ce = p->prm.check_every;
   int enq = 0, c = 0;
   bool pending = false;
   while (true) {
     const int chunk = std::min(ce, std::max(1, limit - enq));
-    for (int i = 0; i < chunk; ++i) HIPCHK(enqueue_one());
+    if (!gkey.empty() && enq > 0 && chunk == ce) {
+      // a full chunk after the first (which may build the hash): one graph
+      // launch of the chunk's kernels, captured on first use
+      if (!p->gexec || p->gkey != gkey) {
+        // captured on a stream of its own (the kernels take p->stream, which
+        // points there meanwhile); nothing runs until the graph is launched
+        p->drop_graph();
+        if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        p->stream = p->cap_stream;
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < ce && e == hipSuccess; ++i) e = enqueue_one();
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+        p->stream = s;
+        if (e != hipSuccess || e2 != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          return fail(GS_EHIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        p->graph = g;
+        HIPCHK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+        p->gkey = gkey;
+      }
+      HIPCHK(hipGraphLaunch(p->gexec, s));
+    } else {
+      for (int i = 0; i < chunk; ++i) HIPCHK(enqueue_one());
+    }
     enq += chunk;
     HIPCHK(hipMemcpyAsync(&p->hstat[c & 1], dstat, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(p->hev[c & 1], s));
@@ -881,7 +924,15 @@ gs_status solve_impl(gs_problem* p, const R* alpha, R* x, gs_stats* stats) {
   p->hash_ready = false;
   DevStatus h{};
   const int limit = p->prm.fixed_iters > 0 ? p->prm.fixed_iters : p->prm.max_iter;
-  const gs_status ds = drive(p, d.st, limit, [&] { return enqueue_iteration<R>(p, d, c, alpha); }, h);
+  // a graph of a chunk of iterations is keyed by everything its kernels take
+  std::string gkey;
+  if (p->prm.graph && !p->prof.on && !pcg_cooperative(p)) {
+    gkey.assign(1, (char)sizeof(R));
+    gkey.append(reinterpret_cast<const char*>(&d), sizeof(d));
+    gkey.append(reinterpret_cast<const char*>(&c), sizeof(c));
+    gkey.append(reinterpret_cast<const char*>(&alpha), sizeof(alpha));
+  }
+  const gs_status ds = drive(p, d.st, limit, [&] { return enqueue_iteration<R>(p, d, c, alpha); }, h, gkey);
   if (ds != GS_OK) return ds;
   HIPCHK(launch_output<R>(d, c, x, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1590,6 +1641,8 @@ void gs_default_params(gs_params* p) {
   p->pcg_eta_min = 0.0;
   p->pcg_coarse = 0;
   p->pcg_per_mesh = 0;
+  p->graph = 0;
+  p->pad_g = 0;
 }
 
 gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** out) {

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
     for n in names:
         assert hasattr(L, n), n
     assert sorted(G.SIGNATURES) == names
-    assert L.gs_version() == 210
+    assert L.gs_version() == 211
 
 
 def _desc(m, precision=4):
