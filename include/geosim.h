@@ -147,7 +147,16 @@ typedef struct {
                              the iteration takes an ordinary launch and
                              profiling is off.  Results are the same as with
                              0 (default): each kernel launched on its own.  */
-  int32_t pad_g;
+  int32_t pcg_store;      /* how the CG kernel stores the state other
+                             workgroups read after a barrier: 1 written
+                             through to memory (the barrier's release then
+                             has little to write back: best while the state
+                             is cache-resident and the iteration waits on
+                             the barrier), 2 through L2 (a row record's
+                             vectors merge into whole lines: fewer HBM writes
+                             when the iteration is bound by memory traffic),
+                             0 (default): 2 above 700,000 rows, else 1.
+                             Results are the same either way.              */
 } gs_params;
 
 /* Safeguards of the accelerated iteration.  Every iteration evaluates the

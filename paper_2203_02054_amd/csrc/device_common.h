@@ -23,21 +23,34 @@ struct alignas(4 * sizeof(R)) W4 {
 // release and acquire fences stay as they are.  `base` must be the same for
 // the whole wavefront (it forms the buffer descriptor) and `i` is an element
 // index from it with i * sizeof(W4) < 2^31.
-template <typename R>
-__device__ __forceinline__ void st_wt(W4<R>* base, unsigned i, const W4<R>& v) {
+// POL is the buffer store's cache-policy operand: 16 (sc1) writes through,
+// 0 is the ordinary write-back store (st_wb below).
+template <int POL, typename R>
+__device__ __forceinline__ void st_buf(W4<R>* base, unsigned i, const W4<R>& v) {
   typedef int v4i __attribute__((ext_vector_type(4)));
-  constexpr int kSc1 = 16;                  // cache-policy operand of the buffer store: sc1
   constexpr int kRawDword3 = 0x00020000;    // raw buffer descriptor word 3 (32-bit data format)
   const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, 0x7fffffff, kRawDword3);
   if constexpr (sizeof(R) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, i * 16u, 0, kSc1);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, i * 16u, 0, POL);
   } else {
     struct Half {
       R a, b;
     };
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, Half{v.x, v.y}), r, i * 32u, 0, kSc1);
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, Half{v.z, v.w}), r, i * 32u + 16u, 0, kSc1);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, Half{v.x, v.y}), r, i * 32u, 0, POL);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, Half{v.z, v.w}), r, i * 32u + 16u, 0, POL);
   }
+}
+template <typename R>
+__device__ __forceinline__ void st_wt(W4<R>* base, unsigned i, const W4<R>& v) {
+  st_buf<16>(base, i, v);
+}
+// The same store through L2 (write-back): the three 16-byte vectors of a row
+// record merge into whole lines there before they reach memory, which pays
+// when the CG state is far larger than the caches and the iteration is bound
+// by memory traffic rather than by the barrier.
+template <typename R>
+__device__ __forceinline__ void st_wb(W4<R>* base, unsigned i, const W4<R>& v) {
+  st_buf<0>(base, i, v);
 }
 
 // A double partial sum stored the same way (an agent-scope relaxed store).

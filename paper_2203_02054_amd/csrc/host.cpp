@@ -239,6 +239,7 @@ gs_status check_params(const gs_params* p) {
   if (p->pcg_coarse != 0 && p->pcg_coarse != 1) return fail(GS_EINVAL, "pcg_coarse must be 0 or 1");
   if (p->pcg_per_mesh != 0 && p->pcg_per_mesh != 1) return fail(GS_EINVAL, "pcg_per_mesh must be 0 or 1");
   if (p->graph != 0 && p->graph != 1) return fail(GS_EINVAL, "graph must be 0 or 1");
+  if (p->pcg_store < 0 || p->pcg_store > 2) return fail(GS_EINVAL, "pcg_store must be 0, 1 or 2");
   return GS_OK;
 }
 
@@ -472,6 +473,8 @@ hipError_t upload(char* base, size_t off, const std::vector<T>& v, hipStream_t s
   return hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
+constexpr int kWbRows = 700000;
+
 // A batch's CG with its own workgroups per mesh.
 bool per_mesh_cg(const gs_problem* p) { return p->prm.pcg_per_mesh && p->M > 1; }
 
@@ -645,6 +648,8 @@ Consts make_consts(const gs_problem* p) {
   c.a_parts = (p->prm.self_collision && p->T < kTetQueryWide) ? cdiv(4L * p->T, kBlock) : cdiv(p->T, kBlock);
   c.ell_w = p->ell_w;
   c.per_mesh = per_mesh_cg(p) ? 1 : 0;
+  // write-back CG state above kWbRows rows (state far beyond the caches)
+  c.cg_wb = (p->prm.pcg_store == 2 || (p->prm.pcg_store == 0 && p->n > kWbRows)) ? 1 : 0;
   c.cg_soa = (!c.per_mesh && pcg_paired(p->prec, p->ell_w, p->n, p->pcg_grid)) ? 1 : 0;
   c.trace_len = p->trace_len;
   c.c1 = p->prm.c1;
@@ -1642,7 +1647,7 @@ void gs_default_params(gs_params* p) {
   p->pcg_coarse = 0;
   p->pcg_per_mesh = 0;
   p->graph = 0;
-  p->pad_g = 0;
+  p->pcg_store = 0;
 }
 
 gs_status gs_create(const gs_mesh_desc* m, const gs_params* prm, gs_problem** out) {

@@ -116,7 +116,8 @@ struct Consts {
   int faa_m;            // Anderson memory of the local/global iteration (0: plain)
   int faa_guard;        // GS_AA_GUARD_*
   int faa_nblk;         // blocks of the acceleration's dot-product kernel
-  int per_mesh;         // a batch's CG runs one workgroup per mesh (grid = M, no grid barrier)
+  int per_mesh;         // a batch's CG runs per mesh (its own workgroups, scalars and stopping test)
+  int cg_wb;            // CG state stored write-back (1) or write-through (0)
   double c1, c2, kappa, tol, pcg_eta;
   double pcg_eta_min;   // > 0: forward solves stop at clamp(previous r_k, pcg_eta_min, pcg_eta)
   double faa_slack;     // relative slack of the guard test

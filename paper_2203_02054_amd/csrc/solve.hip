@@ -600,7 +600,7 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
 template <typename R> struct Chunk { static constexpr int n = 16; };
 template <> struct Chunk<double> { static constexpr int n = 4; };
 
-template <typename R, int MW, bool ADJ, bool PAIR, bool CZ, bool MB>
+template <typename R, int MW, bool ADJ, bool PAIR, bool CZ, bool MB, bool WB = false>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   static_assert(!PAIR || (std::is_same<R, float>::value && MW == 16), "paired lanes: FP32, ELL width 16");
   constexpr int CH = Chunk<R>::n;
@@ -612,6 +612,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // workgroup's rows reach, in two buffers (iteration i's and i+1's)
   static_assert(!(PAIR && CZ), "the coarse correction runs in the unpaired kernels");
   static_assert(!(MB && (PAIR || CZ)), "one workgroup per mesh: the unpaired kernel, Jacobi");
+  static_assert(!(WB && (PAIR || CZ || MB)), "write-back state: the unpaired whole-grid kernel");
   constexpr int CZG = CZ ? kCoarseMaxG : 1;
   __shared__ double cz_c[3][CZG];
   __shared__ double cz_y[2][3][CZG];
@@ -633,7 +634,15 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   // cover lines only partly, yet writing them through still beat assembling
   // the lines in L2 (about 10% per CG iteration on the 378,666-tet gripper at
   // 128 blocks)
-  auto st_state = [&](W4<R>* base, unsigned i, const W4<R>& v) { st_wt(base, i, v); };
+  // (WB: ordinary write-back stores instead, for state far larger than the
+  // caches, where merging a row record's three vectors in L2 saves HBM
+  // writes)
+  auto st_state = [&](W4<R>* base, unsigned i, const W4<R>& v) {
+    if constexpr (WB)
+      st_wb(base, i, v);
+    else
+      st_wt(base, i, v);
+  };
   // each block owns one contiguous range of rows (a multiple of 64 long), so
   // the rows spread over all G blocks however many rows a thread gets
   const int chunk = ((c.n + G - 1) / G + 63) & ~63;
@@ -1498,9 +1507,10 @@ hipError_t launch_output(const Dev<R>& d, const Consts& c, R* xout, hipStream_t 
 
 // The CG kernel for a matrix of ELL width ell_w; pair selects the
 // paired-lane variant (FP32, width 16 only), cz the unpaired variant with the
-// coarse correction, mb the unpaired variant that runs one workgroup per mesh.
+// coarse correction, mb the unpaired variant that runs per mesh, wb the
+// unpaired whole-grid variant with write-back state stores.
 template <typename R>
-const void* pcg_kernel(int ell_w, bool adjoint, bool pair, bool cz, bool mb = false) {
+const void* pcg_kernel(int ell_w, bool adjoint, bool pair, bool cz, bool mb = false, bool wb = false) {
   if (mb) {
     if (adjoint)
       return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, false, true>
@@ -1523,6 +1533,15 @@ const void* pcg_kernel(int ell_w, bool adjoint, bool pair, bool cz, bool mb = fa
                        : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false, true, false>
                                      : (const void*)k_pcg<R, 64, false, false, true, false>;
   }
+  if (wb) {
+    if (adjoint)
+      return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, false, false, true>
+                         : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false, false, false, true>
+                                       : (const void*)k_pcg<R, 64, true, false, false, false, true>;
+    return ell_w <= 16 ? (const void*)k_pcg<R, 16, false, false, false, false, true>
+                       : ell_w <= 32 ? (const void*)k_pcg<R, 32, false, false, false, false, true>
+                                     : (const void*)k_pcg<R, 64, false, false, false, false, true>;
+  }
   if (adjoint)
     return ell_w <= 16 ? (const void*)k_pcg<R, 16, true, false, false, false>
                        : ell_w <= 32 ? (const void*)k_pcg<R, 32, true, false, false, false>
@@ -1543,7 +1562,8 @@ hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s,
   // the adjoint kernels wrote the right-hand side in the layout of the grid
   // the constants were made for
   if (adjoint && c.cg_soa != (pair ? 1 : 0)) return hipErrorInvalidValue;
-  const void* f = pcg_kernel<R>(c.ell_w, adjoint, pair, c.coarse && !pair, mb);
+  const bool cz = c.coarse && !pair;
+  const void* f = pcg_kernel<R>(c.ell_w, adjoint, pair, cz, mb, c.cg_wb && !pair && !cz && !mb);
   if (cooperative) return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s);
   if (ev_start || ev_stop)  // the events take the kernel's own start and end times
     return hipExtLaunchKernel(f, dim3(grid), dim3(kPcgBlock), args, 0, s, ev_start, ev_stop, 0);
@@ -1553,15 +1573,15 @@ hipError_t launch_pcg(const Dev<R>& d, const Consts& c, int grid, hipStream_t s,
 
 // Workgroups of the CG kernel that can be resident at once for a matrix of
 // ELL width ell_w: the smallest occupancy of its variants (forward and
-// adjoint; unpaired, paired, with the coarse correction and per mesh) times
-// the compute units (0 on a runtime error).
+// adjoint; unpaired, paired, with the coarse correction, per mesh and with
+// write-back stores) times the compute units (0 on a runtime error).
 template <typename R>
 int pcg_max_grid(int ell_w) {
   int occ = 1 << 30, dev = 0, cus = 0;
-  for (int v = 0; v < 8; ++v) {
+  for (int v = 0; v < 10; ++v) {
     int o = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, pcg_kernel<R>(ell_w, v & 1, (v >> 1) == 1, (v >> 1) == 2,
-                                                                      (v >> 1) == 3),
+                                                                      (v >> 1) == 3, (v >> 1) == 4),
                                                      kPcgBlock, 0) != hipSuccess)
       return 0;
     occ = std::min(occ, o);

@@ -46,7 +46,7 @@ class Params(ctypes.Structure):
                 ("adj_max_iter", ctypes.c_int32), ("adj_aa_m", ctypes.c_int32), ("aa_m", ctypes.c_int32),
                 ("aa_guard", ctypes.c_int32), ("aa_slack", ctypes.c_double), ("barrier_timeout_ms", ctypes.c_double),
                 ("pcg_eta_min", ctypes.c_double), ("pcg_coarse", ctypes.c_int32), ("pcg_per_mesh", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("pad_g", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("pcg_store", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -211,3 +211,11 @@ def test_per_mesh_cg_parameter_and_plan_validate_on_the_host():
         assert L.gs_cg_plan(h, 1, k) == G.ESTATE  # not bound to a device
     finally:
         L.gs_destroy(h)
+
+
+def test_graph_and_store_parameters_are_validated():
+    m = voxel_box(2, 1, 1)
+    for kw in (dict(graph=-1), dict(graph=2), dict(pcg_store=-1), dict(pcg_store=3)):
+        assert _create(m, **kw)[0] == G.EINVAL, kw
+    p = G.default_params()
+    assert (p.graph, p.pcg_store) == (0, 0)
