@@ -475,6 +475,12 @@ hipError_t upload(char* base, size_t off, const std::vector<T>& v, hipStream_t s
 
 constexpr int kWbRows = 700000;
 
+// The CG state stored write-back: forced, or by default above kWbRows rows
+// (state far beyond the caches, the iteration bound by memory traffic).
+bool store_wb(const gs_problem* p) {
+  return p->prm.pcg_store == 2 || (p->prm.pcg_store == 0 && p->n > kWbRows);
+}
+
 // A batch's CG with its own workgroups per mesh.
 bool per_mesh_cg(const gs_problem* p) { return p->prm.pcg_per_mesh && p->M > 1; }
 
@@ -648,8 +654,7 @@ Consts make_consts(const gs_problem* p) {
   c.a_parts = (p->prm.self_collision && p->T < kTetQueryWide) ? cdiv(4L * p->T, kBlock) : cdiv(p->T, kBlock);
   c.ell_w = p->ell_w;
   c.per_mesh = per_mesh_cg(p) ? 1 : 0;
-  // write-back CG state above kWbRows rows (state far beyond the caches)
-  c.cg_wb = (p->prm.pcg_store == 2 || (p->prm.pcg_store == 0 && p->n > kWbRows)) ? 1 : 0;
+  c.cg_wb = store_wb(p) ? 1 : 0;
   c.cg_soa = (!c.per_mesh && pcg_paired(p->prec, p->ell_w, p->n, p->pcg_grid)) ? 1 : 0;
   c.trace_len = p->trace_len;
   c.c1 = p->prm.c1;

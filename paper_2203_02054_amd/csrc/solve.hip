@@ -1403,8 +1403,15 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
         R aa[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-          jj[k] = ecol[(size_t)(k0 + k) * n + v];
-          aa[k] = evs[(size_t)(k0 + k) * n + v];
+          if constexpr (WB) {
+            // streamed once per iteration: kept from displacing the
+            // neighbours' state lines in L2
+            jj[k] = __builtin_nontemporal_load(&ecol[(size_t)(k0 + k) * n + v]);
+            aa[k] = __builtin_nontemporal_load(&evs[(size_t)(k0 + k) * n + v]);
+          } else {
+            jj[k] = ecol[(size_t)(k0 + k) * n + v];
+            aa[k] = evs[(size_t)(k0 + k) * n + v];
+          }
         }
 
         W4<R> nr[CH], nw[CH], nsv[CH];
