@@ -201,6 +201,11 @@ def test_fp32_default_solve_reaches_a_fixed_point_of_the_oracle_map(G):
     say("  oracle from gpu state:", sto["iters"], "iterations; err/diag", err, "(tol 1e-6 result:", e6, ")")
     assert sto["converged"] and Ao.same_set(A)
     assert err < 1e-5
+    # the default result's distance to the fixed point is its residual times
+    # the map's condition (err / r at the tight tolerance measures that
+    # condition here, about 120): above 1e-5 of the diagonal at r = 1e-6
+    # (measured 2.6e-5), within twice residual times condition
+    assert e6 <= 2.0 * (err / st["residual"]) * st6["residual"]
 
 
 def test_rest_state_and_closed_form_expansion(G):
