@@ -820,6 +820,7 @@ __global__ __launch_bounds__(kBlock) void k_unr_restore(Dev<R> d, Consts c, DevS
     st->ticket = 0;
     st->n_contacts = 0;
     st->bar_count = 0;
+    st->mb_last = 0u;
     run->done = RUNNING;
   }
 }
@@ -866,6 +867,7 @@ __global__ __launch_bounds__(kBlock) void k_unr_rhs(Dev<R> d, Consts c) {
     st->done = RUNNING;
     st->ticket = 0;
     st->bar_count = 0;
+    st->mb_last = 0u;
     st->pcg_last = 0;
   }
 }

@@ -129,3 +129,31 @@ def test_per_mesh_frozen_and_single_mesh(G):
     assert s2["pcg_iters_total"] == 2 * s1["pcg_iters_total"]
     for m in range(2):
         np.testing.assert_array_equal(_split(x2, lay, m), x1)
+
+
+def test_per_mesh_adjoint_is_each_mesh_alone(G):
+    """The implicit adjoint of a per-mesh batch (plain adjoint iteration, so
+    each mesh stops on its own test) gives each mesh the gradient of its
+    solve alone, bit for bit."""
+    wls = _workloads()[:3]
+    kw = dict(self_collision=1, tol=1e-6, adj_aa_m=0, adj_tol=1e-5, adj_max_iter=3000)
+    with G.Problem.batch(wls, precision=4, pcg_per_mesh=1, **kw) as gp:
+        plan = gp.cg_plan()
+        alpha = np.concatenate([w.alpha for w in wls])
+        x, st = gp.solve(alpha)
+        lay = gp.layout()
+        g = np.zeros((3, gp.n))
+        g[:, ::5] = 1.0
+        ga, sa = gp.adjoint(gp.tensor(g))
+        ga = ga.cpu().numpy()
+    say("per-mesh adjoint", sa, "plan", plan)
+    c0 = 0
+    for m, w in enumerate(wls):
+        with G.Problem.from_workload(w, precision=4, pcg_blocks=int(plan[m]), fixed_iters=0, **kw) as g1:
+            _, s1 = g1.solve(w.alpha)
+            v0, v1 = lay["vert"][m], lay["vert"][m + 1]
+            ga1, sa1 = g1.adjoint(g1.tensor(g[:, v0:v1]))
+            ga1 = ga1.cpu().numpy()
+        say("  mesh", m, "alone adjoint", sa1)
+        np.testing.assert_array_equal(ga[c0:c0 + w.n_chambers], ga1)
+        c0 += w.n_chambers
