@@ -49,8 +49,7 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a 256 MiB copy) on
 # the build the counters were taken with, keyed by workload; an entry is
 # removed when its kernel changes.
-PMC_TRAFFIC = {"gripper": 7178472028,     # profiles/gripper_pcg_hbm_traffic.md
-               "batched": 33021439799}    # profiles/batched_pcg_hbm_traffic.md
+PMC_TRAFFIC = {}  # re-measured after the two-level barrier (profiles/*_hbm_traffic.md)
 
 
 def pcg_bytes_per_iteration(info, W):

@@ -358,8 +358,8 @@ gs_status gs_adjoint_unrolled(gs_problem* p, const void* dev_alpha, const void* 
 
 /* Choose the CG kernel's grid for this problem: times `iters` fixed
  * iterations from dev_x (with the stored contact set) for the default grid
- * (about 256 rows per block) and every power-of-two grid that can be
- * resident, keeps the fastest in params.pcg_blocks, and restores dev_x and
+ * (about 256 rows per block) and every grid of 2^k or 3 x 2^k workgroups
+ * that can be resident, keeps the fastest in params.pcg_blocks, and restores dev_x and
  * the stored contact set.  *chosen (may be NULL) receives the grid,
  * *ms_per_iter (may be NULL) its time per outer iteration.  With
  * pcg_per_mesh on a batch the candidates are budgets the per-mesh plan

@@ -336,6 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(Dev<R> d, Consts c) {
     st->energy = 0.0;
     st->bar_count = 0;
     st->mb_last = 0u;
+    for (int i = 0; i <= kBarGroups; ++i) d.bar2[64 * i] = 0u;
   }
 }
 
@@ -821,6 +822,7 @@ __global__ __launch_bounds__(kBlock) void k_unr_restore(Dev<R> d, Consts c, DevS
     st->n_contacts = 0;
     st->bar_count = 0;
     st->mb_last = 0u;
+    for (int i = 0; i <= kBarGroups; ++i) d.bar2[64 * i] = 0u;
     run->done = RUNNING;
   }
 }
@@ -868,6 +870,7 @@ __global__ __launch_bounds__(kBlock) void k_unr_rhs(Dev<R> d, Consts c) {
     st->ticket = 0;
     st->bar_count = 0;
     st->mb_last = 0u;
+    for (int i = 0; i <= kBarGroups; ++i) d.bar2[64 * i] = 0u;
     st->pcg_last = 0;
   }
 }

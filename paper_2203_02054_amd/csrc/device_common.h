@@ -175,6 +175,53 @@ __device__ __forceinline__ bool grid_barrier(unsigned* count, unsigned& target, 
   return ok_sh != 0;
 }
 
+// Two-level grid barrier for larger grids: workgroup b arrives at the
+// counter of group b mod NG (NG = 8: one group per XCD, as consecutive
+// workgroups are placed round-robin over the XCDs), the group's last arrival
+// passes one arrival on to the top counter, and every workgroup waits on the
+// top counter.  G arrivals on one word become at most G/NG per group word
+// plus NG on the top word.  `inst` counts this launch's barriers (the
+// counters are monotonic within a launch and cleared after it); the give-up
+// rule is grid_barrier's.  grp[64 g] is group g's counter (a cache line
+// apart), top the top counter.
+__device__ __forceinline__ bool grid_barrier2(unsigned* grp, unsigned* top, unsigned& inst, unsigned nblocks,
+                                              unsigned NG, int* done, unsigned long long timeout) {
+  __shared__ int ok_sh2;
+  inst += 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned g = blockIdx.x % NG;
+    const unsigned members = (nblocks - g + NG - 1) / NG;  // workgroups b < nblocks with b mod NG = g
+    const unsigned groups = nblocks < NG ? nblocks : NG;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned t = __hip_atomic_fetch_add(grp + 64 * g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t + 1 == inst * members) {
+      // the group's last arrival: what the group published happens before
+      // the top arrival that the waiting workgroups observe
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const unsigned target = inst * groups;
+    int ok = 1;
+    const unsigned long long t0 = wall_clock64();
+    while ((int)(__hip_atomic_load(top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == STALLED ||
+          wall_clock64() - t0 >= timeout) {
+        int expect = RUNNING;
+        __hip_atomic_compare_exchange_strong(done, &expect, (int)STALLED, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok_sh2 = ok;
+  }
+  __syncthreads();
+  return ok_sh2 != 0;
+}
+
 // ---- exact predicates -------------------------------------------------------
 // Six times the signed volume det[p1-p0, p2-p0, p3-p0], evaluated in the
 // order written (contraction off), FP64.

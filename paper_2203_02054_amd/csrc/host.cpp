@@ -60,7 +60,7 @@ struct Layout {
   size_t rcount, alpha_stage, acc_max;
   size_t cz_inv, cz_nb, cz_rho, cz_ri;
   size_t mo_tri, mo_id, mo_node, mo_flag, mo_tgt, mo_nrm, mo_prim;
-  size_t seg, mbar;
+  size_t seg, mbar, bar2;
   size_t total;
 };
 
@@ -355,6 +355,7 @@ Layout make_layout(const gs_problem* p) {
   L.alpha_stage = take((size_t)p->nch * W);
   L.seg = take((size_t)std::max(p->M, kMaxPcgGrid) * sizeof(int4));
   L.mbar = take((size_t)p->M * 4);
+  L.bar2 = take((size_t)kBarWords * 4);
   L.total = align256(off);
   return L;
 }
@@ -462,6 +463,7 @@ Dev<R> make_dev(const gs_problem* p) {
   d.dbg_cap = 0;
   d.seg = (const int4*)(b + L.seg);
   d.mbar = (unsigned*)(b + L.mbar);
+  d.bar2 = (unsigned*)(b + L.bar2);
   return d;
 }
 
@@ -474,6 +476,7 @@ hipError_t upload(char* base, size_t off, const std::vector<T>& v, hipStream_t s
 }
 
 constexpr int kWbRows = 700000;
+constexpr int kBar2Grid = 128;
 
 // The CG state stored write-back: forced, or by default above kWbRows rows
 // (state far beyond the caches, the iteration bound by memory traffic).
@@ -655,6 +658,9 @@ Consts make_consts(const gs_problem* p) {
   c.ell_w = p->ell_w;
   c.per_mesh = per_mesh_cg(p) ? 1 : 0;
   c.cg_wb = store_wb(p) ? 1 : 0;
+  // the two-level grid barrier above kBar2Grid workgroups (one counter takes
+  // every arrival below that, and it measured as fast there)
+  c.bar2 = (!c.per_mesh && p->pcg_grid > kBar2Grid) ? 1 : 0;
   c.cg_soa = (!c.per_mesh && pcg_paired(p->prec, p->ell_w, p->n, p->pcg_grid)) ? 1 : 0;
   c.trace_len = p->trace_len;
   c.c1 = p->prm.c1;
@@ -742,6 +748,7 @@ gs_status bind_impl(gs_problem* p) {
   HIPCHK(hipMemsetAsync(b + L.mchanged, 0, (size_t)p->M * 4, s));
   HIPCHK(hipMemsetAsync(b + L.mdone, 0, (size_t)p->M * 4, s));
   HIPCHK(hipMemsetAsync(b + L.mbar, 0, (size_t)p->M * 4, s));
+  HIPCHK(hipMemsetAsync(b + L.bar2, 0, (size_t)kBarWords * 4, s));
   HIPCHK(hipMemsetAsync(b + L.cact, 0, (size_t)p->S * p->slots, s));
   HIPCHK(hipMemsetAsync(b + L.st, 0, sizeof(DevStatus), s));
   HIPCHK(hipMemsetAsync(b + L.hcount, 0, (size_t)p->H * 4, s));
@@ -2243,10 +2250,16 @@ gs_status gs_autotune(gs_problem* p, const void* alpha, void* x, int32_t iters, 
   const gs_params saved = p->prm;
   const bool prof = p->prof.on;
   p->prof.on = false;
-  // candidates: the default (about 256 rows per block) and every power of two
+  // candidates: the default (about 256 rows per block), every power of two
+  // and every 3 x 2^k (the grids between: row ranges and the barrier's cost
+  // trade against each other)
   std::vector<int> cand = {std::max(1, std::min({cdiv(p->n, kPcgRowsPerBlock), maxg, kMaxPcgGrid, p->nparts / 2}))};
-  for (int g = 1; g <= std::min({maxg, kMaxPcgGrid, p->nparts / 2}); g *= 2)
+  const int glim = std::min({maxg, kMaxPcgGrid, p->nparts / 2});
+  for (int g = 1; g <= glim; g *= 2) {
     if (g != cand[0]) cand.push_back(g);
+    const int h = 3 * g;
+    if (g >= 1 && h <= glim && h < 4 * g && h != cand[0] && (h & (h - 1)) != 0) cand.push_back(h);
+  }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

@@ -19,6 +19,8 @@ constexpr int kPcgRowsPerBlock = 256; // default rows per CG block (grid = n / 2
 // beats prefetching and lane sharing) and is not fused with the local step.
 constexpr int kTetQueryWide = 1 << 18;
 constexpr int kMaxPcgGrid = 1024;     // workgroups of the persistent CG kernel at most
+constexpr int kBarGroups = 8;          // groups of the two-level grid barrier (one per XCD)
+constexpr int kBarWords = 64 * (kBarGroups + 1);  // its group counters a cache line apart, then the top counter
 constexpr int kAaMaxMem = 16;         // Anderson memory at most (forward and adjoint)
 constexpr int kFaaRows = 1024;        // rows per block of the acceleration's dot-product kernel
 constexpr int kStaticCandCap = 1 << 17;  // candidate pairs per list of the allocation-free collision check
@@ -118,6 +120,7 @@ struct Consts {
   int faa_nblk;         // blocks of the acceleration's dot-product kernel
   int per_mesh;         // a batch's CG runs per mesh (its own workgroups, scalars and stopping test)
   int cg_wb;            // CG state stored write-back (1) or write-through (0)
+  int bar2;             // the whole-grid CG kernel uses the two-level grid barrier
   double c1, c2, kappa, tol, pcg_eta;
   double pcg_eta_min;   // > 0: forward solves stop at clamp(previous r_k, pcg_eta_min, pcg_eta)
   double faa_slack;     // relative slack of the guard test
@@ -244,6 +247,7 @@ struct Dev {
   // the mesh's workgroups, the mesh's first workgroup}; barrier counters
   const int4* seg;         // [grid]
   unsigned* mbar;          // [M] arrivals at the mesh's barrier in the running launch (0 between launches)
+  unsigned* bar2;          // [9 * 64] two-level grid barrier: group counters (64 words apart), top counter
 };
 
 // ---------------------------------------------------------------------------

@@ -88,6 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Dev<R> d, Consts c, const R* __
     st->energy = 0.0;
     st->bar_count = 0;
     st->mb_last = 0u;
+    for (int i = 0; i <= kBarGroups; ++i) d.bar2[64 * i] = 0u;
   }
 }
 
@@ -590,6 +591,8 @@ __device__ __forceinline__ void finish_tail(const Dev<R>& d, const Consts& c, in
   st->n_pen = 0;
   st->ticket = 0;
   st->bar_count = 0u;  // every block is past its last barrier
+  if (c.bar2)
+    for (int i = 0; i <= kBarGroups; ++i) d.bar2[64 * i] = 0u;
   __hip_atomic_store(&st->done, code, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -736,6 +739,13 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
   }
   unsigned* bc = &d.st->bar_count;
   unsigned bar_target = 0;  // arrivals the next grid barrier waits for
+  unsigned bar_inst = 0;    // barriers of this launch (two-level barrier)
+  // the whole-grid barrier: flat, or (c.bar2) two-level for larger grids
+  auto wbar = [&]() -> bool {
+    if (c.bar2)
+      return grid_barrier2(d.bar2, d.bar2 + 64 * kBarGroups, bar_inst, G, kBarGroups, &d.st->done, c.bar_timeout);
+    return grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout);
+  };
   // the barrier that publishes the partials: grid-wide, or (MB) the block's
   auto gbar = [&]() -> bool {
     if constexpr (MB) {
@@ -745,7 +755,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       }
       return grid_barrier(d.mbar + sg.x, bar_target, sg.z, &d.st->done, c.bar_timeout);
     } else {
-      return grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout);
+      return wbar();
     }
   };
   W4<R>* __restrict__ x = reinterpret_cast<W4<R>*>(d.dl);
@@ -1026,7 +1036,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
       if (threadIdx.x == 0) d.part_d[blockIdx.x] = bs;
       // a batch: each mesh gets its own weights (the meshes' systems are
       // independent), its sums taken by one block in a fixed order
-      if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
+      if (!wbar()) return;
       const double* q = reinterpret_cast<const double*>(cg0 + 3 * n);
       for (int m = blockIdx.x; m < c.M; m += G) {
         const int v0 = d.mesh[m].vbeg, v1 = d.mesh[m].vend;
@@ -1044,7 +1054,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
           d.mgam[2 * m + 1] = m2;
         }
       }
-      if (!grid_barrier(bc, bar_target, G, &d.st->done, c.bar_timeout)) return;
+      if (!wbar()) return;
     }
     // x_0, r_0 = b - g1 A w1 - g2 A w2 - g3 A w3 and, in the same pass,
     // w_0 = A u_0: the neighbours' r_0 are rebuilt from their
@@ -1482,6 +1492,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg(Dev<R> d, Consts c) {
     if (t == G - 1) {
       d.st->ticket = 0;
       d.st->bar_count = 0u;
+      if (c.bar2)
+        for (int i = 0; i <= kBarGroups; ++i) d.bar2[64 * i] = 0u;
     }
   }
 }
