@@ -45,11 +45,15 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the dominant kernel measured with rocprofv3 counters
-# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a 256 MiB copy) on
-# the build the counters were taken with, keyed by workload; an entry is
-# removed when its kernel changes.
-PMC_TRAFFIC = {}  # re-measured after the two-level barrier (profiles/*_hbm_traffic.md)
+# HBM bytes per CG iteration of the dominant kernel measured with rocprofv3
+# counters (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from 256 MiB
+# device copies; the launch's fixed parts spread over its CG iterations), keyed
+# by workload and CG grid: a run on another grid reports no traffic, and an
+# entry is removed when its kernel changes (profiles/*_hbm_traffic.md).
+PMC_TRAFFIC_PER_CG_ITERATION = {
+    ("gripper", 192): 24140421,    # k_pcg<float, 16, false, false, false, false, false>
+    ("batched", 256): 558327374,   # k_pcg<float, 16, false, false, false, false, true>
+}
 
 
 def pcg_bytes_per_iteration(info, W):
@@ -88,8 +92,9 @@ def roofline_of(prof, info, W, pcg_iters, traffic_key=None):
     per_launch = m * pcg_bytes_per_iteration(info, W)
     achieved = per_launch / (avg_ms / 1e3) / 1e9
     extra = pcg_extra_bytes(info, W)
+    pmc = PMC_TRAFFIC_PER_CG_ITERATION.get(traffic_key)
     return {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": PMC_TRAFFIC.get(traffic_key),
+            "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": int(pmc * m) if pmc else None,
             "kernel": "pcg", "avg_launch_us": round(1e3 * avg_ms, 3), "launches": launches,
             "cg_iterations_per_launch": round(m, 3),
             "bytes_per_cg_iteration": int(pcg_bytes_per_iteration(info, W)),
@@ -208,7 +213,7 @@ def run_batched(G, mg, n_mesh, max_iter, sample, autotune=True):
     _, st_p = gb.solve(alpha, x)
     prof = gb.profile_read()
     gb.profile(False)
-    roof = roofline_of(prof, gb.info, 4, st_p["pcg_iters_total"], "batched")
+    roof = roofline_of(prof, gb.info, 4, st_p["pcg_iters_total"], ("batched", grid))
     # plain path on a sample of the meshes (every n_mesh/sample-th), one by one
     idx = list(range(0, n_mesh, max(1, n_mesh // sample)))[:sample]
     t_plain, work_plain = 0.0, 0
@@ -426,7 +431,7 @@ def main():
     iters = sum(s["iters"] for s in stats)
     pcg_iters = sum(s["pcg_iters_total"] for s in stats)
     value = wl.n_tets * iters / (ms / 1e3)
-    roof = roofline_of(prof, gp.info, W, pst["pcg_iters_total"], wl.name)
+    roof = roofline_of(prof, gp.info, W, pst["pcg_iters_total"], (wl.name, grid))
     solver = {k: getattr(gp.params, k) for k in ("aa_m", "aa_guard", "aa_slack", "pcg_eta", "pcg_eta_min",
                                                    "pcg_max", "tol")}
     out = {

@@ -45,6 +45,15 @@ def test_roofline_record_from_kernel_timings():
     assert r["traffic"] is None  # counters exist only for the measured workloads
 
 
+def test_roofline_traffic_only_for_the_measured_workload_and_grid():
+    info = {"n_verts": 100, "n_tets": 300, "nnz": 1500, "n_query_verts": 40}
+    prof = {"pcg": (2.0, 4)}
+    (wl, grid), per_cg = next(iter(bench.PMC_TRAFFIC_PER_CG_ITERATION.items()))
+    r = bench.roofline_of(prof, info, 4, 40, traffic_key=(wl, grid))
+    assert r["traffic"] == int(per_cg * 10)  # 10 CG iterations per launch
+    assert bench.roofline_of(prof, info, 4, 40, traffic_key=(wl, grid + 1))["traffic"] is None
+
+
 def test_physical_core_count_is_within_the_allowed_cpus():
     cores, allowed = bench.physical_cores()
     assert 1 <= cores <= allowed == len(os.sched_getaffinity(0))
