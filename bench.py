@@ -18,6 +18,9 @@ Extra legs (same JSON line):
   coarse   the headline workload's first 200 outer iterations with the
            Jacobi and with the coarse-corrected CG (fixed count).
   membrane the four-chamber membrane rig solved to 1e-6.
+  finger_sweep  the CG kernel's fraction of HBM peak against size: the
+           finger at voxel sizes 2, 1.2, 0.8 and 0.6 mm (26,880 to 971,634
+           tets), its first 30 outer iterations (fixed count).
   adjoint  gs_adjoint at the converged gripper for the fingertip loss (30
            tip vertices to seeded targets, gradient w.r.t. the 24 chamber
            ratios): gradients per second, and the speedup over a
@@ -326,6 +329,43 @@ def run_coarse(G, wl, grid, iters):
     return res
 
 
+def run_finger_sweep(G, mg, hs=(2.0, 1.2, 0.8, 0.6), iters=30):
+    """The CG kernel's roofline against problem size: the finger (8
+    chambers, alpha 2.0, self-collision, default solver settings) at voxel
+    sizes hs, its first `iters` outer iterations from rest on the autotuned
+    CG grid.  Per size: the time per outer iteration, and the CG kernel's
+    average launch time from per-kernel HIP events in a second run with its
+    fraction of HBM peak by B_pcg.  A fixed iteration count, not a converged
+    solve."""
+    out = []
+    for h in hs:
+        w = mg.finger(h, 8, 2.0)
+        with G.Problem.from_workload(w, precision=4, fixed_iters=iters) as p:
+            a = p.tensor(w.alpha)
+            x0 = p.tensor(w.rest_xyz)
+            grid = p.autotune(a, x0.clone(), iters=min(iters, 8))[0]
+
+            def run():
+                p.reset_contacts()
+                return p.solve(a, x0.clone())[1]
+
+            run()
+            ms, st = timed_on(p.stream, run)
+            p.profile(True)
+            st_p = run()
+            prof = p.profile_read()
+            p.profile(False)
+            roof = roofline_of(prof, p.info, 4, st_p["pcg_iters_total"])
+            out.append({"h_mm": h, "tets": w.n_tets, "verts": w.n_verts, "nnz": p.info["nnz"], "pcg_grid": grid,
+                        "ms_per_outer_iteration": round(ms / st["iters"], 4),
+                        "tet_iterations_per_s": round(w.n_tets * st["iters"] / (ms / 1e3), 1),
+                        "cg_iterations_per_launch": roof["cg_iterations_per_launch"],
+                        "cg_launch_us": roof["avg_launch_us"],
+                        "us_per_cg_iteration": round(roof["avg_launch_us"] / roof["cg_iterations_per_launch"], 3),
+                        "achieved_GBs": roof["achieved"], "frac": roof["frac"]})
+    return {"outer_iterations": iters, "sizes": out}
+
+
 def run_membrane(G, mg):
     """The membrane rig (40,446 tets: four chamber units under a sheet) solved
     from rest to 1e-6: tet-iterations/s, as the headline."""
@@ -352,7 +392,7 @@ def main():
     ap.add_argument("--batched-max-iter", type=int, default=1000)
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-legs", action="store_true", help="skip the coarse-correction and membrane legs")
+    ap.add_argument("--no-legs", action="store_true", help="skip the coarse-correction, membrane and finger size-sweep legs")
     ap.add_argument("--coarse-iters", type=int, default=200)
     ap.add_argument("--adjoint-max-iter", type=int, default=600)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default CG grid (counter runs)")
@@ -486,6 +526,11 @@ def main():
         out["coarse"] = run_coarse(G, wl, grid, a.coarse_iters)
         print("# membrane", file=sys.stderr, flush=True)
         out["membrane"] = run_membrane(G, mg)
+        print("# finger size sweep", file=sys.stderr, flush=True)
+        try:
+            out["finger_sweep"] = run_finger_sweep(G, mg)
+        except Exception as e:  # a supplementary leg: report, do not lose the line
+            out["finger_sweep"] = {"error": f"{type(e).__name__}: {e}"}
     if not a.no_batched:
         out["batched"] = run_batched(G, mg, a.batched_meshes, a.batched_max_iter, a.plain_sample,
                                      autotune=not a.no_autotune)
