@@ -29,6 +29,8 @@ Extra legs (same JSON line):
            rest (iterations capped): sum_i T_i K_i / t over the meshes that
            reached 1e-6 (the capped meshes' work is reported apart), and the
            speedup over solving a sample of the meshes one by one.
+  stream_copy  device-to-device copies of 2 GiB: the streaming bandwidth
+           this GPU reaches, beside the 8 TB/s peak of the roofline.
   cpu_baseline  the FP64 oracle on the host cores for a bounded sample of one
            gripper iteration, with all physical cores of this process's CPU
            share and with one thread.
@@ -366,6 +368,29 @@ def run_finger_sweep(G, mg, hs=(2.0, 1.2, 0.8, 0.6), iters=30):
     return {"outer_iterations": iters, "sizes": out}
 
 
+def run_stream_copy(mib=2048, reps=10):
+    """Device-to-device copies of `mib` MiB (torch's copy kernel): bytes read
+    plus bytes written per second, the bandwidth a streaming kernel reaches on
+    this GPU, beside the 8 TB/s peak the roofline fractions use."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * 4 * n / (ms / 1e3) / 1e9
+    del src, dst
+    return {"bytes_per_copy": 2 * 4 * n, "ms_per_copy": round(ms, 4), "GBs": round(gbs, 1),
+            "frac_of_peak": round(gbs / PEAK_HBM_GBS, 4), "note": "read + write bytes of a device copy"}
+
+
 def run_membrane(G, mg):
     """The membrane rig (40,446 tets: four chamber units under a sheet) solved
     from rest to 1e-6: tet-iterations/s, as the headline."""
@@ -534,6 +559,10 @@ def main():
     if not a.no_batched:
         out["batched"] = run_batched(G, mg, a.batched_meshes, a.batched_max_iter, a.plain_sample,
                                      autotune=not a.no_autotune)
+    try:
+        out["stream_copy"] = run_stream_copy()
+    except Exception as e:  # a supplementary figure: report, do not lose the line
+        out["stream_copy"] = {"error": f"{type(e).__name__}: {e}"}
     if not a.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = run_cpu_baseline(wl)
