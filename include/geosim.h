@@ -131,14 +131,17 @@ typedef struct {
                              workgroup's row range, its matrix from A_el; one
                              mesh, rows-of-three-vectors kernel variant, at
                              most 256 workgroups); 0 (default): Jacobi alone */
-  int32_t pcg_per_mesh;   /* a batch (M > 1) only.  1: the global step's CG runs
-                             one workgroup per mesh, each with its own scalars,
-                             stopping test and iteration count (a mesh's
-                             iterations and positions are those of solving it
-                             alone with pcg_blocks = 1); pcg_blocks is not
-                             used.  0 (default): one CG over the whole batch's
-                             rows with per-mesh warm starts and a shared
-                             stopping test.  Ignored for one mesh.          */
+  int32_t pcg_per_mesh;   /* a batch (M > 1) only.  1 or 2: the global step's
+                             CG runs on each mesh's own workgroups (the plan
+                             gs_cg_plan reports), each mesh with its own
+                             scalars, stopping test and iteration count (a
+                             mesh's iterations and positions are those of
+                             solving it alone with as many CG workgroups);
+                             1 shares the budget pcg_blocks by rows, 2 plans
+                             by longest processing time (see gs_cg_plan).
+                             0 (default): one CG over the whole batch's rows
+                             with per-mesh warm starts and a shared stopping
+                             test.  Ignored for one mesh.                   */
   int32_t graph;          /* 1: gs_solve runs each chunk of check_every outer
                              iterations after the first as one HIP graph
                              launch (the chunk's kernels, captured once and
@@ -369,16 +372,22 @@ gs_status gs_adjoint_unrolled(gs_problem* p, const void* dev_alpha, const void* 
 gs_status gs_autotune(gs_problem* p, const void* dev_alpha, void* dev_x, int32_t iters, int32_t* chosen,
                       double* ms_per_iter);
 
-/* The per-mesh CG plan of a bound batch (params.pcg_per_mesh = 1, M > 1):
- * blocks[m] (host array of M int32, caller-owned) receives the number of CG
- * workgroups mesh m gets.  A mesh's global step (Eq. 8's linear system, one
- * per mesh) is then solved as a solve of that mesh alone with pcg_blocks =
- * blocks[m] would solve it.  The plan gives each mesh one workgroup plus
- * its share, by rows, of the budget (pcg_blocks, else the workgroups that
- * can be resident at once) beyond one per mesh, at most one workgroup per
- * 512 rows.  Without the per-mesh CG every entry is 1.  GS_EINVAL for a null
- * argument or M other than the problem's mesh count; GS_ESTATE before
- * gs_bind. */
+/* The per-mesh CG plan of a bound batch (params.pcg_per_mesh = 1 or 2,
+ * M > 1): blocks[m] (host array of M int32, caller-owned) receives the
+ * number of CG workgroups mesh m gets.  A mesh's global step (Eq. 8's linear
+ * system, one per mesh) is then solved as a solve of that mesh alone with
+ * pcg_blocks = blocks[m] would solve it.  With 1 the plan gives each mesh one
+ * workgroup plus its share, by rows, of the budget (pcg_blocks, else the
+ * workgroups that can be resident at once) beyond one per mesh; all of them
+ * fit on the device at once.  With 2 (longest processing time) every
+ * workgroup gets about (all rows) / budget rows, so a large mesh is split and
+ * a small one keeps one workgroup; the grid may exceed what can be resident,
+ * the split meshes come first in block order within half the resident
+ * capacity, and the single-workgroup meshes follow largest first, the
+ * smallest queueing for the workgroups that finish first.  Either way at
+ * most one workgroup per 512 rows.  Without the per-mesh CG every entry is
+ * 1.  GS_EINVAL for a null argument or M other than the problem's mesh
+ * count; GS_ESTATE before gs_bind. */
 gs_status gs_cg_plan(const gs_problem* p, int32_t M, int32_t* blocks);
 
 /* Implicit adjoint of the last gs_solve (not in the paper: the gradient of

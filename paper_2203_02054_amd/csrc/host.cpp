@@ -237,7 +237,7 @@ gs_status check_params(const gs_params* p) {
     return fail(GS_EINVAL, "barrier_timeout_ms must be >= 0");
   if (!(p->pcg_eta_min >= 0) || !std::isfinite(p->pcg_eta_min)) return fail(GS_EINVAL, "pcg_eta_min must be >= 0");
   if (p->pcg_coarse != 0 && p->pcg_coarse != 1) return fail(GS_EINVAL, "pcg_coarse must be 0 or 1");
-  if (p->pcg_per_mesh != 0 && p->pcg_per_mesh != 1) return fail(GS_EINVAL, "pcg_per_mesh must be 0 or 1");
+  if (p->pcg_per_mesh < 0 || p->pcg_per_mesh > 2) return fail(GS_EINVAL, "pcg_per_mesh must be 0, 1 or 2");
   if (p->graph != 0 && p->graph != 1) return fail(GS_EINVAL, "graph must be 0 or 1");
   if (p->pcg_store < 0 || p->pcg_store > 2) return fail(GS_EINVAL, "pcg_store must be 0, 1 or 2");
   return GS_OK;
@@ -493,10 +493,74 @@ bool per_mesh_cg(const gs_problem* p) { return p->prm.pcg_per_mesh && p->M > 1; 
 // as the rows of that mesh alone split over k_m workgroups of the unpaired
 // kernel.  Uploaded on the problem's stream.
 constexpr int kSegMinRows = 512;
+// The longest-processing-time plan (pcg_per_mesh = 2): the budget B
+// (pcg_blocks, else the workgroups that can be resident at once) is read as
+// the workgroups one pass of the device runs, and every workgroup should get
+// about (all rows) / B rows: mesh m gets ceil(n_m / that) workgroups (at most
+// one per kSegMinRows rows), so a large mesh is split and a small one keeps
+// one.  The grid may then exceed what can be resident, which only a
+// single-workgroup mesh may wait out: the meshes with several workgroups,
+// whose workgroups wait for each other, come first in block order (placed
+// first by an ordinary launch) and together take at most half the resident
+// capacity, the split of the mesh that loses least being undone until they
+// do; the single-workgroup meshes follow, largest first, so the smallest
+// ones queue for the workgroups that finish first.
+void plan_lpt(gs_problem* p, int maxg, std::vector<int>& order) {
+  const int M = p->M;
+  const long B = std::max(1, std::min(p->prm.pcg_blocks > 0 ? p->prm.pcg_blocks : maxg, kMaxPcgGrid));
+  std::vector<long> nm(M);
+  long tot = 0;
+  for (int m = 0; m < M; ++m) tot += (nm[m] = p->vbeg[m + 1] - p->vbeg[m]);
+  const long tgt = std::max(1L, (tot + B - 1) / B);
+  long multi = 0, all = 0;
+  for (int m = 0; m < M; ++m) {
+    const long cap = std::max(1L, nm[m] / kSegMinRows);
+    p->seg_k[m] = (int)std::max(1L, std::min((nm[m] + tgt - 1) / tgt, cap));
+    all += p->seg_k[m];
+    if (p->seg_k[m] > 1) multi += p->seg_k[m];
+  }
+  const long multi_cap = std::max(0, maxg / 2), all_cap = std::max(M, kMaxPcgGrid);
+  while (multi > multi_cap || all > all_cap) {
+    // undo one workgroup of the split mesh whose rows per workgroup grow least
+    int best = -1;
+    double best_rows = 0.0;
+    for (int m = 0; m < M; ++m)
+      if (p->seg_k[m] > 1) {
+        const double r = (double)nm[m] / (p->seg_k[m] - 1);
+        if (best < 0 || r < best_rows) {
+          best = m;
+          best_rows = r;
+        }
+      }
+    if (best < 0) break;
+    multi -= p->seg_k[best];
+    p->seg_k[best] -= 1;
+    all -= 1;
+    if (p->seg_k[best] > 1) multi += p->seg_k[best];
+  }
+  order.resize(M);
+  for (int m = 0; m < M; ++m) order[m] = m;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const bool sa = p->seg_k[a] > 1, sb = p->seg_k[b] > 1;
+    if (sa != sb) return sa;
+    return (double)nm[a] / p->seg_k[a] > (double)nm[b] / p->seg_k[b];
+  });
+}
+
 gs_status plan_segments(gs_problem* p, int maxg) {
   p->seg_k.assign(p->M, 1);
   p->seg.clear();
   if (!per_mesh_cg(p)) return GS_OK;
+  if (p->prm.pcg_per_mesh == 2) {
+    std::vector<int> order;
+    plan_lpt(p, maxg, order);
+    for (int m : order) {
+      const int k = p->seg_k[m], b0 = (int)p->seg.size();
+      for (int j = 0; j < k; ++j) p->seg.push_back(make_int4(m, j, k, b0));
+    }
+    HIPCHK(upload(p->ws, p->lay.seg, p->seg, p->stream));
+    return GS_OK;
+  }
   const int budget = std::min({p->prm.pcg_blocks > 0 ? p->prm.pcg_blocks : maxg, maxg, kMaxPcgGrid});
   const long extra = std::max(0L, (long)budget - p->M);
   for (int m = 0; m < p->M; ++m) {
@@ -778,7 +842,9 @@ gs_status bind_impl(gs_problem* p) {
 // one workgroup per mesh needs no co-residency at all; otherwise the plan
 // fits what can be resident and the same rule applies.
 bool pcg_cooperative(const gs_problem* p) {
-  if (per_mesh_cg(p)) return (int)p->seg.size() > p->M && 2 * (int)p->seg.size() > p->pcg_maxg;
+  // (the longest-processing-time plan keeps its split meshes within half the
+  // resident capacity and at the front, and takes an ordinary launch)
+  if (per_mesh_cg(p)) return p->prm.pcg_per_mesh != 2 && (int)p->seg.size() > p->M && 2 * (int)p->seg.size() > p->pcg_maxg;
   return 2 * p->pcg_grid > p->pcg_maxg;
 }
 int pcg_launch_grid(const gs_problem* p) { return per_mesh_cg(p) ? (int)p->seg.size() : p->pcg_grid; }

@@ -198,8 +198,11 @@ def test_remesh_and_progressive_entry_points_validate_on_the_host():
 
 def test_per_mesh_cg_parameter_and_plan_validate_on_the_host():
     m = voxel_box(2, 1, 1)
-    for v in (-1, 2):
+    for v in (-1, 3):
         assert _create(m, pcg_per_mesh=v)[0] == G.EINVAL, v
+    code, h, _ = _create(m, pcg_per_mesh=2)
+    assert code == G.OK
+    G.lib().gs_destroy(h)
     assert G.default_params().pcg_per_mesh == 0
     L = G.lib()
     k = (ctypes.c_int32 * 1)()

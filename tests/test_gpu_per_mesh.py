@@ -46,14 +46,11 @@ def _split(x, lay, m):
     return x[:, lay["vert"][m]:lay["vert"][m + 1]]
 
 
-@pytest.mark.parametrize("prec,aa_m,budget", [(4, 8, 0), (4, 0, 0), (8, 8, 0), (4, 8, 5)])
-def test_per_mesh_batch_is_each_mesh_alone(G, prec, aa_m, budget):
-    """budget 0: the default plan (several workgroups for the larger meshes,
-    per-mesh barriers); 5: one workgroup per mesh (block barriers)."""
+def _each_mesh_alone(G, prec, aa_m, budget, mode):
     wls = _workloads()
     kw = dict(self_collision=1, tol=1e-6 if prec == 4 else 1e-9, aa_m=aa_m, max_iter=4000)
-    say("per-mesh batch", prec, aa_m, budget, [w.n_tets for w in wls])
-    with G.Problem.batch(wls, precision=prec, pcg_per_mesh=1, pcg_blocks=budget, **kw) as gp:
+    say("per-mesh batch", prec, aa_m, budget, mode, [w.n_tets for w in wls])
+    with G.Problem.batch(wls, precision=prec, pcg_per_mesh=mode, pcg_blocks=budget, **kw) as gp:
         plan = gp.cg_plan()
         alpha = np.concatenate([w.alpha for w in wls])
         xg, st = gp.solve(alpha)
@@ -61,12 +58,12 @@ def test_per_mesh_batch_is_each_mesh_alone(G, prec, aa_m, budget):
         lay = gp.layout()
         xg = xg.cpu().numpy()
     say("  batch:", st, "per-mesh iterations", its, "plan", plan)
-    if budget == len(wls):
+    rows = np.diff(lay["vert"])
+    assert np.all(plan <= np.maximum(1, rows // 512))
+    if mode == 1 and budget == len(wls):
         assert np.all(plan == 1)
-    else:
+    elif mode == 1 or budget == 0:
         assert plan.max() > 1
-        rows = np.diff(lay["vert"])
-        assert np.all(plan <= np.maximum(1, rows // 512))
     assert st["status"] in (G.OK, G.NOT_CONVERGED)
     cg_total = 0
     for m, w in enumerate(wls):
@@ -83,6 +80,21 @@ def test_per_mesh_batch_is_each_mesh_alone(G, prec, aa_m, budget):
             assert its[m] == 0  # not converged in either
         np.testing.assert_array_equal(_split(xg, lay, m), x1)
     assert st["pcg_iters_total"] == cg_total
+
+
+@pytest.mark.parametrize("prec,aa_m,budget", [(4, 8, 0), (4, 0, 0), (8, 8, 0), (4, 8, 5)])
+def test_per_mesh_batch_is_each_mesh_alone(G, prec, aa_m, budget):
+    """budget 0: the default plan (several workgroups for the larger meshes,
+    per-mesh barriers); 5: one workgroup per mesh (block barriers)."""
+    _each_mesh_alone(G, prec, aa_m, budget, 1)
+
+
+@pytest.mark.parametrize("prec,budget", [(4, 0), (8, 0), (4, 3)])
+def test_lpt_plan_batch_is_each_mesh_alone(G, prec, budget):
+    """The longest-processing-time plan (pcg_per_mesh = 2): the split meshes
+    first in block order, the others after them largest first; each mesh is
+    still bit for bit its solve alone with as many CG workgroups."""
+    _each_mesh_alone(G, prec, 8, budget, 2)
 
 
 def test_per_mesh_batch_fp64_matches_oracle(G):
