@@ -143,13 +143,14 @@ def test_per_mesh_frozen_and_single_mesh(G):
         np.testing.assert_array_equal(_split(x2, lay, m), x1)
 
 
-def test_per_mesh_adjoint_is_each_mesh_alone(G):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_per_mesh_adjoint_is_each_mesh_alone(G, mode):
     """The implicit adjoint of a per-mesh batch (plain adjoint iteration, so
     each mesh stops on its own test) gives each mesh the gradient of its
-    solve alone, bit for bit."""
+    solve alone, bit for bit, with either workgroup plan."""
     wls = _workloads()[:3]
     kw = dict(self_collision=1, tol=1e-6, adj_aa_m=0, adj_tol=1e-5, adj_max_iter=3000)
-    with G.Problem.batch(wls, precision=4, pcg_per_mesh=1, **kw) as gp:
+    with G.Problem.batch(wls, precision=4, pcg_per_mesh=mode, **kw) as gp:
         plan = gp.cg_plan()
         alpha = np.concatenate([w.alpha for w in wls])
         x, st = gp.solve(alpha)
